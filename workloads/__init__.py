@@ -1,0 +1,149 @@
+"""Seeded synthetic boundary-displacement workloads.
+
+Shared by the tests (both the oracle side and the GPU side draw inputs from
+here) and by ``bench.py``.  It holds no part of the boundary-integral
+arithmetic: only random numbers, a spectral shaping of white noise with numpy's
+FFT, and the named workload shapes.
+
+The paper's runs are earthquake ruptures on regular boundary grids (Sec. 3-6;
+Poisson ratio 0.25, i.e. c_p/c_s = sqrt(3)).  No field data is used: the
+workloads below are nondimensional stand-ins with mu = 1, c_s = 1,
+c_p = sqrt(3), dx = 1, dt = 0.2.
+
+Random increments: for each plane p and component c a PCG64 stream seeded with
+1000*workload + 10*p + c draws white N(0,1) fields in step order; each field is
+shaped to spectral amplitude |k|^-2 (k = 0 removed) and normalised to unit RMS.
+For the larger workloads a bank of 64 such fields per (plane, component) is
+drawn once and step n uses bank[(7 n) mod 64].
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+SQRT3 = math.sqrt(3.0)
+
+
+@dataclass
+class Workload:
+    ident: int
+    name: str
+    n1: int
+    n3: int
+    planes: list                 # list of dicts: side, mu, cs, cp
+    window_cap: int
+    steps: int
+    window_mode: str = "fixed"
+    eta_w: float = 1.0
+    dt: float = 0.2
+    dx1: float = 1.0
+    dx3: float = 1.0
+    input_kind: str = "increment"
+    bank: int = 0                # 0: fresh field every step; else bank size
+    pulse: bool = False          # Gaussian ramp pulse on u1
+    slip_ramp: float = 0.0       # final uniform slip velocity on u1 (k = 0 mode)
+    extra: dict = field(default_factory=dict)
+
+    def config_dict(self):
+        return dict(n1=self.n1, n3=self.n3, dx1=self.dx1, dx3=self.dx3, dt=self.dt,
+                    planes=[dict(p) for p in self.planes], window_cap=self.window_cap,
+                    window_mode=self.window_mode, eta_w=self.eta_w,
+                    input_kind=self.input_kind)
+
+    def scaled(self, **kw):
+        d = dict(self.__dict__)
+        d.update(kw)
+        return Workload(**d)
+
+
+def _plane(side):
+    return dict(side=side, mu=1.0, cs=1.0, cp=SQRT3)
+
+
+ONE = [_plane(+1)]
+TWO = [_plane(+1), _plane(-1)]
+
+WORKLOADS = {
+    1: Workload(1, "plane64_w100_fp64", 64, 64, ONE, 100, 200),
+    2: Workload(2, "two_planes512_w1000", 512, 512, TWO, 1000, 2000, bank=64, pulse=True),
+    3: Workload(3, "two_planes2048_permode400", 2048, 2048, TWO, 400, 1000,
+                window_mode="per_mode", bank=64),
+    4: Workload(4, "plane256_w300_adjoint", 256, 256, ONE, 300, 500),
+    5: Workload(5, "two_planes1024_w2000_longrun", 1024, 1024, TWO, 2000, 5000,
+                bank=64, slip_ramp=10.0),
+}
+
+
+def shaped_field(rng, n1, n3, dx1=1.0, dx3=1.0):
+    """One white field shaped to spectral amplitude |k|^-2, k = 0 removed, unit RMS."""
+    white = rng.standard_normal((n1, n3))
+    spec = np.fft.rfft2(white)
+    k1 = 2 * np.pi * np.fft.fftfreq(n1, d=dx1)
+    k3 = 2 * np.pi * np.fft.rfftfreq(n3, d=dx3)
+    kk = k1[:, None] ** 2 + k3[None, :] ** 2
+    amp = np.zeros_like(kk)
+    amp[kk > 0] = 1.0 / kk[kk > 0]
+    f = np.fft.irfft2(spec * amp, s=(n1, n3))
+    rms = np.sqrt(np.mean(f * f))
+    return f / rms if rms > 0 else f
+
+
+class Increments:
+    """Deterministic per-step displacement increments du^n [P, 3, n1, n3] float64."""
+
+    def __init__(self, wl: Workload):
+        self.wl = wl
+        P = len(wl.planes)
+        self._rngs = [[np.random.default_rng(1000 * wl.ident + 10 * p + c) for c in range(3)]
+                      for p in range(P)]
+        self._bank = None
+        if wl.bank:
+            self._bank = np.empty((wl.bank, P, 3, wl.n1, wl.n3))
+            for b in range(wl.bank):
+                for p in range(P):
+                    for c in range(3):
+                        self._bank[b, p, c] = shaped_field(self._rngs[p][c], wl.n1, wl.n3,
+                                                           wl.dx1, wl.dx3)
+        self._next = 0
+        self._cache = {}
+        if wl.pulse:
+            x1 = np.arange(wl.n1) - wl.n1 / 2
+            x3 = np.arange(wl.n3) - wl.n3 / 2
+            r2 = x1[:, None] ** 2 + x3[None, :] ** 2
+            self._gauss = 10.0 * np.exp(-r2 / (2.0 * 20.0 ** 2))
+
+    def _random(self, n):
+        wl = self.wl
+        P = len(wl.planes)
+        if self._bank is not None:
+            return self._bank[(7 * n) % wl.bank].copy()
+        # fresh fields: generate sequentially so any n is reproducible
+        while self._next <= n:
+            f = np.empty((P, 3, wl.n1, wl.n3))
+            for p in range(P):
+                for c in range(3):
+                    f[p, c] = shaped_field(self._rngs[p][c], wl.n1, wl.n3, wl.dx1, wl.dx3)
+            self._cache[self._next] = f
+            self._next += 1
+        return self._cache[n].copy()
+
+    def __call__(self, n):
+        wl = self.wl
+        du = self._random(n)
+        if wl.pulse:
+            ramp = lambda m: min(max(m, 0) / 50.0, 1.0)  # noqa: E731
+            du[:, 0] += self._gauss * (ramp(n) - ramp(n - 1))
+        if wl.slip_ramp:
+            v = wl.slip_ramp * n / max(wl.steps - 1, 1)
+            du[:, 0] += v * wl.dt
+        return du
+
+    def history(self, steps):
+        return np.stack([self(n) for n in range(steps)])
+
+
+def absolute_history(du_hist):
+    """u^n = sum_{i<=n} du^i along axis 0."""
+    return np.cumsum(du_hist, axis=0)
