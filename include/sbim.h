@@ -1,0 +1,210 @@
+/*
+ * sbim.h -- C ABI of the MI355X spectral boundary integral (SBIM) library.
+ *
+ * One handle advances the exterior half-spaces of one or two boundary planes
+ * of a regular n1 x n3 grid through time.  Per time step the caller pushes
+ * the boundary displacement (hybrid step item 2, Sec. 2.4) and then asks for
+ * the boundary tractions of that same step (item 3, Sec. 2.4), which follow
+ * the boundary relation of Sec. 2.3 (Eq. SBI):
+ *
+ *     tau_i = tau_inf_i - eta_ij (mu / c_s) du_j/dt + s_i ,
+ *
+ * with eta = diag(1, c_p/c_s, 1) (the paper prints eta_22 = c_s/c_p; the
+ * exact half-space impedance of a normally incident P wave is c_p/c_s, which
+ * is what is used) and s_i the nonlocal term: a 2-D Fourier transform in space
+ * and, per Fourier mode, a truncated time convolution of the displacement
+ * history with the elastodynamic half-space kernels (the paragraph after
+ * Eq. SBI; truncation as cited in Sec. 1).
+ *
+ * Conventions shared by every entry point
+ *   Fields are contiguous device arrays [P][3][n1][n3] (P = nplanes,
+ *   component index 0,1,2 = x1, x2 (plane normal), x3; x3 fastest), in the
+ *   handle's working precision: double for SBIM_FP64, float otherwise.
+ *   Tractions are sigma_i2 on the plane.  Plane p with side = +1 bounds a
+ *   half-space lying on its +x2 side (top boundary of the strip), side = -1
+ *   one lying on its -x2 side.
+ *   Fourier convention: forward exp(-i k.x) over the stored half spectrum
+ *   (i1 = 0..n1-1, i3 = 0..n3/2); k1 = 2 pi m1 / (n1 dx1) with
+ *   m1 = i1 for i1 < n1/2 and i1 - n1 otherwise; k3 = 2 pi i3 / (n3 dx3);
+ *   q = sqrt(k1*k1 + k3*k3).  The inverse takes the real part of the inverse
+ *   transform of the Hermitian extension of the stored half, divided by
+ *   n1*n3 (imaginary parts of the i3 = 0 and i3 = n3/2 columns are dropped).
+ *   History: the displacement is piecewise constant over each step and the
+ *   kernels are integrated exactly over each step; the history before the
+ *   first push is zero.  Mode k keeps W(q) past steps (lag 0 = the step just
+ *   pushed): W = window_cap for SBIM_W_FIXED, or
+ *   W = min(window_cap, ceil(2 pi eta_w / (q c_s dt))) for SBIM_W_PER_MODE.
+ *
+ * Streams and ownership
+ *   Every call enqueues work on the handle's HIP stream (config.stream,
+ *   0 = the null stream) and returns without synchronising, except where a
+ *   comment says otherwise.  The caller owns all field buffers passed in and
+ *   must keep them alive until the stream reaches the call.  The handle owns
+ *   the history ring, kernel tables, running state and scratch; it allocates
+ *   them in sbim_init (the adjoint ring at the first sbim_backward) and frees
+ *   them in sbim_destroy.
+ *
+ * Errors
+ *   Every int-returning call returns SBIM_OK (0) or a negative code and never
+ *   aborts or throws; sbim_last_error gives a message for the last failure on
+ *   that handle.  On an error nothing has been enqueued and the handle's state
+ *   is unchanged.  HIP runtime failures map to SBIM_E_DEVICE.
+ */
+#ifndef SBIM_H
+#define SBIM_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SBIM_OK 0
+#define SBIM_E_INVALID (-1) /* bad argument or configuration */
+#define SBIM_E_OOM (-2)     /* device memory for the requested sizes not available */
+#define SBIM_E_STATE (-3)   /* call out of order (e.g. tractions before any push) */
+#define SBIM_E_DEVICE (-4)  /* HIP runtime error */
+
+/* precision */
+#define SBIM_FP64 0       /* double fields, FFTs, history, kernels, sums */
+#define SBIM_FP32 1       /* float fields, FFTs, history, kernels; plain float sums */
+#define SBIM_FP32_COMP 2  /* as SBIM_FP32 with compensated (Neumaier) history sums */
+/* window_mode */
+#define SBIM_W_FIXED 0
+#define SBIM_W_PER_MODE 1
+/* input_kind */
+#define SBIM_ABSOLUTE 0   /* push receives u^n - u^0 */
+#define SBIM_INCREMENT 1  /* push receives u^n - u^{n-1} */
+
+#define SBIM_MAX_PLANES 2
+
+typedef struct {
+  int side;      /* +1 or -1, see above */
+  double mu;     /* shear modulus, > 0 */
+  double cs;     /* shear wave speed, > 0 */
+  double cp;     /* pressure wave speed, cp > cs * sqrt(4/3) */
+} sbim_plane;
+
+typedef struct {
+  int n1, n3;            /* grid, powers of two in [4, 4096] */
+  double dx1, dx3;       /* grid spacing, > 0 */
+  double dt;             /* time step, > 0 */
+  int nplanes;           /* 1 or 2 */
+  sbim_plane plane[SBIM_MAX_PLANES];
+  int window_cap;        /* >= 1: longest history kept per mode */
+  int window_mode;       /* SBIM_W_FIXED or SBIM_W_PER_MODE */
+  double eta_w;          /* > 0, used by SBIM_W_PER_MODE */
+  int precision;         /* SBIM_FP64, SBIM_FP32 or SBIM_FP32_COMP */
+  int input_kind;        /* SBIM_ABSOLUTE or SBIM_INCREMENT */
+  void *stream;          /* hipStream_t for all work of this handle (0 = null stream) */
+} sbim_config;
+
+typedef struct sbim_handle sbim_handle;
+
+/* Sizes and derived quantities of a handle (host struct filled by sbim_get_info). */
+typedef struct {
+  long long modes_per_plane;   /* n1 * (n3/2 + 1) */
+  long long kernel_classes;    /* distinct (q, W) rows of the kernel tables, all groups */
+  long long ring_bytes;        /* forward history ring */
+  long long table_bytes;       /* kernel tables */
+  long long state_bytes;       /* float64 running state + velocity spectra */
+  long long step;              /* pushes since init / reset */
+  long long backward_step;     /* sbim_backward calls since the last reset */
+  int material_groups;         /* planes sharing (c_s, c_p) share one table and one pass */
+  int lag_split;               /* waves per 64-mode block in the convolution */
+} sbim_info;
+
+/*
+ * sbim_init: validate *cfg, allocate the ring, tables and state on the
+ * current HIP device, and tabulate the kernels (float64 quadrature of the
+ * half-space kernels' branch-cut integrals, rounded to the working precision).
+ * Synchronises the stream before returning.  On success *out is a new handle
+ * (step 0); on failure *out is set to NULL and a message can be fetched with
+ * sbim_last_error(NULL).  SBIM_E_OOM is returned before any allocation when
+ * the sizes exceed the free device memory.
+ */
+int sbim_init(const sbim_config *cfg, sbim_handle **out);
+
+/*
+ * sbim_push_displacement: advance the history by one step.
+ *   u          device [P][3][n1][n3]: u^n - u^0 (SBIM_ABSOLUTE) or
+ *              u^n - u^{n-1} (SBIM_INCREMENT)
+ *   v_or_null  device [P][3][n1][n3] velocity prediction for the damping term
+ *              of this step, or NULL to use (u^n - u^{n-1}) / dt
+ * Exactly one push precedes each sbim_tractions call.
+ */
+int sbim_push_displacement(sbim_handle *h, const void *u, const void *v_or_null);
+
+/*
+ * sbim_tractions: tau^n of the last pushed step into device [P][3][n1][n3].
+ *   tau_inf_or_null  device [P][3][n1][n3] far-field traction added to the
+ *                    result, or NULL for zero.
+ * SBIM_E_STATE if no step was pushed since init/reset.
+ */
+int sbim_tractions(sbim_handle *h, const void *tau_inf_or_null, void *tau);
+
+/*
+ * sbim_backward: one step of the exact transpose of the map from the pushed
+ * inputs to the tractions.  After N forward steps call it for n = N-1, ..., 0
+ * with g = dL/dtau^n (device [P][3][n1][n3]); it writes dL/du^n (with respect
+ * to what push received: u^n - u^0 or the increment) into dL_du, and, when
+ * velocities were pushed explicitly, dL/dv^n into dL_dv (pass NULL when they
+ * were not).  The transpose is the same operator run as a time-reversed
+ * correlation (the per-mode operators are Hermitian), so it needs no forward
+ * state; it keeps its own history of g.  sbim_backward_reset restarts it.
+ */
+int sbim_backward(sbim_handle *h, const void *dL_dtau, void *dL_du, void *dL_dv_or_null);
+int sbim_backward_reset(sbim_handle *h);
+
+/* sbim_reset: zero the history, running state and step counters (forward and backward). */
+int sbim_reset(sbim_handle *h);
+
+/* sbim_destroy: synchronise the stream and free everything; NULL is accepted. */
+int sbim_destroy(sbim_handle *h);
+
+/* Message of the last failure on h (or of the last failed sbim_init when h is NULL). */
+const char *sbim_last_error(const sbim_handle *h);
+
+/* Use another HIP stream for subsequent calls (the previous one is not synchronised). */
+int sbim_set_stream(sbim_handle *h, void *stream);
+
+/* Fill *out (host memory). */
+int sbim_get_info(const sbim_handle *h, sbim_info *out);
+
+/*
+ * Snapshots for checkpointing: the full forward state (ring, running state,
+ * velocity spectra, step counter) is sbim_state_bytes() bytes.  save/load
+ * copy it to/from a caller-owned device buffer of at least that size,
+ * asynchronously on the handle's stream.
+ */
+long long sbim_state_bytes(const sbim_handle *h);
+int sbim_save_state(sbim_handle *h, void *dst_device);
+int sbim_load_state(sbim_handle *h, const void *src_device);
+
+/*
+ * Work of the step with index n (0-based): the number of (plane, mode, lag)
+ * products min(W(q), n+1) summed over planes and modes, and the bytes the
+ * convolution must move for it: history read + kernel rows read + per-mode
+ * inputs/outputs (velocity spectra, geometry, spectrum written).
+ */
+int sbim_step_work(const sbim_handle *h, long long n, double *mode_lags, double *conv_bytes);
+
+/*
+ * Diagnostics (synchronising): the kernel row the handle uses for half-spectrum
+ * bin (i1, i3) of plane p: returns W(q) for that bin (>= 0) or a negative
+ * error, and copies min(W, max_lags) lags of (w11, w12, w22, w33) as float64
+ * into host_out[4][max_lags] (row-major by kernel).
+ */
+int sbim_mode_kernel(sbim_handle *h, int p, int i1, int i3, double *host_out, int max_lags);
+
+/*
+ * Timing of the convolution kernel: when enabled, HIP events bracket every
+ * convolution launch on the handle's stream; sbim_conv_timing synchronises
+ * and returns the summed device time (ms) and the launch count since enable.
+ */
+int sbim_profile_conv(sbim_handle *h, int enable);
+int sbim_conv_timing(sbim_handle *h, double *total_ms, long long *launches);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SBIM_H */

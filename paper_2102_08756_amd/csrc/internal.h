@@ -1,0 +1,146 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/sbim.h"
+
+namespace sbim {
+
+constexpr int kLanes = 64;            // modes per wavefront / per ring block
+constexpr int kTwiddleLog = 12;       // twiddle table covers lengths up to 4096
+constexpr int kTwiddleN = 1 << kTwiddleLog;
+constexpr int kFftThreads = 256;
+constexpr size_t kFftLdsBytes = 65536;  // per work-group LDS budget of the FFT kernels
+constexpr int kGaussN = 32;           // Gauss-Legendre points per quadrature panel
+constexpr int kConvLdsBytes = 65536;  // LDS budget of the convolution's cross-wave reduction
+
+// Largest power-of-two lag split (<= 8) whose S-1 partial sums fit kConvLdsBytes.
+constexpr int conv_max_split(int np, bool fp64, bool comp) {
+  const int per_wave = np * 10 * kLanes * (fp64 ? 8 : 4) * (comp ? 2 : 1);
+  int s = 1;
+  while (s < 8 && (2 * s - 1) * per_wave <= kConvLdsBytes) s *= 2;
+  return s;
+}
+
+// What push_kernel stores as "velocity" for the epilogue.
+enum VelRule : int {
+  VEL_DIFF = 0,   // (x_rot - previous state) / dt
+  VEL_SCALE = 1,  // x_rot / dt
+  VEL_INPUT = 2,  // rotate(spectrum of the supplied velocity)
+  VEL_COPY = 3    // x_rot
+};
+enum StateRule : int { STATE_REPLACE = 0, STATE_ACCUM = 1 };
+
+struct PlaneParams {
+  double mu, cs, eta;
+  int side;
+  int index;        // global plane index (field slot)
+};
+
+// Device arrays and sizes of one material group (planes with equal c_s, c_p).
+struct Group {
+  int np = 0;                     // planes in the group (1 or 2)
+  PlaneParams pl[SBIM_MAX_PLANES];
+  double cs = 0, cp = 0, eta = 0;
+  long long M = 0;                // modes (half spectrum)
+  long long nblocks = 0;          // ceil(M / 64)
+  long long nclasses = 0;         // kernel rows
+  int wmax = 0;                   // largest W(q)
+  long long ring_records = 0;     // sum of block capacities
+  long long table_rows = 0;       // sum over classes of W
+  // device
+  int *nat = nullptr;             // [M] sorted position -> natural flat bin
+  int *cls = nullptr;             // [M] sorted position -> class
+  int *win = nullptr;             // [M] W(q) per sorted position
+  double *geom = nullptr;         // [M][4] q, kh1, kh3, 0 per sorted position
+  long long *blk_off = nullptr;   // [nblocks] first ring record of the block
+  int *blk_cap = nullptr;         // [nblocks] ring capacity of the block (its largest W)
+  long long *lag_off = nullptr;   // [wmax] first table entry of each lag row
+  double *cls_q = nullptr;        // [nclasses]
+  int *cls_w = nullptr;           // [nclasses]
+  void *table = nullptr;          // [table_rows] x 4 reals (w11, w12, w22, w33)
+  void *ring = nullptr;           // [ring_records][np][3][64] complex
+  double *state = nullptr;        // [np][3][M] complex double (rotated frame, sorted)
+  void *vel = nullptr;            // [np][3][M] complex real_t
+  // adjoint (allocated on first use)
+  void *ring_adj = nullptr;
+  double *state_adj = nullptr;    // previous g spectrum (float64)
+  double *lam_adj = nullptr;      // reverse running sum (float64)
+  void *vel_adj = nullptr;
+  // host copies for diagnostics / work accounting
+  std::vector<int> h_nat, h_cls, h_win;
+  std::vector<long long> h_lag_off;
+  std::vector<int> h_cls_w;
+};
+
+}  // namespace sbim
+
+struct sbim_handle {
+  sbim_config cfg;
+  hipStream_t stream = nullptr;
+  int device = 0;
+  bool fp64 = true;
+  bool comp = false;
+  size_t rsize = 8;               // sizeof(real_t)
+  int n1 = 0, n3 = 0, h3 = 0;     // h3 = n3/2 + 1
+  long long nh = 0;               // n1 * h3
+  int ngroups = 0;
+  sbim::Group g[SBIM_MAX_PLANES];
+  long long step = 0;             // pushes done
+  long long bstep = 0;            // backward calls done
+  bool pushed_since_tractions = false;
+  int lag_split = 1;
+  void *twiddle = nullptr;        // [4096] complex real_t, exp(-2 pi i m / 4096)
+  void *spec = nullptr;           // [P][3][n1][h3] complex: spectrum of the pushed field
+  void *spec_v = nullptr;         // same for the velocity / second output
+  void *out_spec = nullptr;       // [P][3][n1][h3] complex: traction spectrum
+  bool profile = false;
+  std::vector<hipEvent_t> ev_start, ev_stop;
+  std::string err;
+};
+
+namespace sbim {
+
+// fft.hip
+hipError_t launch_r2c_rows(bool fp64, const void *in, void *out, long long rows, int n3,
+                           const void *tw, hipStream_t st);
+hipError_t launch_col_fft(bool fp64, void *data, long long outer, int n1, int h3, int dir,
+                          const void *tw, hipStream_t st);
+hipError_t launch_c2r_rows(bool fp64, const void *in, void *out, const void *add_or_null,
+                           long long rows, int n3, double scale, const void *tw, hipStream_t st);
+hipError_t upload_twiddles(bool fp64, void *dst, hipStream_t st);
+
+// kernels.hip
+struct PushLaunch {
+  const void *spec;       // [P][3][nh] complex (natural)
+  const void *spec_v;     // velocity spectrum or null
+  void *ring;
+  double *state;
+  void *vel;
+  long long nh;
+  long long step;         // index of this push
+  double dt;
+  int vel_rule, state_rule;
+};
+hipError_t launch_push(const sbim_handle *h, const Group &g, const PushLaunch &a);
+
+struct ConvLaunch {
+  const void *ring;
+  const void *vel;
+  double *lam;            // non-null: accumulate (conv + instantaneous) into this float64 state
+  void *out_a;            // [P][3][nh] complex: output spectrum
+  void *out_b;            // non-null: damping part written here instead of added to out_a
+  long long nh;
+  long long step;
+};
+hipError_t launch_conv(const sbim_handle *h, const Group &g, const ConvLaunch &a);
+
+hipError_t launch_tabulate(bool fp64, const Group &g, double dt, const double *gl_x,
+                           const double *gl_w, hipStream_t st);
+
+}  // namespace sbim

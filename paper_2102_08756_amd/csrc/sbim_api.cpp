@@ -1,0 +1,774 @@
+// C ABI of the boundary-integral library: configuration checks, the mode
+// ordering and kernel-row classes, device memory, and the per-call launch
+// sequences.  No arithmetic of the method runs here; it all runs in the HIP
+// kernels of fft.hip and kernels.hip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+using sbim::Group;
+
+namespace {
+
+thread_local std::string g_init_error;
+
+int fail(sbim_handle *h, int code, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (h)
+    h->err = buf;
+  else
+    g_init_error = buf;
+  return code;
+}
+
+int hip_fail(sbim_handle *h, hipError_t e, const char *what) {
+  return fail(h, SBIM_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+bool pow2_in(int n, int lo, int hi) { return n >= lo && n <= hi && (n & (n - 1)) == 0; }
+
+bool finite_pos(double x) { return std::isfinite(x) && x > 0; }
+
+// Gauss-Legendre nodes/weights on [-1, 1] by Newton iteration on P_n in long double.
+void gauss_legendre(int n, std::vector<double> &x, std::vector<double> &w) {
+  x.resize(n);
+  w.resize(n);
+  const long double pi = 3.141592653589793238462643383279502884L;
+  for (int i = 0; i < n; ++i) {
+    long double z = cosl(pi * (i + 0.75L) / (n + 0.5L));
+    long double dp = 0;
+    for (int it = 0; it < 100; ++it) {
+      long double p0 = 1, p1 = z;
+      for (int k = 2; k <= n; ++k) {
+        const long double p2 = ((2 * k - 1) * z * p1 - (k - 1) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      dp = n * (z * p1 - p0) / (z * z - 1);
+      const long double dz = p1 / dp;
+      z -= dz;
+      if (fabsl(dz) < 1e-19L) break;
+    }
+    long double p0 = 1, p1 = z;
+    for (int k = 2; k <= n; ++k) {
+      const long double p2 = ((2 * k - 1) * z * p1 - (k - 1) * p0) / k;
+      p0 = p1;
+      p1 = p2;
+    }
+    dp = n * (z * p1 - p0) / (z * z - 1);
+    x[i] = static_cast<double>(z);
+    w[i] = static_cast<double>(2 / ((1 - z * z) * dp * dp));
+  }
+}
+
+struct ModeKey {
+  int w;
+  double q;
+  int nat;
+};
+
+template <typename T>
+hipError_t dev_alloc(T **p, size_t count) {
+  *p = nullptr;
+  if (count == 0) return hipSuccess;
+  return hipMalloc(reinterpret_cast<void **>(p), count * sizeof(T));
+}
+
+hipError_t dev_alloc_bytes(void **p, size_t bytes) {
+  *p = nullptr;
+  if (bytes == 0) return hipSuccess;
+  return hipMalloc(p, bytes);
+}
+
+void free_group(Group &g) {
+  void *ptrs[] = {g.nat,   g.cls,   g.win,   g.geom,      g.blk_off,   g.blk_cap, g.lag_off,
+                  g.cls_q, g.cls_w, g.table, g.ring,      g.state,     g.vel,     g.ring_adj,
+                  g.state_adj, g.lam_adj, g.vel_adj};
+  for (void *p : ptrs)
+    if (p) (void)hipFree(p);
+  g = Group();
+}
+
+void free_handle(sbim_handle *h) {
+  if (!h) return;
+  (void)hipStreamSynchronize(h->stream);
+  for (int i = 0; i < h->ngroups; ++i) free_group(h->g[i]);
+  void *ptrs[] = {h->twiddle, h->spec, h->spec_v, h->out_spec};
+  for (void *p : ptrs)
+    if (p) (void)hipFree(p);
+  for (auto e : h->ev_start) (void)hipEventDestroy(e);
+  for (auto e : h->ev_stop) (void)hipEventDestroy(e);
+  delete h;
+}
+
+long long ring_bytes(const sbim_handle *h, const Group &g) {
+  return g.ring_records * g.np * 3LL * sbim::kLanes * 2 * static_cast<long long>(h->rsize);
+}
+long long table_bytes(const sbim_handle *h, const Group &g) {
+  return g.table_rows * 4LL * static_cast<long long>(h->rsize);
+}
+long long vel_bytes(const sbim_handle *h, const Group &g) {
+  return g.np * 3LL * g.M * 2 * static_cast<long long>(h->rsize);
+}
+long long state_bytes_g(const Group &g) { return g.np * 3LL * g.M * 16; }
+
+int validate(const sbim_config *c) {
+  if (!c) return fail(nullptr, SBIM_E_INVALID, "config is NULL");
+  if (!pow2_in(c->n1, 4, 4096) || !pow2_in(c->n3, 4, 4096))
+    return fail(nullptr, SBIM_E_INVALID, "n1=%d, n3=%d: each must be a power of two in [4, 4096]",
+                c->n1, c->n3);
+  if (!finite_pos(c->dx1) || !finite_pos(c->dx3) || !finite_pos(c->dt))
+    return fail(nullptr, SBIM_E_INVALID, "dx1, dx3 and dt must be finite and > 0");
+  if (c->nplanes < 1 || c->nplanes > SBIM_MAX_PLANES)
+    return fail(nullptr, SBIM_E_INVALID, "nplanes=%d: must be 1 or 2", c->nplanes);
+  for (int p = 0; p < c->nplanes; ++p) {
+    const sbim_plane &pl = c->plane[p];
+    if (pl.side != 1 && pl.side != -1)
+      return fail(nullptr, SBIM_E_INVALID, "plane %d: side must be +1 or -1", p);
+    if (!finite_pos(pl.mu) || !finite_pos(pl.cs) || !std::isfinite(pl.cp))
+      return fail(nullptr, SBIM_E_INVALID, "plane %d: mu, cs must be finite and > 0", p);
+    if (!(pl.cp > pl.cs * std::sqrt(4.0 / 3.0)))
+      return fail(nullptr, SBIM_E_INVALID,
+                  "plane %d: cp=%g must exceed cs*sqrt(4/3)=%g (positive bulk modulus)", p, pl.cp,
+                  pl.cs * std::sqrt(4.0 / 3.0));
+  }
+  if (c->window_cap < 1 || c->window_cap > (1 << 20))
+    return fail(nullptr, SBIM_E_INVALID, "window_cap=%d: must be in [1, 2^20]", c->window_cap);
+  if (c->window_mode != SBIM_W_FIXED && c->window_mode != SBIM_W_PER_MODE)
+    return fail(nullptr, SBIM_E_INVALID, "window_mode=%d unknown", c->window_mode);
+  if (c->window_mode == SBIM_W_PER_MODE && !finite_pos(c->eta_w))
+    return fail(nullptr, SBIM_E_INVALID, "eta_w must be finite and > 0");
+  if (c->precision != SBIM_FP64 && c->precision != SBIM_FP32 && c->precision != SBIM_FP32_COMP)
+    return fail(nullptr, SBIM_E_INVALID, "precision=%d unknown", c->precision);
+  if (c->input_kind != SBIM_ABSOLUTE && c->input_kind != SBIM_INCREMENT)
+    return fail(nullptr, SBIM_E_INVALID, "input_kind=%d unknown", c->input_kind);
+  return SBIM_OK;
+}
+
+// Mode geometry, windows, ordering and classes of one material group (host).
+void plan_group(const sbim_config &c, Group &g, std::vector<double> &geom,
+                std::vector<long long> &blk_off, std::vector<int> &blk_cap,
+                std::vector<double> &cls_q) {
+  const int n1 = c.n1, h3 = c.n3 / 2 + 1;
+  const long long M = static_cast<long long>(n1) * h3;
+  const double two_pi = 2.0 * M_PI;
+  std::vector<ModeKey> keys(M);
+  std::vector<double> qv(M), k1v(M), k3v(M);
+  for (int i1 = 0; i1 < n1; ++i1) {
+    const int m1 = i1 < n1 / 2 ? i1 : i1 - n1;
+    const double k1 = (two_pi * m1) / (n1 * c.dx1);
+    for (int i3 = 0; i3 < h3; ++i3) {
+      const double k3 = (two_pi * i3) / (c.n3 * c.dx3);
+      const double q = std::sqrt(k1 * k1 + k3 * k3);
+      int w = 0;
+      if (q > 0) {
+        if (c.window_mode == SBIM_W_FIXED) {
+          w = c.window_cap;
+        } else {
+          const double x = (two_pi * c.eta_w) / (q * g.cs * c.dt);
+          w = static_cast<int>(std::min(static_cast<double>(c.window_cap), std::ceil(x)));
+        }
+      }
+      const long long f = static_cast<long long>(i1) * h3 + i3;
+      keys[f] = ModeKey{w, q, static_cast<int>(f)};
+      qv[f] = q;
+      k1v[f] = k1;
+      k3v[f] = k3;
+    }
+  }
+  std::sort(keys.begin(), keys.end(), [](const ModeKey &a, const ModeKey &b) {
+    if (a.w != b.w) return a.w > b.w;
+    if (a.q != b.q) return a.q < b.q;
+    return a.nat < b.nat;
+  });
+  g.M = M;
+  g.nblocks = (M + sbim::kLanes - 1) / sbim::kLanes;
+  g.h_nat.resize(M);
+  g.h_cls.resize(M);
+  g.h_win.resize(M);
+  geom.assign(4 * M, 0.0);
+  cls_q.clear();
+  g.h_cls_w.clear();
+  for (long long s = 0; s < M; ++s) {
+    const ModeKey &k = keys[s];
+    if (s == 0 || k.w != keys[s - 1].w || k.q != keys[s - 1].q) {
+      if (k.w > 0) {
+        cls_q.push_back(k.q);
+        g.h_cls_w.push_back(k.w);
+      }
+    }
+    g.h_nat[s] = k.nat;
+    g.h_cls[s] = k.w > 0 ? static_cast<int>(cls_q.size()) - 1 : 0;
+    g.h_win[s] = k.w;
+    const double q = qv[k.nat];
+    geom[4 * s + 0] = q;
+    geom[4 * s + 1] = q > 0 ? k1v[k.nat] / q : 1.0;
+    geom[4 * s + 2] = q > 0 ? k3v[k.nat] / q : 0.0;
+  }
+  g.nclasses = static_cast<long long>(cls_q.size());
+  g.wmax = M > 0 ? keys[0].w : 0;
+  blk_off.resize(g.nblocks);
+  blk_cap.resize(g.nblocks);
+  long long rec = 0;
+  for (long long b = 0; b < g.nblocks; ++b) {
+    blk_off[b] = rec;
+    blk_cap[b] = g.h_win[b * sbim::kLanes];  // sorted by W desc: first lane has the block maximum
+    rec += blk_cap[b];
+  }
+  g.ring_records = rec;
+  // lag-major table rows: classes alive at lag j form the prefix {c : W_c > j}
+  g.h_lag_off.assign(g.wmax, 0);
+  long long off = 0;
+  long long alive = g.nclasses;
+  for (int j = 0; j < g.wmax; ++j) {
+    while (alive > 0 && g.h_cls_w[alive - 1] <= j) --alive;
+    g.h_lag_off[j] = off;
+    off += alive;
+  }
+  g.table_rows = off;
+}
+
+hipError_t upload(void *dst, const void *src, size_t bytes, hipStream_t st) {
+  if (bytes == 0) return hipSuccess;
+  return hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st);
+}
+
+int check_ptr(sbim_handle *h, const void *p, const char *name) {
+  if (!p) return fail(h, SBIM_E_INVALID, "%s is NULL", name);
+  return SBIM_OK;
+}
+
+// Forward real 2-D FFT of a [P][3][n1][n3] field into `spec`.
+hipError_t fft_forward(sbim_handle *h, const void *field, void *spec) {
+  const long long rows = static_cast<long long>(h->cfg.nplanes) * 3 * h->n1;
+  hipError_t e = sbim::launch_r2c_rows(h->fp64, field, spec, rows, h->n3, h->twiddle, h->stream);
+  if (e != hipSuccess) return e;
+  return sbim::launch_col_fft(h->fp64, spec, h->cfg.nplanes * 3LL, h->n1, h->h3, -1, h->twiddle,
+                              h->stream);
+}
+
+// Inverse of a traction spectrum (destroyed) into a [P][3][n1][n3] field.
+hipError_t fft_inverse(sbim_handle *h, void *spec, void *field, const void *add) {
+  hipError_t e = sbim::launch_col_fft(h->fp64, spec, h->cfg.nplanes * 3LL, h->n1, h->h3, +1,
+                                      h->twiddle, h->stream);
+  if (e != hipSuccess) return e;
+  const long long rows = static_cast<long long>(h->cfg.nplanes) * 3 * h->n1;
+  return sbim::launch_c2r_rows(h->fp64, spec, field, add, rows, h->n3,
+                               1.0 / (static_cast<double>(h->n1) * h->n3), h->twiddle, h->stream);
+}
+
+int ensure_adjoint(sbim_handle *h) {
+  for (int i = 0; i < h->ngroups; ++i) {
+    Group &g = h->g[i];
+    if (g.state_adj) continue;
+    const size_t rb = static_cast<size_t>(ring_bytes(h, g));
+    const size_t sb = static_cast<size_t>(state_bytes_g(g));
+    const size_t vb = static_cast<size_t>(vel_bytes(h, g));
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) == hipSuccess && rb + 2 * sb + vb > free_b)
+      return fail(h, SBIM_E_OOM, "adjoint buffers need %zu bytes, %zu free", rb + 2 * sb + vb, free_b);
+    hipError_t e;
+    if ((e = dev_alloc_bytes(&g.ring_adj, rb)) != hipSuccess ||
+        (e = dev_alloc(&g.state_adj, sb / 8)) != hipSuccess ||
+        (e = dev_alloc(&g.lam_adj, sb / 8)) != hipSuccess ||
+        (e = dev_alloc_bytes(&g.vel_adj, vb)) != hipSuccess) {
+      return fail(h, SBIM_E_OOM, "adjoint allocation failed: %s", hipGetErrorString(e));
+    }
+    if (rb) (void)hipMemsetAsync(g.ring_adj, 0, rb, h->stream);
+    (void)hipMemsetAsync(g.state_adj, 0, sb, h->stream);
+    (void)hipMemsetAsync(g.lam_adj, 0, sb, h->stream);
+    (void)hipMemsetAsync(g.vel_adj, 0, vb, h->stream);
+  }
+  return SBIM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sbim_init(const sbim_config *cfg, sbim_handle **out) {
+  if (!out) return fail(nullptr, SBIM_E_INVALID, "out is NULL");
+  *out = nullptr;
+  int rc = validate(cfg);
+  if (rc != SBIM_OK) return rc;
+  sbim_handle *h = new (std::nothrow) sbim_handle();
+  if (!h) return fail(nullptr, SBIM_E_OOM, "host allocation failed");
+  h->cfg = *cfg;
+  h->stream = static_cast<hipStream_t>(cfg->stream);
+  h->fp64 = cfg->precision == SBIM_FP64;
+  h->comp = cfg->precision == SBIM_FP32_COMP;
+  h->rsize = h->fp64 ? 8 : 4;
+  h->n1 = cfg->n1;
+  h->n3 = cfg->n3;
+  h->h3 = cfg->n3 / 2 + 1;
+  h->nh = static_cast<long long>(h->n1) * h->h3;
+  hipError_t e = hipGetDevice(&h->device);
+  if (e != hipSuccess) {
+    delete h;
+    return fail(nullptr, SBIM_E_DEVICE, "hipGetDevice: %s", hipGetErrorString(e));
+  }
+
+  // material groups: planes with equal (c_s, c_p) share kernel tables and one pass
+  for (int p = 0; p < cfg->nplanes; ++p) {
+    const sbim_plane &pl = cfg->plane[p];
+    int gi = -1;
+    for (int i = 0; i < h->ngroups; ++i)
+      if (h->g[i].cs == pl.cs && h->g[i].cp == pl.cp) gi = i;
+    if (gi < 0) {
+      gi = h->ngroups++;
+      h->g[gi].cs = pl.cs;
+      h->g[gi].cp = pl.cp;
+      h->g[gi].eta = pl.cp / pl.cs;
+    }
+    Group &g = h->g[gi];
+    g.pl[g.np++] = sbim::PlaneParams{pl.mu, pl.cs, pl.cp / pl.cs, pl.side, p};
+  }
+
+  struct HostPlan {
+    std::vector<double> geom, cls_q;
+    std::vector<long long> blk_off;
+    std::vector<int> blk_cap;
+  };
+  std::vector<HostPlan> plan(h->ngroups);
+  size_t need = 0;
+  long long total_blocks = 0;
+  for (int i = 0; i < h->ngroups; ++i) {
+    Group &g = h->g[i];
+    plan_group(*cfg, g, plan[i].geom, plan[i].blk_off, plan[i].blk_cap, plan[i].cls_q);
+    need += ring_bytes(h, g) + table_bytes(h, g) + state_bytes_g(g) + vel_bytes(h, g);
+    need += g.M * (4 * 3 + 32) + g.nblocks * 12 + g.wmax * 8 + g.nclasses * 12;
+    total_blocks += g.nblocks;
+  }
+  const size_t spec_bytes = static_cast<size_t>(cfg->nplanes) * 3 * h->nh * 2 * h->rsize;
+  need += 3 * spec_bytes + sbim::kTwiddleN * 2 * h->rsize;
+  size_t free_b = 0, total_b = 0;
+  e = hipMemGetInfo(&free_b, &total_b);
+  if (e != hipSuccess) {
+    free_handle(h);
+    return fail(nullptr, SBIM_E_DEVICE, "hipMemGetInfo: %s", hipGetErrorString(e));
+  }
+  if (need > free_b) {
+    free_handle(h);
+    return fail(nullptr, SBIM_E_OOM, "needs %zu bytes of device memory, %zu free", need, free_b);
+  }
+
+  // lag split: aim at >= 4096 waves in the convolution, within the LDS budget
+  int split = 1;
+  while (split < 8 && total_blocks * split < 4096) split *= 2;
+  for (int i = 0; i < h->ngroups; ++i)
+    split = std::min(split, sbim::conv_max_split(h->g[i].np, h->fp64, h->comp));
+  h->lag_split = split;
+
+  std::vector<double> glx, glw;
+  gauss_legendre(sbim::kGaussN, glx, glw);
+  double *d_glx = nullptr, *d_glw = nullptr;
+
+#define TRY(expr)                                         \
+  do {                                                    \
+    e = (expr);                                           \
+    if (e != hipSuccess) {                                \
+      const int code = (e == hipErrorOutOfMemory) ? SBIM_E_OOM : SBIM_E_DEVICE; \
+      if (d_glx) (void)hipFree(d_glx);                    \
+      if (d_glw) (void)hipFree(d_glw);                    \
+      free_handle(h);                                     \
+      return fail(nullptr, code, "%s: %s", #expr, hipGetErrorString(e)); \
+    }                                                     \
+  } while (0)
+
+  TRY(dev_alloc_bytes(&h->twiddle, sbim::kTwiddleN * 2 * h->rsize));
+  TRY(dev_alloc_bytes(&h->spec, spec_bytes));
+  TRY(dev_alloc_bytes(&h->spec_v, spec_bytes));
+  TRY(dev_alloc_bytes(&h->out_spec, spec_bytes));
+  TRY(sbim::upload_twiddles(h->fp64, h->twiddle, h->stream));
+  TRY(dev_alloc(&d_glx, glx.size()));
+  TRY(dev_alloc(&d_glw, glw.size()));
+  TRY(upload(d_glx, glx.data(), glx.size() * sizeof(double), h->stream));
+  TRY(upload(d_glw, glw.data(), glw.size() * sizeof(double), h->stream));
+  for (int i = 0; i < h->ngroups; ++i) {
+    Group &g = h->g[i];
+    HostPlan &hp = plan[i];
+    TRY(dev_alloc(&g.nat, g.M));
+    TRY(dev_alloc(&g.cls, g.M));
+    TRY(dev_alloc(&g.win, g.M));
+    TRY(dev_alloc(&g.geom, 4 * g.M));
+    TRY(dev_alloc(&g.blk_off, g.nblocks));
+    TRY(dev_alloc(&g.blk_cap, g.nblocks));
+    TRY(dev_alloc(&g.lag_off, g.wmax));
+    TRY(dev_alloc(&g.cls_q, g.nclasses));
+    TRY(dev_alloc(&g.cls_w, g.nclasses));
+    TRY(dev_alloc_bytes(&g.table, table_bytes(h, g)));
+    TRY(dev_alloc_bytes(&g.ring, ring_bytes(h, g)));
+    TRY(dev_alloc(&g.state, state_bytes_g(g) / 8));
+    TRY(dev_alloc_bytes(&g.vel, vel_bytes(h, g)));
+    TRY(upload(g.nat, g.h_nat.data(), g.M * sizeof(int), h->stream));
+    TRY(upload(g.cls, g.h_cls.data(), g.M * sizeof(int), h->stream));
+    TRY(upload(g.win, g.h_win.data(), g.M * sizeof(int), h->stream));
+    TRY(upload(g.geom, hp.geom.data(), hp.geom.size() * sizeof(double), h->stream));
+    TRY(upload(g.blk_off, hp.blk_off.data(), hp.blk_off.size() * sizeof(long long), h->stream));
+    TRY(upload(g.blk_cap, hp.blk_cap.data(), hp.blk_cap.size() * sizeof(int), h->stream));
+    TRY(upload(g.lag_off, g.h_lag_off.data(), g.h_lag_off.size() * sizeof(long long), h->stream));
+    TRY(upload(g.cls_q, hp.cls_q.data(), hp.cls_q.size() * sizeof(double), h->stream));
+    TRY(upload(g.cls_w, g.h_cls_w.data(), g.h_cls_w.size() * sizeof(int), h->stream));
+    if (ring_bytes(h, g)) TRY(hipMemsetAsync(g.ring, 0, ring_bytes(h, g), h->stream));
+    TRY(hipMemsetAsync(g.state, 0, state_bytes_g(g), h->stream));
+    TRY(hipMemsetAsync(g.vel, 0, vel_bytes(h, g), h->stream));
+    TRY(sbim::launch_tabulate(h->fp64, g, cfg->dt, d_glx, d_glw, h->stream));
+    // the host vectors must outlive the asynchronous copies
+    TRY(hipStreamSynchronize(h->stream));
+  }
+  TRY(hipStreamSynchronize(h->stream));
+#undef TRY
+  (void)hipFree(d_glx);
+  (void)hipFree(d_glw);
+  *out = h;
+  return SBIM_OK;
+}
+
+int sbim_push_displacement(sbim_handle *h, const void *u, const void *v) {
+  if (!h) return fail(nullptr, SBIM_E_INVALID, "handle is NULL");
+  int rc = check_ptr(h, u, "u");
+  if (rc) return rc;
+  hipError_t e = fft_forward(h, u, h->spec);
+  if (e != hipSuccess) return hip_fail(h, e, "forward FFT of u");
+  if (v) {
+    e = fft_forward(h, v, h->spec_v);
+    if (e != hipSuccess) return hip_fail(h, e, "forward FFT of v");
+  }
+  const bool incr = h->cfg.input_kind == SBIM_INCREMENT;
+  for (int i = 0; i < h->ngroups; ++i) {
+    Group &g = h->g[i];
+    sbim::PushLaunch a;
+    a.spec = h->spec;
+    a.spec_v = v ? h->spec_v : nullptr;
+    a.ring = g.ring;
+    a.state = g.state;
+    a.vel = g.vel;
+    a.nh = h->nh;
+    a.step = h->step;
+    a.dt = h->cfg.dt;
+    a.state_rule = incr ? sbim::STATE_ACCUM : sbim::STATE_REPLACE;
+    a.vel_rule = v ? sbim::VEL_INPUT : (incr ? sbim::VEL_SCALE : sbim::VEL_DIFF);
+    e = sbim::launch_push(h, g, a);
+    if (e != hipSuccess) return hip_fail(h, e, "push kernel");
+  }
+  h->step += 1;
+  h->pushed_since_tractions = true;
+  return SBIM_OK;
+}
+
+int sbim_tractions(sbim_handle *h, const void *tau_inf, void *tau) {
+  if (!h) return fail(nullptr, SBIM_E_INVALID, "handle is NULL");
+  int rc = check_ptr(h, tau, "tau");
+  if (rc) return rc;
+  if (h->step == 0) return fail(h, SBIM_E_STATE, "sbim_tractions before any push");
+  for (int i = 0; i < h->ngroups; ++i) {
+    Group &g = h->g[i];
+    sbim::ConvLaunch a;
+    a.ring = g.ring;
+    a.vel = g.vel;
+    a.lam = nullptr;
+    a.out_a = h->out_spec;
+    a.out_b = nullptr;
+    a.nh = h->nh;
+    a.step = h->step - 1;
+    hipError_t e;
+    if (h->profile) {
+      hipEvent_t e0, e1;
+      if ((e = hipEventCreate(&e0)) != hipSuccess || (e = hipEventCreate(&e1)) != hipSuccess)
+        return hip_fail(h, e, "hipEventCreate");
+      h->ev_start.push_back(e0);
+      h->ev_stop.push_back(e1);
+      (void)hipEventRecord(e0, h->stream);
+      e = sbim::launch_conv(h, g, a);
+      (void)hipEventRecord(e1, h->stream);
+    } else {
+      e = sbim::launch_conv(h, g, a);
+    }
+    if (e != hipSuccess) return hip_fail(h, e, "convolution kernel");
+  }
+  hipError_t e = fft_inverse(h, h->out_spec, tau, tau_inf);
+  if (e != hipSuccess) return hip_fail(h, e, "inverse FFT");
+  h->pushed_since_tractions = false;
+  return SBIM_OK;
+}
+
+int sbim_backward(sbim_handle *h, const void *g_tau, void *du, void *dv) {
+  if (!h) return fail(nullptr, SBIM_E_INVALID, "handle is NULL");
+  int rc = check_ptr(h, g_tau, "dL_dtau");
+  if (rc) return rc;
+  rc = check_ptr(h, du, "dL_du");
+  if (rc) return rc;
+  rc = ensure_adjoint(h);
+  if (rc) return rc;
+  hipError_t e = fft_forward(h, g_tau, h->spec);
+  if (e != hipSuccess) return hip_fail(h, e, "forward FFT of dL/dtau");
+  const bool incr = h->cfg.input_kind == SBIM_INCREMENT;
+  for (int i = 0; i < h->ngroups; ++i) {
+    Group &g = h->g[i];
+    sbim::PushLaunch a;
+    a.spec = h->spec;
+    a.spec_v = nullptr;
+    a.ring = g.ring_adj;
+    a.state = g.state_adj;
+    a.vel = g.vel_adj;
+    a.nh = h->nh;
+    a.step = h->bstep;
+    a.dt = h->cfg.dt;
+    a.state_rule = sbim::STATE_REPLACE;
+    // transpose of the velocity rule of the forward push
+    a.vel_rule = dv ? sbim::VEL_COPY : (incr ? sbim::VEL_SCALE : sbim::VEL_DIFF);
+    e = sbim::launch_push(h, g, a);
+    if (e != hipSuccess) return hip_fail(h, e, "adjoint push kernel");
+    sbim::ConvLaunch c;
+    c.ring = g.ring_adj;
+    c.vel = g.vel_adj;
+    c.lam = incr ? g.lam_adj : nullptr;
+    c.out_a = h->out_spec;
+    c.out_b = dv ? h->spec_v : nullptr;
+    c.nh = h->nh;
+    c.step = h->bstep;
+    e = sbim::launch_conv(h, g, c);
+    if (e != hipSuccess) return hip_fail(h, e, "adjoint convolution kernel");
+  }
+  e = fft_inverse(h, h->out_spec, du, nullptr);
+  if (e != hipSuccess) return hip_fail(h, e, "inverse FFT of dL/du");
+  if (dv) {
+    e = fft_inverse(h, h->spec_v, dv, nullptr);
+    if (e != hipSuccess) return hip_fail(h, e, "inverse FFT of dL/dv");
+  }
+  h->bstep += 1;
+  return SBIM_OK;
+}
+
+int sbim_backward_reset(sbim_handle *h) {
+  if (!h) return fail(nullptr, SBIM_E_INVALID, "handle is NULL");
+  for (int i = 0; i < h->ngroups; ++i) {
+    Group &g = h->g[i];
+    if (!g.state_adj) continue;
+    const size_t rb = static_cast<size_t>(ring_bytes(h, g));
+    hipError_t e = hipSuccess;
+    if (rb) e = hipMemsetAsync(g.ring_adj, 0, rb, h->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(g.state_adj, 0, state_bytes_g(g), h->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(g.lam_adj, 0, state_bytes_g(g), h->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(g.vel_adj, 0, vel_bytes(h, g), h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "clearing adjoint state");
+  }
+  h->bstep = 0;
+  return SBIM_OK;
+}
+
+int sbim_reset(sbim_handle *h) {
+  if (!h) return fail(nullptr, SBIM_E_INVALID, "handle is NULL");
+  for (int i = 0; i < h->ngroups; ++i) {
+    Group &g = h->g[i];
+    hipError_t e = hipSuccess;
+    if (ring_bytes(h, g)) e = hipMemsetAsync(g.ring, 0, ring_bytes(h, g), h->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(g.state, 0, state_bytes_g(g), h->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(g.vel, 0, vel_bytes(h, g), h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "clearing state");
+  }
+  h->step = 0;
+  h->pushed_since_tractions = false;
+  return sbim_backward_reset(h);
+}
+
+int sbim_destroy(sbim_handle *h) {
+  free_handle(h);
+  return SBIM_OK;
+}
+
+const char *sbim_last_error(const sbim_handle *h) {
+  return h ? h->err.c_str() : g_init_error.c_str();
+}
+
+int sbim_set_stream(sbim_handle *h, void *stream) {
+  if (!h) return fail(nullptr, SBIM_E_INVALID, "handle is NULL");
+  h->stream = static_cast<hipStream_t>(stream);
+  h->cfg.stream = stream;
+  return SBIM_OK;
+}
+
+int sbim_get_info(const sbim_handle *h, sbim_info *out) {
+  if (!h || !out) return fail(nullptr, SBIM_E_INVALID, "handle or out is NULL");
+  std::memset(out, 0, sizeof *out);
+  out->modes_per_plane = h->nh;
+  for (int i = 0; i < h->ngroups; ++i) {
+    const Group &g = h->g[i];
+    out->kernel_classes += g.nclasses;
+    out->ring_bytes += ring_bytes(h, g);
+    out->table_bytes += table_bytes(h, g);
+    out->state_bytes += state_bytes_g(g) + vel_bytes(h, g);
+  }
+  out->step = h->step;
+  out->backward_step = h->bstep;
+  out->material_groups = h->ngroups;
+  out->lag_split = h->lag_split;
+  return SBIM_OK;
+}
+
+long long sbim_state_bytes(const sbim_handle *h) {
+  if (!h) return -1;
+  long long b = 256;  // header: step counter
+  for (int i = 0; i < h->ngroups; ++i) {
+    const Group &g = h->g[i];
+    b += ring_bytes(h, g) + state_bytes_g(g) + vel_bytes(h, g);
+  }
+  return b;
+}
+
+int sbim_save_state(sbim_handle *h, void *dst) {
+  if (!h) return fail(nullptr, SBIM_E_INVALID, "handle is NULL");
+  int rc = check_ptr(h, dst, "dst");
+  if (rc) return rc;
+  char *d = static_cast<char *>(dst);
+  hipError_t e = hipMemcpyAsync(d, &h->step, sizeof(long long), hipMemcpyHostToDevice, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);  // &h->step may change after return
+  d += 256;
+  for (int i = 0; i < h->ngroups && e == hipSuccess; ++i) {
+    Group &g = h->g[i];
+    const size_t rb = ring_bytes(h, g), sb = state_bytes_g(g), vb = vel_bytes(h, g);
+    if (rb) e = hipMemcpyAsync(d, g.ring, rb, hipMemcpyDeviceToDevice, h->stream);
+    d += rb;
+    if (e == hipSuccess) e = hipMemcpyAsync(d, g.state, sb, hipMemcpyDeviceToDevice, h->stream);
+    d += sb;
+    if (e == hipSuccess) e = hipMemcpyAsync(d, g.vel, vb, hipMemcpyDeviceToDevice, h->stream);
+    d += vb;
+  }
+  if (e != hipSuccess) return hip_fail(h, e, "sbim_save_state");
+  return SBIM_OK;
+}
+
+int sbim_load_state(sbim_handle *h, const void *src) {
+  if (!h) return fail(nullptr, SBIM_E_INVALID, "handle is NULL");
+  int rc = check_ptr(h, src, "src");
+  if (rc) return rc;
+  const char *s = static_cast<const char *>(src);
+  long long step = 0;
+  hipError_t e = hipMemcpyAsync(&step, s, sizeof(long long), hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "sbim_load_state header");
+  if (step < 0) return fail(h, SBIM_E_INVALID, "snapshot header is corrupt");
+  s += 256;
+  for (int i = 0; i < h->ngroups && e == hipSuccess; ++i) {
+    Group &g = h->g[i];
+    const size_t rb = ring_bytes(h, g), sb = state_bytes_g(g), vb = vel_bytes(h, g);
+    if (rb) e = hipMemcpyAsync(g.ring, s, rb, hipMemcpyDeviceToDevice, h->stream);
+    s += rb;
+    if (e == hipSuccess) e = hipMemcpyAsync(g.state, s, sb, hipMemcpyDeviceToDevice, h->stream);
+    s += sb;
+    if (e == hipSuccess) e = hipMemcpyAsync(g.vel, s, vb, hipMemcpyDeviceToDevice, h->stream);
+    s += vb;
+  }
+  if (e != hipSuccess) return hip_fail(h, e, "sbim_load_state");
+  h->step = step;
+  h->pushed_since_tractions = false;
+  return SBIM_OK;
+}
+
+int sbim_step_work(const sbim_handle *h, long long n, double *mode_lags, double *conv_bytes) {
+  if (!h || !mode_lags || !conv_bytes || n < 0)
+    return fail(nullptr, SBIM_E_INVALID, "bad arguments to sbim_step_work");
+  const double r = static_cast<double>(h->rsize);
+  double lags = 0, bytes = 0;
+  for (int i = 0; i < h->ngroups; ++i) {
+    const Group &g = h->g[i];
+    double mode_lag_g = 0;
+    for (long long s = 0; s < g.M; ++s) {
+      const long long w = std::min<long long>(g.h_win[s], n + 1);
+      mode_lag_g += static_cast<double>(w);
+      // per-mode reads/writes of the epilogue: win, cls, nat (4 B each), geom (3 doubles),
+      // velocity and lag-0 history (read), traction spectrum (write)
+      bytes += 12 + 24 + g.np * 3 * 2 * r * (g.h_win[s] > 0 ? 3 : 2);
+    }
+    lags += mode_lag_g * g.np;
+    bytes += mode_lag_g * g.np * 3 * 2 * r;  // history
+    for (long long c = 0; c < g.nclasses; ++c)
+      bytes += std::min<long long>(g.h_cls_w[c], n + 1) * 4 * r;  // kernel rows
+    bytes += g.nblocks * 12.0;
+  }
+  *mode_lags = lags;
+  *conv_bytes = bytes;
+  return SBIM_OK;
+}
+
+int sbim_mode_kernel(sbim_handle *h, int p, int i1, int i3, double *host_out, int max_lags) {
+  if (!h) return fail(nullptr, SBIM_E_INVALID, "handle is NULL");
+  if (p < 0 || p >= h->cfg.nplanes || i1 < 0 || i1 >= h->n1 || i3 < 0 || i3 >= h->h3 ||
+      max_lags < 0 || (max_lags > 0 && !host_out))
+    return fail(h, SBIM_E_INVALID, "bad arguments to sbim_mode_kernel");
+  const Group *gp = nullptr;
+  for (int i = 0; i < h->ngroups; ++i)
+    for (int k = 0; k < h->g[i].np; ++k)
+      if (h->g[i].pl[k].index == p) gp = &h->g[i];
+  const Group &g = *gp;
+  const int f = i1 * h->h3 + i3;
+  long long s = -1;
+  for (long long t = 0; t < g.M; ++t)
+    if (g.h_nat[t] == f) s = t;
+  const int w = g.h_win[s];
+  if (w == 0) return 0;
+  const int c = g.h_cls[s];
+  hipError_t e = hipStreamSynchronize(h->stream);
+  const int nl = std::min(w, max_lags);
+  std::vector<char> tmp(4 * h->rsize);
+  for (int j = 0; j < nl && e == hipSuccess; ++j) {
+    const char *src = static_cast<const char *>(g.table) + (g.h_lag_off[j] + c) * 4 * h->rsize;
+    e = hipMemcpy(tmp.data(), src, 4 * h->rsize, hipMemcpyDeviceToHost);
+    for (int k = 0; k < 4; ++k) {
+      double v;
+      if (h->fp64)
+        std::memcpy(&v, tmp.data() + 8 * k, 8);
+      else {
+        float fv;
+        std::memcpy(&fv, tmp.data() + 4 * k, 4);
+        v = fv;
+      }
+      host_out[static_cast<long long>(k) * max_lags + j] = v;
+    }
+  }
+  if (e != hipSuccess) return hip_fail(h, e, "sbim_mode_kernel copy");
+  return w;
+}
+
+int sbim_profile_conv(sbim_handle *h, int enable) {
+  if (!h) return fail(nullptr, SBIM_E_INVALID, "handle is NULL");
+  (void)hipStreamSynchronize(h->stream);
+  for (auto e : h->ev_start) (void)hipEventDestroy(e);
+  for (auto e : h->ev_stop) (void)hipEventDestroy(e);
+  h->ev_start.clear();
+  h->ev_stop.clear();
+  h->profile = enable != 0;
+  return SBIM_OK;
+}
+
+int sbim_conv_timing(sbim_handle *h, double *total_ms, long long *launches) {
+  if (!h || !total_ms || !launches) return fail(nullptr, SBIM_E_INVALID, "bad arguments");
+  hipError_t e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "sbim_conv_timing sync");
+  double tot = 0;
+  for (size_t i = 0; i < h->ev_start.size(); ++i) {
+    float ms = 0;
+    e = hipEventElapsedTime(&ms, h->ev_start[i], h->ev_stop[i]);
+    if (e != hipSuccess) return hip_fail(h, e, "hipEventElapsedTime");
+    tot += ms;
+  }
+  *total_ms = tot;
+  *launches = static_cast<long long>(h->ev_start.size());
+  return SBIM_OK;
+}
+
+}  // extern "C"

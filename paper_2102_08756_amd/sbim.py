@@ -1,0 +1,375 @@
+"""Thin Python binding of the HIP boundary-integral library (``include/sbim.h``).
+
+Argument marshalling only: every step of the method runs in the library's HIP
+kernels.  PyTorch supplies device memory and the current HIP stream.  The
+library must be built (``paper_2102_08756_amd.build``); importing this module
+without it raises instead of falling back to anything.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from dataclasses import dataclass, field
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_lib", "libsbim.so")
+
+SBIM_OK, SBIM_E_INVALID, SBIM_E_OOM, SBIM_E_STATE, SBIM_E_DEVICE = 0, -1, -2, -3, -4
+PRECISIONS = {"fp64": 0, "fp32": 1, "fp32_comp": 2}
+WINDOW_MODES = {"fixed": 0, "per_mode": 1}
+INPUT_KINDS = {"absolute": 0, "increment": 1}
+ERROR_NAMES = {SBIM_E_INVALID: "SBIM_E_INVALID", SBIM_E_OOM: "SBIM_E_OOM",
+               SBIM_E_STATE: "SBIM_E_STATE", SBIM_E_DEVICE: "SBIM_E_DEVICE"}
+
+# every symbol the header declares
+EXPORTS = (
+    "sbim_init", "sbim_push_displacement", "sbim_tractions", "sbim_backward",
+    "sbim_backward_reset", "sbim_reset", "sbim_destroy", "sbim_last_error", "sbim_set_stream",
+    "sbim_get_info", "sbim_state_bytes", "sbim_save_state", "sbim_load_state", "sbim_step_work",
+    "sbim_mode_kernel", "sbim_profile_conv", "sbim_conv_timing",
+)
+
+
+class _Plane(ctypes.Structure):
+    _fields_ = [("side", ctypes.c_int), ("mu", ctypes.c_double), ("cs", ctypes.c_double),
+                ("cp", ctypes.c_double)]
+
+
+class _Config(ctypes.Structure):
+    _fields_ = [("n1", ctypes.c_int), ("n3", ctypes.c_int), ("dx1", ctypes.c_double),
+                ("dx3", ctypes.c_double), ("dt", ctypes.c_double), ("nplanes", ctypes.c_int),
+                ("plane", _Plane * 2), ("window_cap", ctypes.c_int), ("window_mode", ctypes.c_int),
+                ("eta_w", ctypes.c_double), ("precision", ctypes.c_int),
+                ("input_kind", ctypes.c_int), ("stream", ctypes.c_void_p)]
+
+
+class _Info(ctypes.Structure):
+    _fields_ = [("modes_per_plane", ctypes.c_longlong), ("kernel_classes", ctypes.c_longlong),
+                ("ring_bytes", ctypes.c_longlong), ("table_bytes", ctypes.c_longlong),
+                ("state_bytes", ctypes.c_longlong), ("step", ctypes.c_longlong),
+                ("backward_step", ctypes.c_longlong), ("material_groups", ctypes.c_int),
+                ("lag_split", ctypes.c_int)]
+
+
+_lib = None
+
+
+def load_library(path=LIB_PATH):
+    """Load the built library and declare its C signatures (fails loudly when absent)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build the HIP library first "
+                           "(python -c 'import __graft_entry__ as g; g.build()')")
+    L = ctypes.CDLL(path)
+    vp, i, ll, d = ctypes.c_void_p, ctypes.c_int, ctypes.c_longlong, ctypes.c_double
+    sig = {
+        "sbim_init": (i, [ctypes.POINTER(_Config), ctypes.POINTER(vp)]),
+        "sbim_push_displacement": (i, [vp, vp, vp]),
+        "sbim_tractions": (i, [vp, vp, vp]),
+        "sbim_backward": (i, [vp, vp, vp, vp]),
+        "sbim_backward_reset": (i, [vp]),
+        "sbim_reset": (i, [vp]),
+        "sbim_destroy": (i, [vp]),
+        "sbim_last_error": (ctypes.c_char_p, [vp]),
+        "sbim_set_stream": (i, [vp, vp]),
+        "sbim_get_info": (i, [vp, ctypes.POINTER(_Info)]),
+        "sbim_state_bytes": (ll, [vp]),
+        "sbim_save_state": (i, [vp, vp]),
+        "sbim_load_state": (i, [vp, vp]),
+        "sbim_step_work": (i, [vp, ll, ctypes.POINTER(d), ctypes.POINTER(d)]),
+        "sbim_mode_kernel": (i, [vp, i, i, i, ctypes.POINTER(d), i]),
+        "sbim_profile_conv": (i, [vp, i]),
+        "sbim_conv_timing": (i, [vp, ctypes.POINTER(d), ctypes.POINTER(ll)]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = L
+    return L
+
+
+class SBIMError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{ERROR_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+@dataclass
+class Plane:
+    side: int = 1
+    mu: float = 1.0
+    cs: float = 1.0
+    cp: float = math.sqrt(3.0)
+
+
+@dataclass
+class Config:
+    n1: int
+    n3: int
+    dx1: float = 1.0
+    dx3: float = 1.0
+    dt: float = 0.2
+    planes: list = field(default_factory=lambda: [Plane()])
+    window_cap: int = 100
+    window_mode: str = "fixed"
+    eta_w: float = 1.0
+    precision: str = "fp64"
+    input_kind: str = "absolute"
+
+    @staticmethod
+    def from_dict(d, **overrides):
+        d = dict(d)
+        d.update(overrides)
+        d["planes"] = [p if isinstance(p, Plane) else Plane(**p) for p in d.get("planes", [{}])]
+        return Config(**d)
+
+    @property
+    def dtype(self):
+        return torch.float64 if self.precision == "fp64" else torch.float32
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+class SBIM:
+    """One library handle: the exterior half-spaces of one or two boundary planes."""
+
+    def __init__(self, cfg: Config, device=None):
+        self.cfg = cfg
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self._L = load_library()
+        c = _Config()
+        c.n1, c.n3, c.dx1, c.dx3, c.dt = cfg.n1, cfg.n3, cfg.dx1, cfg.dx3, cfg.dt
+        c.nplanes = len(cfg.planes)
+        if not 1 <= c.nplanes <= 2:
+            raise ValueError("one or two planes")
+        for k, p in enumerate(cfg.planes):
+            c.plane[k] = _Plane(int(p.side), float(p.mu), float(p.cs), float(p.cp))
+        c.window_cap = int(cfg.window_cap)
+        c.window_mode = WINDOW_MODES[cfg.window_mode]
+        c.eta_w = float(cfg.eta_w)
+        c.precision = PRECISIONS[cfg.precision]
+        c.input_kind = INPUT_KINDS[cfg.input_kind]
+        with torch.cuda.device(self.device):
+            self._stream = torch.cuda.current_stream(self.device)
+            c.stream = ctypes.c_void_p(self._stream.cuda_stream)
+            h = ctypes.c_void_p()
+            rc = self._L.sbim_init(ctypes.byref(c), ctypes.byref(h))
+        if rc != SBIM_OK:
+            raise SBIMError(rc, self._L.sbim_last_error(None).decode())
+        self._h = h
+        self.dtype = cfg.dtype
+        self.P = c.nplanes
+        self.shape = (self.P, 3, cfg.n1, cfg.n3)
+
+    # -------------------------------------------------------------- helpers
+    def _check(self, rc):
+        if rc != SBIM_OK:
+            raise SBIMError(rc, self._L.sbim_last_error(self._h).decode())
+
+    def _sync_stream(self):
+        s = torch.cuda.current_stream(self.device)
+        if s.cuda_stream != self._stream.cuda_stream:
+            self._stream = s
+            self._check(self._L.sbim_set_stream(self._h, ctypes.c_void_p(s.cuda_stream)))
+
+    def _field(self, t, name, allow_none=False):
+        if t is None:
+            if allow_none:
+                return None
+            raise ValueError(f"{name} is required")
+        if not isinstance(t, torch.Tensor) or t.device != self.device:
+            raise ValueError(f"{name}: expected a tensor on {self.device}")
+        if tuple(t.shape) != self.shape or t.dtype != self.dtype or not t.is_contiguous():
+            raise ValueError(f"{name}: expected contiguous {self.dtype} {self.shape}, got "
+                             f"{t.dtype} {tuple(t.shape)} contiguous={t.is_contiguous()}")
+        return t
+
+    def new_field(self):
+        return torch.empty(self.shape, dtype=self.dtype, device=self.device)
+
+    # ------------------------------------------------------------- the ABI
+    def push(self, u, v=None):
+        self._field(u, "u")
+        self._field(v, "v", allow_none=True)
+        self._sync_stream()
+        self._check(self._L.sbim_push_displacement(self._h, _ptr(u), _ptr(v)))
+
+    def tractions(self, tau_inf=None, out=None):
+        self._field(tau_inf, "tau_inf", allow_none=True)
+        out = self.new_field() if out is None else self._field(out, "out")
+        self._sync_stream()
+        self._check(self._L.sbim_tractions(self._h, _ptr(tau_inf), _ptr(out)))
+        return out
+
+    def step(self, u, v=None, tau_inf=None, out=None):
+        self.push(u, v)
+        return self.tractions(tau_inf, out)
+
+    def backward(self, g, du=None, dv=None, with_velocity=False):
+        """One reverse step: returns dL/du (and dL/dv when ``with_velocity``)."""
+        self._field(g, "dL_dtau")
+        du = self.new_field() if du is None else self._field(du, "dL_du")
+        if with_velocity and dv is None:
+            dv = self.new_field()
+        self._field(dv, "dL_dv", allow_none=True)
+        self._sync_stream()
+        self._check(self._L.sbim_backward(self._h, _ptr(g), _ptr(du), _ptr(dv)))
+        return (du, dv) if with_velocity else du
+
+    def backward_reset(self):
+        self._check(self._L.sbim_backward_reset(self._h))
+
+    def reset(self):
+        self._sync_stream()
+        self._check(self._L.sbim_reset(self._h))
+
+    def info(self):
+        i = _Info()
+        self._check(self._L.sbim_get_info(self._h, ctypes.byref(i)))
+        return {k: getattr(i, k) for k, _ in _Info._fields_}
+
+    def state_bytes(self):
+        return int(self._L.sbim_state_bytes(self._h))
+
+    def save_state(self, buf=None):
+        if buf is None:
+            buf = torch.empty(self.state_bytes(), dtype=torch.uint8, device=self.device)
+        if buf.numel() < self.state_bytes() or buf.device != self.device:
+            raise ValueError("snapshot buffer too small or on the wrong device")
+        self._sync_stream()
+        self._check(self._L.sbim_save_state(self._h, _ptr(buf)))
+        return buf
+
+    def load_state(self, buf):
+        if buf.numel() < self.state_bytes() or buf.device != self.device:
+            raise ValueError("snapshot buffer too small or on the wrong device")
+        self._sync_stream()
+        self._check(self._L.sbim_load_state(self._h, _ptr(buf)))
+
+    def step_work(self, n):
+        a, b = ctypes.c_double(), ctypes.c_double()
+        self._check(self._L.sbim_step_work(self._h, int(n), ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
+
+    def mode_kernel(self, p, i1, i3, max_lags):
+        import numpy as np
+        buf = (ctypes.c_double * (4 * max(max_lags, 1)))()
+        rc = self._L.sbim_mode_kernel(self._h, p, i1, i3, buf, max_lags)
+        if rc < 0:
+            self._check(rc)
+        w = np.frombuffer(buf, dtype=np.float64).reshape(4, max(max_lags, 1))[:, :min(rc, max_lags)]
+        return rc, w.copy()
+
+    def profile_conv(self, enable=True):
+        self._check(self._L.sbim_profile_conv(self._h, 1 if enable else 0))
+
+    def conv_timing(self):
+        ms, n = ctypes.c_double(), ctypes.c_longlong()
+        self._check(self._L.sbim_conv_timing(self._h, ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, n.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._L.sbim_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ------------------------------------------------------------------ autograd
+
+class SBIMRun(torch.autograd.Function):
+    """tau_hist = SBIMRun.apply(sbim, u_hist[, v_hist]) over N steps from a reset handle.
+
+    The backward runs the library's transpose (``sbim_backward``) over
+    n = N-1 .. 0; the operator is linear, so nothing of the forward is kept.
+    """
+
+    @staticmethod
+    def forward(ctx, sbim: SBIM, u_hist, v_hist=None):
+        sbim.reset()
+        N = u_hist.shape[0]
+        out = torch.empty((N,) + sbim.shape, dtype=sbim.dtype, device=sbim.device)
+        for n in range(N):
+            sbim.push(u_hist[n].contiguous(), None if v_hist is None else v_hist[n].contiguous())
+            sbim.tractions(out=out[n])
+        ctx.sbim = sbim
+        ctx.with_v = v_hist is not None
+        return out
+
+    @staticmethod
+    def backward(ctx, g_hist):
+        sbim = ctx.sbim
+        sbim.backward_reset()
+        N = g_hist.shape[0]
+        du = torch.empty_like(g_hist)
+        dv = torch.empty_like(g_hist) if ctx.with_v else None
+        g_hist = g_hist.contiguous()
+        for n in range(N - 1, -1, -1):
+            sbim.backward(g_hist[n], du=du[n], dv=dv[n] if dv is not None else None,
+                          with_velocity=ctx.with_v)
+        return None, du, dv
+
+
+class _CheckpointedLoss(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, sbim, every, loss_fn, u_hist, v_hist):
+        sbim.reset()
+        N = u_hist.shape[0]
+        snaps = []
+        total = torch.zeros((), dtype=sbim.dtype, device=sbim.device)
+        tau = sbim.new_field()
+        for n in range(N):
+            if n % every == 0:
+                snaps.append(sbim.save_state())
+            sbim.push(u_hist[n].contiguous(), None if v_hist is None else v_hist[n].contiguous())
+            sbim.tractions(out=tau)
+            total = total + loss_fn(tau, n).detach()
+        ctx.sbim, ctx.every, ctx.loss_fn, ctx.snaps = sbim, every, loss_fn, snaps
+        ctx.save_for_backward(u_hist, v_hist if v_hist is not None else torch.empty(0))
+        ctx.with_v = v_hist is not None
+        return total
+
+    @staticmethod
+    def backward(ctx, gout):
+        sbim, every, loss_fn = ctx.sbim, ctx.every, ctx.loss_fn
+        u_hist, v_hist = ctx.saved_tensors
+        v_hist = v_hist if ctx.with_v else None
+        N = u_hist.shape[0]
+        du = torch.empty_like(u_hist)
+        dv = torch.empty_like(u_hist) if ctx.with_v else None
+        sbim.backward_reset()
+        for seg in range((N - 1) // every, -1, -1):
+            a, b = seg * every, min(N, (seg + 1) * every)
+            sbim.load_state(ctx.snaps[seg])      # recompute this segment's tractions
+            taus = []
+            for n in range(a, b):
+                sbim.push(u_hist[n].contiguous(), None if v_hist is None else v_hist[n].contiguous())
+                taus.append(sbim.tractions())
+            for n in range(b - 1, a - 1, -1):
+                t = taus[n - a].detach().requires_grad_(True)
+                with torch.enable_grad():
+                    (g,) = torch.autograd.grad(loss_fn(t, n), t)
+                g = (g * gout).contiguous()
+                sbim.backward(g, du=du[n], dv=dv[n] if dv is not None else None,
+                              with_velocity=ctx.with_v)
+        return None, None, None, du, dv
+
+
+def checkpointed_loss(sbim: SBIM, u_hist, loss_fn, every=50, v_hist=None):
+    """L = sum_n loss_fn(tau^n, n) without keeping tau^n: snapshots every ``every``
+    steps in the forward, and per-segment recomputation of tau in the backward.
+    The handle's forward state is left at the end of the first segment afterwards."""
+    return _CheckpointedLoss.apply(sbim, int(every), loss_fn, u_hist, v_hist)

@@ -1,0 +1,146 @@
+"""GPU parity of the HIP path against the float64 CPU oracle, through the C ABI.
+
+Tolerances (relative L2 over all planes, components, cells and steps):
+float64 path 1e-12, float32 paths 1e-5, both against the float64 oracle.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads
+from paper_2102_08756_amd import SBIM, Config, SBIMRun
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-12, "fp32": 1e-5, "fp32_comp": 1e-5}
+DEV = "cuda:0"
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
+
+
+def run_gpu(cfg_d, u_hist, precision, v_hist=None, tau_inf=None):
+    cfg = Config.from_dict(cfg_d, precision=precision)
+    sb = SBIM(cfg, device=DEV)
+    dt = cfg.dtype
+    out = np.empty(u_hist.shape)
+    u_t = torch.tensor(u_hist, dtype=dt, device=DEV)
+    v_t = torch.tensor(v_hist, dtype=dt, device=DEV) if v_hist is not None else None
+    ti = torch.tensor(tau_inf, dtype=dt, device=DEV) if tau_inf is not None else None
+    for n in range(u_hist.shape[0]):
+        sb.push(u_t[n], None if v_t is None else v_t[n])
+        out[n] = sb.tractions(None if ti is None else ti[n]).double().cpu().numpy()
+    sb.close()
+    return out
+
+
+SMALL = {
+    "square16_fixed": dict(n1=16, n3=16, window_cap=6, planes=[dict(side=1)]),
+    "rect8x32_permode": dict(n1=8, n3=32, dx1=0.7, dx3=1.3, window_cap=9, window_mode="per_mode",
+                             eta_w=0.5, planes=[dict(side=-1, mu=2.0, cs=0.8, cp=1.7)]),
+    "two_planes_two_materials": dict(n1=16, n3=8, window_cap=5,
+                                     planes=[dict(side=1), dict(side=-1, mu=1.5, cs=1.2, cp=2.5)]),
+    "two_planes_shared": dict(n1=32, n3=16, window_cap=12, planes=[dict(side=1), dict(side=-1)]),
+    "tiny4": dict(n1=4, n3=4, window_cap=3, planes=[dict(side=1), dict(side=-1)]),
+}
+
+
+def _inputs(cfg_d, steps, seed):
+    rng = np.random.default_rng(seed)
+    P = len(cfg_d["planes"])
+    shape = (steps, P, 3, cfg_d["n1"], cfg_d["n3"])
+    return rng.standard_normal(shape), rng.standard_normal(shape), rng.standard_normal(shape)
+
+
+@pytest.mark.parametrize("name", sorted(SMALL))
+@pytest.mark.parametrize("kind", ["absolute", "increment"])
+def test_small_fp64(name, kind):
+    cfg_d = dict(SMALL[name], input_kind=kind)
+    u, v, ti = _inputs(cfg_d, 11, 1)
+    ref = oracle.forward(cfg_d, u)
+    got = run_gpu(cfg_d, u, "fp64")
+    assert rel_l2(got, ref) < TOL["fp64"]
+    # explicit velocity and far-field traction
+    ref = oracle.forward(cfg_d, u, v, ti)
+    got = run_gpu(cfg_d, u, "fp64", v, ti)
+    assert rel_l2(got, ref) < TOL["fp64"]
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp32_comp"])
+@pytest.mark.parametrize("name", ["square16_fixed", "two_planes_two_materials", "rect8x32_permode"])
+def test_small_fp32(name, precision):
+    cfg_d = dict(SMALL[name], input_kind="increment")
+    u, v, ti = _inputs(cfg_d, 11, 2)
+    ref = oracle.forward(cfg_d, u, v, ti)
+    got = run_gpu(cfg_d, u, precision, v, ti)
+    assert rel_l2(got, ref) < TOL[precision]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_comp", "fp32"])
+def test_workload_plane64_w100(precision):
+    """The 64x64, W = 100, 200-step single-plane workload in full."""
+    wl = workloads.WORKLOADS[1]
+    du = workloads.Increments(wl).history(wl.steps)
+    cfg_d = wl.config_dict()
+    ref = oracle.forward(cfg_d, du)
+    got = run_gpu(cfg_d, du, precision)
+    err = rel_l2(got, ref)
+    print(f"plane64_w100 {precision}: rel-L2 {err:.3e}")
+    assert err < TOL[precision]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_kernel_tables_match_oracle(precision):
+    cfg_d = dict(n1=64, n3=32, dx1=1.0, dx3=2.0, dt=0.2, window_cap=150, window_mode="per_mode",
+                 eta_w=3.0, planes=[dict(side=1), dict(side=-1, mu=1.0, cs=0.7, cp=1.5)])
+    sb = SBIM(Config.from_dict(cfg_d, precision=precision), device=DEV)
+    ocfg = oracle.Config.from_dict(cfg_d)
+    q, _, _ = oracle.mode_geometry(ocfg)
+    rng = np.random.default_rng(3)
+    picks = [(0, 1), (1, 0), (32, 16), (63, 5), (17, 9)] + [tuple(x) for x in rng.integers(0, [64, 17], (10, 2))]
+    for p in range(2):
+        pl = ocfg.planes[p]
+        for i1, i3 in picks:
+            W = int(oracle.mode_window(q[i1, i3], pl.cs, ocfg.dt, ocfg))
+            w_gpu, tab = sb.mode_kernel(p, i1, i3, 400)
+            assert w_gpu == W, (p, i1, i3)
+            if W == 0:
+                continue
+            ref = oracle.kernels.lag_weights(q[i1, i3], pl.cs, ocfg.dt, W, pl.cp / pl.cs)
+            if precision == "fp64":
+                np.testing.assert_allclose(tab, ref, rtol=0, atol=1e-15)
+            else:
+                np.testing.assert_allclose(tab, ref.astype(np.float32), rtol=0,
+                                           atol=1e-7 * np.abs(ref).max())
+    sb.close()
+
+
+@pytest.mark.parametrize("kind", ["absolute", "increment"])
+@pytest.mark.parametrize("with_v", [False, True])
+def test_adjoint_fp64(kind, with_v):
+    cfg_d = dict(SMALL["two_planes_two_materials"], input_kind=kind, window_mode="per_mode",
+                 eta_w=0.8)
+    u, v, _ = _inputs(cfg_d, 9, 4)
+    g = np.random.default_rng(5).standard_normal(u.shape)
+    du_ref, dv_ref = oracle.adjoint(cfg_d, g, with_velocity=with_v)
+    sb = SBIM(Config.from_dict(cfg_d, precision="fp64"), device=DEV)
+    ut = torch.tensor(u, device=DEV, requires_grad=True)
+    vt = torch.tensor(v, device=DEV, requires_grad=True) if with_v else None
+    tau = SBIMRun.apply(sb, ut, vt)
+    (tau * torch.tensor(g, device=DEV)).sum().backward()
+    assert rel_l2(ut.grad.cpu().numpy(), du_ref) < 1e-12
+    if with_v:
+        assert rel_l2(vt.grad.cpu().numpy(), dv_ref) < 1e-12
+    sb.close()
+
+
+def test_deterministic_bitwise():
+    cfg_d = dict(SMALL["two_planes_shared"], input_kind="increment")
+    u, _, _ = _inputs(cfg_d, 15, 6)
+    a = run_gpu(cfg_d, u, "fp32_comp")
+    b = run_gpu(cfg_d, u, "fp32_comp")
+    assert np.array_equal(a, b)
