@@ -1,0 +1,304 @@
+"""Benchmark of the boundary-integral (SBIM) traction update on one MI355X.
+
+Workload (default): two boundary planes of 512 x 512, three displacement
+components, mu = 1, c_s = 1, c_p = sqrt(3), dx = 1, dt = 0.2, history window
+1000 steps, 2000 time steps; inputs are the seeded |k|^-2 increment fields
+(bank of 64 per plane and component) plus a Gaussian ramp pulse of width 20
+cells on u1.  A "step" is one push of the displacement plus one traction
+evaluation (forward FFT, history update, convolution, inverse FFT); the timed
+region is the whole 2000-step job from an empty history, inputs resident in
+HBM.  Reported: mode-history-steps per second (sum over steps, planes and modes
+of min(W, n+1)) for the compensated float32 form (headline), plain float32 and
+float64, the float32-vs-float64 relative L2 error, the convolution kernel's
+HBM roofline fraction, and the float64 CPU oracle on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "SBIM mode·history-steps/s + % HBM peak; FP32 vs FP64 at 1e-5 rel L2"
+UNIT = "mode·history-steps/s"
+HBM_PEAK_GBS = 8000.0
+PROFILES = os.path.join(ROOT, "profiles")
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "internal.h"):
+        with open(os.path.join(ROOT, "paper_2102_08756_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic(workload, precision):
+    """Per-dispatch HBM bytes of the convolution from the committed rocprofv3 counter summary,
+    scaled by the copy-kernel calibration; None if absent or taken on other kernel sources."""
+    path = os.path.join(PROFILES, "conv_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    want = f"{workload} {precision} "
+    src = None
+    val = None
+    for line in open(path):
+        if line.startswith("kernel_source_hash"):
+            src = line.split("=", 1)[1].strip()
+        if line.startswith(want):
+            parts = line.split()
+            val = float(parts[2])
+    if src != kernel_source_hash() or val is None:
+        return None
+    return val
+
+
+class Inputs:
+    """Per-step increments resident in HBM: the 64-field bank plus the pulse-ramp steps."""
+
+    def __init__(self, wl, dtype, device):
+        import torch
+        import workloads
+        inc = workloads.Increments(wl)
+        self.bank = torch.tensor(inc._bank, dtype=dtype, device=device) if inc._bank is not None else None
+        special = []
+        n = 0
+        while True:  # steps whose increment differs from the plain bank entry
+            d = inc(n)
+            if self.bank is not None and n > 0 and np.array_equal(d, inc._bank[(7 * n) % wl.bank]):
+                break
+            special.append(torch.tensor(d, dtype=dtype, device=device))
+            n += 1
+            if self.bank is None and n >= wl.steps:
+                break
+        self.special = special
+        self.wl = wl
+
+    def __call__(self, n):
+        if n < len(self.special):
+            return self.special[n]
+        return self.bank[(7 * n) % self.wl.bank]
+
+
+def run_job(sb, inputs, steps, tau):
+    for n in range(steps):
+        sb.push(inputs(n))
+        sb.tractions(out=tau)
+
+
+def measure_form(wl, precision, steps, warmup, device, inputs_cache):
+    import torch
+    from paper_2102_08756_amd import SBIM, Config
+    cfg = Config.from_dict(wl.config_dict(), precision=precision)
+    t0 = time.time()
+    sb = SBIM(cfg, device=device)
+    t_init = time.time() - t0
+    key = cfg.dtype
+    if key not in inputs_cache:
+        inputs_cache[key] = Inputs(wl, cfg.dtype, device)
+    inputs = inputs_cache[key]
+    tau = sb.new_field()
+    # warmup (also grows the conv event pool), then reset to an empty history
+    sb.profile_conv(True)
+    run_job(sb, inputs, warmup, tau)
+    sb.reset()
+    sb.profile_conv(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    run_job(sb, inputs, steps, tau)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    conv_ms, launches = sb.conv_timing()
+    sb.profile_conv(False)
+    lags = 0.0
+    conv_bytes = 0.0
+    for n in range(steps):
+        a, b = sb.step_work(n)
+        lags += a
+        conv_bytes += b
+    info = sb.info()
+    sb.close()
+    del sb
+    torch.cuda.empty_cache()
+    gbs = conv_bytes / (conv_ms * 1e-3) / 1e9
+    traffic = read_traffic(wl.name, precision)
+    return {
+        "value": lags / elapsed,
+        "ms_per_step": 1e3 * elapsed / steps,
+        "elapsed_s": elapsed,
+        "init_s": t_init,
+        "mode_lags": lags,
+        "roofline": {
+            "bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": gbs / HBM_PEAK_GBS,
+            "traffic": traffic,
+            "algorithmic_bytes_per_launch": conv_bytes / launches if launches else None,
+            "avg_launch_ms": conv_ms / launches if launches else None,
+            "launches": launches,
+        },
+        "info": info,
+    }
+
+
+def accuracy(wl, steps, device, inputs_cache, forms=("fp32_comp", "fp32")):
+    """Relative L2 of float32 forms against float64 on the same inputs, whole job and worst step."""
+    import torch
+    from paper_2102_08756_amd import SBIM, Config
+    ref = SBIM(Config.from_dict(wl.config_dict(), precision="fp64"), device=device)
+    others = {f: SBIM(Config.from_dict(wl.config_dict(), precision=f), device=device) for f in forms}
+    in64 = inputs_cache[torch.float64]
+    in32 = inputs_cache[torch.float32]
+    num = {f: torch.zeros((), dtype=torch.float64, device=device) for f in forms}
+    worst = {f: torch.zeros((), dtype=torch.float64, device=device) for f in forms}
+    den = torch.zeros((), dtype=torch.float64, device=device)
+    t64 = ref.new_field()
+    t32 = {f: others[f].new_field() for f in forms}
+    for n in range(steps):
+        ref.push(in64(n))
+        ref.tractions(out=t64)
+        d = (t64 * t64).sum()
+        den += d
+        for f in forms:
+            others[f].push(in32(n))
+            others[f].tractions(out=t32[f])
+            e = ((t32[f].double() - t64) ** 2).sum()
+            num[f] += e
+            worst[f] = torch.maximum(worst[f], torch.sqrt(e / d))
+    out = {}
+    for f in forms:
+        out[f"{f}_vs_fp64_rel_l2"] = float(torch.sqrt(num[f] / den))
+        out[f"{f}_vs_fp64_worst_step_rel_l2"] = float(worst[f])
+    ref.close()
+    for s in others.values():
+        s.close()
+    return out
+
+
+def cpu_baseline(wl, sample_modes=64, seed=0):
+    """float64 oracle on one steady-state step: full naive DFTs, convolution on sampled modes."""
+    import oracle
+    from oracle import dft
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
+    except Exception:
+        cores = os.cpu_count()
+    cfg = oracle.Config.from_dict(wl.config_dict())
+    rng = np.random.default_rng(seed)
+    P = len(cfg.planes)
+    h = cfg.n3 // 2 + 1
+    W = cfg.window_cap
+    fields = rng.standard_normal((P, 3, cfg.n1, cfg.n3))
+    t0 = time.perf_counter()
+    spec = dft.forward_half(fields)
+    t_fwd = time.perf_counter() - t0
+    t_conv = 0.0
+    nm_total = 0
+    for p in range(P):
+        i1 = rng.integers(0, cfg.n1, sample_modes)
+        i3 = rng.integers(0, h, sample_modes)
+        op = oracle.sbim.PlaneOperator(cfg, p, (i1, i3))          # kernel weights: init, not timed
+        U = rng.standard_normal((W, 3, sample_modes)) + 1j * rng.standard_normal((W, 3, sample_modes))
+        V = rng.standard_normal((3, sample_modes)) + 1j * rng.standard_normal((3, sample_modes))
+        t0 = time.perf_counter()
+        op.apply_last(U, V)
+        t_conv += time.perf_counter() - t0
+        nm_total += sample_modes
+    t0 = time.perf_counter()
+    dft.inverse_half(spec, cfg.n3)
+    t_inv = time.perf_counter() - t0
+    M = cfg.n1 * h
+    step_s = t_fwd + t_inv + t_conv * (P * M) / nm_total
+    lags = P * M * W
+    return {
+        "value": lags / step_s, "unit": UNIT, "cores": cores, "kind": "oracle",
+        "sample": (f"one steady-state step (W={W}) of {wl.name}: naive DFT forward+inverse of all "
+                   f"{P}x3 fields timed in full ({t_fwd + t_inv:.2f} s); direct convolution timed on "
+                   f"{sample_modes} random modes per plane ({t_conv:.3f} s) and scaled to all "
+                   f"{P}x{M} modes; kernel weights excluded (init)"),
+        "step_s_extrapolated": step_s,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=None, help="timed steps (default: the whole job)")
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--workload", type=int, default=2)
+    ap.add_argument("--forms", default="fp32_comp,fp32,fp64")
+    ap.add_argument("--no-accuracy", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--calibrate-copy", type=float, default=0.0,
+                    help="only run a torch device copy of this many GiB (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+    import torch
+    import workloads
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU visible"}))
+        sys.exit(1)
+    device = "cuda:0"
+    if args.calibrate_copy:
+        n = int(args.calibrate_copy * 2 ** 30 / 4)
+        a = torch.ones(n, dtype=torch.float32, device=device)
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_each_way": 4 * n, "dispatches": 5}))
+        return
+    wl = workloads.WORKLOADS[args.workload]
+    steps = args.steps or wl.steps
+    forms = [f for f in args.forms.split(",") if f]
+    cache = {}
+    res = {}
+    for f in forms:
+        res[f] = measure_form(wl, f, steps, args.warmup, device, cache)
+        print(f"[bench] {f}: {res[f]['value']:.4e} {UNIT}, {res[f]['ms_per_step']:.3f} ms/step, "
+              f"conv {res[f]['roofline']['achieved']:.0f} GB/s ({100 * res[f]['roofline']['frac']:.1f}% of HBM peak)",
+              file=sys.stderr, flush=True)
+    acc = None
+    if not args.no_accuracy and "fp64" in forms and len(forms) > 1:
+        for dt in (torch.float32, torch.float64):
+            if dt not in cache:
+                cache[dt] = Inputs(wl, dt, device)
+        acc = accuracy(wl, steps, device, cache, [f for f in forms if f != "fp64"])
+        print(f"[bench] accuracy: {acc}", file=sys.stderr, flush=True)
+    cpu = None if args.no_cpu else cpu_baseline(wl)
+    head = forms[0]
+    r = res[head]
+    line = {
+        "metric": METRIC, "value": r["value"], "unit": UNIT, "n_gpus": 1, "steps": steps,
+        "warmup": args.warmup, "ms_per_step": r["ms_per_step"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if head == "fp64" else "f32", "data": "synthetic",
+        "config": {"workload": wl.name, "n1": wl.n1, "n3": wl.n3, "planes": len(wl.planes),
+                   "window_cap": wl.window_cap, "window_mode": wl.window_mode,
+                   "time_steps": steps, "precision": head, "input_kind": wl.input_kind},
+        "roofline": {k: v for k, v in r["roofline"].items()},
+        "cpu_baseline": cpu,
+        "forms": {f: {"value": res[f]["value"], "ms_per_step": res[f]["ms_per_step"],
+                      "conv_GBs": res[f]["roofline"]["achieved"],
+                      "conv_frac": res[f]["roofline"]["frac"], "init_s": res[f]["init_s"],
+                      "ring_bytes": res[f]["info"]["ring_bytes"],
+                      "table_bytes": res[f]["info"]["table_bytes"],
+                      "kernel_classes": res[f]["info"]["kernel_classes"]} for f in forms},
+        "accuracy": acc,
+        "kernel_source_hash": kernel_source_hash(),
+    }
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

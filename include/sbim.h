@@ -109,7 +109,7 @@ typedef struct {
   long long step;              /* pushes since init / reset */
   long long backward_step;     /* sbim_backward calls since the last reset */
   int material_groups;         /* planes sharing (c_s, c_p) share one table and one pass */
-  int lag_split;               /* waves per 64-mode block in the convolution */
+  int lag_split;               /* lag chunks per 64-mode block in the history stream */
 } sbim_info;
 
 /*
@@ -180,10 +180,12 @@ int sbim_save_state(sbim_handle *h, void *dst_device);
 int sbim_load_state(sbim_handle *h, const void *src_device);
 
 /*
- * Work of the step with index n (0-based): the number of (plane, mode, lag)
- * products min(W(q), n+1) summed over planes and modes, and the bytes the
- * convolution must move for it: history read + kernel rows read + per-mode
- * inputs/outputs (velocity spectra, geometry, spectrum written).
+ * Work of the step with index n (0-based): *mode_lags = the number of
+ * (plane, mode, lag) products, i.e. min(W(q), n+1) summed over planes and
+ * modes; *conv_bytes = the bytes the history-stream kernel must move for that
+ * step: the history those products read, the kernel rows they use (once per
+ * distinct row), the per-mode row/window indices and the partial sums it
+ * writes.
  */
 int sbim_step_work(const sbim_handle *h, long long n, double *mode_lags, double *conv_bytes);
 
@@ -196,9 +198,10 @@ int sbim_step_work(const sbim_handle *h, long long n, double *mode_lags, double 
 int sbim_mode_kernel(sbim_handle *h, int p, int i1, int i3, double *host_out, int max_lags);
 
 /*
- * Timing of the convolution kernel: when enabled, HIP events bracket every
- * convolution launch on the handle's stream; sbim_conv_timing synchronises
- * and returns the summed device time (ms) and the launch count since enable.
+ * Timing of the history-stream kernel (the dominant kernel of a step): when
+ * enabled, HIP events bracket each of its launches made by sbim_tractions on
+ * the handle's stream; sbim_conv_timing synchronises and returns the summed
+ * device time (ms) and the launch count since the last sbim_profile_conv.
  */
 int sbim_profile_conv(sbim_handle *h, int enable);
 int sbim_conv_timing(sbim_handle *h, double *total_ms, long long *launches);

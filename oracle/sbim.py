@@ -189,6 +189,16 @@ class PlaneOperator:
                 out[n] += np.einsum("jmab,jbm->am", self.K[:L], past, optimize=True)
         return out
 
+    def apply_last(self, U_hist, V_last):
+        """tau_hat of the last step only: the same direct sum as ``apply`` for n = N-1."""
+        N = U_hist.shape[0]
+        out = np.einsum("mab,bm->am", self.I, U_hist[-1]) + np.einsum("mab,bm->am", self.D, V_last)
+        L = min(N, self.Wmax)
+        if L:
+            past = U_hist[N - L:][::-1]
+            out += np.einsum("jmab,jbm->am", self.K[:L], past, optimize=True)
+        return out
+
     def apply_adjoint(self, G_hist):
         """(lam_U, lam_V): the conjugate-transposed operators run backwards in time.
 

@@ -1,10 +1,12 @@
-// Real 2-D FFT of boundary fields on gfx950: row real-to-complex / complex-to-real
-// transforms and strided column transforms, each done by one work-group in LDS
-// with Stockham autosort radix-4 passes (one radix-2 pass when log2 N is odd).
-//
-// Conventions (the paper fixes none): forward exp(-i k.x), stored half spectrum
-// [n1][n3/2+1]; the inverse drops the imaginary parts of the i3 = 0 and
-// i3 = n3/2 columns and applies the caller's scale (1/(n1 n3) for tractions).
+// Real 2-D FFT of boundary fields on gfx950.  Every transform runs in LDS with
+// Stockham autosort radix-4 passes (one radix-2 pass when log2 N is odd), and
+// every pass reads and writes contiguous rows:
+//   forward  [F][n1][n3] real --r2c along x3, written transposed--> [F][h3][n1]
+//            --complex FFT along contiguous x1 rows--> spectrum [F][h3][n1];
+//   inverse  the same two steps backwards.
+// Conventions (the paper fixes none): forward exp(-i k.x) on the stored half
+// spectrum (h3 = n3/2 + 1 bins along x3); the inverse drops the imaginary parts
+// of the i3 = 0 and i3 = n3/2 bins and applies the caller's scale.
 #include <cmath>
 
 #include "internal.h"
@@ -122,107 +124,128 @@ __device__ void lds_fft(cplx<R> *buf, int N, int logN, int nseq, int dir,
   }
 }
 
+// Points per work-group in LDS: at most 16 per thread (register staging of a
+// pass), i.e. 4096, which is also the largest transform length.
 template <typename R>
-constexpr int lds_elems() { return static_cast<int>(kFftLdsBytes / sizeof(cplx<R>)); }
+constexpr int lds_elems() { return kFftThreads * kFftPerThread; }
 
-// Rows of n3 reals -> n3/2+1 complex bins.  Pairs (x[2m], x[2m+1]) form a
-// half-length complex sequence; its FFT Z gives
+// Forward, step 1: rows x1 in [x0, x0 + R) of one field; each row of n3 reals
+// becomes n3/2+1 bins.  Pairs (x[2m], x[2m+1]) form a half-length complex
+// sequence z; with Z = FFT(z)
 //   X[k] = (Z[k] + conj Z[Nh-k]) / 2 - i e^{-2 pi i k/n3} (Z[k] - conj Z[Nh-k]) / 2.
+// The bins are written transposed, spec[f][k][x1], R consecutive x1 at a time.
 template <typename R>
-__global__ __launch_bounds__(kFftThreads) void r2c_rows_kernel(
-    const R *__restrict__ in, cplx<R> *__restrict__ out, long long rows, int n3, int logNh,
-    int rows_per_wg, const cplx<R> *__restrict__ tw) {
+__global__ __launch_bounds__(kFftThreads) void r2c_t_kernel(
+    const R *__restrict__ in, cplx<R> *__restrict__ spec, int n1, int n3, int logNh, int rows,
+    const cplx<R> *__restrict__ tw) {
   extern __shared__ unsigned char smem_raw[];
   cplx<R> *buf = reinterpret_cast<cplx<R> *>(smem_raw);
   const int Nh = n3 >> 1;
   const int h3 = Nh + 1;
-  const long long row0 = static_cast<long long>(blockIdx.x) * rows_per_wg;
-  const int nb = static_cast<int>(min(static_cast<long long>(rows_per_wg), rows - row0));
-  const cplx<R> *src = reinterpret_cast<const cplx<R> *>(in + row0 * n3);
-  for (int e = threadIdx.x; e < nb * Nh; e += kFftThreads) buf[e] = src[e];
+  const int tiles = n1 / rows;
+  const int f = blockIdx.x / tiles;
+  const int x0 = (blockIdx.x - f * tiles) * rows;
+  const cplx<R> *src =
+      reinterpret_cast<const cplx<R> *>(in + (static_cast<long long>(f) * n1 + x0) * n3);
+  for (int e = threadIdx.x; e < rows * Nh; e += kFftThreads) buf[e] = src[e];
   __syncthreads();
-  lds_fft<R, kFftThreads, lds_elems<R>() / kFftThreads>(buf, Nh, logNh, nb, -1, tw);
+  lds_fft<R, kFftThreads, kFftPerThread>(buf, Nh, logNh, rows, -1, tw);
   const int step = kTwiddleN / n3;
-  for (int e = threadIdx.x; e < nb * h3; e += kFftThreads) {
-    const int r = e / h3;
-    const int k = e - r * h3;
+  cplx<R> *dst = spec + static_cast<long long>(f) * h3 * n1 + x0;
+  for (int e = threadIdx.x; e < rows * h3; e += kFftThreads) {
+    const int k = e / rows;
+    const int r = e - k * rows;
     const cplx<R> zk = buf[r * Nh + (k == Nh ? 0 : k)];
     const cplx<R> zc = cconj<R>(buf[r * Nh + (k == 0 ? 0 : Nh - k)]);
     const cplx<R> ev = {(zk.x + zc.x) * R(0.5), (zk.y + zc.y) * R(0.5)};
     const cplx<R> od = {(zk.x - zc.x) * R(0.5), (zk.y - zc.y) * R(0.5)};
     const cplx<R> t = cmul<R>(od, twiddle<R>(tw, k * step, -1));
-    out[(row0 + r) * h3 + k] = cplx<R>{ev.x + t.y, ev.y - t.x};  // ev - i t
+    dst[static_cast<long long>(k) * n1 + r] = cplx<R>{ev.x + t.y, ev.y - t.x};  // ev - i t
   }
 }
 
-// n3/2+1 complex bins -> n3 reals (unnormalised inverse, then * scale, + add).
+// Complex FFT along contiguous rows of length n (in place); `per` rows per work-group.
 template <typename R>
-__global__ __launch_bounds__(kFftThreads) void c2r_rows_kernel(
-    const cplx<R> *__restrict__ in, R *__restrict__ out, const R *__restrict__ add,
-    long long rows, int n3, int logNh, int rows_per_wg, R scale,
+__global__ __launch_bounds__(kFftThreads) void cfft_rows_kernel(
+    cplx<R> *__restrict__ data, long long nrows, int n, int logn, int per, int dir,
     const cplx<R> *__restrict__ tw) {
+  extern __shared__ unsigned char smem_raw[];
+  cplx<R> *buf = reinterpret_cast<cplx<R> *>(smem_raw);
+  const long long row0 = static_cast<long long>(blockIdx.x) * per;
+  const int nb = static_cast<int>(min(static_cast<long long>(per), nrows - row0));
+  cplx<R> *base = data + row0 * n;
+  for (int e = threadIdx.x; e < nb * n; e += kFftThreads) buf[e] = base[e];
+  __syncthreads();
+  lds_fft<R, kFftThreads, kFftPerThread>(buf, n, logn, nb, dir, tw);
+  for (int e = threadIdx.x; e < nb * n; e += kFftThreads) base[e] = buf[e];
+}
+
+// Inverse, last step: rows x1 in [x0, x0 + R) of one field from the transposed
+// spectrum spec[f][k][x1] (k = 0..n3/2, imaginary parts of k = 0 and k = n3/2
+// dropped).  With Y the row's bins,
+//   Z[k] = (Y[k] + conj Y[Nh-k]) + i e^{+2 pi i k/n3} (Y[k] - conj Y[Nh-k]),
+// an inverse half-length FFT gives x[2m] + i x[2m+1]; the result is scaled and
+// the optional field `add` is added.
+template <typename R>
+__global__ __launch_bounds__(kFftThreads) void c2r_t_kernel(
+    const cplx<R> *__restrict__ spec, R *__restrict__ out, const R *__restrict__ add, int n1,
+    int n3, int logNh, int rows, R scale, const cplx<R> *__restrict__ tw) {
   extern __shared__ unsigned char smem_raw[];
   cplx<R> *buf = reinterpret_cast<cplx<R> *>(smem_raw);
   const int Nh = n3 >> 1;
   const int h3 = Nh + 1;
-  const long long row0 = static_cast<long long>(blockIdx.x) * rows_per_wg;
-  const int nb = static_cast<int>(min(static_cast<long long>(rows_per_wg), rows - row0));
-  const int step = kTwiddleN / n3;
-  for (int e = threadIdx.x; e < nb * Nh; e += kFftThreads) {
-    const int r = e / Nh;
-    const int k = e - r * Nh;
-    const cplx<R> *row = in + (row0 + r) * h3;
-    cplx<R> yk = row[k];
-    cplx<R> ym = row[Nh - k];
-    if (k == 0) {  // the i3 = 0 and i3 = n3/2 bins enter through their real parts only
-      yk.y = R(0);
-      ym.y = R(0);
-    }
-    const cplx<R> yc = cconj<R>(ym);
-    const cplx<R> a = cadd<R>(yk, yc);
-    const cplx<R> b = cmul<R>(csub<R>(yk, yc), twiddle<R>(tw, k * step, +1));
-    buf[e] = cplx<R>{a.x - b.y, a.y + b.x};  // a + i b
+  cplx<R> *nyq = buf + rows * Nh;  // bin k = Nh of each row
+  const int tiles = n1 / rows;
+  const int f = blockIdx.x / tiles;
+  const int x0 = (blockIdx.x - f * tiles) * rows;
+  const cplx<R> *src = spec + static_cast<long long>(f) * h3 * n1 + x0;
+  for (int e = threadIdx.x; e < rows * h3; e += kFftThreads) {
+    const int k = e / rows;
+    const int r = e - k * rows;
+    const cplx<R> v = src[static_cast<long long>(k) * n1 + r];
+    if (k < Nh)
+      buf[r * Nh + k] = v;
+    else
+      nyq[r] = v;
   }
   __syncthreads();
-  lds_fft<R, kFftThreads, lds_elems<R>() / kFftThreads>(buf, Nh, logNh, nb, +1, tw);
-  cplx<R> *dst = reinterpret_cast<cplx<R> *>(out + row0 * n3);
-  const cplx<R> *addp = add ? reinterpret_cast<const cplx<R> *>(add + row0 * n3) : nullptr;
-  for (int e = threadIdx.x; e < nb * Nh; e += kFftThreads) {
+  const int step = kTwiddleN / n3;
+  const int half = Nh / 2 + 1;
+  for (int e = threadIdx.x; e < rows * half; e += kFftThreads) {
+    const int r = e / half;
+    const int k = e - r * half;
+    cplx<R> *row = buf + r * Nh;
+    if (k == 0) {
+      const R y0 = row[0].x, yn = nyq[r].x;
+      row[0] = cplx<R>{y0 + yn, y0 - yn};
+    } else {
+      const int m = Nh - k;
+      const cplx<R> yk = row[k], ym = row[m];
+      const cplx<R> a1 = cadd<R>(yk, cconj<R>(ym));
+      const cplx<R> b1 = cmul<R>(csub<R>(yk, cconj<R>(ym)), twiddle<R>(tw, k * step, +1));
+      row[k] = cplx<R>{a1.x - b1.y, a1.y + b1.x};
+      if (m != k) {
+        const cplx<R> a2 = cadd<R>(ym, cconj<R>(yk));
+        const cplx<R> b2 = cmul<R>(csub<R>(ym, cconj<R>(yk)), twiddle<R>(tw, m * step, +1));
+        row[m] = cplx<R>{a2.x - b2.y, a2.y + b2.x};
+      }
+    }
+  }
+  __syncthreads();
+  lds_fft<R, kFftThreads, kFftPerThread>(buf, Nh, logNh, rows, +1, tw);
+  const long long o = (static_cast<long long>(f) * n1 + x0) * n3;
+  cplx<R> *dst = reinterpret_cast<cplx<R> *>(out + o);
+  const cplx<R> *addp = add ? reinterpret_cast<const cplx<R> *>(add + o) : nullptr;
+  for (int e = threadIdx.x; e < rows * Nh; e += kFftThreads) {
     cplx<R> z = buf[e];
     z.x *= scale;
     z.y *= scale;
     if (addp) {
-      const cplx<R> s = addp[e];
-      z.x += s.x;
-      z.y += s.y;
+      const cplx<R> a = addp[e];
+      z.x += a.x;
+      z.y += a.y;
     }
     dst[e] = z;
-  }
-}
-
-// In-place FFT along n1 of every column of [outer][n1][h3]; a work-group takes
-// a tile of up to `tile` adjacent columns of one outer slice.
-template <typename R>
-__global__ __launch_bounds__(kFftThreads) void col_fft_kernel(
-    cplx<R> *__restrict__ data, int n1, int logn1, int h3, int tile, int ntiles, int dir,
-    const cplx<R> *__restrict__ tw) {
-  extern __shared__ unsigned char smem_raw[];
-  cplx<R> *buf = reinterpret_cast<cplx<R> *>(smem_raw);
-  const long long o = blockIdx.x / ntiles;
-  const int c0 = (blockIdx.x - static_cast<int>(o) * ntiles) * tile;
-  const int tc = min(tile, h3 - c0);
-  cplx<R> *base = data + o * static_cast<long long>(n1) * h3 + c0;
-  for (int e = threadIdx.x; e < n1 * tc; e += kFftThreads) {
-    const int r = e / tc;
-    const int c = e - r * tc;
-    buf[c * n1 + r] = base[static_cast<long long>(r) * h3 + c];
-  }
-  __syncthreads();
-  lds_fft<R, kFftThreads, lds_elems<R>() / kFftThreads>(buf, n1, logn1, tc, dir, tw);
-  for (int e = threadIdx.x; e < n1 * tc; e += kFftThreads) {
-    const int r = e / tc;
-    const int c = e - r * tc;
-    base[static_cast<long long>(r) * h3 + c] = buf[c * n1 + r];
   }
 }
 
@@ -232,64 +255,66 @@ int ilog2(int n) {
   return l;
 }
 
+// x1 rows per work-group of the real<->complex kernels: up to 8 (64-byte runs of
+// the transposed spectrum in float32), within the LDS budget.
 template <typename R>
-hipError_t r2c_impl(const void *in, void *out, long long rows, int n3, const void *tw,
-                    hipStream_t st) {
-  const int Nh = n3 / 2;
-  const int per = max(1, lds_elems<R>() / Nh);
-  const long long grid = (rows + per - 1) / per;
-  const size_t lds = static_cast<size_t>(per) * Nh * sizeof(cplx<R>);
-  hipLaunchKernelGGL(r2c_rows_kernel<R>, dim3(static_cast<unsigned>(grid)), dim3(kFftThreads),
-                     lds, st, static_cast<const R *>(in), static_cast<cplx<R> *>(out), rows, n3,
-                     ilog2(Nh), per, static_cast<const cplx<R> *>(tw));
-  return hipGetLastError();
+int tile_rows(int n1, int Nh) {
+  return max(1, min(min(8, n1), lds_elems<R>() / Nh));
 }
 
 template <typename R>
-hipError_t c2r_impl(const void *in, void *out, const void *add, long long rows, int n3,
-                    double scale, const void *tw, hipStream_t st) {
-  const int Nh = n3 / 2;
-  const int per = max(1, lds_elems<R>() / Nh);
-  const long long grid = (rows + per - 1) / per;
-  const size_t lds = static_cast<size_t>(per) * Nh * sizeof(cplx<R>);
-  hipLaunchKernelGGL(c2r_rows_kernel<R>, dim3(static_cast<unsigned>(grid)), dim3(kFftThreads),
-                     lds, st, static_cast<const cplx<R> *>(in), static_cast<R *>(out),
-                     static_cast<const R *>(add), rows, n3, ilog2(Nh), per, static_cast<R>(scale),
+hipError_t forward_impl(const void *in, void *spec, int F, int n1, int n3, const void *tw,
+                        hipStream_t st) {
+  const int Nh = n3 / 2, h3 = Nh + 1;
+  const int rows = tile_rows<R>(n1, Nh);
+  hipLaunchKernelGGL(r2c_t_kernel<R>, dim3(static_cast<unsigned>(F * (n1 / rows))),
+                     dim3(kFftThreads), static_cast<size_t>(rows) * Nh * sizeof(cplx<R>), st,
+                     static_cast<const R *>(in), static_cast<cplx<R> *>(spec), n1, n3, ilog2(Nh),
+                     rows, static_cast<const cplx<R> *>(tw));
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const long long nrows = static_cast<long long>(F) * h3;
+  const int per = max(1, min(lds_elems<R>() / n1, 1024 / n1));
+  hipLaunchKernelGGL(cfft_rows_kernel<R>, dim3(static_cast<unsigned>((nrows + per - 1) / per)),
+                     dim3(kFftThreads), static_cast<size_t>(per) * n1 * sizeof(cplx<R>), st,
+                     static_cast<cplx<R> *>(spec), nrows, n1, ilog2(n1), per, -1,
                      static_cast<const cplx<R> *>(tw));
   return hipGetLastError();
 }
 
 template <typename R>
-hipError_t col_impl(void *data, long long outer, int n1, int h3, int dir, const void *tw,
-                    hipStream_t st) {
-  const int tile = max(1, min(16, lds_elems<R>() / n1));
-  const int ntiles = (h3 + tile - 1) / tile;
-  const long long grid = outer * ntiles;
-  const size_t lds = static_cast<size_t>(tile) * n1 * sizeof(cplx<R>);
-  hipLaunchKernelGGL(col_fft_kernel<R>, dim3(static_cast<unsigned>(grid)), dim3(kFftThreads), lds,
-                     st, static_cast<cplx<R> *>(data), n1, ilog2(n1), h3, tile, ntiles, dir,
+hipError_t inverse_impl(void *spec, void *out, const void *add, int F, int n1, int n3,
+                        double scale, const void *tw, hipStream_t st) {
+  const int Nh = n3 / 2, h3 = Nh + 1;
+  const long long nrows = static_cast<long long>(F) * h3;
+  const int per = max(1, min(lds_elems<R>() / n1, 1024 / n1));
+  hipLaunchKernelGGL(cfft_rows_kernel<R>, dim3(static_cast<unsigned>((nrows + per - 1) / per)),
+                     dim3(kFftThreads), static_cast<size_t>(per) * n1 * sizeof(cplx<R>), st,
+                     static_cast<cplx<R> *>(spec), nrows, n1, ilog2(n1), per, +1,
+                     static_cast<const cplx<R> *>(tw));
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int rows = tile_rows<R>(n1, Nh);
+  hipLaunchKernelGGL(c2r_t_kernel<R>, dim3(static_cast<unsigned>(F * (n1 / rows))),
+                     dim3(kFftThreads), static_cast<size_t>(rows) * (Nh + 1) * sizeof(cplx<R>), st,
+                     static_cast<const cplx<R> *>(spec), static_cast<R *>(out),
+                     static_cast<const R *>(add), n1, n3, ilog2(Nh), rows, static_cast<R>(scale),
                      static_cast<const cplx<R> *>(tw));
   return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_r2c_rows(bool fp64, const void *in, void *out, long long rows, int n3,
-                           const void *tw, hipStream_t st) {
-  return fp64 ? r2c_impl<double>(in, out, rows, n3, tw, st)
-              : r2c_impl<float>(in, out, rows, n3, tw, st);
+hipError_t launch_fft_forward(bool fp64, const void *in, void *spec, int F, int n1, int n3,
+                              const void *tw, hipStream_t st) {
+  return fp64 ? forward_impl<double>(in, spec, F, n1, n3, tw, st)
+              : forward_impl<float>(in, spec, F, n1, n3, tw, st);
 }
 
-hipError_t launch_c2r_rows(bool fp64, const void *in, void *out, const void *add, long long rows,
-                           int n3, double scale, const void *tw, hipStream_t st) {
-  return fp64 ? c2r_impl<double>(in, out, add, rows, n3, scale, tw, st)
-              : c2r_impl<float>(in, out, add, rows, n3, scale, tw, st);
-}
-
-hipError_t launch_col_fft(bool fp64, void *data, long long outer, int n1, int h3, int dir,
-                          const void *tw, hipStream_t st) {
-  return fp64 ? col_impl<double>(data, outer, n1, h3, dir, tw, st)
-              : col_impl<float>(data, outer, n1, h3, dir, tw, st);
+hipError_t launch_fft_inverse(bool fp64, void *spec, void *out, const void *add, int F, int n1,
+                              int n3, double scale, const void *tw, hipStream_t st) {
+  return fp64 ? inverse_impl<double>(spec, out, add, F, n1, n3, scale, tw, st)
+              : inverse_impl<float>(spec, out, add, F, n1, n3, scale, tw, st);
 }
 
 // Twiddles exp(-2 pi i m / 4096), m = 0..4095, from long-double sin/cos on the host.

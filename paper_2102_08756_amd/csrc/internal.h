@@ -15,17 +15,11 @@ constexpr int kLanes = 64;            // modes per wavefront / per ring block
 constexpr int kTwiddleLog = 12;       // twiddle table covers lengths up to 4096
 constexpr int kTwiddleN = 1 << kTwiddleLog;
 constexpr int kFftThreads = 256;
-constexpr size_t kFftLdsBytes = 65536;  // per work-group LDS budget of the FFT kernels
+constexpr int kFftPerThread = 16;     // transform points per thread in the LDS FFT kernels
 constexpr int kGaussN = 32;           // Gauss-Legendre points per quadrature panel
-constexpr int kConvLdsBytes = 65536;  // LDS budget of the convolution's cross-wave reduction
-
-// Largest power-of-two lag split (<= 8) whose S-1 partial sums fit kConvLdsBytes.
-constexpr int conv_max_split(int np, bool fp64, bool comp) {
-  const int per_wave = np * 10 * kLanes * (fp64 ? 8 : 4) * (comp ? 2 : 1);
-  int s = 1;
-  while (s < 8 && (2 * s - 1) * per_wave <= kConvLdsBytes) s *= 2;
-  return s;
-}
+constexpr int kMaxChunks = 64;        // largest lag split of the convolution
+constexpr long long kTargetItems = 8192;  // aim for this many work items per convolution
+constexpr int kMinChunkLags = 16;     // shortest lag chunk worth a work item
 
 // What push_kernel stores as "velocity" for the epilogue.
 enum VelRule : int {
@@ -54,12 +48,13 @@ struct Group {
   long long ring_records = 0;     // sum of block capacities
   long long table_rows = 0;       // sum over classes of W
   // device
-  int *nat = nullptr;             // [M] sorted position -> natural flat bin
+  int *nat = nullptr;             // [M] sorted position -> spectrum bin i3 * n1 + i1
   int *cls = nullptr;             // [M] sorted position -> class
   int *win = nullptr;             // [M] W(q) per sorted position
   double *geom = nullptr;         // [M][4] q, kh1, kh3, 0 per sorted position
   long long *blk_off = nullptr;   // [nblocks] first ring record of the block
   int *blk_cap = nullptr;         // [nblocks] ring capacity of the block (its largest W)
+  int *blk_stride = nullptr;      // [nblocks] records between consecutive slots of the block
   long long *lag_off = nullptr;   // [wmax] first table entry of each lag row
   double *cls_q = nullptr;        // [nclasses]
   int *cls_w = nullptr;           // [nclasses]
@@ -67,6 +62,7 @@ struct Group {
   void *ring = nullptr;           // [ring_records][np][3][64] complex
   double *state = nullptr;        // [np][3][M] complex double (rotated frame, sorted)
   void *vel = nullptr;            // [np][3][M] complex real_t
+  void *partial = nullptr;        // [chunks][np * 10][M] real_t: per-chunk history sums
   // adjoint (allocated on first use)
   void *ring_adj = nullptr;
   double *state_adj = nullptr;    // previous g spectrum (float64)
@@ -94,25 +90,25 @@ struct sbim_handle {
   long long step = 0;             // pushes done
   long long bstep = 0;            // backward calls done
   bool pushed_since_tractions = false;
-  int lag_split = 1;
+  int lag_split = 1;               // lag chunks per 64-mode block in the convolution
   void *twiddle = nullptr;        // [4096] complex real_t, exp(-2 pi i m / 4096)
-  void *spec = nullptr;           // [P][3][n1][h3] complex: spectrum of the pushed field
+  void *spec = nullptr;           // [P][3][h3][n1] complex: spectrum of the pushed field
   void *spec_v = nullptr;         // same for the velocity / second output
-  void *out_spec = nullptr;       // [P][3][n1][h3] complex: traction spectrum
+  void *out_spec = nullptr;       // [P][3][h3][n1] complex: traction spectrum
   bool profile = false;
-  std::vector<hipEvent_t> ev_start, ev_stop;
+  std::vector<hipEvent_t> ev_start, ev_stop;  // reusable pool
+  size_t ev_used = 0;                          // pairs recorded since sbim_profile_conv
   std::string err;
 };
 
 namespace sbim {
 
-// fft.hip
-hipError_t launch_r2c_rows(bool fp64, const void *in, void *out, long long rows, int n3,
-                           const void *tw, hipStream_t st);
-hipError_t launch_col_fft(bool fp64, void *data, long long outer, int n1, int h3, int dir,
-                          const void *tw, hipStream_t st);
-hipError_t launch_c2r_rows(bool fp64, const void *in, void *out, const void *add_or_null,
-                           long long rows, int n3, double scale, const void *tw, hipStream_t st);
+// fft.hip: fields [F][n1][n3] real <-> spectrum [F][n3/2+1][n1] complex
+hipError_t launch_fft_forward(bool fp64, const void *in, void *spec, int F, int n1, int n3,
+                              const void *tw, hipStream_t st);
+// (spec is overwritten) out = scale * inverse(spec) + add_or_null
+hipError_t launch_fft_inverse(bool fp64, void *spec, void *out, const void *add_or_null, int F,
+                              int n1, int n3, double scale, const void *tw, hipStream_t st);
 hipError_t upload_twiddles(bool fp64, void *dst, hipStream_t st);
 
 // kernels.hip
@@ -138,7 +134,10 @@ struct ConvLaunch {
   long long nh;
   long long step;
 };
-hipError_t launch_conv(const sbim_handle *h, const Group &g, const ConvLaunch &a);
+// Two launches: the history stream (bracketed by ev0/ev1 when they are non-null)
+// and the per-mode epilogue.
+hipError_t launch_conv(const sbim_handle *h, const Group &g, const ConvLaunch &a,
+                       hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 
 hipError_t launch_tabulate(bool fp64, const Group &g, double dt, const double *gl_x,
                            const double *gl_w, hipStream_t st);

@@ -8,9 +8,10 @@
 //   tabulate_kernel  float64 quadrature of the per-lag kernel weights.
 //
 // Layouts (one material group; modes sorted by (W desc, q asc), 64 per block):
-//   ring    [record][plane][component L,N,T][64 lanes] complex, where block b
-//           owns records blk_off[b] .. blk_off[b] + blk_cap[b] - 1 and step n
-//           lives in record blk_off[b] + n mod blk_cap[b];
+//   ring    [record][plane][component L,N,T][64 lanes] complex.  Step n of
+//           block b lives in record blk_off[b] + (n mod blk_cap[b]) * blk_stride[b]:
+//           consecutive blocks of equal capacity form a run laid out slot-major
+//           (stride = run length), so one history slot of a run is contiguous;
 //   table   lag-major rows: entry lag_off[j] + class holds (w11, w12, w22, w33);
 //           classes are sorted by W desc, so the classes alive at lag j are a
 //           prefix of the row.
@@ -37,9 +38,9 @@ __global__ __launch_bounds__(256) void push_kernel(
     const cplx<R> *__restrict__ spec, const cplx<R> *__restrict__ spec_v,
     cplx<R> *__restrict__ ring, double2 *__restrict__ state, cplx<R> *__restrict__ vel,
     const int *__restrict__ nat, const double *__restrict__ geom,
-    const long long *__restrict__ blk_off, const int *__restrict__ blk_cap, long long M,
-    long long nh, int np, int plane0, int plane1, long long step, double inv_dt, int vel_rule,
-    int state_rule) {
+    const long long *__restrict__ blk_off, const int *__restrict__ blk_cap,
+    const int *__restrict__ blk_stride, long long M, long long nh, int np, int plane0, int plane1,
+    long long step, double inv_dt, int vel_rule, int state_rule) {
   const long long s = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (s >= M) return;
   const long long natural = nat[s];
@@ -48,7 +49,7 @@ __global__ __launch_bounds__(256) void push_kernel(
   const long long b = s >> 6;
   const int lane = static_cast<int>(s & 63);
   const int cap = blk_cap[b];
-  const long long rec = cap > 0 ? blk_off[b] + step % cap : 0;
+  const long long rec = cap > 0 ? blk_off[b] + (step % cap) * blk_stride[b] : 0;
   for (int p = 0; p < np; ++p) {
     const int pg = p == 0 ? plane0 : plane1;
     double2 x[3];
@@ -135,18 +136,65 @@ template <> struct Acc<float, true> {
 // Five complex history sums per plane: C11[U_L], C12[U_N], C22[U_N], C12[U_L], C33[U_T].
 constexpr int kSums = 10;  // real accumulators per plane
 
-template <typename R, int NP, bool COMP, int S, int BLK>
-__global__ __launch_bounds__(kLanes *S) void conv_kernel(
+// Lags handled per unrolled chunk: loads of U lags are issued before their FMAs.
+template <typename R> constexpr int conv_unroll() { return sizeof(R) == 8 ? 2 : 4; }
+
+// One lag for all planes of the lane's mode: weights of the lane's kernel row
+// (zero once the lag passes the lane's own window W(q): such lanes read the
+// row of class 0, which is alive at every lag of the block, and discard it).
+template <typename R, int NP>
+__device__ __forceinline__ void load_lag(const cplx<R> *__restrict__ ring,
+                                         const typename W4<R>::T *__restrict__ table,
+                                         const long long *__restrict__ lag_off, long long record,
+                                         int lane, int j, int llane, int cl,
+                                         typename W4<R>::T &w, cplx<R> (&u)[NP][3]) {
+  const bool on = j < llane;
+  w = table[lag_off[j] + (on ? cl : 0)];
+  if (!on) w = typename W4<R>::T{R(0), R(0), R(0), R(0)};
+  const cplx<R> *r = ring + record * NP * 3 * kLanes + lane;
+#pragma unroll
+  for (int p = 0; p < NP; ++p)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) u[p][c] = r[(p * 3 + c) * kLanes];
+}
+
+// part[p][.] += w * u for the five history sums of each plane.
+template <typename R, int NP>
+__device__ __forceinline__ void fma_lag(R (&part)[NP][kSums], const typename W4<R>::T &w,
+                                        const cplx<R> (&u)[NP][3]) {
+#pragma unroll
+  for (int p = 0; p < NP; ++p) {
+    part[p][0] = fma(w.x, u[p][0].x, part[p][0]);
+    part[p][1] = fma(w.x, u[p][0].y, part[p][1]);
+    part[p][2] = fma(w.y, u[p][1].x, part[p][2]);
+    part[p][3] = fma(w.y, u[p][1].y, part[p][3]);
+    part[p][4] = fma(w.z, u[p][1].x, part[p][4]);
+    part[p][5] = fma(w.z, u[p][1].y, part[p][5]);
+    part[p][6] = fma(w.y, u[p][0].x, part[p][6]);
+    part[p][7] = fma(w.y, u[p][0].y, part[p][7]);
+    part[p][8] = fma(w.w, u[p][2].x, part[p][8]);
+    part[p][9] = fma(w.w, u[p][2].y, part[p][9]);
+  }
+}
+
+// Work-item split of the history sums.  Item (b, c) = block b of 64 modes and
+// chunk c of its lags; one wavefront per item streams the chunk's history
+// records and kernel rows and writes its ten partial sums per plane:
+//   partial[(c * NP * 10 + k) * M + s],  k = plane * 10 + sum index.
+// Items are small and uniform, so the dispatch has no long tail.
+template <typename R, int NP, bool COMP>
+__global__ __launch_bounds__(kLanes) void conv_stream_kernel(
     const cplx<R> *__restrict__ ring, const typename W4<R>::T *__restrict__ table,
-    const cplx<R> *__restrict__ vel, double2 *__restrict__ lam, cplx<R> *__restrict__ out_a,
-    cplx<R> *__restrict__ out_b, const int *__restrict__ nat, const int *__restrict__ cls,
-    const int *__restrict__ win, const double *__restrict__ geom,
+    R *__restrict__ partial, const int *__restrict__ cls, const int *__restrict__ win,
     const long long *__restrict__ blk_off, const int *__restrict__ blk_cap,
-    const long long *__restrict__ lag_off, long long M, long long nh, long long step,
-    PlaneParams p0, PlaneParams p1) {
-  const int b = blockIdx.x;
-  const int lane = threadIdx.x & (kLanes - 1);
-  const int wv = threadIdx.x >> 6;
+    const int *__restrict__ blk_stride, const long long *__restrict__ lag_off, long long M,
+    long long step, int chunks, int nblocks) {
+  constexpr int U = conv_unroll<R>();
+  // chunk-major item order: the waves in flight at any time work on the same
+  // lag range of consecutive blocks, whose records are adjacent in memory
+  const int ch = blockIdx.x / nblocks;
+  const int b = blockIdx.x - ch * nblocks;
+  const int lane = threadIdx.x;
   const long long s = static_cast<long long>(b) * kLanes + lane;
   const bool valid = s < M;
   const int cap = blk_cap[b];
@@ -155,89 +203,126 @@ __global__ __launch_bounds__(kLanes *S) void conv_kernel(
   const int wl = valid ? win[s] : 0;
   const int llane = static_cast<int>(min(static_cast<long long>(wl), navail));
   const int cl = valid ? cls[s] : 0;
-  const int per = (lblk + S - 1) / S;
-  const int j0 = min(lblk, wv * per);
+  const int per = (lblk + chunks - 1) / chunks;
+  const int j0 = min(lblk, ch * per);
   const int j1 = min(lblk, j0 + per);
   const long long base = cap > 0 ? blk_off[b] : 0;
+  const long long stride = blk_stride[b];
 
   Acc<R, COMP> acc[NP][kSums];
   if (j0 < j1) {
-    long long rec = (step - j0) % cap;
-    for (int jb = j0; jb < j1; jb += BLK) {
+    int rec = static_cast<int>((step - j0) % cap);  // ring slot of lag j0
+    int j = j0;
+    if (cap >= U) {
+      for (; j + U <= j1; j += U) {
+        typename W4<R>::T w[U];
+        cplx<R> u[U][NP][3];
+#pragma unroll
+        for (int t = 0; t < U; ++t) {
+          const int rr = rec - t < 0 ? rec - t + cap : rec - t;
+          load_lag<R, NP>(ring, table, lag_off, base + rr * stride, lane, j + t, llane, cl, w[t],
+                          u[t]);
+        }
+        if constexpr (COMP) {
+          R part[NP][kSums];
+#pragma unroll
+          for (int p = 0; p < NP; ++p)
+#pragma unroll
+            for (int k = 0; k < kSums; ++k) part[p][k] = R(0);
+#pragma unroll
+          for (int t = 0; t < U; ++t) fma_lag<R, NP>(part, w[t], u[t]);
+#pragma unroll
+          for (int p = 0; p < NP; ++p)
+#pragma unroll
+            for (int k = 0; k < kSums; ++k) acc[p][k].fold(part[p][k]);
+        } else {
+          R sums[NP][kSums];
+#pragma unroll
+          for (int p = 0; p < NP; ++p)
+#pragma unroll
+            for (int k = 0; k < kSums; ++k) sums[p][k] = acc[p][k].s;
+#pragma unroll
+          for (int t = 0; t < U; ++t) fma_lag<R, NP>(sums, w[t], u[t]);
+#pragma unroll
+          for (int p = 0; p < NP; ++p)
+#pragma unroll
+            for (int k = 0; k < kSums; ++k) acc[p][k].s = sums[p][k];
+        }
+        rec -= U;
+        if (rec < 0) rec += cap;
+      }
+    }
+    for (; j < j1; ++j) {  // remaining lags one at a time
+      typename W4<R>::T w;
+      cplx<R> u[NP][3];
+      load_lag<R, NP>(ring, table, lag_off, base + rec * stride, lane, j, llane, cl, w, u);
       R part[NP][kSums];
 #pragma unroll
       for (int p = 0; p < NP; ++p)
 #pragma unroll
-        for (int k = 0; k < kSums; ++k) part[p][k] = R(0);
-#pragma unroll
-      for (int t = 0; t < BLK; ++t) {
-        const int j = jb + t;
-        if (j < j1 && j < llane) {
-          const typename W4<R>::T w = table[lag_off[j] + cl];
-#pragma unroll
-          for (int p = 0; p < NP; ++p) {
-            const cplx<R> *r = ring + ((base + rec) * NP + p) * 3 * kLanes + lane;
-            const cplx<R> uL = r[0];
-            const cplx<R> uN = r[kLanes];
-            const cplx<R> uT = r[2 * kLanes];
-            part[p][0] = fma(w.x, uL.x, part[p][0]);
-            part[p][1] = fma(w.x, uL.y, part[p][1]);
-            part[p][2] = fma(w.y, uN.x, part[p][2]);
-            part[p][3] = fma(w.y, uN.y, part[p][3]);
-            part[p][4] = fma(w.z, uN.x, part[p][4]);
-            part[p][5] = fma(w.z, uN.y, part[p][5]);
-            part[p][6] = fma(w.y, uL.x, part[p][6]);
-            part[p][7] = fma(w.y, uL.y, part[p][7]);
-            part[p][8] = fma(w.w, uT.x, part[p][8]);
-            part[p][9] = fma(w.w, uT.y, part[p][9]);
-          }
-        }
-        rec = (rec == 0) ? cap - 1 : rec - 1;
-      }
-#pragma unroll
-      for (int p = 0; p < NP; ++p)
-#pragma unroll
-        for (int k = 0; k < kSums; ++k) acc[p][k].fold(part[p][k]);
-    }
-  }
-
-  // combine the S lag ranges of this block: wave 0 folds waves 1..S-1 in order
-  // (deterministic; one partial at a time to keep register pressure low)
-  if constexpr (S > 1) {
-    __shared__ R red_s[S - 1][NP * kSums][kLanes];
-    __shared__ R red_c[COMP ? S - 1 : 1][COMP ? NP * kSums : 1][kLanes];
-    if (wv > 0) {
-#pragma unroll
-      for (int p = 0; p < NP; ++p)
-#pragma unroll
-        for (int k = 0; k < kSums; ++k) {
-          red_s[wv - 1][p * kSums + k][lane] = acc[p][k].s;
-          if constexpr (COMP) red_c[wv - 1][p * kSums + k][lane] = acc[p][k].comp();
-        }
-    }
-    __syncthreads();
-    if (wv != 0) return;
-#pragma unroll 1
-    for (int w = 0; w < S - 1; ++w) {
+        for (int k = 0; k < kSums; ++k) part[p][k] = COMP ? R(0) : acc[p][k].s;
+      fma_lag<R, NP>(part, w, u);
 #pragma unroll
       for (int p = 0; p < NP; ++p)
 #pragma unroll
         for (int k = 0; k < kSums; ++k) {
           if constexpr (COMP)
-            acc[p][k].fold_pair(red_s[w][p * kSums + k][lane], red_c[w][p * kSums + k][lane]);
+            acc[p][k].fold(part[p][k]);
           else
-            acc[p][k].fold(red_s[w][p * kSums + k][lane]);
+            acc[p][k].s = part[p][k];
         }
+      rec = rec == 0 ? cap - 1 : rec - 1;
     }
   }
   if (!valid) return;
+#pragma unroll
+  for (int p = 0; p < NP; ++p)
+#pragma unroll
+    for (int k = 0; k < kSums; ++k)
+      partial[(static_cast<long long>(ch) * NP * kSums + p * kSums + k) * M + s] = acc[p][k].value();
+}
 
-  // epilogue: damping + instantaneous + nonlocal terms, rotate back, scatter
+// Per mode: fold the chunk partials in chunk order (compensated for the
+// compensated form), add damping and instantaneous terms, rotate back to
+// (x1, x2, x3) and scatter into the natural half-spectrum layout.
+template <typename R, int NP, bool COMP>
+__global__ __launch_bounds__(256) void conv_epilogue_kernel(
+    const R *__restrict__ partial, const cplx<R> *__restrict__ ring,
+    const cplx<R> *__restrict__ vel, double2 *__restrict__ lam, cplx<R> *__restrict__ out_a,
+    cplx<R> *__restrict__ out_b, const int *__restrict__ nat, const int *__restrict__ win,
+    const double *__restrict__ geom, const long long *__restrict__ blk_off,
+    const int *__restrict__ blk_cap, const int *__restrict__ blk_stride, long long M, long long nh,
+    long long step, int chunks, PlaneParams p0, PlaneParams p1) {
+  const long long s = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (s >= M) return;
+  const long long b = s >> 6;
+  const int lane = static_cast<int>(s & 63);
+  const int cap = blk_cap[b];
+  const int wl = win[s];
   const double q = geom[4 * s + 0];
   const R kh1 = static_cast<R>(geom[4 * s + 1]);
   const R kh3 = static_cast<R>(geom[4 * s + 2]);
   const long long natural = nat[s];
-  const long long rec0 = cap > 0 ? base + step % cap : 0;
+  const long long rec0 = cap > 0 ? blk_off[b] + (step % cap) * blk_stride[b] : 0;
+  // fold the chunk partials, chunk by chunk (all sums of a chunk loaded together)
+  R cs_all[NP][kSums];
+  {
+    Acc<R, COMP> a[NP][kSums];
+    for (int c = 0; c < chunks; ++c) {
+      const R *pc = partial + static_cast<long long>(c) * NP * kSums * M + s;
+      R v[NP * kSums];
+#pragma unroll
+      for (int k = 0; k < NP * kSums; ++k) v[k] = pc[k * M];
+#pragma unroll
+      for (int p = 0; p < NP; ++p)
+#pragma unroll
+        for (int k = 0; k < kSums; ++k) a[p][k].fold(v[p * kSums + k]);
+    }
+#pragma unroll
+    for (int p = 0; p < NP; ++p)
+#pragma unroll
+      for (int k = 0; k < kSums; ++k) cs_all[p][k] = a[p][k].value();
+  }
 #pragma unroll
   for (int p = 0; p < NP; ++p) {
     const PlaneParams &pp = p == 0 ? p0 : p1;
@@ -246,6 +331,7 @@ __global__ __launch_bounds__(kLanes *S) void conv_kernel(
     const R damp = static_cast<R>(pp.mu / pp.cs);
     const R inst = static_cast<R>((2.0 - pp.eta) * pp.mu * q);
     const R eta = static_cast<R>(pp.eta);
+    const R *cs = cs_all[p];
     cplx<R> u[3] = {{R(0), R(0)}, {R(0), R(0)}, {R(0), R(0)}};
     if (cap > 0 && wl > 0) {
       const cplx<R> *r = ring + (rec0 * NP + p) * 3 * kLanes + lane;
@@ -256,9 +342,6 @@ __global__ __launch_bounds__(kLanes *S) void conv_kernel(
     cplx<R> v[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) v[c] = vel[(static_cast<long long>(p) * 3 + c) * M + s];
-    R cs[kSums];
-#pragma unroll
-    for (int k = 0; k < kSums; ++k) cs[k] = acc[p][k].value();
     // conv + instantaneous (rotated frame):
     //   A_L = -sg mu q C11 + i (2-eta) mu q U_N - i mu q C12[U_N]
     //   A_N = -sg mu q C22 - i (2-eta) mu q U_L + i mu q C12[U_L]
@@ -420,34 +503,35 @@ __global__ __launch_bounds__(256) void tabulate_kernel(
   }
 }
 
-template <typename R, int NP, bool COMP, int S>
-hipError_t conv_launch_s(const sbim_handle *h, const Group &g, const ConvLaunch &a) {
-  constexpr int BLK = COMP ? 4 : 1;
+template <typename R, int NP, bool COMP>
+hipError_t conv_launch_np(const sbim_handle *h, const Group &g, const ConvLaunch &a,
+                          hipEvent_t ev0, hipEvent_t ev1) {
   const PlaneParams p1 = g.np > 1 ? g.pl[1] : g.pl[0];
-  hipLaunchKernelGGL((conv_kernel<R, NP, COMP, S, BLK>), dim3(static_cast<unsigned>(g.nblocks)),
-                     dim3(kLanes * S), 0, h->stream, static_cast<const cplx<R> *>(a.ring),
-                     static_cast<const typename W4<R>::T *>(g.table),
-                     static_cast<const cplx<R> *>(a.vel), reinterpret_cast<double2 *>(a.lam),
-                     static_cast<cplx<R> *>(a.out_a), static_cast<cplx<R> *>(a.out_b), g.nat,
-                     g.cls, g.win, g.geom, g.blk_off, g.blk_cap, g.lag_off, g.M, a.nh, a.step,
-                     g.pl[0], p1);
+  const int chunks = h->lag_split;
+  const long long items = g.nblocks * chunks;
+  if (ev0) (void)hipEventRecord(ev0, h->stream);
+  hipLaunchKernelGGL((conv_stream_kernel<R, NP, COMP>), dim3(static_cast<unsigned>(items)),
+                     dim3(kLanes), 0, h->stream, static_cast<const cplx<R> *>(a.ring),
+                     static_cast<const typename W4<R>::T *>(g.table), static_cast<R *>(g.partial),
+                     g.cls, g.win, g.blk_off, g.blk_cap, g.blk_stride, g.lag_off, g.M, a.step,
+                     chunks, static_cast<int>(g.nblocks));
+  if (ev1) (void)hipEventRecord(ev1, h->stream);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((conv_epilogue_kernel<R, NP, COMP>), dim3(static_cast<unsigned>((g.M + 255) / 256)),
+                     dim3(256), 0, h->stream, static_cast<const R *>(g.partial),
+                     static_cast<const cplx<R> *>(a.ring), static_cast<const cplx<R> *>(a.vel),
+                     reinterpret_cast<double2 *>(a.lam), static_cast<cplx<R> *>(a.out_a),
+                     static_cast<cplx<R> *>(a.out_b), g.nat, g.win, g.geom, g.blk_off, g.blk_cap,
+                     g.blk_stride, g.M, a.nh, a.step, chunks, g.pl[0], p1);
   return hipGetLastError();
 }
 
-template <typename R, int NP, bool COMP>
-hipError_t conv_launch_np(const sbim_handle *h, const Group &g, const ConvLaunch &a) {
-  constexpr int kMax = conv_max_split(NP, sizeof(R) == 8, COMP);
-  switch (h->lag_split) {
-    case 1: return conv_launch_s<R, NP, COMP, 1>(h, g, a);
-    case 2: return conv_launch_s<R, NP, COMP, (kMax < 2 ? kMax : 2)>(h, g, a);
-    case 4: return conv_launch_s<R, NP, COMP, (kMax < 4 ? kMax : 4)>(h, g, a);
-    default: return conv_launch_s<R, NP, COMP, (kMax < 8 ? kMax : 8)>(h, g, a);
-  }
-}
-
 template <typename R, bool COMP>
-hipError_t conv_launch_r(const sbim_handle *h, const Group &g, const ConvLaunch &a) {
-  return g.np == 2 ? conv_launch_np<R, 2, COMP>(h, g, a) : conv_launch_np<R, 1, COMP>(h, g, a);
+hipError_t conv_launch_r(const sbim_handle *h, const Group &g, const ConvLaunch &a,
+                         hipEvent_t ev0, hipEvent_t ev1) {
+  return g.np == 2 ? conv_launch_np<R, 2, COMP>(h, g, a, ev0, ev1)
+                   : conv_launch_np<R, 1, COMP>(h, g, a, ev0, ev1);
 }
 
 }  // namespace
@@ -460,22 +544,23 @@ hipError_t launch_push(const sbim_handle *h, const Group &g, const PushLaunch &a
     hipLaunchKernelGGL(push_kernel<double>, dim3(grid), dim3(256), 0, h->stream,
                        static_cast<const double2 *>(a.spec), static_cast<const double2 *>(a.spec_v),
                        static_cast<double2 *>(a.ring), reinterpret_cast<double2 *>(a.state),
-                       static_cast<double2 *>(a.vel), g.nat, g.geom, g.blk_off, g.blk_cap, g.M,
+                       static_cast<double2 *>(a.vel), g.nat, g.geom, g.blk_off, g.blk_cap, g.blk_stride, g.M,
                        a.nh, g.np, p0, p1, a.step, 1.0 / a.dt, a.vel_rule, a.state_rule);
   } else {
     hipLaunchKernelGGL(push_kernel<float>, dim3(grid), dim3(256), 0, h->stream,
                        static_cast<const float2 *>(a.spec), static_cast<const float2 *>(a.spec_v),
                        static_cast<float2 *>(a.ring), reinterpret_cast<double2 *>(a.state),
-                       static_cast<float2 *>(a.vel), g.nat, g.geom, g.blk_off, g.blk_cap, g.M,
+                       static_cast<float2 *>(a.vel), g.nat, g.geom, g.blk_off, g.blk_cap, g.blk_stride, g.M,
                        a.nh, g.np, p0, p1, a.step, 1.0 / a.dt, a.vel_rule, a.state_rule);
   }
   return hipGetLastError();
 }
 
-hipError_t launch_conv(const sbim_handle *h, const Group &g, const ConvLaunch &a) {
-  if (h->fp64) return conv_launch_r<double, false>(h, g, a);
-  if (h->comp) return conv_launch_r<float, true>(h, g, a);
-  return conv_launch_r<float, false>(h, g, a);
+hipError_t launch_conv(const sbim_handle *h, const Group &g, const ConvLaunch &a, hipEvent_t ev0,
+                       hipEvent_t ev1) {
+  if (h->fp64) return conv_launch_r<double, false>(h, g, a, ev0, ev1);
+  if (h->comp) return conv_launch_r<float, true>(h, g, a, ev0, ev1);
+  return conv_launch_r<float, false>(h, g, a, ev0, ev1);
 }
 
 hipError_t launch_tabulate(bool fp64, const Group &g, double dt, const double *gl_x,

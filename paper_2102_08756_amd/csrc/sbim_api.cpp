@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <numeric>
@@ -95,9 +96,9 @@ hipError_t dev_alloc_bytes(void **p, size_t bytes) {
 }
 
 void free_group(Group &g) {
-  void *ptrs[] = {g.nat,   g.cls,   g.win,   g.geom,      g.blk_off,   g.blk_cap, g.lag_off,
-                  g.cls_q, g.cls_w, g.table, g.ring,      g.state,     g.vel,     g.ring_adj,
-                  g.state_adj, g.lam_adj, g.vel_adj};
+  void *ptrs[] = {g.nat,   g.cls,   g.win,   g.geom,      g.blk_off,   g.blk_cap, g.blk_stride, g.lag_off,
+                  g.cls_q, g.cls_w, g.table, g.ring,      g.state,     g.vel,     g.partial,
+                  g.ring_adj, g.state_adj, g.lam_adj, g.vel_adj};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   g = Group();
@@ -125,6 +126,9 @@ long long vel_bytes(const sbim_handle *h, const Group &g) {
   return g.np * 3LL * g.M * 2 * static_cast<long long>(h->rsize);
 }
 long long state_bytes_g(const Group &g) { return g.np * 3LL * g.M * 16; }
+long long partial_bytes(const sbim_handle *h, const Group &g) {
+  return static_cast<long long>(h->lag_split) * g.np * 10LL * g.M * static_cast<long long>(h->rsize);
+}
 
 int validate(const sbim_config *c) {
   if (!c) return fail(nullptr, SBIM_E_INVALID, "config is NULL");
@@ -162,7 +166,7 @@ int validate(const sbim_config *c) {
 // Mode geometry, windows, ordering and classes of one material group (host).
 void plan_group(const sbim_config &c, Group &g, std::vector<double> &geom,
                 std::vector<long long> &blk_off, std::vector<int> &blk_cap,
-                std::vector<double> &cls_q) {
+                std::vector<int> &blk_stride, std::vector<double> &cls_q) {
   const int n1 = c.n1, h3 = c.n3 / 2 + 1;
   const long long M = static_cast<long long>(n1) * h3;
   const double two_pi = 2.0 * M_PI;
@@ -183,7 +187,7 @@ void plan_group(const sbim_config &c, Group &g, std::vector<double> &geom,
           w = static_cast<int>(std::min(static_cast<double>(c.window_cap), std::ceil(x)));
         }
       }
-      const long long f = static_cast<long long>(i1) * h3 + i3;
+      const long long f = static_cast<long long>(i3) * n1 + i1;  // spectrum bin
       keys[f] = ModeKey{w, q, static_cast<int>(f)};
       qv[f] = q;
       k1v[f] = k1;
@@ -223,11 +227,20 @@ void plan_group(const sbim_config &c, Group &g, std::vector<double> &geom,
   g.wmax = M > 0 ? keys[0].w : 0;
   blk_off.resize(g.nblocks);
   blk_cap.resize(g.nblocks);
-  long long rec = 0;
-  for (long long b = 0; b < g.nblocks; ++b) {
-    blk_off[b] = rec;
+  blk_stride.resize(g.nblocks);
+  for (long long b = 0; b < g.nblocks; ++b)
     blk_cap[b] = g.h_win[b * sbim::kLanes];  // sorted by W desc: first lane has the block maximum
-    rec += blk_cap[b];
+  // runs of consecutive blocks with equal capacity are stored slot-major
+  long long rec = 0;
+  for (long long b0 = 0; b0 < g.nblocks;) {
+    long long b1 = b0;
+    while (b1 < g.nblocks && blk_cap[b1] == blk_cap[b0]) ++b1;
+    for (long long b = b0; b < b1; ++b) {
+      blk_off[b] = rec + (b - b0);
+      blk_stride[b] = static_cast<int>(b1 - b0);
+    }
+    rec += static_cast<long long>(blk_cap[b0]) * (b1 - b0);
+    b0 = b1;
   }
   g.ring_records = rec;
   // lag-major table rows: classes alive at lag j form the prefix {c : W_c > j}
@@ -254,21 +267,15 @@ int check_ptr(sbim_handle *h, const void *p, const char *name) {
 
 // Forward real 2-D FFT of a [P][3][n1][n3] field into `spec`.
 hipError_t fft_forward(sbim_handle *h, const void *field, void *spec) {
-  const long long rows = static_cast<long long>(h->cfg.nplanes) * 3 * h->n1;
-  hipError_t e = sbim::launch_r2c_rows(h->fp64, field, spec, rows, h->n3, h->twiddle, h->stream);
-  if (e != hipSuccess) return e;
-  return sbim::launch_col_fft(h->fp64, spec, h->cfg.nplanes * 3LL, h->n1, h->h3, -1, h->twiddle,
-                              h->stream);
+  return sbim::launch_fft_forward(h->fp64, field, spec, h->cfg.nplanes * 3, h->n1, h->n3,
+                                  h->twiddle, h->stream);
 }
 
 // Inverse of a traction spectrum (destroyed) into a [P][3][n1][n3] field.
 hipError_t fft_inverse(sbim_handle *h, void *spec, void *field, const void *add) {
-  hipError_t e = sbim::launch_col_fft(h->fp64, spec, h->cfg.nplanes * 3LL, h->n1, h->h3, +1,
-                                      h->twiddle, h->stream);
-  if (e != hipSuccess) return e;
-  const long long rows = static_cast<long long>(h->cfg.nplanes) * 3 * h->n1;
-  return sbim::launch_c2r_rows(h->fp64, spec, field, add, rows, h->n3,
-                               1.0 / (static_cast<double>(h->n1) * h->n3), h->twiddle, h->stream);
+  return sbim::launch_fft_inverse(h->fp64, spec, field, add, h->cfg.nplanes * 3, h->n1, h->n3,
+                                  1.0 / (static_cast<double>(h->n1) * h->n3), h->twiddle,
+                                  h->stream);
 }
 
 int ensure_adjoint(sbim_handle *h) {
@@ -341,16 +348,17 @@ int sbim_init(const sbim_config *cfg, sbim_handle **out) {
   struct HostPlan {
     std::vector<double> geom, cls_q;
     std::vector<long long> blk_off;
-    std::vector<int> blk_cap;
+    std::vector<int> blk_cap, blk_stride;
   };
   std::vector<HostPlan> plan(h->ngroups);
   size_t need = 0;
   long long total_blocks = 0;
   for (int i = 0; i < h->ngroups; ++i) {
     Group &g = h->g[i];
-    plan_group(*cfg, g, plan[i].geom, plan[i].blk_off, plan[i].blk_cap, plan[i].cls_q);
+    plan_group(*cfg, g, plan[i].geom, plan[i].blk_off, plan[i].blk_cap, plan[i].blk_stride,
+               plan[i].cls_q);
     need += ring_bytes(h, g) + table_bytes(h, g) + state_bytes_g(g) + vel_bytes(h, g);
-    need += g.M * (4 * 3 + 32) + g.nblocks * 12 + g.wmax * 8 + g.nclasses * 12;
+    need += g.M * (4 * 3 + 32) + g.nblocks * 16 + g.wmax * 8 + g.nclasses * 12;
     total_blocks += g.nblocks;
   }
   const size_t spec_bytes = static_cast<size_t>(cfg->nplanes) * 3 * h->nh * 2 * h->rsize;
@@ -366,12 +374,26 @@ int sbim_init(const sbim_config *cfg, sbim_handle **out) {
     return fail(nullptr, SBIM_E_OOM, "needs %zu bytes of device memory, %zu free", need, free_b);
   }
 
-  // lag split: aim at >= 4096 waves in the convolution, within the LDS budget
-  int split = 1;
-  while (split < 8 && total_blocks * split < 4096) split *= 2;
+  // lag chunks per block: about kTargetItems uniform work items for the history
+  // stream, none shorter than kMinChunkLags lags
+  int wmax_all = 0;
+  for (int i = 0; i < h->ngroups; ++i) wmax_all = std::max(wmax_all, h->g[i].wmax);
+  long long split = (sbim::kTargetItems + total_blocks - 1) / std::max(1LL, total_blocks);
+  split = std::min<long long>(split, std::max(1, wmax_all / sbim::kMinChunkLags));
+  split = std::max(1LL, std::min<long long>(split, sbim::kMaxChunks));
+  if (const char *env = std::getenv("SBIM_LAG_SPLIT")) {  // tuning override in [1, kMaxChunks]
+    const int v = std::atoi(env);
+    if (v >= 1 && v <= sbim::kMaxChunks) split = v;
+  }
+  h->lag_split = static_cast<int>(split);
+  size_t need_partial = 0;
   for (int i = 0; i < h->ngroups; ++i)
-    split = std::min(split, sbim::conv_max_split(h->g[i].np, h->fp64, h->comp));
-  h->lag_split = split;
+    need_partial += static_cast<size_t>(partial_bytes(h, h->g[i]));
+  if (need + need_partial > free_b) {
+    free_handle(h);
+    return fail(nullptr, SBIM_E_OOM, "needs %zu bytes of device memory, %zu free",
+                need + need_partial, free_b);
+  }
 
   std::vector<double> glx, glw;
   gauss_legendre(sbim::kGaussN, glx, glw);
@@ -407,6 +429,7 @@ int sbim_init(const sbim_config *cfg, sbim_handle **out) {
     TRY(dev_alloc(&g.geom, 4 * g.M));
     TRY(dev_alloc(&g.blk_off, g.nblocks));
     TRY(dev_alloc(&g.blk_cap, g.nblocks));
+    TRY(dev_alloc(&g.blk_stride, g.nblocks));
     TRY(dev_alloc(&g.lag_off, g.wmax));
     TRY(dev_alloc(&g.cls_q, g.nclasses));
     TRY(dev_alloc(&g.cls_w, g.nclasses));
@@ -414,12 +437,14 @@ int sbim_init(const sbim_config *cfg, sbim_handle **out) {
     TRY(dev_alloc_bytes(&g.ring, ring_bytes(h, g)));
     TRY(dev_alloc(&g.state, state_bytes_g(g) / 8));
     TRY(dev_alloc_bytes(&g.vel, vel_bytes(h, g)));
+    TRY(dev_alloc_bytes(&g.partial, partial_bytes(h, g)));
     TRY(upload(g.nat, g.h_nat.data(), g.M * sizeof(int), h->stream));
     TRY(upload(g.cls, g.h_cls.data(), g.M * sizeof(int), h->stream));
     TRY(upload(g.win, g.h_win.data(), g.M * sizeof(int), h->stream));
     TRY(upload(g.geom, hp.geom.data(), hp.geom.size() * sizeof(double), h->stream));
     TRY(upload(g.blk_off, hp.blk_off.data(), hp.blk_off.size() * sizeof(long long), h->stream));
     TRY(upload(g.blk_cap, hp.blk_cap.data(), hp.blk_cap.size() * sizeof(int), h->stream));
+    TRY(upload(g.blk_stride, hp.blk_stride.data(), hp.blk_stride.size() * sizeof(int), h->stream));
     TRY(upload(g.lag_off, g.h_lag_off.data(), g.h_lag_off.size() * sizeof(long long), h->stream));
     TRY(upload(g.cls_q, hp.cls_q.data(), hp.cls_q.size() * sizeof(double), h->stream));
     TRY(upload(g.cls_w, g.h_cls_w.data(), g.h_cls_w.size() * sizeof(int), h->stream));
@@ -487,14 +512,18 @@ int sbim_tractions(sbim_handle *h, const void *tau_inf, void *tau) {
     a.step = h->step - 1;
     hipError_t e;
     if (h->profile) {
-      hipEvent_t e0, e1;
-      if ((e = hipEventCreate(&e0)) != hipSuccess || (e = hipEventCreate(&e1)) != hipSuccess)
-        return hip_fail(h, e, "hipEventCreate");
-      h->ev_start.push_back(e0);
-      h->ev_stop.push_back(e1);
-      (void)hipEventRecord(e0, h->stream);
-      e = sbim::launch_conv(h, g, a);
-      (void)hipEventRecord(e1, h->stream);
+      if (h->ev_used == h->ev_start.size()) {  // grow the reusable event pool
+        hipEvent_t e0, e1;
+        if ((e = hipEventCreate(&e0)) != hipSuccess) return hip_fail(h, e, "hipEventCreate");
+        if ((e = hipEventCreate(&e1)) != hipSuccess) {
+          (void)hipEventDestroy(e0);
+          return hip_fail(h, e, "hipEventCreate");
+        }
+        h->ev_start.push_back(e0);
+        h->ev_stop.push_back(e1);
+      }
+      e = sbim::launch_conv(h, g, a, h->ev_start[h->ev_used], h->ev_stop[h->ev_used]);
+      ++h->ev_used;
     } else {
       e = sbim::launch_conv(h, g, a);
     }
@@ -687,18 +716,15 @@ int sbim_step_work(const sbim_handle *h, long long n, double *mode_lags, double 
   for (int i = 0; i < h->ngroups; ++i) {
     const Group &g = h->g[i];
     double mode_lag_g = 0;
-    for (long long s = 0; s < g.M; ++s) {
-      const long long w = std::min<long long>(g.h_win[s], n + 1);
-      mode_lag_g += static_cast<double>(w);
-      // per-mode reads/writes of the epilogue: win, cls, nat (4 B each), geom (3 doubles),
-      // velocity and lag-0 history (read), traction spectrum (write)
-      bytes += 12 + 24 + g.np * 3 * 2 * r * (g.h_win[s] > 0 ? 3 : 2);
-    }
+    for (long long s = 0; s < g.M; ++s) mode_lag_g += static_cast<double>(std::min<long long>(g.h_win[s], n + 1));
     lags += mode_lag_g * g.np;
-    bytes += mode_lag_g * g.np * 3 * 2 * r;  // history
+    // history stream: the history each mode needs, the kernel rows each class
+    // needs, per-mode class/window indices, and the partial sums written
+    bytes += mode_lag_g * g.np * 3 * 2 * r;
     for (long long c = 0; c < g.nclasses; ++c)
-      bytes += std::min<long long>(g.h_cls_w[c], n + 1) * 4 * r;  // kernel rows
-    bytes += g.nblocks * 12.0;
+      bytes += std::min<long long>(g.h_cls_w[c], n + 1) * 4 * r;
+    bytes += g.M * 8.0 + g.nblocks * 16.0;
+    bytes += static_cast<double>(partial_bytes(h, g));
   }
   *mode_lags = lags;
   *conv_bytes = bytes;
@@ -715,7 +741,7 @@ int sbim_mode_kernel(sbim_handle *h, int p, int i1, int i3, double *host_out, in
     for (int k = 0; k < h->g[i].np; ++k)
       if (h->g[i].pl[k].index == p) gp = &h->g[i];
   const Group &g = *gp;
-  const int f = i1 * h->h3 + i3;
+  const int f = i3 * h->n1 + i1;
   long long s = -1;
   for (long long t = 0; t < g.M; ++t)
     if (g.h_nat[t] == f) s = t;
@@ -746,11 +772,9 @@ int sbim_mode_kernel(sbim_handle *h, int p, int i1, int i3, double *host_out, in
 
 int sbim_profile_conv(sbim_handle *h, int enable) {
   if (!h) return fail(nullptr, SBIM_E_INVALID, "handle is NULL");
-  (void)hipStreamSynchronize(h->stream);
-  for (auto e : h->ev_start) (void)hipEventDestroy(e);
-  for (auto e : h->ev_stop) (void)hipEventDestroy(e);
-  h->ev_start.clear();
-  h->ev_stop.clear();
+  hipError_t e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "sbim_profile_conv sync");
+  h->ev_used = 0;
   h->profile = enable != 0;
   return SBIM_OK;
 }
@@ -760,14 +784,14 @@ int sbim_conv_timing(sbim_handle *h, double *total_ms, long long *launches) {
   hipError_t e = hipStreamSynchronize(h->stream);
   if (e != hipSuccess) return hip_fail(h, e, "sbim_conv_timing sync");
   double tot = 0;
-  for (size_t i = 0; i < h->ev_start.size(); ++i) {
+  for (size_t i = 0; i < h->ev_used; ++i) {
     float ms = 0;
     e = hipEventElapsedTime(&ms, h->ev_start[i], h->ev_stop[i]);
     if (e != hipSuccess) return hip_fail(h, e, "hipEventElapsedTime");
     tot += ms;
   }
   *total_ms = tot;
-  *launches = static_cast<long long>(h->ev_start.size());
+  *launches = static_cast<long long>(h->ev_used);
   return SBIM_OK;
 }
 
