@@ -62,30 +62,27 @@ def read_traffic(workload, precision):
 
 
 class Inputs:
-    """Per-step increments resident in HBM: the 64-field bank plus the pulse-ramp steps."""
+    """Per-step increments resident in HBM: each distinct field of the workload
+    (bank entries and the pulse-ramp steps) uploaded once.  A workload with a
+    uniform slip ramp adds its uniform part with one device add per step."""
 
     def __init__(self, wl, dtype, device):
         import torch
         import workloads
-        inc = workloads.Increments(wl)
-        self.bank = torch.tensor(inc._bank, dtype=dtype, device=device) if inc._bank is not None else None
-        special = []
-        n = 0
-        while True:  # steps whose increment differs from the plain bank entry
-            d = inc(n)
-            if self.bank is not None and n > 0 and np.array_equal(d, inc._bank[(7 * n) % wl.bank]):
-                break
-            special.append(torch.tensor(d, dtype=dtype, device=device))
-            n += 1
-            if self.bank is None and n >= wl.steps:
-                break
-        self.special = special
-        self.wl = wl
+        fields, self.index, self.uniform = workloads.step_sources(wl)
+        self.fields = [torch.tensor(f, dtype=dtype, device=device) for f in fields]
+        self.has_uniform = bool(wl.slip_ramp)
+        self.scratch = torch.empty_like(self.fields[0]) if self.has_uniform else None
+        self.dtype, self.device = dtype, device
 
     def __call__(self, n):
-        if n < len(self.special):
-            return self.special[n]
-        return self.bank[(7 * n) % self.wl.bank]
+        f = self.fields[self.index(n)]
+        if not self.has_uniform:
+            return f
+        import torch
+        u = torch.tensor(self.uniform(n), dtype=self.dtype, device=self.device)
+        torch.add(f, u[:, :, None, None], out=self.scratch)
+        return self.scratch
 
 
 def run_job(sb, inputs, steps, tau):

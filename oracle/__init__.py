@@ -19,4 +19,5 @@ library routines (numpy.fft, scipy.special, mpmath inverse Laplace) and
 invariants; see each test for the pin it provides.
 """
 from . import dft, kernels, sbim  # noqa: F401
-from .sbim import Config, Plane, forward, adjoint, spectra, mode_geometry, mode_window  # noqa: F401
+from .sbim import (Config, Plane, forward, adjoint, spectra, mode_geometry,  # noqa: F401
+                   mode_window, mode_response)

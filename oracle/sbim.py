@@ -327,3 +327,16 @@ def adjoint(cfg, g_hist, with_velocity=False, chunk=None, weights_cache=None):
     du = dft.inverse_half(du_hat, cfg.n3)
     dv = dft.inverse_half(dv_hat, cfg.n3) if dv_hat is not None else None
     return du, dv
+
+
+def mode_response(cfg, p, bins, U_hist, V_hist, weights_cache=None):
+    """tau_hat of plane p at selected half-spectrum bins, every step.
+
+    bins: (i1, i3) index arrays; U_hist, V_hist: [N, 3, len(bins)] spectra of
+    the displacement and velocity at those bins (as ``spectra`` defines them).
+    Returns [N, 3, len(bins)] in the (x1, x2, x3) frame.
+    """
+    if not isinstance(cfg, Config):
+        cfg = Config.from_dict(cfg)
+    op = PlaneOperator(cfg, p, bins, weights_cache)
+    return op.apply(np.asarray(U_hist, dtype=complex), np.asarray(V_hist, dtype=complex))

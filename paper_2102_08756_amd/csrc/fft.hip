@@ -134,9 +134,10 @@ constexpr int lds_elems() { return kFftThreads * kFftPerThread; }
 // sequence z; with Z = FFT(z)
 //   X[k] = (Z[k] + conj Z[Nh-k]) / 2 - i e^{-2 pi i k/n3} (Z[k] - conj Z[Nh-k]) / 2.
 // The bins are written transposed, spec[f][k][x1], R consecutive x1 at a time.
-template <typename R>
+// Input reals of type Rin are widened to the transform's type R on load.
+template <typename Rin, typename R>
 __global__ __launch_bounds__(kFftThreads) void r2c_t_kernel(
-    const R *__restrict__ in, cplx<R> *__restrict__ spec, int n1, int n3, int logNh, int rows,
+    const Rin *__restrict__ in, cplx<R> *__restrict__ spec, int n1, int n3, int logNh, int rows,
     const cplx<R> *__restrict__ tw) {
   extern __shared__ unsigned char smem_raw[];
   cplx<R> *buf = reinterpret_cast<cplx<R> *>(smem_raw);
@@ -145,9 +146,12 @@ __global__ __launch_bounds__(kFftThreads) void r2c_t_kernel(
   const int tiles = n1 / rows;
   const int f = blockIdx.x / tiles;
   const int x0 = (blockIdx.x - f * tiles) * rows;
-  const cplx<R> *src =
-      reinterpret_cast<const cplx<R> *>(in + (static_cast<long long>(f) * n1 + x0) * n3);
-  for (int e = threadIdx.x; e < rows * Nh; e += kFftThreads) buf[e] = src[e];
+  const cplx<Rin> *src =
+      reinterpret_cast<const cplx<Rin> *>(in + (static_cast<long long>(f) * n1 + x0) * n3);
+  for (int e = threadIdx.x; e < rows * Nh; e += kFftThreads) {
+    const cplx<Rin> v = src[e];
+    buf[e] = cplx<R>{static_cast<R>(v.x), static_cast<R>(v.y)};
+  }
   __syncthreads();
   lds_fft<R, kFftThreads, kFftPerThread>(buf, Nh, logNh, rows, -1, tw);
   const int step = kTwiddleN / n3;
@@ -262,15 +266,15 @@ int tile_rows(int n1, int Nh) {
   return max(1, min(min(8, n1), lds_elems<R>() / Nh));
 }
 
-template <typename R>
+template <typename Rin, typename R>
 hipError_t forward_impl(const void *in, void *spec, int F, int n1, int n3, const void *tw,
                         hipStream_t st) {
   const int Nh = n3 / 2, h3 = Nh + 1;
   const int rows = tile_rows<R>(n1, Nh);
-  hipLaunchKernelGGL(r2c_t_kernel<R>, dim3(static_cast<unsigned>(F * (n1 / rows))),
+  hipLaunchKernelGGL((r2c_t_kernel<Rin, R>), dim3(static_cast<unsigned>(F * (n1 / rows))),
                      dim3(kFftThreads), static_cast<size_t>(rows) * Nh * sizeof(cplx<R>), st,
-                     static_cast<const R *>(in), static_cast<cplx<R> *>(spec), n1, n3, ilog2(Nh),
-                     rows, static_cast<const cplx<R> *>(tw));
+                     static_cast<const Rin *>(in), static_cast<cplx<R> *>(spec), n1, n3,
+                     ilog2(Nh), rows, static_cast<const cplx<R> *>(tw));
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const long long nrows = static_cast<long long>(F) * h3;
@@ -305,10 +309,10 @@ hipError_t inverse_impl(void *spec, void *out, const void *add, int F, int n1, i
 
 }  // namespace
 
-hipError_t launch_fft_forward(bool fp64, const void *in, void *spec, int F, int n1, int n3,
-                              const void *tw, hipStream_t st) {
-  return fp64 ? forward_impl<double>(in, spec, F, n1, n3, tw, st)
-              : forward_impl<float>(in, spec, F, n1, n3, tw, st);
+hipError_t launch_fft_forward(bool in_fp64, const void *in, void *spec, int F, int n1, int n3,
+                              const void *tw64, hipStream_t st) {
+  return in_fp64 ? forward_impl<double, double>(in, spec, F, n1, n3, tw64, st)
+                 : forward_impl<float, double>(in, spec, F, n1, n3, tw64, st);
 }
 
 hipError_t launch_fft_inverse(bool fp64, void *spec, void *out, const void *add, int F, int n1,

@@ -92,8 +92,9 @@ struct sbim_handle {
   bool pushed_since_tractions = false;
   int lag_split = 1;               // lag chunks per 64-mode block in the convolution
   void *twiddle = nullptr;        // [4096] complex real_t, exp(-2 pi i m / 4096)
-  void *spec = nullptr;           // [P][3][h3][n1] complex: spectrum of the pushed field
-  void *spec_v = nullptr;         // same for the velocity / second output
+  void *twiddle64 = nullptr;      // the same in float64 (== twiddle for SBIM_FP64)
+  void *spec = nullptr;           // [P][3][h3][n1] complex float64: spectrum of the pushed field
+  void *spec_v = nullptr;         // same for the velocity; second traction output of backward
   void *out_spec = nullptr;       // [P][3][h3][n1] complex: traction spectrum
   bool profile = false;
   std::vector<hipEvent_t> ev_start, ev_stop;  // reusable pool
@@ -103,9 +104,11 @@ struct sbim_handle {
 
 namespace sbim {
 
-// fft.hip: fields [F][n1][n3] real <-> spectrum [F][n3/2+1][n1] complex
-hipError_t launch_fft_forward(bool fp64, const void *in, void *spec, int F, int n1, int n3,
-                              const void *tw, hipStream_t st);
+// fft.hip: fields [F][n1][n3] real <-> spectrum [F][n3/2+1][n1] complex.
+// The forward transform always computes in float64 (its output feeds the
+// float64 running state); in_fp64 selects the type of the input field.
+hipError_t launch_fft_forward(bool in_fp64, const void *in, void *spec, int F, int n1, int n3,
+                              const void *tw64, hipStream_t st);
 // (spec is overwritten) out = scale * inverse(spec) + add_or_null
 hipError_t launch_fft_inverse(bool fp64, void *spec, void *out, const void *add_or_null, int F,
                               int n1, int n3, double scale, const void *tw, hipStream_t st);
@@ -113,8 +116,8 @@ hipError_t upload_twiddles(bool fp64, void *dst, hipStream_t st);
 
 // kernels.hip
 struct PushLaunch {
-  const void *spec;       // [P][3][nh] complex (natural)
-  const void *spec_v;     // velocity spectrum or null
+  const void *spec;       // [P][3][nh] complex float64 (spectrum layout)
+  const void *spec_v;     // velocity spectrum (same type) or null
   void *ring;
   double *state;
   void *vel;

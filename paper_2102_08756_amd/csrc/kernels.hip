@@ -35,7 +35,7 @@ template <> struct W4<double> { using T = double4; };
 
 template <typename R>
 __global__ __launch_bounds__(256) void push_kernel(
-    const cplx<R> *__restrict__ spec, const cplx<R> *__restrict__ spec_v,
+    const double2 *__restrict__ spec, const double2 *__restrict__ spec_v,
     cplx<R> *__restrict__ ring, double2 *__restrict__ state, cplx<R> *__restrict__ vel,
     const int *__restrict__ nat, const double *__restrict__ geom,
     const long long *__restrict__ blk_off, const int *__restrict__ blk_cap,
@@ -54,10 +54,7 @@ __global__ __launch_bounds__(256) void push_kernel(
     const int pg = p == 0 ? plane0 : plane1;
     double2 x[3];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      const cplx<R> v = spec[(pg * 3 + c) * nh + natural];
-      x[c] = double2{static_cast<double>(v.x), static_cast<double>(v.y)};
-    }
+    for (int c = 0; c < 3; ++c) x[c] = spec[(pg * 3 + c) * nh + natural];
     // (1, 2, 3) -> (L, N, T)
     const double2 xr[3] = {{kh1 * x[0].x + kh3 * x[2].x, kh1 * x[0].y + kh3 * x[2].y},
                            x[1],
@@ -66,10 +63,7 @@ __global__ __launch_bounds__(256) void push_kernel(
     if (vel_rule == VEL_INPUT) {
       double2 y[3];
 #pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        const cplx<R> v = spec_v[(pg * 3 + c) * nh + natural];
-        y[c] = double2{static_cast<double>(v.x), static_cast<double>(v.y)};
-      }
+      for (int c = 0; c < 3; ++c) y[c] = spec_v[(pg * 3 + c) * nh + natural];
       vr[0] = double2{kh1 * y[0].x + kh3 * y[2].x, kh1 * y[0].y + kh3 * y[2].y};
       vr[1] = y[1];
       vr[2] = double2{-kh3 * y[0].x + kh1 * y[2].x, -kh3 * y[0].y + kh1 * y[2].y};
@@ -548,7 +542,7 @@ hipError_t launch_push(const sbim_handle *h, const Group &g, const PushLaunch &a
                        a.nh, g.np, p0, p1, a.step, 1.0 / a.dt, a.vel_rule, a.state_rule);
   } else {
     hipLaunchKernelGGL(push_kernel<float>, dim3(grid), dim3(256), 0, h->stream,
-                       static_cast<const float2 *>(a.spec), static_cast<const float2 *>(a.spec_v),
+                       static_cast<const double2 *>(a.spec), static_cast<const double2 *>(a.spec_v),
                        static_cast<float2 *>(a.ring), reinterpret_cast<double2 *>(a.state),
                        static_cast<float2 *>(a.vel), g.nat, g.geom, g.blk_off, g.blk_cap, g.blk_stride, g.M,
                        a.nh, g.np, p0, p1, a.step, 1.0 / a.dt, a.vel_rule, a.state_rule);

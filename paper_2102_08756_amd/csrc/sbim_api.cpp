@@ -108,6 +108,7 @@ void free_handle(sbim_handle *h) {
   if (!h) return;
   (void)hipStreamSynchronize(h->stream);
   for (int i = 0; i < h->ngroups; ++i) free_group(h->g[i]);
+  if (h->twiddle64 && h->twiddle64 != h->twiddle) (void)hipFree(h->twiddle64);
   void *ptrs[] = {h->twiddle, h->spec, h->spec_v, h->out_spec};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
@@ -268,7 +269,7 @@ int check_ptr(sbim_handle *h, const void *p, const char *name) {
 // Forward real 2-D FFT of a [P][3][n1][n3] field into `spec`.
 hipError_t fft_forward(sbim_handle *h, const void *field, void *spec) {
   return sbim::launch_fft_forward(h->fp64, field, spec, h->cfg.nplanes * 3, h->n1, h->n3,
-                                  h->twiddle, h->stream);
+                                  h->twiddle64, h->stream);
 }
 
 // Inverse of a traction spectrum (destroyed) into a [P][3][n1][n3] field.
@@ -361,8 +362,10 @@ int sbim_init(const sbim_config *cfg, sbim_handle **out) {
     need += g.M * (4 * 3 + 32) + g.nblocks * 16 + g.wmax * 8 + g.nclasses * 12;
     total_blocks += g.nblocks;
   }
-  const size_t spec_bytes = static_cast<size_t>(cfg->nplanes) * 3 * h->nh * 2 * h->rsize;
-  need += 3 * spec_bytes + sbim::kTwiddleN * 2 * h->rsize;
+  // input spectra are float64 in every form; the traction spectrum is real_t
+  const size_t spec_bytes = static_cast<size_t>(cfg->nplanes) * 3 * h->nh * 2 * sizeof(double);
+  const size_t out_bytes = static_cast<size_t>(cfg->nplanes) * 3 * h->nh * 2 * h->rsize;
+  need += 2 * spec_bytes + out_bytes + sbim::kTwiddleN * 2 * (h->rsize + sizeof(double));
   size_t free_b = 0, total_b = 0;
   e = hipMemGetInfo(&free_b, &total_b);
   if (e != hipSuccess) {
@@ -412,9 +415,15 @@ int sbim_init(const sbim_config *cfg, sbim_handle **out) {
   } while (0)
 
   TRY(dev_alloc_bytes(&h->twiddle, sbim::kTwiddleN * 2 * h->rsize));
+  if (h->fp64) {
+    h->twiddle64 = h->twiddle;
+  } else {
+    TRY(dev_alloc_bytes(&h->twiddle64, sbim::kTwiddleN * 2 * sizeof(double)));
+    TRY(sbim::upload_twiddles(true, h->twiddle64, h->stream));
+  }
   TRY(dev_alloc_bytes(&h->spec, spec_bytes));
   TRY(dev_alloc_bytes(&h->spec_v, spec_bytes));
-  TRY(dev_alloc_bytes(&h->out_spec, spec_bytes));
+  TRY(dev_alloc_bytes(&h->out_spec, out_bytes));
   TRY(sbim::upload_twiddles(h->fp64, h->twiddle, h->stream));
   TRY(dev_alloc(&d_glx, glx.size()));
   TRY(dev_alloc(&d_glw, glw.size()));

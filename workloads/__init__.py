@@ -2,7 +2,7 @@
 
 Shared by the tests (both the oracle side and the GPU side draw inputs from
 here) and by ``bench.py``.  It holds no part of the boundary-integral
-arithmetic: only random numbers, a spectral shaping of white noise with numpy's
+arithmetic: only random numbers, a spectral shaping of white noise with scipy's
 FFT, and the named workload shapes.
 
 The paper's runs are earthquake ruptures on regular boundary grids (Sec. 3-6;
@@ -19,6 +19,7 @@ drawn once and step n uses bank[(7 n) mod 64].
 from __future__ import annotations
 
 import math
+import os
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -78,14 +79,16 @@ WORKLOADS = {
 
 def shaped_field(rng, n1, n3, dx1=1.0, dx3=1.0):
     """One white field shaped to spectral amplitude |k|^-2, k = 0 removed, unit RMS."""
+    import scipy.fft as sfft
     white = rng.standard_normal((n1, n3))
-    spec = np.fft.rfft2(white)
+    workers = min(16, os.cpu_count() or 1)
+    spec = sfft.rfft2(white, workers=workers)
     k1 = 2 * np.pi * np.fft.fftfreq(n1, d=dx1)
     k3 = 2 * np.pi * np.fft.rfftfreq(n3, d=dx3)
     kk = k1[:, None] ** 2 + k3[None, :] ** 2
     amp = np.zeros_like(kk)
     amp[kk > 0] = 1.0 / kk[kk > 0]
-    f = np.fft.irfft2(spec * amp, s=(n1, n3))
+    f = sfft.irfft2(spec * amp, s=(n1, n3), workers=workers)
     rms = np.sqrt(np.mean(f * f))
     return f / rms if rms > 0 else f
 
@@ -129,16 +132,25 @@ class Increments:
             self._next += 1
         return self._cache[n].copy()
 
-    def __call__(self, n):
+    def uniform(self, n):
+        """[P, 3] spatially uniform part of du^n (the slip ramp on u1; zero otherwise)."""
+        wl = self.wl
+        out = np.zeros((len(wl.planes), 3))
+        if wl.slip_ramp:
+            out[:, 0] = wl.slip_ramp * n / max(wl.steps - 1, 1) * wl.dt
+        return out
+
+    def varying(self, n):
+        """du^n without its uniform part: the random field plus the pulse ramp."""
         wl = self.wl
         du = self._random(n)
         if wl.pulse:
             ramp = lambda m: min(max(m, 0) / 50.0, 1.0)  # noqa: E731
             du[:, 0] += self._gauss * (ramp(n) - ramp(n - 1))
-        if wl.slip_ramp:
-            v = wl.slip_ramp * n / max(wl.steps - 1, 1)
-            du[:, 0] += v * wl.dt
         return du
+
+    def __call__(self, n):
+        return self.varying(n) + self.uniform(n)[:, :, None, None]
 
     def history(self, steps):
         return np.stack([self(n) for n in range(steps)])
@@ -147,3 +159,34 @@ class Increments:
 def absolute_history(du_hist):
     """u^n = sum_{i<=n} du^i along axis 0."""
     return np.cumsum(du_hist, axis=0)
+
+
+def step_sources(wl: Workload):
+    """(fields, index, uniform) with du^n = fields[index(n)] + uniform(n)[:, :, None, None].
+
+    ``fields`` are the distinct spatially varying increments of the workload
+    (bank entries plus the steps that differ from them), ``uniform(n)`` the
+    [P, 3] uniform part.  Lets consumers transform each distinct field once.
+    """
+    inc = Increments(wl)
+    fields = []
+    special = {}
+    n = 0
+    while True:
+        d = inc.varying(n)
+        if inc._bank is not None and n > 0 and np.array_equal(d, inc._bank[(7 * n) % wl.bank]):
+            break
+        special[n] = len(fields)
+        fields.append(d)
+        n += 1
+        if inc._bank is None and n >= wl.steps:
+            break
+    base = len(fields)
+    if inc._bank is not None:
+        fields.extend(inc._bank)
+
+    def index(m):
+        if m in special:
+            return special[m]
+        return base + (7 * m) % wl.bank
+    return fields, index, inc.uniform
