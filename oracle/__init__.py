@@ -20,4 +20,4 @@ invariants; see each test for the pin it provides.
 """
 from . import dft, kernels, sbim  # noqa: F401
 from .sbim import (Config, Plane, forward, adjoint, spectra, mode_geometry,  # noqa: F401
-                   mode_window, mode_response)
+                   mode_window, mode_response, adjoint_response)

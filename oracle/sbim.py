@@ -283,6 +283,29 @@ def forward(cfg, u_hist, v_hist=None, tau_inf_hist=None, chunk=None, weights_cac
     return tau
 
 
+def _input_chain(cfg, lam_u, lam_v, with_velocity):
+    """Transpose of ``spectra``'s definitions of U^n and V^n (time on axis 0).
+
+    lam_u, lam_v: dL/dU^n and dL/dV^n; returns the spectra of dL/du^n and
+    dL/dv^n (None without an explicit velocity).
+    """
+    if with_velocity:
+        dv_hat = lam_v
+        du_hat = lam_u
+    else:
+        dv_hat = None
+        if cfg.input_kind == "absolute":
+            nxt = np.concatenate([lam_v[1:], np.zeros_like(lam_v[:1])], axis=0)
+            du_hat = lam_u + (lam_v - nxt) / cfg.dt
+        else:
+            du_hat = lam_u.copy()
+    if cfg.input_kind == "increment":
+        du_hat = np.flip(np.cumsum(np.flip(du_hat, axis=0), axis=0), axis=0)
+        if not with_velocity:
+            du_hat = du_hat + lam_v / cfg.dt
+    return du_hat, dv_hat
+
+
 def adjoint(cfg, g_hist, with_velocity=False, chunk=None, weights_cache=None):
     """Transpose of ``forward`` applied to g = dL/dtau (tau_inf excluded).
 
@@ -309,21 +332,7 @@ def adjoint(cfg, g_hist, with_velocity=False, chunk=None, weights_cache=None):
             lvp[:, :, f] = lv
     lam_u = lam_u.reshape(N, P, 3, cfg.n1, h)
     lam_v = lam_v.reshape(N, P, 3, cfg.n1, h)
-    # chain through the definitions of U^n and V^n (transposes of ``spectra``)
-    if with_velocity:
-        dv_hat = lam_v
-        du_hat = lam_u
-    else:
-        dv_hat = None
-        if cfg.input_kind == "absolute":
-            nxt = np.concatenate([lam_v[1:], np.zeros_like(lam_v[:1])], axis=0)
-            du_hat = lam_u + (lam_v - nxt) / cfg.dt
-        else:
-            du_hat = lam_u.copy()
-    if cfg.input_kind == "increment":
-        du_hat = np.flip(np.cumsum(np.flip(du_hat, axis=0), axis=0), axis=0)
-        if not with_velocity:
-            du_hat = du_hat + lam_v / cfg.dt
+    du_hat, dv_hat = _input_chain(cfg, lam_u, lam_v, with_velocity)
     du = dft.inverse_half(du_hat, cfg.n3)
     dv = dft.inverse_half(dv_hat, cfg.n3) if dv_hat is not None else None
     return du, dv
@@ -340,3 +349,16 @@ def mode_response(cfg, p, bins, U_hist, V_hist, weights_cache=None):
         cfg = Config.from_dict(cfg)
     op = PlaneOperator(cfg, p, bins, weights_cache)
     return op.apply(np.asarray(U_hist, dtype=complex), np.asarray(V_hist, dtype=complex))
+
+
+def adjoint_response(cfg, p, bins, G_hist, with_velocity=False, weights_cache=None):
+    """Spectra of dL/du (and dL/dv) of plane p at selected bins, every step.
+
+    G_hist: [N, 3, len(bins)] spectrum of g = dL/dtau at those bins; the same
+    transpose as ``adjoint`` restricted to the bins.
+    """
+    if not isinstance(cfg, Config):
+        cfg = Config.from_dict(cfg)
+    op = PlaneOperator(cfg, p, bins, weights_cache)
+    lam_u, lam_v = op.apply_adjoint(np.asarray(G_hist, dtype=complex))
+    return _input_chain(cfg, lam_u, lam_v, with_velocity)

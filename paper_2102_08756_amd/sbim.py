@@ -15,7 +15,8 @@ from dataclasses import dataclass, field
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "_lib", "libsbim.so")
+# SBIM_LIBRARY selects another build of the same library (e.g. a tuning variant)
+LIB_PATH = os.environ.get("SBIM_LIBRARY") or os.path.join(_HERE, "_lib", "libsbim.so")
 
 SBIM_OK, SBIM_E_INVALID, SBIM_E_OOM, SBIM_E_STATE, SBIM_E_DEVICE = 0, -1, -2, -3, -4
 PRECISIONS = {"fp64": 0, "fp32": 1, "fp32_comp": 2}
