@@ -8,6 +8,7 @@
 // spectrum (h3 = n3/2 + 1 bins along x3); the inverse drops the imaginary parts
 // of the i3 = 0 and i3 = n3/2 bins and applies the caller's scale.
 #include <cmath>
+#include <type_traits>
 
 #include "internal.h"
 
@@ -124,10 +125,7 @@ __device__ void lds_fft(cplx<R> *buf, int N, int logN, int nseq, int dir,
   }
 }
 
-// Points per work-group in LDS: at most 16 per thread (register staging of a
-// pass), i.e. 4096, which is also the largest transform length.
-template <typename R>
-constexpr int lds_elems() { return kFftThreads * kFftPerThread; }
+static_assert(kFftThreads * kFftPerThread == 4096, "one work-group covers the longest transform");
 
 // Forward, step 1: rows x1 in [x0, x0 + R) of one field; each row of n3 reals
 // becomes n3/2+1 bins.  Pairs (x[2m], x[2m+1]) form a half-length complex
@@ -135,7 +133,7 @@ constexpr int lds_elems() { return kFftThreads * kFftPerThread; }
 //   X[k] = (Z[k] + conj Z[Nh-k]) / 2 - i e^{-2 pi i k/n3} (Z[k] - conj Z[Nh-k]) / 2.
 // The bins are written transposed, spec[f][k][x1], R consecutive x1 at a time.
 // Input reals of type Rin are widened to the transform's type R on load.
-template <typename Rin, typename R>
+template <typename Rin, typename R, int MAXV>
 __global__ __launch_bounds__(kFftThreads) void r2c_t_kernel(
     const Rin *__restrict__ in, cplx<R> *__restrict__ spec, int n1, int n3, int logNh, int rows,
     const cplx<R> *__restrict__ tw) {
@@ -153,7 +151,7 @@ __global__ __launch_bounds__(kFftThreads) void r2c_t_kernel(
     buf[e] = cplx<R>{static_cast<R>(v.x), static_cast<R>(v.y)};
   }
   __syncthreads();
-  lds_fft<R, kFftThreads, kFftPerThread>(buf, Nh, logNh, rows, -1, tw);
+  lds_fft<R, kFftThreads, MAXV>(buf, Nh, logNh, rows, -1, tw);
   const int step = kTwiddleN / n3;
   cplx<R> *dst = spec + static_cast<long long>(f) * h3 * n1 + x0;
   for (int e = threadIdx.x; e < rows * h3; e += kFftThreads) {
@@ -169,7 +167,7 @@ __global__ __launch_bounds__(kFftThreads) void r2c_t_kernel(
 }
 
 // Complex FFT along contiguous rows of length n (in place); `per` rows per work-group.
-template <typename R>
+template <typename R, int MAXV>
 __global__ __launch_bounds__(kFftThreads) void cfft_rows_kernel(
     cplx<R> *__restrict__ data, long long nrows, int n, int logn, int per, int dir,
     const cplx<R> *__restrict__ tw) {
@@ -180,7 +178,7 @@ __global__ __launch_bounds__(kFftThreads) void cfft_rows_kernel(
   cplx<R> *base = data + row0 * n;
   for (int e = threadIdx.x; e < nb * n; e += kFftThreads) buf[e] = base[e];
   __syncthreads();
-  lds_fft<R, kFftThreads, kFftPerThread>(buf, n, logn, nb, dir, tw);
+  lds_fft<R, kFftThreads, MAXV>(buf, n, logn, nb, dir, tw);
   for (int e = threadIdx.x; e < nb * n; e += kFftThreads) base[e] = buf[e];
 }
 
@@ -190,7 +188,7 @@ __global__ __launch_bounds__(kFftThreads) void cfft_rows_kernel(
 //   Z[k] = (Y[k] + conj Y[Nh-k]) + i e^{+2 pi i k/n3} (Y[k] - conj Y[Nh-k]),
 // an inverse half-length FFT gives x[2m] + i x[2m+1]; the result is scaled and
 // the optional field `add` is added.
-template <typename R>
+template <typename R, int MAXV>
 __global__ __launch_bounds__(kFftThreads) void c2r_t_kernel(
     const cplx<R> *__restrict__ spec, R *__restrict__ out, const R *__restrict__ add, int n1,
     int n3, int logNh, int rows, R scale, const cplx<R> *__restrict__ tw) {
@@ -236,7 +234,7 @@ __global__ __launch_bounds__(kFftThreads) void c2r_t_kernel(
     }
   }
   __syncthreads();
-  lds_fft<R, kFftThreads, kFftPerThread>(buf, Nh, logNh, rows, +1, tw);
+  lds_fft<R, kFftThreads, MAXV>(buf, Nh, logNh, rows, +1, tw);
   const long long o = (static_cast<long long>(f) * n1 + x0) * n3;
   cplx<R> *dst = reinterpret_cast<cplx<R> *>(out + o);
   const cplx<R> *addp = add ? reinterpret_cast<const cplx<R> *>(add + o) : nullptr;
@@ -259,52 +257,66 @@ int ilog2(int n) {
   return l;
 }
 
-// x1 rows per work-group of the real<->complex kernels: up to 8 (64-byte runs of
-// the transposed spectrum in float32), within the LDS budget.
+// Work-group shapes: about 1024 points per work-group (one radix-4 butterfly per
+// thread per pass) when the transform allows it; MAXV, the points a thread
+// stages in registers per pass, is the smallest power of two that covers it.
+int tile_rows(int n1, int Nh) { return max(1, min(min(8, n1), 1024 / Nh)); }
+int rows_per_group(int n) { return max(1, 1024 / n); }
+
+template <typename F>
+hipError_t with_maxv(int points, F &&launch) {
+  if (points <= kFftThreads * 4) return launch(std::integral_constant<int, 4>());
+  if (points <= kFftThreads * 8) return launch(std::integral_constant<int, 8>());
+  return launch(std::integral_constant<int, 16>());
+}
+
 template <typename R>
-int tile_rows(int n1, int Nh) {
-  return max(1, min(min(8, n1), lds_elems<R>() / Nh));
+hipError_t cfft_launch(void *spec, long long nrows, int n, int dir, const void *tw,
+                       hipStream_t st) {
+  const int per = rows_per_group(n);
+  return with_maxv(per * n, [&](auto mv) {
+    hipLaunchKernelGGL((cfft_rows_kernel<R, decltype(mv)::value>),
+                       dim3(static_cast<unsigned>((nrows + per - 1) / per)), dim3(kFftThreads),
+                       static_cast<size_t>(per) * n * sizeof(cplx<R>), st,
+                       static_cast<cplx<R> *>(spec), nrows, n, ilog2(n), per, dir,
+                       static_cast<const cplx<R> *>(tw));
+    return hipGetLastError();
+  });
 }
 
 template <typename Rin, typename R>
 hipError_t forward_impl(const void *in, void *spec, int F, int n1, int n3, const void *tw,
                         hipStream_t st) {
   const int Nh = n3 / 2, h3 = Nh + 1;
-  const int rows = tile_rows<R>(n1, Nh);
-  hipLaunchKernelGGL((r2c_t_kernel<Rin, R>), dim3(static_cast<unsigned>(F * (n1 / rows))),
-                     dim3(kFftThreads), static_cast<size_t>(rows) * Nh * sizeof(cplx<R>), st,
-                     static_cast<const Rin *>(in), static_cast<cplx<R> *>(spec), n1, n3,
-                     ilog2(Nh), rows, static_cast<const cplx<R> *>(tw));
-  hipError_t e = hipGetLastError();
+  const int rows = tile_rows(n1, Nh);
+  hipError_t e = with_maxv(rows * Nh, [&](auto mv) {
+    hipLaunchKernelGGL((r2c_t_kernel<Rin, R, decltype(mv)::value>),
+                       dim3(static_cast<unsigned>(F * (n1 / rows))), dim3(kFftThreads),
+                       static_cast<size_t>(rows) * Nh * sizeof(cplx<R>), st,
+                       static_cast<const Rin *>(in), static_cast<cplx<R> *>(spec), n1, n3,
+                       ilog2(Nh), rows, static_cast<const cplx<R> *>(tw));
+    return hipGetLastError();
+  });
   if (e != hipSuccess) return e;
-  const long long nrows = static_cast<long long>(F) * h3;
-  const int per = max(1, min(lds_elems<R>() / n1, 1024 / n1));
-  hipLaunchKernelGGL(cfft_rows_kernel<R>, dim3(static_cast<unsigned>((nrows + per - 1) / per)),
-                     dim3(kFftThreads), static_cast<size_t>(per) * n1 * sizeof(cplx<R>), st,
-                     static_cast<cplx<R> *>(spec), nrows, n1, ilog2(n1), per, -1,
-                     static_cast<const cplx<R> *>(tw));
-  return hipGetLastError();
+  return cfft_launch<R>(spec, static_cast<long long>(F) * h3, n1, -1, tw, st);
 }
 
 template <typename R>
 hipError_t inverse_impl(void *spec, void *out, const void *add, int F, int n1, int n3,
                         double scale, const void *tw, hipStream_t st) {
   const int Nh = n3 / 2, h3 = Nh + 1;
-  const long long nrows = static_cast<long long>(F) * h3;
-  const int per = max(1, min(lds_elems<R>() / n1, 1024 / n1));
-  hipLaunchKernelGGL(cfft_rows_kernel<R>, dim3(static_cast<unsigned>((nrows + per - 1) / per)),
-                     dim3(kFftThreads), static_cast<size_t>(per) * n1 * sizeof(cplx<R>), st,
-                     static_cast<cplx<R> *>(spec), nrows, n1, ilog2(n1), per, +1,
-                     static_cast<const cplx<R> *>(tw));
-  hipError_t e = hipGetLastError();
+  hipError_t e = cfft_launch<R>(spec, static_cast<long long>(F) * h3, n1, +1, tw, st);
   if (e != hipSuccess) return e;
-  const int rows = tile_rows<R>(n1, Nh);
-  hipLaunchKernelGGL(c2r_t_kernel<R>, dim3(static_cast<unsigned>(F * (n1 / rows))),
-                     dim3(kFftThreads), static_cast<size_t>(rows) * (Nh + 1) * sizeof(cplx<R>), st,
-                     static_cast<const cplx<R> *>(spec), static_cast<R *>(out),
-                     static_cast<const R *>(add), n1, n3, ilog2(Nh), rows, static_cast<R>(scale),
-                     static_cast<const cplx<R> *>(tw));
-  return hipGetLastError();
+  const int rows = tile_rows(n1, Nh);
+  return with_maxv(rows * Nh, [&](auto mv) {
+    hipLaunchKernelGGL((c2r_t_kernel<R, decltype(mv)::value>),
+                       dim3(static_cast<unsigned>(F * (n1 / rows))), dim3(kFftThreads),
+                       static_cast<size_t>(rows) * (Nh + 1) * sizeof(cplx<R>), st,
+                       static_cast<const cplx<R> *>(spec), static_cast<R *>(out),
+                       static_cast<const R *>(add), n1, n3, ilog2(Nh), rows,
+                       static_cast<R>(scale), static_cast<const cplx<R> *>(tw));
+    return hipGetLastError();
+  });
 }
 
 }  // namespace

@@ -7,7 +7,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/sbim.h"
+#include "sbim.h"
 
 namespace sbim {
 

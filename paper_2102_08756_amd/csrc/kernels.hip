@@ -41,8 +41,11 @@ __global__ __launch_bounds__(256) void push_kernel(
     const long long *__restrict__ blk_off, const int *__restrict__ blk_cap,
     const int *__restrict__ blk_stride, long long M, long long nh, int np, int plane0, int plane1,
     long long step, double inv_dt, int vel_rule, int state_rule) {
-  const long long s = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (s >= M) return;
+  // one thread per (mode, plane); consecutive threads take consecutive modes
+  const long long t = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= M * np) return;
+  const int p = static_cast<int>(t / M);
+  const long long s = t - p * M;
   const long long natural = nat[s];
   const double kh1 = geom[4 * s + 1];
   const double kh3 = geom[4 * s + 2];
@@ -50,7 +53,7 @@ __global__ __launch_bounds__(256) void push_kernel(
   const int lane = static_cast<int>(s & 63);
   const int cap = blk_cap[b];
   const long long rec = cap > 0 ? blk_off[b] + (step % cap) * blk_stride[b] : 0;
-  for (int p = 0; p < np; ++p) {
+  {
     const int pg = p == 0 ? plane0 : plane1;
     double2 x[3];
 #pragma unroll
@@ -131,7 +134,11 @@ template <> struct Acc<float, true> {
 constexpr int kSums = 10;  // real accumulators per plane
 
 // Lags handled per unrolled chunk: loads of U lags are issued before their FMAs.
-template <typename R> constexpr int conv_unroll() { return sizeof(R) == 8 ? 2 : 4; }
+// (Measured on gfx950: 4 for plain float32; 2 for float64 and for the
+// compensated form, whose extra registers otherwise cost a wave per SIMD.)
+template <typename R, bool COMP> constexpr int conv_unroll() {
+  return (sizeof(R) == 8 || COMP) ? 2 : 4;
+}
 
 // One lag for all planes of the lane's mode: weights of the lane's kernel row
 // (zero once the lag passes the lane's own window W(q): such lanes read the
@@ -145,11 +152,18 @@ __device__ __forceinline__ void load_lag(const cplx<R> *__restrict__ ring,
   const bool on = j < llane;
   w = table[lag_off[j] + (on ? cl : 0)];
   if (!on) w = typename W4<R>::T{R(0), R(0), R(0), R(0)};
+  // the history is read once per step: non-temporal loads keep it from
+  // displacing the kernel rows and indices in the caches
   const cplx<R> *r = ring + record * NP * 3 * kLanes + lane;
+  typedef R nv2 __attribute__((ext_vector_type(2)));
 #pragma unroll
   for (int p = 0; p < NP; ++p)
 #pragma unroll
-    for (int c = 0; c < 3; ++c) u[p][c] = r[(p * 3 + c) * kLanes];
+    for (int c = 0; c < 3; ++c) {
+      const nv2 v =
+          __builtin_nontemporal_load(reinterpret_cast<const nv2 *>(r + (p * 3 + c) * kLanes));
+      u[p][c] = cplx<R>{v.x, v.y};
+    }
 }
 
 // part[p][.] += w * u for the five history sums of each plane.
@@ -183,7 +197,7 @@ __global__ __launch_bounds__(kLanes) void conv_stream_kernel(
     const long long *__restrict__ blk_off, const int *__restrict__ blk_cap,
     const int *__restrict__ blk_stride, const long long *__restrict__ lag_off, long long M,
     long long step, int chunks, int nblocks) {
-  constexpr int U = conv_unroll<R>();
+  constexpr int U = conv_unroll<R, COMP>();
   // chunk-major item order: the waves in flight at any time work on the same
   // lag range of consecutive blocks, whose records are adjacent in memory
   const int ch = blockIdx.x / nblocks;
@@ -273,7 +287,9 @@ __global__ __launch_bounds__(kLanes) void conv_stream_kernel(
   for (int p = 0; p < NP; ++p)
 #pragma unroll
     for (int k = 0; k < kSums; ++k)
-      partial[(static_cast<long long>(ch) * NP * kSums + p * kSums + k) * M + s] = acc[p][k].value();
+      __builtin_nontemporal_store(  // read once, by the epilogue
+          acc[p][k].value(),
+          partial + (static_cast<long long>(ch) * NP * kSums + p * kSums + k) * M + s);
 }
 
 // Per mode: fold the chunk partials in chunk order (compensated for the
@@ -287,8 +303,11 @@ __global__ __launch_bounds__(256) void conv_epilogue_kernel(
     const double *__restrict__ geom, const long long *__restrict__ blk_off,
     const int *__restrict__ blk_cap, const int *__restrict__ blk_stride, long long M, long long nh,
     long long step, int chunks, PlaneParams p0, PlaneParams p1) {
-  const long long s = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (s >= M) return;
+  // one thread per (mode, plane); consecutive threads take consecutive modes
+  const long long t = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= M * NP) return;
+  const int p = static_cast<int>(t / M);
+  const long long s = t - p * M;
   const long long b = s >> 6;
   const int lane = static_cast<int>(s & 63);
   const int cap = blk_cap[b];
@@ -298,34 +317,29 @@ __global__ __launch_bounds__(256) void conv_epilogue_kernel(
   const R kh3 = static_cast<R>(geom[4 * s + 2]);
   const long long natural = nat[s];
   const long long rec0 = cap > 0 ? blk_off[b] + (step % cap) * blk_stride[b] : 0;
-  // fold the chunk partials, chunk by chunk (all sums of a chunk loaded together)
-  R cs_all[NP][kSums];
+  // fold the chunk partials in chunk order (ten sums of a chunk loaded together)
+  R cs[kSums];
   {
-    Acc<R, COMP> a[NP][kSums];
+    Acc<R, COMP> a[kSums];
+#pragma unroll 4
     for (int c = 0; c < chunks; ++c) {
-      const R *pc = partial + static_cast<long long>(c) * NP * kSums * M + s;
-      R v[NP * kSums];
+      const R *pc = partial + (static_cast<long long>(c) * NP + p) * kSums * M + s;
+      R v[kSums];
 #pragma unroll
-      for (int k = 0; k < NP * kSums; ++k) v[k] = pc[k * M];
+      for (int k = 0; k < kSums; ++k) v[k] = pc[k * M];
 #pragma unroll
-      for (int p = 0; p < NP; ++p)
-#pragma unroll
-        for (int k = 0; k < kSums; ++k) a[p][k].fold(v[p * kSums + k]);
+      for (int k = 0; k < kSums; ++k) a[k].fold(v[k]);
     }
 #pragma unroll
-    for (int p = 0; p < NP; ++p)
-#pragma unroll
-      for (int k = 0; k < kSums; ++k) cs_all[p][k] = a[p][k].value();
+    for (int k = 0; k < kSums; ++k) cs[k] = a[k].value();
   }
-#pragma unroll
-  for (int p = 0; p < NP; ++p) {
+  {
     const PlaneParams &pp = p == 0 ? p0 : p1;
     const R sg = static_cast<R>(pp.side);
     const R muq = static_cast<R>(pp.mu * q);
     const R damp = static_cast<R>(pp.mu / pp.cs);
     const R inst = static_cast<R>((2.0 - pp.eta) * pp.mu * q);
     const R eta = static_cast<R>(pp.eta);
-    const R *cs = cs_all[p];
     cplx<R> u[3] = {{R(0), R(0)}, {R(0), R(0)}, {R(0), R(0)}};
     if (cap > 0 && wl > 0) {
       const cplx<R> *r = ring + (rec0 * NP + p) * 3 * kLanes + lane;
@@ -512,7 +526,8 @@ hipError_t conv_launch_np(const sbim_handle *h, const Group &g, const ConvLaunch
   if (ev1) (void)hipEventRecord(ev1, h->stream);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((conv_epilogue_kernel<R, NP, COMP>), dim3(static_cast<unsigned>((g.M + 255) / 256)),
+  hipLaunchKernelGGL((conv_epilogue_kernel<R, NP, COMP>),
+                     dim3(static_cast<unsigned>((g.M * NP + 255) / 256)),
                      dim3(256), 0, h->stream, static_cast<const R *>(g.partial),
                      static_cast<const cplx<R> *>(a.ring), static_cast<const cplx<R> *>(a.vel),
                      reinterpret_cast<double2 *>(a.lam), static_cast<cplx<R> *>(a.out_a),
@@ -531,7 +546,7 @@ hipError_t conv_launch_r(const sbim_handle *h, const Group &g, const ConvLaunch 
 }  // namespace
 
 hipError_t launch_push(const sbim_handle *h, const Group &g, const PushLaunch &a) {
-  const unsigned grid = static_cast<unsigned>((g.M + 255) / 256);
+  const unsigned grid = static_cast<unsigned>((g.M * g.np + 255) / 256);
   const int p0 = g.pl[0].index;
   const int p1 = g.np > 1 ? g.pl[1].index : p0;
   if (h->fp64) {
