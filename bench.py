@@ -145,17 +145,21 @@ def measure_form(wl, precision, steps, warmup, device, inputs_cache):
     }
 
 
-def accuracy(wl, steps, device, inputs_cache, forms=("fp32_comp", "fp32")):
-    """Relative L2 of float32 forms against float64 on the same inputs, whole job and worst step."""
+def accuracy(wl, steps, device, inputs_cache, forms=("fp32_comp", "fp32"), block=500):
+    """Relative L2 of float32 forms against float64 on the same inputs: whole job, worst
+    single step, and per block of ``block`` steps (to show how the error grows with time)."""
     import torch
     from paper_2102_08756_amd import SBIM, Config
     ref = SBIM(Config.from_dict(wl.config_dict(), precision="fp64"), device=device)
     others = {f: SBIM(Config.from_dict(wl.config_dict(), precision=f), device=device) for f in forms}
     in64 = inputs_cache[torch.float64]
     in32 = inputs_cache[torch.float32]
-    num = {f: torch.zeros((), dtype=torch.float64, device=device) for f in forms}
-    worst = {f: torch.zeros((), dtype=torch.float64, device=device) for f in forms}
-    den = torch.zeros((), dtype=torch.float64, device=device)
+    zero = lambda: torch.zeros((), dtype=torch.float64, device=device)  # noqa: E731
+    num = {f: zero() for f in forms}
+    bnum = {f: zero() for f in forms}
+    worst = {f: zero() for f in forms}
+    den, bden = zero(), zero()
+    blocks = {f: [] for f in forms}
     t64 = ref.new_field()
     t32 = {f: others[f].new_field() for f in forms}
     for n in range(steps):
@@ -163,16 +167,26 @@ def accuracy(wl, steps, device, inputs_cache, forms=("fp32_comp", "fp32")):
         ref.tractions(out=t64)
         d = (t64 * t64).sum()
         den += d
+        bden += d
         for f in forms:
             others[f].push(in32(n))
             others[f].tractions(out=t32[f])
             e = ((t32[f].double() - t64) ** 2).sum()
             num[f] += e
+            bnum[f] += e
             worst[f] = torch.maximum(worst[f], torch.sqrt(e / d))
-    out = {}
+        if (n + 1) % block == 0 or n + 1 == steps:
+            for f in forms:
+                blocks[f].append(float(torch.sqrt(bnum[f] / bden)))
+                bnum[f].zero_()
+            bden.zero_()
+            print(f"[bench] accuracy: step {n + 1}/{steps}: "
+                  + ", ".join(f"{f} {blocks[f][-1]:.3e}" for f in forms), file=sys.stderr, flush=True)
+    out = {"block_steps": block}
     for f in forms:
         out[f"{f}_vs_fp64_rel_l2"] = float(torch.sqrt(num[f] / den))
         out[f"{f}_vs_fp64_worst_step_rel_l2"] = float(worst[f])
+        out[f"{f}_vs_fp64_rel_l2_per_block"] = blocks[f]
     ref.close()
     for s in others.values():
         s.close()
