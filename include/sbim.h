@@ -109,7 +109,7 @@ typedef struct {
   long long step;              /* pushes since init / reset */
   long long backward_step;     /* sbim_backward calls since the last reset */
   int material_groups;         /* planes sharing (c_s, c_p) share one table and one pass */
-  int lag_split;               /* lag chunks per 64-mode block in the history stream */
+  int sweep_depth;             /* steps served by one pass over a block's history */
 } sbim_info;
 
 /*
@@ -129,7 +129,12 @@ int sbim_init(const sbim_config *cfg, sbim_handle **out);
  *              u^n - u^{n-1} (SBIM_INCREMENT)
  *   v_or_null  device [P][3][n1][n3] velocity prediction for the damping term
  *              of this step, or NULL to use (u^n - u^{n-1}) / dt
- * Exactly one push precedes each sbim_tractions call.
+ * Exactly one push precedes each sbim_tractions call.  The push also runs the
+ * history sweep of this step: the 64-mode blocks whose turn it is (one in
+ * sweep_depth of them, in rotation) read their whole history window once and
+ * store the part of each of the next sweep_depth steps' history sums that
+ * this history already fixes; every step thus reads each history entry
+ * 1/sweep_depth times on average.
  */
 int sbim_push_displacement(sbim_handle *h, const void *u, const void *v_or_null);
 
@@ -137,6 +142,9 @@ int sbim_push_displacement(sbim_handle *h, const void *u, const void *v_or_null)
  * sbim_tractions: tau^n of the last pushed step into device [P][3][n1][n3].
  *   tau_inf_or_null  device [P][3][n1][n3] far-field traction added to the
  *                    result, or NULL for zero.
+ * It adds to each mode's pending sum the lags newer than its block's last
+ * sweep, so it reads no state that it changes: calling it again before the
+ * next push returns the same tractions.
  * SBIM_E_STATE if no step was pushed since init/reset.
  */
 int sbim_tractions(sbim_handle *h, const void *tau_inf_or_null, void *tau);
@@ -171,7 +179,8 @@ int sbim_get_info(const sbim_handle *h, sbim_info *out);
 
 /*
  * Snapshots for checkpointing: the full forward state (ring, running state,
- * velocity spectra, step counter) is sbim_state_bytes() bytes.  save/load
+ * velocity spectra, pending history sums of the coming steps, step counter)
+ * is sbim_state_bytes() bytes.  save/load
  * copy it to/from a caller-owned device buffer of at least that size,
  * asynchronously on the handle's stream.
  */
@@ -181,11 +190,12 @@ int sbim_load_state(sbim_handle *h, const void *src_device);
 
 /*
  * Work of the step with index n (0-based): *mode_lags = the number of
- * (plane, mode, lag) products, i.e. min(W(q), n+1) summed over planes and
- * modes; *conv_bytes = the bytes the history-stream kernel must move for that
- * step: the history those products read, the kernel rows they use (once per
- * distinct row), the per-mode row/window indices and the partial sums it
- * writes.
+ * (plane, mode, lag) products of that step's history sums, i.e. min(W(q), n+1)
+ * summed over planes and modes; *conv_bytes = the bytes the history sweep
+ * launched by that step's push must move: the history of the modes whose
+ * block sweeps at step n (phase n mod sweep_depth), the kernel rows of each
+ * distinct row class in those blocks, their row/window indices and block
+ * descriptors, and the sweep_depth pending sums written per mode and plane.
  */
 int sbim_step_work(const sbim_handle *h, long long n, double *mode_lags, double *conv_bytes);
 
@@ -198,8 +208,8 @@ int sbim_step_work(const sbim_handle *h, long long n, double *mode_lags, double 
 int sbim_mode_kernel(sbim_handle *h, int p, int i1, int i3, double *host_out, int max_lags);
 
 /*
- * Timing of the history-stream kernel (the dominant kernel of a step): when
- * enabled, HIP events bracket each of its launches made by sbim_tractions on
+ * Timing of the history sweep (the dominant kernel of a step): when enabled,
+ * HIP events bracket each of its launches made by sbim_push_displacement on
  * the handle's stream; sbim_conv_timing synchronises and returns the summed
  * device time (ms) and the launch count since the last sbim_profile_conv.
  */

@@ -17,9 +17,8 @@ constexpr int kTwiddleN = 1 << kTwiddleLog;
 constexpr int kFftThreads = 256;
 constexpr int kFftPerThread = 16;     // transform points per thread in the LDS FFT kernels
 constexpr int kGaussN = 32;           // Gauss-Legendre points per quadrature panel
-constexpr int kMaxChunks = 64;        // largest lag split of the convolution
-constexpr long long kTargetItems = 8192;  // aim for this many work items per convolution
-constexpr int kMinChunkLags = 16;     // shortest lag chunk worth a work item
+constexpr int kLagGroups = 4;         // lag chunks per sweep wavefront (16 lanes each)
+constexpr int kMaxSweep = 8;          // deepest sweep: steps served by one pass over a history
 
 // What push_kernel stores as "velocity" for the epilogue.
 enum VelRule : int {
@@ -46,7 +45,7 @@ struct Group {
   long long nclasses = 0;         // kernel rows
   int wmax = 0;                   // largest W(q)
   long long ring_records = 0;     // sum of block capacities
-  long long table_rows = 0;       // sum over classes of W
+  long long table_rows = 0;       // sum over classes of W + 1
   // device
   int *nat = nullptr;             // [M] sorted position -> spectrum bin i3 * n1 + i1
   int *cls = nullptr;             // [M] sorted position -> class
@@ -55,23 +54,24 @@ struct Group {
   long long *blk_off = nullptr;   // [nblocks] first ring record of the block
   int *blk_cap = nullptr;         // [nblocks] ring capacity of the block (its largest W)
   int *blk_stride = nullptr;      // [nblocks] records between consecutive slots of the block
-  long long *lag_off = nullptr;   // [wmax] first table entry of each lag row
+  long long *cls_off = nullptr;   // [nclasses] first table entry of each class
   double *cls_q = nullptr;        // [nclasses]
   int *cls_w = nullptr;           // [nclasses]
   void *table = nullptr;          // [table_rows] x 4 reals (w11, w12, w22, w33)
   void *ring = nullptr;           // [ring_records][np][3][64] complex
   double *state = nullptr;        // [np][3][M] complex double (rotated frame, sorted)
   void *vel = nullptr;            // [np][3][M] complex real_t
-  void *partial = nullptr;        // [chunks][np * 10][M] real_t: per-chunk history sums
+  void *pending = nullptr;        // [depth][np][10][M] real_t: history sums of coming steps
   // adjoint (allocated on first use)
   void *ring_adj = nullptr;
+  void *pending_adj = nullptr;
   double *state_adj = nullptr;    // previous g spectrum (float64)
   double *lam_adj = nullptr;      // reverse running sum (float64)
   void *vel_adj = nullptr;
   // host copies for diagnostics / work accounting
   std::vector<int> h_nat, h_cls, h_win;
-  std::vector<long long> h_lag_off;
-  std::vector<int> h_cls_w;
+  std::vector<long long> h_cls_off;
+  std::vector<int> h_cls_w, h_blk_cap;
 };
 
 }  // namespace sbim
@@ -90,7 +90,7 @@ struct sbim_handle {
   long long step = 0;             // pushes done
   long long bstep = 0;            // backward calls done
   bool pushed_since_tractions = false;
-  int lag_split = 1;               // lag chunks per 64-mode block in the convolution
+  int depth = 1;                  // sweep depth: steps served by one pass over a block's history
   void *twiddle = nullptr;        // [4096] complex real_t, exp(-2 pi i m / 4096)
   void *twiddle64 = nullptr;      // the same in float64 (== twiddle for SBIM_FP64)
   void *spec = nullptr;           // [P][3][h3][n1] complex float64: spectrum of the pushed field
@@ -128,8 +128,24 @@ struct PushLaunch {
 };
 hipError_t launch_push(const sbim_handle *h, const Group &g, const PushLaunch &a);
 
+// The history sums are split over time.  Block b of 64 modes has phase
+// b mod depth; at each step n the blocks of phase n mod depth sweep their whole
+// history once and store, for each of the steps n .. n+depth-1, the part of
+// that step's sum over the history up to step n ("pending" sums).  The
+// epilogue of step n adds to the pending sum of each mode the lags newer than
+// its block's last sweep (fewer than depth of them).
+struct SweepLaunch {
+  const void *ring;
+  void *pending;
+  long long step;
+};
+// One launch (bracketed by ev0/ev1 when they are non-null).
+hipError_t launch_sweep(const sbim_handle *h, const Group &g, const SweepLaunch &a,
+                        hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+
 struct ConvLaunch {
   const void *ring;
+  const void *pending;
   const void *vel;
   double *lam;            // non-null: accumulate (conv + instantaneous) into this float64 state
   void *out_a;            // [P][3][nh] complex: output spectrum
@@ -137,10 +153,9 @@ struct ConvLaunch {
   long long nh;
   long long step;
 };
-// Two launches: the history stream (bracketed by ev0/ev1 when they are non-null)
-// and the per-mode epilogue.
-hipError_t launch_conv(const sbim_handle *h, const Group &g, const ConvLaunch &a,
-                       hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+// Per-mode epilogue: pending sum + newest lags, damping and instantaneous
+// terms, rotation back to (x1, x2, x3), scatter into the spectrum.
+hipError_t launch_conv(const sbim_handle *h, const Group &g, const ConvLaunch &a);
 
 hipError_t launch_tabulate(bool fp64, const Group &g, double dt, const double *gl_x,
                            const double *gl_w, hipStream_t st);

@@ -1,20 +1,22 @@
 // Mode-space kernels of the boundary-integral step on gfx950:
-//   push_kernel      rotate a new spectrum into the wavevector frame, update the
-//                    float64 running state, store the history ring slot and the
-//                    velocity spectrum used by the damping term;
-//   conv_kernel      the truncated history convolution (the nonlocal term of
-//                    Eq. SBI, Sec. 2.3) fused with the damping and instantaneous
-//                    terms and the rotation back to (x1, x2, x3);
-//   tabulate_kernel  float64 quadrature of the per-lag kernel weights.
+//   push_kernel          rotate a new spectrum into the wavevector frame, update
+//                        the float64 running state, store the history ring slot
+//                        and the velocity spectrum used by the damping term;
+//   sweep_kernel         the truncated history convolution (the nonlocal term of
+//                        Eq. SBI, Sec. 2.3), one pass over a block's history
+//                        serving several steps;
+//   conv_epilogue_kernel the newest lags, damping and instantaneous terms and the
+//                        rotation back to (x1, x2, x3);
+//   tabulate_kernel      float64 quadrature of the per-lag kernel weights.
 //
 // Layouts (one material group; modes sorted by (W desc, q asc), 64 per block):
 //   ring    [record][plane][component L,N,T][64 lanes] complex.  Step n of
 //           block b lives in record blk_off[b] + (n mod blk_cap[b]) * blk_stride[b]:
-//           consecutive blocks of equal capacity form a run laid out slot-major
-//           (stride = run length), so one history slot of a run is contiguous;
-//   table   lag-major rows: entry lag_off[j] + class holds (w11, w12, w22, w33);
-//           classes are sorted by W desc, so the classes alive at lag j are a
-//           prefix of the row.
+//           consecutive blocks of one sweep phase (b mod depth) with equal
+//           capacity form a run laid out slot-major (stride = run length), so
+//           one history slot of a run is contiguous;
+//   table   class-major rows: entry cls_off[class] + j holds (w11, w12, w22, w33)
+//           of lag j, j < W of the class.
 #include <cmath>
 
 #include "internal.h"
@@ -115,220 +117,273 @@ template <typename R, bool COMP> struct Acc;
 template <typename R> struct Acc<R, false> {
   R s = R(0);
   __device__ __forceinline__ void fold(R x) { s += x; }
-  __device__ __forceinline__ void fold_pair(R x, R) { s += x; }
   __device__ __forceinline__ R value() const { return s; }
-  __device__ __forceinline__ R comp() const { return R(0); }
+  // add the accumulator of the lane `off` lanes away (butterfly reduction)
+  __device__ __forceinline__ void fold_lane(int off) { s += __shfl_xor(s, off); }
 };
 template <> struct Acc<float, true> {
   float s = 0.f, c = 0.f;
   __device__ __forceinline__ void fold(float x) { neumaier(s, c, x); }
-  __device__ __forceinline__ void fold_pair(float x, float xc) {
-    neumaier(s, c, x);
-    c += xc;
-  }
   __device__ __forceinline__ float value() const { return s + c; }
-  __device__ __forceinline__ float comp() const { return c; }
+  __device__ __forceinline__ void fold_lane(int off) {
+    const float s2 = __shfl_xor(s, off);
+    const float c2 = __shfl_xor(c, off);
+    neumaier(s, c, s2);
+    c += c2;
+  }
 };
 
 // Five complex history sums per plane: C11[U_L], C12[U_N], C22[U_N], C12[U_L], C33[U_T].
 constexpr int kSums = 10;  // real accumulators per plane
 
-// Lags handled per unrolled chunk: loads of U lags are issued before their FMAs.
-// (Measured on gfx950: 4 for plain float32; 2 for float64 and for the
-// compensated form, whose extra registers otherwise cost a wave per SIMD.)
-template <typename R, bool COMP> constexpr int conv_unroll() {
-  return (sizeof(R) == 8 || COMP) ? 2 : 4;
+// part[.] += w * u for the five history sums of one plane.
+template <typename R>
+__device__ __forceinline__ void fma_lag(R (&part)[kSums], const typename W4<R>::T &w,
+                                        const cplx<R> (&u)[3]) {
+  part[0] = fma(w.x, u[0].x, part[0]);
+  part[1] = fma(w.x, u[0].y, part[1]);
+  part[2] = fma(w.y, u[1].x, part[2]);
+  part[3] = fma(w.y, u[1].y, part[3]);
+  part[4] = fma(w.z, u[1].x, part[4]);
+  part[5] = fma(w.z, u[1].y, part[5]);
+  part[6] = fma(w.y, u[0].x, part[6]);
+  part[7] = fma(w.y, u[0].y, part[7]);
+  part[8] = fma(w.w, u[2].x, part[8]);
+  part[9] = fma(w.w, u[2].y, part[9]);
 }
 
-// One lag for all planes of the lane's mode: weights of the lane's kernel row
-// (zero once the lag passes the lane's own window W(q): such lanes read the
-// row of class 0, which is alive at every lag of the block, and discard it).
-template <typename R, int NP>
-__device__ __forceinline__ void load_lag(const cplx<R> *__restrict__ ring,
-                                         const typename W4<R>::T *__restrict__ table,
-                                         const long long *__restrict__ lag_off, long long record,
-                                         int lane, int j, int llane, int cl,
-                                         typename W4<R>::T &w, cplx<R> (&u)[NP][3]) {
-  const bool on = j < llane;
-  w = table[lag_off[j] + (on ? cl : 0)];
-  if (!on) w = typename W4<R>::T{R(0), R(0), R(0), R(0)};
-  // the history is read once per step: non-temporal loads keep it from
-  // displacing the kernel rows and indices in the caches
-  const cplx<R> *r = ring + record * NP * 3 * kLanes + lane;
+// History entries whose loads the sweep issues together (measured on gfx950,
+// 512x512 x 2 planes, W = 1000): float32 at depth 8 fits three wavefronts per
+// SIMD only with pairs; the compensated form gains from groups of four, whose
+// products are folded into the compensated sums together.
+template <typename R, int S, bool COMP> constexpr int sweep_group() {
+  constexpr int g = COMP ? 4 : (sizeof(R) == 8 || S >= 8 ? 2 : 4);
+  return S < g ? S : g;
+}
+
+// Rows k0 .. k0+S-1 of a mode's kernel.  A class's W rows are followed by a
+// zero row, so clamping the lag to W gives zero from the window on.
+template <typename R, int S>
+__device__ __forceinline__ void load_rows(typename W4<R>::T (&w)[S],
+                                          const typename W4<R>::T *__restrict__ rowp, int k0,
+                                          int wl) {
+#pragma unroll
+  for (int k = 0; k < S; ++k) w[k] = rowp[min(k0 + k, wl)];
+}
+
+// S consecutive history entries (lags i .. i+S-1) against rows i .. i+2S-2,
+// held as A = rows i .. i+S-1 and B = rows i+S .. i+2S-1.  hp / x point at the
+// ring record / slot of lag i and are advanced past lag i+S-1.
+template <typename R, int S, bool COMP>
+__device__ __forceinline__ void sweep_span(Acc<R, COMP> (&acc)[S][kSums],
+                                           const typename W4<R>::T (&A)[S],
+                                           const typename W4<R>::T (&B)[S],
+                                           const cplx<R> *__restrict__ &hp, int &x, int cap,
+                                           long long dstep, long long dwrap) {
+  constexpr int G = sweep_group<R, S, COMP>();
   typedef R nv2 __attribute__((ext_vector_type(2)));
 #pragma unroll
-  for (int p = 0; p < NP; ++p)
+  for (int g0 = 0; g0 < S; g0 += G) {
+    cplx<R> u[G][3];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      const nv2 v =
-          __builtin_nontemporal_load(reinterpret_cast<const nv2 *>(r + (p * 3 + c) * kLanes));
-      u[p][c] = cplx<R>{v.x, v.y};
-    }
-}
-
-// part[p][.] += w * u for the five history sums of each plane.
-template <typename R, int NP>
-__device__ __forceinline__ void fma_lag(R (&part)[NP][kSums], const typename W4<R>::T &w,
-                                        const cplx<R> (&u)[NP][3]) {
+    for (int t = 0; t < G; ++t) {
+      // the history is read once per sweep: non-temporal loads keep it from
+      // displacing the kernel rows in the caches
 #pragma unroll
-  for (int p = 0; p < NP; ++p) {
-    part[p][0] = fma(w.x, u[p][0].x, part[p][0]);
-    part[p][1] = fma(w.x, u[p][0].y, part[p][1]);
-    part[p][2] = fma(w.y, u[p][1].x, part[p][2]);
-    part[p][3] = fma(w.y, u[p][1].y, part[p][3]);
-    part[p][4] = fma(w.z, u[p][1].x, part[p][4]);
-    part[p][5] = fma(w.z, u[p][1].y, part[p][5]);
-    part[p][6] = fma(w.y, u[p][0].x, part[p][6]);
-    part[p][7] = fma(w.y, u[p][0].y, part[p][7]);
-    part[p][8] = fma(w.w, u[p][2].x, part[p][8]);
-    part[p][9] = fma(w.w, u[p][2].y, part[p][9]);
-  }
-}
-
-// Work-item split of the history sums.  Item (b, c) = block b of 64 modes and
-// chunk c of its lags; one wavefront per item streams the chunk's history
-// records and kernel rows and writes its ten partial sums per plane:
-//   partial[(c * NP * 10 + k) * M + s],  k = plane * 10 + sum index.
-// Items are small and uniform, so the dispatch has no long tail.
-template <typename R, int NP, bool COMP>
-__global__ __launch_bounds__(kLanes) void conv_stream_kernel(
-    const cplx<R> *__restrict__ ring, const typename W4<R>::T *__restrict__ table,
-    R *__restrict__ partial, const int *__restrict__ cls, const int *__restrict__ win,
-    const long long *__restrict__ blk_off, const int *__restrict__ blk_cap,
-    const int *__restrict__ blk_stride, const long long *__restrict__ lag_off, long long M,
-    long long step, int chunks, int nblocks) {
-  constexpr int U = conv_unroll<R, COMP>();
-  // chunk-major item order: the waves in flight at any time work on the same
-  // lag range of consecutive blocks, whose records are adjacent in memory
-  const int ch = blockIdx.x / nblocks;
-  const int b = blockIdx.x - ch * nblocks;
-  const int lane = threadIdx.x;
-  const long long s = static_cast<long long>(b) * kLanes + lane;
-  const bool valid = s < M;
-  const int cap = blk_cap[b];
-  const long long navail = step + 1;
-  const int lblk = static_cast<int>(min(static_cast<long long>(cap), navail));
-  const int wl = valid ? win[s] : 0;
-  const int llane = static_cast<int>(min(static_cast<long long>(wl), navail));
-  const int cl = valid ? cls[s] : 0;
-  const int per = (lblk + chunks - 1) / chunks;
-  const int j0 = min(lblk, ch * per);
-  const int j1 = min(lblk, j0 + per);
-  const long long base = cap > 0 ? blk_off[b] : 0;
-  const long long stride = blk_stride[b];
-
-  Acc<R, COMP> acc[NP][kSums];
-  if (j0 < j1) {
-    int rec = static_cast<int>((step - j0) % cap);  // ring slot of lag j0
-    int j = j0;
-    if (cap >= U) {
-      for (; j + U <= j1; j += U) {
-        typename W4<R>::T w[U];
-        cplx<R> u[U][NP][3];
-#pragma unroll
-        for (int t = 0; t < U; ++t) {
-          const int rr = rec - t < 0 ? rec - t + cap : rec - t;
-          load_lag<R, NP>(ring, table, lag_off, base + rr * stride, lane, j + t, llane, cl, w[t],
-                          u[t]);
-        }
-        if constexpr (COMP) {
-          R part[NP][kSums];
-#pragma unroll
-          for (int p = 0; p < NP; ++p)
-#pragma unroll
-            for (int k = 0; k < kSums; ++k) part[p][k] = R(0);
-#pragma unroll
-          for (int t = 0; t < U; ++t) fma_lag<R, NP>(part, w[t], u[t]);
-#pragma unroll
-          for (int p = 0; p < NP; ++p)
-#pragma unroll
-            for (int k = 0; k < kSums; ++k) acc[p][k].fold(part[p][k]);
-        } else {
-          R sums[NP][kSums];
-#pragma unroll
-          for (int p = 0; p < NP; ++p)
-#pragma unroll
-            for (int k = 0; k < kSums; ++k) sums[p][k] = acc[p][k].s;
-#pragma unroll
-          for (int t = 0; t < U; ++t) fma_lag<R, NP>(sums, w[t], u[t]);
-#pragma unroll
-          for (int p = 0; p < NP; ++p)
-#pragma unroll
-            for (int k = 0; k < kSums; ++k) acc[p][k].s = sums[p][k];
-        }
-        rec -= U;
-        if (rec < 0) rec += cap;
+      for (int c = 0; c < 3; ++c) {
+        const nv2 v = __builtin_nontemporal_load(reinterpret_cast<const nv2 *>(hp + c * kLanes));
+        u[t][c] = cplx<R>{v.x, v.y};
       }
+      const bool wrap = x == 0;  // next older slot
+      hp += wrap ? dwrap - dstep : -dstep;
+      x = wrap ? cap - 1 : x - 1;
     }
-    for (; j < j1; ++j) {  // remaining lags one at a time
-      typename W4<R>::T w;
-      cplx<R> u[NP][3];
-      load_lag<R, NP>(ring, table, lag_off, base + rec * stride, lane, j, llane, cl, w, u);
-      R part[NP][kSums];
+    if constexpr (COMP) {
+      R part[S][kSums];
 #pragma unroll
-      for (int p = 0; p < NP; ++p)
+      for (int s = 0; s < S; ++s)
 #pragma unroll
-        for (int k = 0; k < kSums; ++k) part[p][k] = COMP ? R(0) : acc[p][k].s;
-      fma_lag<R, NP>(part, w, u);
+        for (int k = 0; k < kSums; ++k) part[s][k] = R(0);
 #pragma unroll
-      for (int p = 0; p < NP; ++p)
+      for (int t = 0; t < G; ++t)
 #pragma unroll
-        for (int k = 0; k < kSums; ++k) {
-          if constexpr (COMP)
-            acc[p][k].fold(part[p][k]);
-          else
-            acc[p][k].s = part[p][k];
+        for (int s = 0; s < S; ++s) {
+          const int k = g0 + t + s;
+          fma_lag<R>(part[s], k < S ? A[k] : B[k - S], u[t]);
         }
-      rec = rec == 0 ? cap - 1 : rec - 1;
+#pragma unroll
+      for (int s = 0; s < S; ++s)
+#pragma unroll
+        for (int k = 0; k < kSums; ++k) acc[s][k].fold(part[s][k]);
+    } else {
+      R sums[S][kSums];
+#pragma unroll
+      for (int s = 0; s < S; ++s)
+#pragma unroll
+        for (int k = 0; k < kSums; ++k) sums[s][k] = acc[s][k].s;
+#pragma unroll
+      for (int t = 0; t < G; ++t)
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+          const int k = g0 + t + s;
+          fma_lag<R>(sums[s], k < S ? A[k] : B[k - S], u[t]);
+        }
+#pragma unroll
+      for (int s = 0; s < S; ++s)
+#pragma unroll
+        for (int k = 0; k < kSums; ++k) acc[s][k].s = sums[s][k];
     }
   }
-  if (!valid) return;
-#pragma unroll
-  for (int p = 0; p < NP; ++p)
-#pragma unroll
-    for (int k = 0; k < kSums; ++k)
-      __builtin_nontemporal_store(  // read once, by the epilogue
-          acc[p][k].value(),
-          partial + (static_cast<long long>(ch) * NP * kSums + p * kSums + k) * M + s);
 }
 
-// Per mode: fold the chunk partials in chunk order (compensated for the
-// compensated form), add damping and instantaneous terms, rotate back to
-// (x1, x2, x3) and scatter into the natural half-spectrum layout.
-template <typename R, int NP, bool COMP>
+// The sweep of one step n.  Blocks of phase n mod S read their whole history
+// once, U^{n-i} for i = 0 .. min(cap, n+1)-1, and form for each coming step
+// n+s (s = 0 .. S-1) its sum over that history:
+//   pending[(n+s) mod S] = sum_{i} w_{i+s} (x) U^{n-i}   (lags i+s inside the window).
+// Each history entry thus serves S steps.  The kernel rows i .. i+2S-2 that a
+// span of S entries needs are held in two register arrays used in turn, so
+// each row is loaded once and never moved.
+//
+// Lag chunks are whole spans long, so chunks never overlap and no lane needs a
+// mask: chunks reach past min(cap, n+1) by less than 4 spans, and a lag
+// i >= min(cap, n+1) either meets zero kernel rows (i + s >= cap >= W) or a
+// ring slot not written since the last reset, which holds zero.
+//
+// Work item (one wavefront) = (block of the phase, plane, quarter of the
+// block's 64 modes).  Its 64 lanes are 16 modes x 4 lag chunks: lane l takes
+// mode l mod 16 of the quarter and chunk l / 16 of the lags, so each history
+// load fetches four 128-byte segments, one per chunk.  The chunks are then
+// summed by a butterfly over lanes l ^ 16, l ^ 32 (fixed order, so the result
+// is bitwise reproducible).
+template <typename R, int S, bool COMP>
+__global__ __launch_bounds__(kLanes) void sweep_kernel(
+    const cplx<R> *__restrict__ ring, const typename W4<R>::T *__restrict__ table,
+    R *__restrict__ pending, const int *__restrict__ cls, const int *__restrict__ win,
+    const long long *__restrict__ blk_off, const int *__restrict__ blk_cap,
+    const int *__restrict__ blk_stride, const long long *__restrict__ cls_off, int cls_w0,
+    long long M, long long step, int np, long long nphase) {
+  using W = typename W4<R>::T;
+  constexpr int Q = kLanes / kLagGroups;  // modes per item
+  // Items of one block get ids congruent mod 8, so they run on one XCD and
+  // share the block's kernel rows in its L2.
+  const int per_blk = kLagGroups * np;
+  const long long item = blockIdx.x;
+  const long long kb = (item / (8LL * per_blk)) * 8 + (item & 7);
+  if (kb >= nphase) return;
+  const int r = static_cast<int>((item >> 3) % per_blk);
+  const int p = r / kLagGroups;
+  const long long b = step % S + S * kb;
+  const int lane = threadIdx.x;
+  const int lg = lane / Q;
+  const int col = (r % kLagGroups) * Q + lane % Q;  // lane of the mode in its block
+  const long long sm = b * kLanes + col;
+  const bool valid = sm < M;
+  const int cap = blk_cap[b];
+  const int imax = static_cast<int>(min(static_cast<long long>(cap), step + 1));
+  const int wl = valid ? win[sm] : 0;
+  const int cl = valid ? cls[sm] : 0;
+  const int per = (imax + kLagGroups * S - 1) / (kLagGroups * S) * S;  // lags per chunk
+  const int i0 = lg * per;
+
+  Acc<R, COMP> acc[S][kSums];
+  if (per > 0) {  // then cap > 0, so the block has a mode with W > 0 and class 0 exists
+    const long long rec_len = static_cast<long long>(np) * 3 * kLanes;
+    const long long dstep = blk_stride[b] * rec_len;  // elements between consecutive slots
+    const long long dwrap = static_cast<long long>(cap) * dstep;
+    // ring slot of lag i0 (i0 may pass step)
+    int x = static_cast<int>((((step - i0) % cap) + cap) % cap);
+    const cplx<R> *hp = ring + (blk_off[b] + static_cast<long long>(x) * blk_stride[b]) * rec_len +
+                        static_cast<long long>(p) * 3 * kLanes + col;
+    // a mode without history (W = 0) reads the zero row after class 0's rows
+    const W *rowp = wl > 0 ? table + cls_off[cl] : table + cls_off[0] + cls_w0;
+    W ra[S], rb[S];
+    load_rows<R, S>(ra, rowp, i0, wl);
+    for (int it = 0; it < per; it += 2 * S) {
+      const int i = i0 + it;
+      load_rows<R, S>(rb, rowp, i + S, wl);
+      sweep_span<R, S, COMP>(acc, ra, rb, hp, x, cap, dstep, dwrap);
+      if (it + S >= per) break;
+      load_rows<R, S>(ra, rowp, i + 2 * S, wl);
+      sweep_span<R, S, COMP>(acc, rb, ra, hp, x, cap, dstep, dwrap);
+    }
+  }
+  // sum the four lag chunks of each mode; lanes of chunk 0 store
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    const long long slot = (step + s) % S;
+#pragma unroll
+    for (int k = 0; k < kSums; ++k) {
+      acc[s][k].fold_lane(Q);
+      acc[s][k].fold_lane(2 * Q);
+      if (lg == 0 && valid)
+        pending[((slot * np + p) * kSums + k) * M + sm] = acc[s][k].value();
+    }
+  }
+}
+
+// Per (mode, plane): the pending sum of this step plus the lags newer than the
+// block's last sweep (compensated for the compensated form), damping and
+// instantaneous terms, rotation back to (x1, x2, x3), scatter into the natural
+// half-spectrum layout.
+template <typename R, bool COMP>
 __global__ __launch_bounds__(256) void conv_epilogue_kernel(
-    const R *__restrict__ partial, const cplx<R> *__restrict__ ring,
-    const cplx<R> *__restrict__ vel, double2 *__restrict__ lam, cplx<R> *__restrict__ out_a,
-    cplx<R> *__restrict__ out_b, const int *__restrict__ nat, const int *__restrict__ win,
-    const double *__restrict__ geom, const long long *__restrict__ blk_off,
-    const int *__restrict__ blk_cap, const int *__restrict__ blk_stride, long long M, long long nh,
-    long long step, int chunks, PlaneParams p0, PlaneParams p1) {
+    const R *__restrict__ pending, const cplx<R> *__restrict__ ring,
+    const typename W4<R>::T *__restrict__ table, const long long *__restrict__ cls_off,
+    const int *__restrict__ cls, const cplx<R> *__restrict__ vel, double2 *__restrict__ lam,
+    cplx<R> *__restrict__ out_a, cplx<R> *__restrict__ out_b, const int *__restrict__ nat,
+    const int *__restrict__ win, const double *__restrict__ geom,
+    const long long *__restrict__ blk_off, const int *__restrict__ blk_cap,
+    const int *__restrict__ blk_stride, long long M, long long nh, long long step, int np,
+    int depth, PlaneParams p0, PlaneParams p1) {
   // one thread per (mode, plane); consecutive threads take consecutive modes
   const long long t = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (t >= M * NP) return;
+  if (t >= M * np) return;
   const int p = static_cast<int>(t / M);
   const long long s = t - p * M;
   const long long b = s >> 6;
   const int lane = static_cast<int>(s & 63);
   const int cap = blk_cap[b];
   const int wl = win[s];
+  const int cl = cls[s];
   const double q = geom[4 * s + 0];
   const R kh1 = static_cast<R>(geom[4 * s + 1]);
   const R kh3 = static_cast<R>(geom[4 * s + 2]);
   const long long natural = nat[s];
-  const long long rec0 = cap > 0 ? blk_off[b] + (step % cap) * blk_stride[b] : 0;
-  // fold the chunk partials in chunk order (ten sums of a chunk loaded together)
+  const long long rec_len = static_cast<long long>(np) * 3 * kLanes;
+  const cplx<R> *rp = ring + static_cast<long long>(p) * 3 * kLanes + lane;
+  const long long base = blk_off[b];
+  const long long stride = blk_stride[b];
+  const int sl = static_cast<int>(step % depth);
+  const int phi = static_cast<int>(b % depth);
+  // lags not in the pending sum: those newer than the block's last sweep, or
+  // all of them before its first sweep (step < phi < depth)
+  const bool swept = step >= phi;
+  const int fresh = min(wl, swept ? (sl - phi + depth) % depth : static_cast<int>(step) + 1);
+  const int x0 = cap > 0 ? static_cast<int>(step % cap) : 0;
   R cs[kSums];
   {
     Acc<R, COMP> a[kSums];
-#pragma unroll 4
-    for (int c = 0; c < chunks; ++c) {
-      const R *pc = partial + (static_cast<long long>(c) * NP + p) * kSums * M + s;
-      R v[kSums];
+    if (swept) {
 #pragma unroll
-      for (int k = 0; k < kSums; ++k) v[k] = pc[k * M];
+      for (int k = 0; k < kSums; ++k) a[k].s = pending[((sl * np + p) * kSums + k) * M + s];
+    }
+    for (int j = 0; j < fresh; ++j) {
+      int x = x0 - j;
+      if (x < 0) x += cap;
+      const cplx<R> *qp = rp + (base + static_cast<long long>(x) * stride) * rec_len;
+      const cplx<R> u[3] = {qp[0], qp[kLanes], qp[2 * kLanes]};
+      const typename W4<R>::T w = table[cls_off[cl] + j];
+      R part[kSums];
 #pragma unroll
-      for (int k = 0; k < kSums; ++k) a[k].fold(v[k]);
+      for (int k = 0; k < kSums; ++k) part[k] = COMP ? R(0) : a[k].s;
+      fma_lag<R>(part, w, u);
+#pragma unroll
+      for (int k = 0; k < kSums; ++k) {
+        if constexpr (COMP)
+          a[k].fold(part[k]);
+        else
+          a[k].s = part[k];
+      }
     }
 #pragma unroll
     for (int k = 0; k < kSums; ++k) cs[k] = a[k].value();
@@ -342,10 +397,10 @@ __global__ __launch_bounds__(256) void conv_epilogue_kernel(
     const R eta = static_cast<R>(pp.eta);
     cplx<R> u[3] = {{R(0), R(0)}, {R(0), R(0)}, {R(0), R(0)}};
     if (cap > 0 && wl > 0) {
-      const cplx<R> *r = ring + (rec0 * NP + p) * 3 * kLanes + lane;
-      u[0] = r[0];
-      u[1] = r[kLanes];
-      u[2] = r[2 * kLanes];
+      const cplx<R> *qp = rp + (base + static_cast<long long>(x0) * stride) * rec_len;
+      u[0] = qp[0];
+      u[1] = qp[kLanes];
+      u[2] = qp[2 * kLanes];
     }
     cplx<R> v[3];
 #pragma unroll
@@ -459,7 +514,7 @@ __device__ Node make_node(int i, int npan, double eta, double dT, const double *
 // accurate to ~1e-16 absolute however many periods it spans.
 template <typename R>
 __global__ __launch_bounds__(256) void tabulate_kernel(
-    typename W4<R>::T *__restrict__ table, const long long *__restrict__ lag_off,
+    typename W4<R>::T *__restrict__ table, const long long *__restrict__ cls_off,
     const double *__restrict__ cls_q, const int *__restrict__ cls_w, double cs, double dt,
     double eta, double rate, const double *__restrict__ gl_x, const double *__restrict__ gl_w) {
   __shared__ Node nodes[256];
@@ -473,7 +528,7 @@ __global__ __launch_bounds__(256) void tabulate_kernel(
   const double two_pi_hi = 6.283185307179586;      // nearest double to 2 pi
   const double two_pi_lo = 2.4492935982947064e-16;  // 2 pi - two_pi_hi
   const double inv_two_pi = 0.15915494309189535;
-  for (int jb = 0; jb < W; jb += 256) {
+  for (int jb = 0; jb <= W; jb += 256) {  // j = W: the zero row
     const int j = jb + threadIdx.x;
     const double m = j + 0.5;
     double w11 = 0, w12 = 0, w22 = 0, w33 = 0;
@@ -506,41 +561,54 @@ __global__ __launch_bounds__(256) void tabulate_kernel(
       o.y = static_cast<R>(w12);
       o.z = static_cast<R>(w22);
       o.w = static_cast<R>(w33);
-      table[lag_off[j] + c] = o;
+      table[cls_off[c] + j] = o;
     }
+    if (j == W) table[cls_off[c] + W] = typename W4<R>::T{R(0), R(0), R(0), R(0)};
   }
 }
 
-template <typename R, int NP, bool COMP>
-hipError_t conv_launch_np(const sbim_handle *h, const Group &g, const ConvLaunch &a,
+template <typename R, int S, bool COMP>
+hipError_t sweep_launch_s(const sbim_handle *h, const Group &g, const SweepLaunch &a,
                           hipEvent_t ev0, hipEvent_t ev1) {
-  const PlaneParams p1 = g.np > 1 ? g.pl[1] : g.pl[0];
-  const int chunks = h->lag_split;
-  const long long items = g.nblocks * chunks;
+  const int phase = static_cast<int>(a.step % S);
+  const long long nphase = g.nblocks > phase ? (g.nblocks - phase + S - 1) / S : 0;
+  const long long items = (nphase + 7) / 8 * 8 * kLagGroups * g.np;
   if (ev0) (void)hipEventRecord(ev0, h->stream);
-  hipLaunchKernelGGL((conv_stream_kernel<R, NP, COMP>), dim3(static_cast<unsigned>(items)),
-                     dim3(kLanes), 0, h->stream, static_cast<const cplx<R> *>(a.ring),
-                     static_cast<const typename W4<R>::T *>(g.table), static_cast<R *>(g.partial),
-                     g.cls, g.win, g.blk_off, g.blk_cap, g.blk_stride, g.lag_off, g.M, a.step,
-                     chunks, static_cast<int>(g.nblocks));
+  if (items > 0)
+    hipLaunchKernelGGL((sweep_kernel<R, S, COMP>), dim3(static_cast<unsigned>(items)), dim3(kLanes),
+                       0, h->stream, static_cast<const cplx<R> *>(a.ring),
+                       static_cast<const typename W4<R>::T *>(g.table),
+                       static_cast<R *>(a.pending), g.cls, g.win, g.blk_off, g.blk_cap,
+                       g.blk_stride, g.cls_off, g.wmax, g.M, a.step, g.np, nphase);
   if (ev1) (void)hipEventRecord(ev1, h->stream);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((conv_epilogue_kernel<R, NP, COMP>),
-                     dim3(static_cast<unsigned>((g.M * NP + 255) / 256)),
-                     dim3(256), 0, h->stream, static_cast<const R *>(g.partial),
-                     static_cast<const cplx<R> *>(a.ring), static_cast<const cplx<R> *>(a.vel),
-                     reinterpret_cast<double2 *>(a.lam), static_cast<cplx<R> *>(a.out_a),
-                     static_cast<cplx<R> *>(a.out_b), g.nat, g.win, g.geom, g.blk_off, g.blk_cap,
-                     g.blk_stride, g.M, a.nh, a.step, chunks, g.pl[0], p1);
   return hipGetLastError();
 }
 
 template <typename R, bool COMP>
-hipError_t conv_launch_r(const sbim_handle *h, const Group &g, const ConvLaunch &a,
-                         hipEvent_t ev0, hipEvent_t ev1) {
-  return g.np == 2 ? conv_launch_np<R, 2, COMP>(h, g, a, ev0, ev1)
-                   : conv_launch_np<R, 1, COMP>(h, g, a, ev0, ev1);
+hipError_t sweep_launch_r(const sbim_handle *h, const Group &g, const SweepLaunch &a,
+                          hipEvent_t ev0, hipEvent_t ev1) {
+  switch (h->depth) {
+    case 1: return sweep_launch_s<R, 1, COMP>(h, g, a, ev0, ev1);
+    case 2: return sweep_launch_s<R, 2, COMP>(h, g, a, ev0, ev1);
+    case 4: return sweep_launch_s<R, 4, COMP>(h, g, a, ev0, ev1);
+    case 8: return sweep_launch_s<R, 8, COMP>(h, g, a, ev0, ev1);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <typename R, bool COMP>
+hipError_t conv_launch_r(const sbim_handle *h, const Group &g, const ConvLaunch &a) {
+  const PlaneParams p1 = g.np > 1 ? g.pl[1] : g.pl[0];
+  hipLaunchKernelGGL((conv_epilogue_kernel<R, COMP>),
+                     dim3(static_cast<unsigned>((g.M * g.np + 255) / 256)), dim3(256), 0,
+                     h->stream, static_cast<const R *>(a.pending),
+                     static_cast<const cplx<R> *>(a.ring),
+                     static_cast<const typename W4<R>::T *>(g.table), g.cls_off, g.cls,
+                     static_cast<const cplx<R> *>(a.vel), reinterpret_cast<double2 *>(a.lam),
+                     static_cast<cplx<R> *>(a.out_a), static_cast<cplx<R> *>(a.out_b), g.nat,
+                     g.win, g.geom, g.blk_off, g.blk_cap, g.blk_stride, g.M, a.nh, a.step, g.np,
+                     h->depth, g.pl[0], p1);
+  return hipGetLastError();
 }
 
 }  // namespace
@@ -565,11 +633,17 @@ hipError_t launch_push(const sbim_handle *h, const Group &g, const PushLaunch &a
   return hipGetLastError();
 }
 
-hipError_t launch_conv(const sbim_handle *h, const Group &g, const ConvLaunch &a, hipEvent_t ev0,
-                       hipEvent_t ev1) {
-  if (h->fp64) return conv_launch_r<double, false>(h, g, a, ev0, ev1);
-  if (h->comp) return conv_launch_r<float, true>(h, g, a, ev0, ev1);
-  return conv_launch_r<float, false>(h, g, a, ev0, ev1);
+hipError_t launch_sweep(const sbim_handle *h, const Group &g, const SweepLaunch &a,
+                        hipEvent_t ev0, hipEvent_t ev1) {
+  if (h->fp64) return sweep_launch_r<double, false>(h, g, a, ev0, ev1);
+  if (h->comp) return sweep_launch_r<float, true>(h, g, a, ev0, ev1);
+  return sweep_launch_r<float, false>(h, g, a, ev0, ev1);
+}
+
+hipError_t launch_conv(const sbim_handle *h, const Group &g, const ConvLaunch &a) {
+  if (h->fp64) return conv_launch_r<double, false>(h, g, a);
+  if (h->comp) return conv_launch_r<float, true>(h, g, a);
+  return conv_launch_r<float, false>(h, g, a);
 }
 
 hipError_t launch_tabulate(bool fp64, const Group &g, double dt, const double *gl_x,
@@ -578,11 +652,11 @@ hipError_t launch_tabulate(bool fp64, const Group &g, double dt, const double *g
   const double rate = fmax(1.0, (g.eta * g.eta - 1.0) / 2.0);
   if (fp64) {
     hipLaunchKernelGGL(tabulate_kernel<double>, dim3(static_cast<unsigned>(g.nclasses)), dim3(256),
-                       0, st, static_cast<double4 *>(g.table), g.lag_off, g.cls_q, g.cls_w, g.cs, dt,
+                       0, st, static_cast<double4 *>(g.table), g.cls_off, g.cls_q, g.cls_w, g.cs, dt,
                        g.eta, rate, gl_x, gl_w);
   } else {
     hipLaunchKernelGGL(tabulate_kernel<float>, dim3(static_cast<unsigned>(g.nclasses)), dim3(256),
-                       0, st, static_cast<float4 *>(g.table), g.lag_off, g.cls_q, g.cls_w, g.cs, dt,
+                       0, st, static_cast<float4 *>(g.table), g.cls_off, g.cls_q, g.cls_w, g.cs, dt,
                        g.eta, rate, gl_x, gl_w);
   }
   return hipGetLastError();

@@ -96,9 +96,9 @@ hipError_t dev_alloc_bytes(void **p, size_t bytes) {
 }
 
 void free_group(Group &g) {
-  void *ptrs[] = {g.nat,   g.cls,   g.win,   g.geom,      g.blk_off,   g.blk_cap, g.blk_stride, g.lag_off,
-                  g.cls_q, g.cls_w, g.table, g.ring,      g.state,     g.vel,     g.partial,
-                  g.ring_adj, g.state_adj, g.lam_adj, g.vel_adj};
+  void *ptrs[] = {g.nat,   g.cls,   g.win,   g.geom,      g.blk_off,   g.blk_cap, g.blk_stride, g.cls_off,
+                  g.cls_q, g.cls_w, g.table, g.ring,      g.state,     g.vel,     g.pending,
+                  g.ring_adj, g.state_adj, g.lam_adj, g.vel_adj, g.pending_adj};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   g = Group();
@@ -127,8 +127,8 @@ long long vel_bytes(const sbim_handle *h, const Group &g) {
   return g.np * 3LL * g.M * 2 * static_cast<long long>(h->rsize);
 }
 long long state_bytes_g(const Group &g) { return g.np * 3LL * g.M * 16; }
-long long partial_bytes(const sbim_handle *h, const Group &g) {
-  return static_cast<long long>(h->lag_split) * g.np * 10LL * g.M * static_cast<long long>(h->rsize);
+long long pending_bytes(const sbim_handle *h, const Group &g) {
+  return static_cast<long long>(h->depth) * g.np * 10LL * g.M * static_cast<long long>(h->rsize);
 }
 
 int validate(const sbim_config *c) {
@@ -165,7 +165,7 @@ int validate(const sbim_config *c) {
 }
 
 // Mode geometry, windows, ordering and classes of one material group (host).
-void plan_group(const sbim_config &c, Group &g, std::vector<double> &geom,
+void plan_group(const sbim_config &c, int depth, Group &g, std::vector<double> &geom,
                 std::vector<long long> &blk_off, std::vector<int> &blk_cap,
                 std::vector<int> &blk_stride, std::vector<double> &cls_q) {
   const int n1 = c.n1, h3 = c.n3 / 2 + 1;
@@ -231,27 +231,33 @@ void plan_group(const sbim_config &c, Group &g, std::vector<double> &geom,
   blk_stride.resize(g.nblocks);
   for (long long b = 0; b < g.nblocks; ++b)
     blk_cap[b] = g.h_win[b * sbim::kLanes];  // sorted by W desc: first lane has the block maximum
-  // runs of consecutive blocks with equal capacity are stored slot-major
+  g.h_blk_cap = blk_cap;
+  // Blocks of one sweep phase (b mod depth) are stored together; within a
+  // phase, runs of consecutive blocks with equal capacity are stored slot-major.
   long long rec = 0;
-  for (long long b0 = 0; b0 < g.nblocks;) {
-    long long b1 = b0;
-    while (b1 < g.nblocks && blk_cap[b1] == blk_cap[b0]) ++b1;
-    for (long long b = b0; b < b1; ++b) {
-      blk_off[b] = rec + (b - b0);
-      blk_stride[b] = static_cast<int>(b1 - b0);
+  for (int ph = 0; ph < depth; ++ph) {
+    for (long long b0 = ph; b0 < g.nblocks;) {
+      long long b1 = b0, len = 0;
+      while (b1 < g.nblocks && blk_cap[b1] == blk_cap[b0]) {
+        b1 += depth;
+        ++len;
+      }
+      for (long long b = b0, i = 0; b < b1; b += depth, ++i) {
+        blk_off[b] = rec + i;
+        blk_stride[b] = static_cast<int>(len);
+      }
+      rec += static_cast<long long>(blk_cap[b0]) * len;
+      b0 = b1;
     }
-    rec += static_cast<long long>(blk_cap[b0]) * (b1 - b0);
-    b0 = b1;
   }
   g.ring_records = rec;
-  // lag-major table rows: classes alive at lag j form the prefix {c : W_c > j}
-  g.h_lag_off.assign(g.wmax, 0);
+  // class-major table: the W_c rows of class c start at entry cls_off[c] and
+  // are followed by one zero row
+  g.h_cls_off.assign(g.nclasses, 0);
   long long off = 0;
-  long long alive = g.nclasses;
-  for (int j = 0; j < g.wmax; ++j) {
-    while (alive > 0 && g.h_cls_w[alive - 1] <= j) --alive;
-    g.h_lag_off[j] = off;
-    off += alive;
+  for (long long c = 0; c < g.nclasses; ++c) {
+    g.h_cls_off[c] = off;
+    off += g.h_cls_w[c] + 1;
   }
   g.table_rows = off;
 }
@@ -287,10 +293,13 @@ int ensure_adjoint(sbim_handle *h) {
     const size_t sb = static_cast<size_t>(state_bytes_g(g));
     const size_t vb = static_cast<size_t>(vel_bytes(h, g));
     size_t free_b = 0, total_b = 0;
-    if (hipMemGetInfo(&free_b, &total_b) == hipSuccess && rb + 2 * sb + vb > free_b)
-      return fail(h, SBIM_E_OOM, "adjoint buffers need %zu bytes, %zu free", rb + 2 * sb + vb, free_b);
+    const size_t need = rb + 2 * sb + vb + static_cast<size_t>(pending_bytes(h, g));
+    if (hipMemGetInfo(&free_b, &total_b) == hipSuccess && need > free_b)
+      return fail(h, SBIM_E_OOM, "adjoint buffers need %zu bytes, %zu free", need, free_b);
     hipError_t e;
+    const size_t pb = static_cast<size_t>(pending_bytes(h, g));
     if ((e = dev_alloc_bytes(&g.ring_adj, rb)) != hipSuccess ||
+        (e = dev_alloc_bytes(&g.pending_adj, pb)) != hipSuccess ||
         (e = dev_alloc(&g.state_adj, sb / 8)) != hipSuccess ||
         (e = dev_alloc(&g.lam_adj, sb / 8)) != hipSuccess ||
         (e = dev_alloc_bytes(&g.vel_adj, vb)) != hipSuccess) {
@@ -301,6 +310,35 @@ int ensure_adjoint(sbim_handle *h) {
     (void)hipMemsetAsync(g.lam_adj, 0, sb, h->stream);
     (void)hipMemsetAsync(g.vel_adj, 0, vb, h->stream);
   }
+  return SBIM_OK;
+}
+
+// The history sweep of step `step` for one group; bracketed by a pair of the
+// handle's reusable events while sbim_profile_conv is on.
+int sweep_group(sbim_handle *h, Group &g, const void *ring, void *pending, long long step,
+                bool timed) {
+  sbim::SweepLaunch a;
+  a.ring = ring;
+  a.pending = pending;
+  a.step = step;
+  hipError_t e;
+  if (timed && h->profile) {
+    if (h->ev_used == h->ev_start.size()) {  // grow the reusable event pool
+      hipEvent_t e0, e1;
+      if ((e = hipEventCreate(&e0)) != hipSuccess) return hip_fail(h, e, "hipEventCreate");
+      if ((e = hipEventCreate(&e1)) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return hip_fail(h, e, "hipEventCreate");
+      }
+      h->ev_start.push_back(e0);
+      h->ev_stop.push_back(e1);
+    }
+    e = sbim::launch_sweep(h, g, a, h->ev_start[h->ev_used], h->ev_stop[h->ev_used]);
+    ++h->ev_used;
+  } else {
+    e = sbim::launch_sweep(h, g, a);
+  }
+  if (e != hipSuccess) return hip_fail(h, e, "history sweep kernel");
   return SBIM_OK;
 }
 
@@ -351,16 +389,24 @@ int sbim_init(const sbim_config *cfg, sbim_handle **out) {
     std::vector<long long> blk_off;
     std::vector<int> blk_cap, blk_stride;
   };
+  // Sweep depth: steps served by one pass over a block's history.  Deeper
+  // sweeps divide the history traffic but hold depth x 10 sums per lane in
+  // registers; these depths keep float32 at three and float64 / compensated
+  // sums at two wavefronts per SIMD.
+  h->depth = h->fp64 ? 4 : (h->comp ? 4 : 8);
+  if (const char *env = std::getenv("SBIM_SWEEP_DEPTH")) {  // tuning override: 1, 2, 4 or 8
+    const int v = std::atoi(env);
+    if (v == 1 || v == 2 || v == 4 || v == 8) h->depth = v;
+  }
   std::vector<HostPlan> plan(h->ngroups);
   size_t need = 0;
-  long long total_blocks = 0;
   for (int i = 0; i < h->ngroups; ++i) {
     Group &g = h->g[i];
-    plan_group(*cfg, g, plan[i].geom, plan[i].blk_off, plan[i].blk_cap, plan[i].blk_stride,
-               plan[i].cls_q);
+    plan_group(*cfg, h->depth, g, plan[i].geom, plan[i].blk_off, plan[i].blk_cap,
+               plan[i].blk_stride, plan[i].cls_q);
     need += ring_bytes(h, g) + table_bytes(h, g) + state_bytes_g(g) + vel_bytes(h, g);
-    need += g.M * (4 * 3 + 32) + g.nblocks * 16 + g.wmax * 8 + g.nclasses * 12;
-    total_blocks += g.nblocks;
+    need += pending_bytes(h, g);
+    need += g.M * (4 * 3 + 32) + g.nblocks * 16 + g.nclasses * 20;
   }
   // input spectra are float64 in every form; the traction spectrum is real_t
   const size_t spec_bytes = static_cast<size_t>(cfg->nplanes) * 3 * h->nh * 2 * sizeof(double);
@@ -377,26 +423,6 @@ int sbim_init(const sbim_config *cfg, sbim_handle **out) {
     return fail(nullptr, SBIM_E_OOM, "needs %zu bytes of device memory, %zu free", need, free_b);
   }
 
-  // lag chunks per block: about kTargetItems uniform work items for the history
-  // stream, none shorter than kMinChunkLags lags
-  int wmax_all = 0;
-  for (int i = 0; i < h->ngroups; ++i) wmax_all = std::max(wmax_all, h->g[i].wmax);
-  long long split = (sbim::kTargetItems + total_blocks - 1) / std::max(1LL, total_blocks);
-  split = std::min<long long>(split, std::max(1, wmax_all / sbim::kMinChunkLags));
-  split = std::max(1LL, std::min<long long>(split, sbim::kMaxChunks));
-  if (const char *env = std::getenv("SBIM_LAG_SPLIT")) {  // tuning override in [1, kMaxChunks]
-    const int v = std::atoi(env);
-    if (v >= 1 && v <= sbim::kMaxChunks) split = v;
-  }
-  h->lag_split = static_cast<int>(split);
-  size_t need_partial = 0;
-  for (int i = 0; i < h->ngroups; ++i)
-    need_partial += static_cast<size_t>(partial_bytes(h, h->g[i]));
-  if (need + need_partial > free_b) {
-    free_handle(h);
-    return fail(nullptr, SBIM_E_OOM, "needs %zu bytes of device memory, %zu free",
-                need + need_partial, free_b);
-  }
 
   std::vector<double> glx, glw;
   gauss_legendre(sbim::kGaussN, glx, glw);
@@ -439,14 +465,14 @@ int sbim_init(const sbim_config *cfg, sbim_handle **out) {
     TRY(dev_alloc(&g.blk_off, g.nblocks));
     TRY(dev_alloc(&g.blk_cap, g.nblocks));
     TRY(dev_alloc(&g.blk_stride, g.nblocks));
-    TRY(dev_alloc(&g.lag_off, g.wmax));
+    TRY(dev_alloc(&g.cls_off, g.nclasses));
     TRY(dev_alloc(&g.cls_q, g.nclasses));
     TRY(dev_alloc(&g.cls_w, g.nclasses));
     TRY(dev_alloc_bytes(&g.table, table_bytes(h, g)));
     TRY(dev_alloc_bytes(&g.ring, ring_bytes(h, g)));
     TRY(dev_alloc(&g.state, state_bytes_g(g) / 8));
     TRY(dev_alloc_bytes(&g.vel, vel_bytes(h, g)));
-    TRY(dev_alloc_bytes(&g.partial, partial_bytes(h, g)));
+    TRY(dev_alloc_bytes(&g.pending, pending_bytes(h, g)));
     TRY(upload(g.nat, g.h_nat.data(), g.M * sizeof(int), h->stream));
     TRY(upload(g.cls, g.h_cls.data(), g.M * sizeof(int), h->stream));
     TRY(upload(g.win, g.h_win.data(), g.M * sizeof(int), h->stream));
@@ -454,12 +480,13 @@ int sbim_init(const sbim_config *cfg, sbim_handle **out) {
     TRY(upload(g.blk_off, hp.blk_off.data(), hp.blk_off.size() * sizeof(long long), h->stream));
     TRY(upload(g.blk_cap, hp.blk_cap.data(), hp.blk_cap.size() * sizeof(int), h->stream));
     TRY(upload(g.blk_stride, hp.blk_stride.data(), hp.blk_stride.size() * sizeof(int), h->stream));
-    TRY(upload(g.lag_off, g.h_lag_off.data(), g.h_lag_off.size() * sizeof(long long), h->stream));
+    TRY(upload(g.cls_off, g.h_cls_off.data(), g.h_cls_off.size() * sizeof(long long), h->stream));
     TRY(upload(g.cls_q, hp.cls_q.data(), hp.cls_q.size() * sizeof(double), h->stream));
     TRY(upload(g.cls_w, g.h_cls_w.data(), g.h_cls_w.size() * sizeof(int), h->stream));
     if (ring_bytes(h, g)) TRY(hipMemsetAsync(g.ring, 0, ring_bytes(h, g), h->stream));
     TRY(hipMemsetAsync(g.state, 0, state_bytes_g(g), h->stream));
     TRY(hipMemsetAsync(g.vel, 0, vel_bytes(h, g), h->stream));
+    TRY(hipMemsetAsync(g.pending, 0, pending_bytes(h, g), h->stream));
     TRY(sbim::launch_tabulate(h->fp64, g, cfg->dt, d_glx, d_glw, h->stream));
     // the host vectors must outlive the asynchronous copies
     TRY(hipStreamSynchronize(h->stream));
@@ -498,6 +525,8 @@ int sbim_push_displacement(sbim_handle *h, const void *u, const void *v) {
     a.vel_rule = v ? sbim::VEL_INPUT : (incr ? sbim::VEL_SCALE : sbim::VEL_DIFF);
     e = sbim::launch_push(h, g, a);
     if (e != hipSuccess) return hip_fail(h, e, "push kernel");
+    rc = sweep_group(h, g, g.ring, g.pending, h->step, true);
+    if (rc) return rc;
   }
   h->step += 1;
   h->pushed_since_tractions = true;
@@ -513,30 +542,15 @@ int sbim_tractions(sbim_handle *h, const void *tau_inf, void *tau) {
     Group &g = h->g[i];
     sbim::ConvLaunch a;
     a.ring = g.ring;
+    a.pending = g.pending;
     a.vel = g.vel;
     a.lam = nullptr;
     a.out_a = h->out_spec;
     a.out_b = nullptr;
     a.nh = h->nh;
     a.step = h->step - 1;
-    hipError_t e;
-    if (h->profile) {
-      if (h->ev_used == h->ev_start.size()) {  // grow the reusable event pool
-        hipEvent_t e0, e1;
-        if ((e = hipEventCreate(&e0)) != hipSuccess) return hip_fail(h, e, "hipEventCreate");
-        if ((e = hipEventCreate(&e1)) != hipSuccess) {
-          (void)hipEventDestroy(e0);
-          return hip_fail(h, e, "hipEventCreate");
-        }
-        h->ev_start.push_back(e0);
-        h->ev_stop.push_back(e1);
-      }
-      e = sbim::launch_conv(h, g, a, h->ev_start[h->ev_used], h->ev_stop[h->ev_used]);
-      ++h->ev_used;
-    } else {
-      e = sbim::launch_conv(h, g, a);
-    }
-    if (e != hipSuccess) return hip_fail(h, e, "convolution kernel");
+    const hipError_t e = sbim::launch_conv(h, g, a);
+    if (e != hipSuccess) return hip_fail(h, e, "convolution epilogue kernel");
   }
   hipError_t e = fft_inverse(h, h->out_spec, tau, tau_inf);
   if (e != hipSuccess) return hip_fail(h, e, "inverse FFT");
@@ -571,8 +585,11 @@ int sbim_backward(sbim_handle *h, const void *g_tau, void *du, void *dv) {
     a.vel_rule = dv ? sbim::VEL_COPY : (incr ? sbim::VEL_SCALE : sbim::VEL_DIFF);
     e = sbim::launch_push(h, g, a);
     if (e != hipSuccess) return hip_fail(h, e, "adjoint push kernel");
+    rc = sweep_group(h, g, g.ring_adj, g.pending_adj, h->bstep, false);
+    if (rc) return rc;
     sbim::ConvLaunch c;
     c.ring = g.ring_adj;
+    c.pending = g.pending_adj;
     c.vel = g.vel_adj;
     c.lam = incr ? g.lam_adj : nullptr;
     c.out_a = h->out_spec;
@@ -580,7 +597,7 @@ int sbim_backward(sbim_handle *h, const void *g_tau, void *du, void *dv) {
     c.nh = h->nh;
     c.step = h->bstep;
     e = sbim::launch_conv(h, g, c);
-    if (e != hipSuccess) return hip_fail(h, e, "adjoint convolution kernel");
+    if (e != hipSuccess) return hip_fail(h, e, "adjoint convolution epilogue kernel");
   }
   e = fft_inverse(h, h->out_spec, du, nullptr);
   if (e != hipSuccess) return hip_fail(h, e, "inverse FFT of dL/du");
@@ -654,7 +671,7 @@ int sbim_get_info(const sbim_handle *h, sbim_info *out) {
   out->step = h->step;
   out->backward_step = h->bstep;
   out->material_groups = h->ngroups;
-  out->lag_split = h->lag_split;
+  out->sweep_depth = h->depth;
   return SBIM_OK;
 }
 
@@ -663,7 +680,7 @@ long long sbim_state_bytes(const sbim_handle *h) {
   long long b = 256;  // header: step counter
   for (int i = 0; i < h->ngroups; ++i) {
     const Group &g = h->g[i];
-    b += ring_bytes(h, g) + state_bytes_g(g) + vel_bytes(h, g);
+    b += ring_bytes(h, g) + state_bytes_g(g) + vel_bytes(h, g) + pending_bytes(h, g);
   }
   return b;
 }
@@ -685,6 +702,9 @@ int sbim_save_state(sbim_handle *h, void *dst) {
     d += sb;
     if (e == hipSuccess) e = hipMemcpyAsync(d, g.vel, vb, hipMemcpyDeviceToDevice, h->stream);
     d += vb;
+    const size_t pb = pending_bytes(h, g);
+    if (e == hipSuccess) e = hipMemcpyAsync(d, g.pending, pb, hipMemcpyDeviceToDevice, h->stream);
+    d += pb;
   }
   if (e != hipSuccess) return hip_fail(h, e, "sbim_save_state");
   return SBIM_OK;
@@ -710,6 +730,9 @@ int sbim_load_state(sbim_handle *h, const void *src) {
     s += sb;
     if (e == hipSuccess) e = hipMemcpyAsync(g.vel, s, vb, hipMemcpyDeviceToDevice, h->stream);
     s += vb;
+    const size_t pb = pending_bytes(h, g);
+    if (e == hipSuccess) e = hipMemcpyAsync(g.pending, s, pb, hipMemcpyDeviceToDevice, h->stream);
+    s += pb;
   }
   if (e != hipSuccess) return hip_fail(h, e, "sbim_load_state");
   h->step = step;
@@ -721,19 +744,32 @@ int sbim_step_work(const sbim_handle *h, long long n, double *mode_lags, double 
   if (!h || !mode_lags || !conv_bytes || n < 0)
     return fail(nullptr, SBIM_E_INVALID, "bad arguments to sbim_step_work");
   const double r = static_cast<double>(h->rsize);
+  const int S = h->depth;
   double lags = 0, bytes = 0;
   for (int i = 0; i < h->ngroups; ++i) {
     const Group &g = h->g[i];
     double mode_lag_g = 0;
-    for (long long s = 0; s < g.M; ++s) mode_lag_g += static_cast<double>(std::min<long long>(g.h_win[s], n + 1));
+    for (long long s = 0; s < g.M; ++s)
+      mode_lag_g += static_cast<double>(std::min<long long>(g.h_win[s], n + 1));
     lags += mode_lag_g * g.np;
-    // history stream: the history each mode needs, the kernel rows each class
-    // needs, per-mode class/window indices, and the partial sums written
-    bytes += mode_lag_g * g.np * 3 * 2 * r;
-    for (long long c = 0; c < g.nclasses; ++c)
-      bytes += std::min<long long>(g.h_cls_w[c], n + 1) * 4 * r;
-    bytes += g.M * 8.0 + g.nblocks * 16.0;
-    bytes += static_cast<double>(partial_bytes(h, g));
+    // the sweep of step n: blocks of phase n mod S read the history each of
+    // their modes needs, the kernel rows of each distinct class of the block
+    // (lags up to min(cap, n+1) + S - 2), the per-mode class/window indices
+    // and block descriptors, and write S pending sums per mode and plane
+    for (long long b = n % S; b < g.nblocks; b += S) {
+      const long long imax = std::min<long long>(g.h_blk_cap[b], n + 1);
+      int last_cls = -1;
+      for (long long s = b * sbim::kLanes; s < std::min(g.M, (b + 1) * sbim::kLanes); ++s) {
+        const int w = g.h_win[s];
+        bytes += std::min<long long>(w, n + 1) * g.np * 3.0 * 2.0 * r;
+        bytes += 8.0 + S * g.np * 10.0 * r;
+        if (w > 0 && g.h_cls[s] != last_cls) {
+          last_cls = g.h_cls[s];
+          bytes += std::min<long long>(w, imax + S - 1) * 4.0 * r;
+        }
+      }
+      bytes += 16.0;
+    }
   }
   *mode_lags = lags;
   *conv_bytes = bytes;
@@ -761,7 +797,7 @@ int sbim_mode_kernel(sbim_handle *h, int p, int i1, int i3, double *host_out, in
   const int nl = std::min(w, max_lags);
   std::vector<char> tmp(4 * h->rsize);
   for (int j = 0; j < nl && e == hipSuccess; ++j) {
-    const char *src = static_cast<const char *>(g.table) + (g.h_lag_off[j] + c) * 4 * h->rsize;
+    const char *src = static_cast<const char *>(g.table) + (g.h_cls_off[c] + j) * 4 * h->rsize;
     e = hipMemcpy(tmp.data(), src, 4 * h->rsize, hipMemcpyDeviceToHost);
     for (int k = 0; k < 4; ++k) {
       double v;

@@ -52,7 +52,7 @@ class _Info(ctypes.Structure):
                 ("ring_bytes", ctypes.c_longlong), ("table_bytes", ctypes.c_longlong),
                 ("state_bytes", ctypes.c_longlong), ("step", ctypes.c_longlong),
                 ("backward_step", ctypes.c_longlong), ("material_groups", ctypes.c_int),
-                ("lag_split", ctypes.c_int)]
+                ("sweep_depth", ctypes.c_int)]
 
 
 _lib = None

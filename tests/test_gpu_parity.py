@@ -144,3 +144,55 @@ def test_deterministic_bitwise():
     a = run_gpu(cfg_d, u, "fp32_comp")
     b = run_gpu(cfg_d, u, "fp32_comp")
     assert np.array_equal(a, b)
+
+
+# Several 64-mode blocks with ragged per-mode windows, run long enough for
+# every block to sweep many times: exercises the split of each history sum
+# into the block's last sweep and the newer lags, at every sweep depth.
+SWEEP_CFG = dict(n1=32, n3=64, dx1=1.0, dx3=0.8, dt=0.2, window_cap=40, window_mode="per_mode",
+                 eta_w=1.5, input_kind="increment", planes=[dict(side=1), dict(side=-1)])
+
+
+@pytest.fixture(scope="module")
+def sweep_case():
+    u, _, _ = _inputs(SWEEP_CFG, 90, 7)
+    return u, oracle.forward(SWEEP_CFG, u)
+
+
+@pytest.mark.parametrize("depth", [1, 2, 4, 8])
+@pytest.mark.parametrize("precision", ["fp64", "fp32_comp", "fp32"])
+def test_sweep_depths(sweep_case, depth, precision, monkeypatch):
+    monkeypatch.setenv("SBIM_SWEEP_DEPTH", str(depth))
+    u, ref = sweep_case
+    sb = SBIM(Config.from_dict(SWEEP_CFG, precision=precision), device=DEV)
+    assert sb.info()["sweep_depth"] == depth
+    sb.close()
+    got = run_gpu(SWEEP_CFG, u, precision)
+    err = rel_l2(got, ref)
+    print(f"sweep depth {depth} {precision}: rel-L2 {err:.3e}")
+    assert err < TOL[precision]
+
+
+def test_tractions_repeatable_and_snapshots_mid_rotation():
+    """tractions() changes no state; a snapshot taken at a step that is not a
+    multiple of the sweep depth restores the pending sums exactly."""
+    u = _inputs(SWEEP_CFG, 40, 8)[0]
+    sb = SBIM(Config.from_dict(SWEEP_CFG, precision="fp32"), device=DEV)
+    depth = sb.info()["sweep_depth"]
+    ut = torch.tensor(u, dtype=torch.float32, device=DEV)
+    snap = torch.empty(sb.state_bytes(), dtype=torch.uint8, device=DEV)
+    cut = 3 * depth + 3
+    first = []
+    for n in range(40):
+        sb.push(ut[n])
+        a = sb.tractions().clone()
+        b = sb.tractions().clone()
+        assert torch.equal(a, b), n
+        first.append(a)
+        if n == cut:
+            sb.save_state(snap)
+    sb.load_state(snap)
+    for n in range(cut + 1, 40):
+        sb.push(ut[n])
+        assert torch.equal(sb.tractions(), first[n]), n
+    sb.close()
