@@ -123,7 +123,13 @@ template <typename R> struct Acc<R, false> {
 };
 template <> struct Acc<float, true> {
   float s = 0.f, c = 0.f;
-  __device__ __forceinline__ void fold(float x) { neumaier(s, c, x); }
+  // Kahan's compensated addition (c holds the part of the sum lost by s)
+  __device__ __forceinline__ void fold(float x) {
+    const float y = x + c;
+    const float t = s + y;
+    c = y - (t - s);
+    s = t;
+  }
   __device__ __forceinline__ float value() const { return s + c; }
   __device__ __forceinline__ void fold_lane(int off) {
     const float s2 = __shfl_xor(s, off);
@@ -153,11 +159,10 @@ __device__ __forceinline__ void fma_lag(R (&part)[kSums], const typename W4<R>::
 }
 
 // History entries whose loads the sweep issues together (measured on gfx950,
-// 512x512 x 2 planes, W = 1000): float32 at depth 8 fits three wavefronts per
-// SIMD only with pairs; the compensated form gains from groups of four, whose
-// products are folded into the compensated sums together.
+// 512x512 x 2 planes, W = 1000): float32 at depth 8, float64 and the
+// compensated form fit one more wavefront per SIMD with pairs.
 template <typename R, int S, bool COMP> constexpr int sweep_group() {
-  constexpr int g = COMP ? 4 : (sizeof(R) == 8 || S >= 8 ? 2 : 4);
+  constexpr int g = (COMP || sizeof(R) == 8 || S >= 8) ? 2 : 4;
   return S < g ? S : g;
 }
 
@@ -171,16 +176,15 @@ __device__ __forceinline__ void load_rows(typename W4<R>::T (&w)[S],
   for (int k = 0; k < S; ++k) w[k] = rowp[min(k0 + k, wl)];
 }
 
-// S consecutive history entries (lags i .. i+S-1) against rows i .. i+2S-2,
-// held as A = rows i .. i+S-1 and B = rows i+S .. i+2S-1.  hp / x point at the
-// ring record / slot of lag i and are advanced past lag i+S-1.
-template <typename R, int S, bool COMP>
-__device__ __forceinline__ void sweep_span(Acc<R, COMP> (&acc)[S][kSums],
-                                           const typename W4<R>::T (&A)[S],
+// sums[s] += products of S consecutive history entries (lags i .. i+S-1) with
+// rows i+s .. i+s+S-1, the rows held as A = rows i .. i+S-1 and
+// B = rows i+S .. i+2S-1.  hp / x point at the ring record / slot of lag i
+// and are advanced past lag i+S-1.
+template <typename R, int S, int G>
+__device__ __forceinline__ void sweep_span(R (&sums)[S][kSums], const typename W4<R>::T (&A)[S],
                                            const typename W4<R>::T (&B)[S],
                                            const cplx<R> *__restrict__ &hp, int &x, int cap,
                                            long long dstep, long long dwrap) {
-  constexpr int G = sweep_group<R, S, COMP>();
   typedef R nv2 __attribute__((ext_vector_type(2)));
 #pragma unroll
   for (int g0 = 0; g0 < S; g0 += G) {
@@ -198,41 +202,13 @@ __device__ __forceinline__ void sweep_span(Acc<R, COMP> (&acc)[S][kSums],
       hp += wrap ? dwrap - dstep : -dstep;
       x = wrap ? cap - 1 : x - 1;
     }
-    if constexpr (COMP) {
-      R part[S][kSums];
 #pragma unroll
-      for (int s = 0; s < S; ++s)
+    for (int t = 0; t < G; ++t)
 #pragma unroll
-        for (int k = 0; k < kSums; ++k) part[s][k] = R(0);
-#pragma unroll
-      for (int t = 0; t < G; ++t)
-#pragma unroll
-        for (int s = 0; s < S; ++s) {
-          const int k = g0 + t + s;
-          fma_lag<R>(part[s], k < S ? A[k] : B[k - S], u[t]);
-        }
-#pragma unroll
-      for (int s = 0; s < S; ++s)
-#pragma unroll
-        for (int k = 0; k < kSums; ++k) acc[s][k].fold(part[s][k]);
-    } else {
-      R sums[S][kSums];
-#pragma unroll
-      for (int s = 0; s < S; ++s)
-#pragma unroll
-        for (int k = 0; k < kSums; ++k) sums[s][k] = acc[s][k].s;
-#pragma unroll
-      for (int t = 0; t < G; ++t)
-#pragma unroll
-        for (int s = 0; s < S; ++s) {
-          const int k = g0 + t + s;
-          fma_lag<R>(sums[s], k < S ? A[k] : B[k - S], u[t]);
-        }
-#pragma unroll
-      for (int s = 0; s < S; ++s)
-#pragma unroll
-        for (int k = 0; k < kSums; ++k) acc[s][k].s = sums[s][k];
-    }
+      for (int s = 0; s < S; ++s) {
+        const int k = g0 + t + s;
+        fma_lag<R>(sums[s], k < S ? A[k] : B[k - S], u[t]);
+      }
   }
 }
 
@@ -285,6 +261,14 @@ __global__ __launch_bounds__(kLanes) void sweep_kernel(
   const int per = (imax + kLagGroups * S - 1) / (kLagGroups * S) * S;  // lags per chunk
   const int i0 = lg * per;
 
+  constexpr int G = sweep_group<R, S, COMP>();
+  // plain form: the running sums; compensated form: the products since the
+  // last fold into the compensated accumulators (2S lags, one span pair)
+  R sums[S][kSums];
+#pragma unroll
+  for (int s = 0; s < S; ++s)
+#pragma unroll
+    for (int k = 0; k < kSums; ++k) sums[s][k] = R(0);
   Acc<R, COMP> acc[S][kSums];
   if (per > 0) {  // then cap > 0, so the block has a mode with W > 0 and class 0 exists
     const long long rec_len = static_cast<long long>(np) * 3 * kLanes;
@@ -301,12 +285,25 @@ __global__ __launch_bounds__(kLanes) void sweep_kernel(
     for (int it = 0; it < per; it += 2 * S) {
       const int i = i0 + it;
       load_rows<R, S>(rb, rowp, i + S, wl);
-      sweep_span<R, S, COMP>(acc, ra, rb, hp, x, cap, dstep, dwrap);
+      sweep_span<R, S, G>(sums, ra, rb, hp, x, cap, dstep, dwrap);
       if (it + S >= per) break;
       load_rows<R, S>(ra, rowp, i + 2 * S, wl);
-      sweep_span<R, S, COMP>(acc, rb, ra, hp, x, cap, dstep, dwrap);
+      sweep_span<R, S, G>(sums, rb, ra, hp, x, cap, dstep, dwrap);
+      if constexpr (COMP) {
+#pragma unroll
+        for (int s = 0; s < S; ++s)
+#pragma unroll
+          for (int k = 0; k < kSums; ++k) {
+            acc[s][k].fold(sums[s][k]);
+            sums[s][k] = R(0);
+          }
+      }
     }
   }
+#pragma unroll
+  for (int s = 0; s < S; ++s)
+#pragma unroll
+    for (int k = 0; k < kSums; ++k) acc[s][k].fold(sums[s][k]);
   // sum the four lag chunks of each mode; lanes of chunk 0 store
 #pragma unroll
   for (int s = 0; s < S; ++s) {
@@ -591,6 +588,7 @@ hipError_t sweep_launch_r(const sbim_handle *h, const Group &g, const SweepLaunc
     case 1: return sweep_launch_s<R, 1, COMP>(h, g, a, ev0, ev1);
     case 2: return sweep_launch_s<R, 2, COMP>(h, g, a, ev0, ev1);
     case 4: return sweep_launch_s<R, 4, COMP>(h, g, a, ev0, ev1);
+    case 6: return sweep_launch_s<R, 6, COMP>(h, g, a, ev0, ev1);
     case 8: return sweep_launch_s<R, 8, COMP>(h, g, a, ev0, ev1);
     default: return hipErrorInvalidValue;
   }

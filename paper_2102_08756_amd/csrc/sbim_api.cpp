@@ -391,12 +391,13 @@ int sbim_init(const sbim_config *cfg, sbim_handle **out) {
   };
   // Sweep depth: steps served by one pass over a block's history.  Deeper
   // sweeps divide the history traffic but hold depth x 10 sums per lane in
-  // registers; these depths keep float32 at three and float64 / compensated
-  // sums at two wavefronts per SIMD.
-  h->depth = h->fp64 ? 4 : (h->comp ? 4 : 8);
-  if (const char *env = std::getenv("SBIM_SWEEP_DEPTH")) {  // tuning override: 1, 2, 4 or 8
+  // registers (measured best on gfx950, two planes 512x512, W = 1000: 8 for
+  // float32, 6 for float64 and for the compensated form, whose sums take two
+  // registers each).
+  h->depth = h->comp || h->fp64 ? 6 : 8;
+  if (const char *env = std::getenv("SBIM_SWEEP_DEPTH")) {  // tuning override: 1, 2, 4, 6 or 8
     const int v = std::atoi(env);
-    if (v == 1 || v == 2 || v == 4 || v == 8) h->depth = v;
+    if (v == 1 || v == 2 || v == 4 || v == 6 || v == 8) h->depth = v;
   }
   std::vector<HostPlan> plan(h->ngroups);
   size_t need = 0;
