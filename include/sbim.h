@@ -130,11 +130,11 @@ int sbim_init(const sbim_config *cfg, sbim_handle **out);
  *   v_or_null  device [P][3][n1][n3] velocity prediction for the damping term
  *              of this step, or NULL to use (u^n - u^{n-1}) / dt
  * Exactly one push precedes each sbim_tractions call.  The push also runs the
- * history sweep of this step: the 64-mode blocks whose turn it is (one in
- * sweep_depth of them, in rotation) read their whole history window once and
- * store the part of each of the next sweep_depth steps' history sums that
- * this history already fixes; every step thus reads each history entry
- * 1/sweep_depth times on average.
+ * history sweep of this step, in the same launch: the 64-mode blocks whose
+ * turn it is (one in sweep_depth of them, in rotation) read their history
+ * window before this step once and store the part of each of the next
+ * sweep_depth steps' history sums that this history already fixes; every
+ * step thus reads each history entry 1/sweep_depth times on average.
  */
 int sbim_push_displacement(sbim_handle *h, const void *u, const void *v_or_null);
 
@@ -142,9 +142,9 @@ int sbim_push_displacement(sbim_handle *h, const void *u, const void *v_or_null)
  * sbim_tractions: tau^n of the last pushed step into device [P][3][n1][n3].
  *   tau_inf_or_null  device [P][3][n1][n3] far-field traction added to the
  *                    result, or NULL for zero.
- * It adds to each mode's pending sum the lags newer than its block's last
- * sweep, so it reads no state that it changes: calling it again before the
- * next push returns the same tractions.
+ * It adds to each mode's pending sum the lags from its block's last sweep on,
+ * so it reads no state that it changes: calling it again before the next push
+ * returns the same tractions.
  * SBIM_E_STATE if no step was pushed since init/reset.
  */
 int sbim_tractions(sbim_handle *h, const void *tau_inf_or_null, void *tau);
@@ -191,11 +191,13 @@ int sbim_load_state(sbim_handle *h, const void *src_device);
 /*
  * Work of the step with index n (0-based): *mode_lags = the number of
  * (plane, mode, lag) products of that step's history sums, i.e. min(W(q), n+1)
- * summed over planes and modes; *conv_bytes = the bytes the history sweep
- * launched by that step's push must move: the history of the modes whose
- * block sweeps at step n (phase n mod sweep_depth), the kernel rows of each
- * distinct row class in those blocks, their row/window indices and block
- * descriptors, and the sweep_depth pending sums written per mode and plane.
+ * summed over planes and modes; *conv_bytes = the bytes that the one launch
+ * of that step's push must move: the history sweep (the history before step
+ * n of the modes whose block sweeps at step n, phase n mod sweep_depth; the
+ * kernel rows of each distinct row class in those blocks; their row/window
+ * indices and block descriptors; the sweep_depth pending sums written per mode
+ * and plane) and the push itself (spectrum gathered, float64 state read and
+ * written, ring slot and velocity written, per-mode bin and direction).
  */
 int sbim_step_work(const sbim_handle *h, long long n, double *mode_lags, double *conv_bytes);
 
@@ -208,10 +210,11 @@ int sbim_step_work(const sbim_handle *h, long long n, double *mode_lags, double 
 int sbim_mode_kernel(sbim_handle *h, int p, int i1, int i3, double *host_out, int max_lags);
 
 /*
- * Timing of the history sweep (the dominant kernel of a step): when enabled,
- * HIP events bracket each of its launches made by sbim_push_displacement on
- * the handle's stream; sbim_conv_timing synchronises and returns the summed
- * device time (ms) and the launch count since the last sbim_profile_conv.
+ * Timing of the push / history sweep launch (the dominant kernel of a step):
+ * when enabled, HIP events bracket each of its launches made by
+ * sbim_push_displacement on the handle's stream; sbim_conv_timing synchronises
+ * and returns the summed device time (ms) and the launch count since the last
+ * sbim_profile_conv.
  */
 int sbim_profile_conv(sbim_handle *h, int enable);
 int sbim_conv_timing(sbim_handle *h, double *total_ms, long long *launches);

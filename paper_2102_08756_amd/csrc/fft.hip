@@ -1,6 +1,6 @@
 // Real 2-D FFT of boundary fields on gfx950.  Every transform runs in LDS with
-// Stockham autosort radix-4 passes (one radix-2 pass when log2 N is odd), and
-// every pass reads and writes contiguous rows:
+// Stockham autosort radix-8 passes (and one radix-4 or radix-2 pass for the
+// remaining factor), and every pass reads and writes contiguous rows:
 //   forward  [F][n1][n3] real --r2c along x3, written transposed--> [F][h3][n1]
 //            --complex FFT along contiguous x1 rows--> spectrum [F][h3][n1];
 //   inverse  the same two steps backwards.
@@ -39,21 +39,99 @@ __device__ __forceinline__ cplx<R> twiddle(const cplx<R> *__restrict__ tw, int m
   return t;
 }
 
-// In-place FFT of nseq contiguous sequences of length N = 2^logN held in LDS.
-// Every thread of the work-group must call it.  Each pass stages its inputs
-// in registers, synchronises, then writes the Stockham-ordered outputs.
+// (1 + dir i) / sqrt(2) times a, i.e. a * exp(dir i pi / 4).
+template <typename R>
+__device__ __forceinline__ cplx<R> rot8(cplx<R> a, int dir) {
+  const R h = R(0.70710678118654752440);
+  return dir < 0 ? cplx<R>{(a.x + a.y) * h, (a.y - a.x) * h}
+                 : cplx<R>{(a.x - a.y) * h, (a.y + a.x) * h};
+}
+// dir i a
+template <typename R>
+__device__ __forceinline__ cplx<R> rot4(cplx<R> a, int dir) {
+  return dir < 0 ? cplx<R>{a.y, -a.x} : cplx<R>{-a.y, a.x};
+}
+
+// In-place FFT of nseq contiguous sequences of length N = 2^logN held in LDS:
+// Stockham autosort passes of radix 8 (then one of radix 4 or 2 for the
+// remaining factor).  Every thread of the work-group must call it.  Each pass
+// stages its inputs in registers, synchronises, then writes the outputs.
 template <typename R, int NT, int MAXV>
 __device__ void lds_fft(cplx<R> *buf, int N, int logN, int nseq, int dir,
                         const cplx<R> *__restrict__ tw) {
   const int total = N * nseq;
   int logNs = 0;
-  // radix-4 passes
-  for (; logNs + 2 <= logN; logNs += 2) {
+  constexpr int B8 = (MAXV + 7) / 8;  // radix-8 butterflies per thread and pass
+  // radix-8 passes
+  for (; logNs + 3 <= logN; logNs += 3) {
+    const int q8 = N >> 3;
+    const int nbf = total >> 3;
+    cplx<R> v[B8][8];
+#pragma unroll
+    for (int t = 0; t < B8; ++t) {
+      const int g = threadIdx.x + t * NT;
+      if (g < nbf) {
+        const int b = g >> (logN - 3);
+        const int j = g & (q8 - 1);
+        const int base = b * N + j;
+#pragma unroll
+        for (int r = 0; r < 8; ++r) v[t][r] = buf[base + r * q8];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < B8; ++t) {
+      const int g = threadIdx.x + t * NT;
+      if (g < nbf) {
+        const int b = g >> (logN - 3);
+        const int j = g & (q8 - 1);
+        const int Ns = 1 << logNs;
+        const int k = j & (Ns - 1);
+        const int step = kTwiddleN >> (logNs + 3);  // 4096 / (8 Ns)
+        cplx<R> a[8];
+        a[0] = v[t][0];
+#pragma unroll
+        for (int r = 1; r < 8; ++r) a[r] = cmul<R>(v[t][r], twiddle<R>(tw, r * k * step, dir));
+        // 8-point DFT as radix 2 x radix 4: e_r = a_r + a_{r+4},
+        // o_r = (a_r - a_{r+4}) exp(dir 2 pi i r / 8); X[2m] = DFT4(e), X[2m+1] = DFT4(o)
+        cplx<R> e[4], o[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          e[r] = cadd<R>(a[r], a[r + 4]);
+          o[r] = csub<R>(a[r], a[r + 4]);
+        }
+        o[1] = rot8<R>(o[1], dir);
+        o[2] = rot4<R>(o[2], dir);
+        o[3] = rot4<R>(rot8<R>(o[3], dir), dir);
+        const int out = b * N + ((j >> logNs) << (logNs + 3)) + k;
+        {
+          const cplx<R> t0 = cadd<R>(e[0], e[2]), t1 = csub<R>(e[0], e[2]);
+          const cplx<R> t2 = cadd<R>(e[1], e[3]), t3 = rot4<R>(csub<R>(e[1], e[3]), dir);
+          buf[out] = cadd<R>(t0, t2);
+          buf[out + 2 * Ns] = cadd<R>(t1, t3);
+          buf[out + 4 * Ns] = csub<R>(t0, t2);
+          buf[out + 6 * Ns] = csub<R>(t1, t3);
+        }
+        {
+          const cplx<R> t0 = cadd<R>(o[0], o[2]), t1 = csub<R>(o[0], o[2]);
+          const cplx<R> t2 = cadd<R>(o[1], o[3]), t3 = rot4<R>(csub<R>(o[1], o[3]), dir);
+          buf[out + Ns] = cadd<R>(t0, t2);
+          buf[out + 3 * Ns] = cadd<R>(t1, t3);
+          buf[out + 5 * Ns] = csub<R>(t0, t2);
+          buf[out + 7 * Ns] = csub<R>(t1, t3);
+        }
+      }
+    }
+    __syncthreads();
+  }
+  // one radix-4 pass when 2 factors of two remain
+  if (logNs + 2 == logN) {
     const int q4 = N >> 2;
     const int nbf = total >> 2;
-    cplx<R> v[MAXV / 4][4];
+    constexpr int B4 = (MAXV + 3) / 4;
+    cplx<R> v[B4][4];
 #pragma unroll
-    for (int t = 0; t < MAXV / 4; ++t) {
+    for (int t = 0; t < B4; ++t) {
       const int g = threadIdx.x + t * NT;
       if (g < nbf) {
         const int b = g >> (logN - 2);
@@ -65,7 +143,7 @@ __device__ void lds_fft(cplx<R> *buf, int N, int logN, int nseq, int dir,
     }
     __syncthreads();
 #pragma unroll
-    for (int t = 0; t < MAXV / 4; ++t) {
+    for (int t = 0; t < B4; ++t) {
       const int g = threadIdx.x + t * NT;
       if (g < nbf) {
         const int b = g >> (logN - 2);
@@ -78,9 +156,9 @@ __device__ void lds_fft(cplx<R> *buf, int N, int logN, int nseq, int dir,
         cplx<R> a2 = cmul<R>(v[t][2], twiddle<R>(tw, 2 * k * step, dir));
         cplx<R> a3 = cmul<R>(v[t][3], twiddle<R>(tw, 3 * k * step, dir));
         cplx<R> t0 = cadd<R>(a0, a2), t1 = csub<R>(a0, a2);
-        cplx<R> t2 = cadd<R>(a1, a3), d = csub<R>(a1, a3);
-        // t3 = dir * i * (a1 - a3): -i for the forward transform, +i for the inverse
-        cplx<R> t3 = (dir < 0) ? cplx<R>{d.y, -d.x} : cplx<R>{-d.y, d.x};
+        cplx<R> t2 = cadd<R>(a1, a3);
+        // dir * i * (a1 - a3): -i for the forward transform, +i for the inverse
+        cplx<R> t3 = rot4<R>(csub<R>(a1, a3), dir);
         const int out = b * N + ((j >> logNs) << (logNs + 2)) + k;
         buf[out] = cadd<R>(t0, t2);
         buf[out + Ns] = cadd<R>(t1, t3);
@@ -89,8 +167,9 @@ __device__ void lds_fft(cplx<R> *buf, int N, int logN, int nseq, int dir,
       }
     }
     __syncthreads();
+    logNs += 2;
   }
-  // final radix-2 pass when log2 N is odd
+  // one radix-2 pass when 1 factor of two remains
   if (logNs < logN) {
     const int h2 = N >> 1;
     const int nbf = total >> 1;

@@ -126,22 +126,51 @@ struct PushLaunch {
   double dt;
   int vel_rule, state_rule;
 };
-hipError_t launch_push(const sbim_handle *h, const Group &g, const PushLaunch &a);
 
 // The history sums are split over time.  Block b of 64 modes has phase
-// b mod depth; at each step n the blocks of phase n mod depth sweep their whole
-// history once and store, for each of the steps n .. n+depth-1, the part of
-// that step's sum over the history up to step n ("pending" sums).  The
-// epilogue of step n adds to the pending sum of each mode the lags newer than
-// its block's last sweep (fewer than depth of them).
+// b mod depth; at each step n the blocks of phase n mod depth sweep their
+// history before step n once and store, for each of the steps n .. n+depth-1,
+// the part of that step's sum over that history ("pending" sums).  The
+// epilogue of step n adds to the pending sum of each mode the lags from its
+// block's last sweep on (at most depth of them).
 struct SweepLaunch {
   const void *ring;
   void *pending;
   long long step;
 };
-// One launch (bracketed by ev0/ev1 when they are non-null).
-hipError_t launch_sweep(const sbim_handle *h, const Group &g, const SweepLaunch &a,
-                        hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+// One launch: the sweep of step `step` and the push of that step (bracketed
+// by ev0/ev1 when they are non-null).
+hipError_t launch_step(const sbim_handle *h, const Group &g, const PushLaunch &p,
+                       const SweepLaunch &w, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+
+// Kernel arguments (device pointers) of the two item kinds of that launch.
+struct PushArgs {
+  const void *spec, *spec_v;
+  void *ring;
+  double2 *state;
+  void *vel;
+  const int *nat;
+  const double *geom;
+  const long long *blk_off;
+  const int *blk_cap, *blk_stride;
+  long long M, nh;
+  int np, plane0, plane1;
+  long long step;
+  double inv_dt;
+  int vel_rule, state_rule;
+};
+struct SweepArgs {
+  const void *ring, *table;
+  void *pending;
+  const int *cls, *win;
+  const long long *blk_off;
+  const int *blk_cap, *blk_stride;
+  const long long *cls_off;
+  int cls_w0;             // rows of class 0 (its zero row follows them)
+  long long M, step;
+  int np;
+  long long nphase;       // blocks of this step's phase
+};
 
 struct ConvLaunch {
   const void *ring;

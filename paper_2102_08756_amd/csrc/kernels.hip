@@ -1,10 +1,11 @@
 // Mode-space kernels of the boundary-integral step on gfx950:
-//   push_kernel          rotate a new spectrum into the wavevector frame, update
-//                        the float64 running state, store the history ring slot
-//                        and the velocity spectrum used by the damping term;
-//   sweep_kernel         the truncated history convolution (the nonlocal term of
-//                        Eq. SBI, Sec. 2.3), one pass over a block's history
-//                        serving several steps;
+//   step_kernel          two kinds of items in one launch: the push (rotate a new
+//                        spectrum into the wavevector frame, update the float64
+//                        running state, store the history ring slot and the
+//                        velocity spectrum used by the damping term) and the
+//                        history sweep (the truncated history convolution, the
+//                        nonlocal term of Eq. SBI, Sec. 2.3: one pass over a
+//                        block's history serving several steps);
 //   conv_epilogue_kernel the newest lags, damping and instantaneous terms and the
 //                        rotation back to (x1, x2, x3);
 //   tabulate_kernel      float64 quadrature of the per-lag kernel weights.
@@ -35,68 +36,65 @@ template <> struct W4<double> { using T = double4; };
 
 // ------------------------------------------------------------------ push
 
+// Push of one (mode, plane): rotate the new spectrum into the wavevector
+// frame, update the float64 running state, store the ring slot and the
+// velocity spectrum used by the damping term.
 template <typename R>
-__global__ __launch_bounds__(256) void push_kernel(
-    const double2 *__restrict__ spec, const double2 *__restrict__ spec_v,
-    cplx<R> *__restrict__ ring, double2 *__restrict__ state, cplx<R> *__restrict__ vel,
-    const int *__restrict__ nat, const double *__restrict__ geom,
-    const long long *__restrict__ blk_off, const int *__restrict__ blk_cap,
-    const int *__restrict__ blk_stride, long long M, long long nh, int np, int plane0, int plane1,
-    long long step, double inv_dt, int vel_rule, int state_rule) {
-  // one thread per (mode, plane); consecutive threads take consecutive modes
-  const long long t = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (t >= M * np) return;
-  const int p = static_cast<int>(t / M);
-  const long long s = t - p * M;
-  const long long natural = nat[s];
-  const double kh1 = geom[4 * s + 1];
-  const double kh3 = geom[4 * s + 2];
+__device__ __forceinline__ void push_mode(const PushArgs &a, int p, long long s) {
+  const double2 *__restrict__ spec = static_cast<const double2 *>(a.spec);
+  const double2 *__restrict__ spec_v = static_cast<const double2 *>(a.spec_v);
+  cplx<R> *__restrict__ ring = static_cast<cplx<R> *>(a.ring);
+  double2 *__restrict__ state = a.state;
+  cplx<R> *__restrict__ vel = static_cast<cplx<R> *>(a.vel);
+  const long long M = a.M, nh = a.nh;
+  const int np = a.np;
+  const long long natural = a.nat[s];
+  const double kh1 = a.geom[4 * s + 1];
+  const double kh3 = a.geom[4 * s + 2];
   const long long b = s >> 6;
   const int lane = static_cast<int>(s & 63);
-  const int cap = blk_cap[b];
-  const long long rec = cap > 0 ? blk_off[b] + (step % cap) * blk_stride[b] : 0;
-  {
-    const int pg = p == 0 ? plane0 : plane1;
-    double2 x[3];
+  const int cap = a.blk_cap[b];
+  const long long rec = cap > 0 ? a.blk_off[b] + (a.step % cap) * a.blk_stride[b] : 0;
+  const int pg = p == 0 ? a.plane0 : a.plane1;
+  double2 x[3];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) x[c] = spec[(pg * 3 + c) * nh + natural];
-    // (1, 2, 3) -> (L, N, T)
-    const double2 xr[3] = {{kh1 * x[0].x + kh3 * x[2].x, kh1 * x[0].y + kh3 * x[2].y},
-                           x[1],
-                           {-kh3 * x[0].x + kh1 * x[2].x, -kh3 * x[0].y + kh1 * x[2].y}};
-    double2 vr[3];
-    if (vel_rule == VEL_INPUT) {
-      double2 y[3];
+  for (int c = 0; c < 3; ++c) x[c] = spec[(pg * 3 + c) * nh + natural];
+  // (1, 2, 3) -> (L, N, T)
+  const double2 xr[3] = {{kh1 * x[0].x + kh3 * x[2].x, kh1 * x[0].y + kh3 * x[2].y},
+                         x[1],
+                         {-kh3 * x[0].x + kh1 * x[2].x, -kh3 * x[0].y + kh1 * x[2].y}};
+  double2 vr[3];
+  if (a.vel_rule == VEL_INPUT) {
+    double2 y[3];
 #pragma unroll
-      for (int c = 0; c < 3; ++c) y[c] = spec_v[(pg * 3 + c) * nh + natural];
-      vr[0] = double2{kh1 * y[0].x + kh3 * y[2].x, kh1 * y[0].y + kh3 * y[2].y};
-      vr[1] = y[1];
-      vr[2] = double2{-kh3 * y[0].x + kh1 * y[2].x, -kh3 * y[0].y + kh1 * y[2].y};
-    }
+    for (int c = 0; c < 3; ++c) y[c] = spec_v[(pg * 3 + c) * nh + natural];
+    vr[0] = double2{kh1 * y[0].x + kh3 * y[2].x, kh1 * y[0].y + kh3 * y[2].y};
+    vr[1] = y[1];
+    vr[2] = double2{-kh3 * y[0].x + kh1 * y[2].x, -kh3 * y[0].y + kh1 * y[2].y};
+  }
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      const long long si = (static_cast<long long>(p) * 3 + c) * M + s;
-      const double2 prev = state[si];
-      double2 now;
-      if (state_rule == STATE_ACCUM)
-        now = double2{prev.x + xr[c].x, prev.y + xr[c].y};
-      else
-        now = xr[c];
-      state[si] = now;
-      double2 v;
-      if (vel_rule == VEL_DIFF)
-        v = double2{(now.x - prev.x) * inv_dt, (now.y - prev.y) * inv_dt};
-      else if (vel_rule == VEL_SCALE)
-        v = double2{xr[c].x * inv_dt, xr[c].y * inv_dt};
-      else if (vel_rule == VEL_INPUT)
-        v = vr[c];
-      else
-        v = xr[c];
-      vel[si] = cplx<R>{static_cast<R>(v.x), static_cast<R>(v.y)};
-      if (cap > 0)
-        ring[((rec * np + p) * 3 + c) * kLanes + lane] =
-            cplx<R>{static_cast<R>(now.x), static_cast<R>(now.y)};
-    }
+  for (int c = 0; c < 3; ++c) {
+    const long long si = (static_cast<long long>(p) * 3 + c) * M + s;
+    const double2 prev = state[si];
+    double2 now;
+    if (a.state_rule == STATE_ACCUM)
+      now = double2{prev.x + xr[c].x, prev.y + xr[c].y};
+    else
+      now = xr[c];
+    state[si] = now;
+    double2 v;
+    if (a.vel_rule == VEL_DIFF)
+      v = double2{(now.x - prev.x) * a.inv_dt, (now.y - prev.y) * a.inv_dt};
+    else if (a.vel_rule == VEL_SCALE)
+      v = double2{xr[c].x * a.inv_dt, xr[c].y * a.inv_dt};
+    else if (a.vel_rule == VEL_INPUT)
+      v = vr[c];
+    else
+      v = xr[c];
+    vel[si] = cplx<R>{static_cast<R>(v.x), static_cast<R>(v.y)};
+    if (cap > 0)
+      ring[((rec * np + p) * 3 + c) * kLanes + lane] =
+          cplx<R>{static_cast<R>(now.x), static_cast<R>(now.y)};
   }
 }
 
@@ -163,7 +161,7 @@ __device__ __forceinline__ void fma_lag(R (&part)[kSums], const typename W4<R>::
 // compensated form fit one more wavefront per SIMD with pairs.
 template <typename R, int S, bool COMP> constexpr int sweep_group() {
   constexpr int g = (COMP || sizeof(R) == 8 || S >= 8) ? 2 : 4;
-  return S < g ? S : g;
+  return S % g == 0 ? g : (S % 2 == 0 ? 2 : 1);  // a divisor of the span
 }
 
 // Rows k0 .. k0+S-1 of a mode's kernel.  A class's W rows are followed by a
@@ -185,6 +183,7 @@ __device__ __forceinline__ void sweep_span(R (&sums)[S][kSums], const typename W
                                            const typename W4<R>::T (&B)[S],
                                            const cplx<R> *__restrict__ &hp, int &x, int cap,
                                            long long dstep, long long dwrap) {
+  static_assert(S % G == 0, "load groups must tile the span");
   typedef R nv2 __attribute__((ext_vector_type(2)));
 #pragma unroll
   for (int g0 = 0; g0 < S; g0 += G) {
@@ -212,18 +211,20 @@ __device__ __forceinline__ void sweep_span(R (&sums)[S][kSums], const typename W
   }
 }
 
-// The sweep of one step n.  Blocks of phase n mod S read their whole history
-// once, U^{n-i} for i = 0 .. min(cap, n+1)-1, and form for each coming step
-// n+s (s = 0 .. S-1) its sum over that history:
-//   pending[(n+s) mod S] = sum_{i} w_{i+s} (x) U^{n-i}   (lags i+s inside the window).
+// The sweep of step n.  Blocks of phase n mod S read their history before
+// step n once, U^{n-i} for i = 1 .. min(cap-1, n), and form for each coming
+// step n+s (s = 0 .. S-1) its sum over that history:
+//   pending[(n+s) mod S] = sum_{i>=1} w_{i+s} (x) U^{n-i}   (lags i+s inside the window).
+// It does not read U^n, so it runs in the same launch as the push of step n.
 // Each history entry thus serves S steps.  The kernel rows i .. i+2S-2 that a
 // span of S entries needs are held in two register arrays used in turn, so
 // each row is loaded once and never moved.
 //
 // Lag chunks are whole spans long, so chunks never overlap and no lane needs a
-// mask: chunks reach past min(cap, n+1) by less than 4 spans, and a lag
-// i >= min(cap, n+1) either meets zero kernel rows (i + s >= cap >= W) or a
-// ring slot not written since the last reset, which holds zero.
+// mask: chunks reach past the last entry by less than 4 spans, and a lag
+// i > min(cap-1, n) either meets zero kernel rows (i + s >= cap >= W) or a
+// ring slot not written since the last reset, which holds zero (the slot that
+// the concurrent push writes is lag cap, whose rows are zero).
 //
 // Work item (one wavefront) = (block of the phase, plane, quarter of the
 // block's 64 modes).  Its 64 lanes are 16 modes x 4 lag chunks: lane l takes
@@ -232,20 +233,19 @@ __device__ __forceinline__ void sweep_span(R (&sums)[S][kSums], const typename W
 // summed by a butterfly over lanes l ^ 16, l ^ 32 (fixed order, so the result
 // is bitwise reproducible).
 template <typename R, int S, bool COMP>
-__global__ __launch_bounds__(kLanes) void sweep_kernel(
-    const cplx<R> *__restrict__ ring, const typename W4<R>::T *__restrict__ table,
-    R *__restrict__ pending, const int *__restrict__ cls, const int *__restrict__ win,
-    const long long *__restrict__ blk_off, const int *__restrict__ blk_cap,
-    const int *__restrict__ blk_stride, const long long *__restrict__ cls_off, int cls_w0,
-    long long M, long long step, int np, long long nphase) {
+__device__ __forceinline__ void sweep_item(const SweepArgs &a, long long item) {
   using W = typename W4<R>::T;
+  const cplx<R> *__restrict__ ring = static_cast<const cplx<R> *>(a.ring);
+  const W *__restrict__ table = static_cast<const W *>(a.table);
+  R *__restrict__ pending = static_cast<R *>(a.pending);
+  const long long M = a.M, step = a.step;
+  const int np = a.np;
   constexpr int Q = kLanes / kLagGroups;  // modes per item
   // Items of one block get ids congruent mod 8, so they run on one XCD and
   // share the block's kernel rows in its L2.
   const int per_blk = kLagGroups * np;
-  const long long item = blockIdx.x;
   const long long kb = (item / (8LL * per_blk)) * 8 + (item & 7);
-  if (kb >= nphase) return;
+  if (kb >= a.nphase) return;
   const int r = static_cast<int>((item >> 3) % per_blk);
   const int p = r / kLagGroups;
   const long long b = step % S + S * kb;
@@ -254,12 +254,13 @@ __global__ __launch_bounds__(kLanes) void sweep_kernel(
   const int col = (r % kLagGroups) * Q + lane % Q;  // lane of the mode in its block
   const long long sm = b * kLanes + col;
   const bool valid = sm < M;
-  const int cap = blk_cap[b];
-  const int imax = static_cast<int>(min(static_cast<long long>(cap), step + 1));
-  const int wl = valid ? win[sm] : 0;
-  const int cl = valid ? cls[sm] : 0;
-  const int per = (imax + kLagGroups * S - 1) / (kLagGroups * S) * S;  // lags per chunk
-  const int i0 = lg * per;
+  const int cap = a.blk_cap[b];
+  // history entries before step n that any lag of the window can reach
+  const int nent = static_cast<int>(max(0LL, min(static_cast<long long>(cap) - 1, step)));
+  const int wl = valid ? a.win[sm] : 0;
+  const int cl = valid ? a.cls[sm] : 0;
+  const int per = (nent + kLagGroups * S - 1) / (kLagGroups * S) * S;  // lags per chunk
+  const int i0 = 1 + lg * per;
 
   constexpr int G = sweep_group<R, S, COMP>();
   // plain form: the running sums; compensated form: the products since the
@@ -270,16 +271,17 @@ __global__ __launch_bounds__(kLanes) void sweep_kernel(
 #pragma unroll
     for (int k = 0; k < kSums; ++k) sums[s][k] = R(0);
   Acc<R, COMP> acc[S][kSums];
-  if (per > 0) {  // then cap > 0, so the block has a mode with W > 0 and class 0 exists
+  if (per > 0) {  // then cap > 1, so the block has a mode with W > 0 and class 0 exists
     const long long rec_len = static_cast<long long>(np) * 3 * kLanes;
-    const long long dstep = blk_stride[b] * rec_len;  // elements between consecutive slots
+    const long long dstep = a.blk_stride[b] * rec_len;  // elements between consecutive slots
     const long long dwrap = static_cast<long long>(cap) * dstep;
     // ring slot of lag i0 (i0 may pass step)
     int x = static_cast<int>((((step - i0) % cap) + cap) % cap);
-    const cplx<R> *hp = ring + (blk_off[b] + static_cast<long long>(x) * blk_stride[b]) * rec_len +
+    const cplx<R> *hp = ring +
+                        (a.blk_off[b] + static_cast<long long>(x) * a.blk_stride[b]) * rec_len +
                         static_cast<long long>(p) * 3 * kLanes + col;
     // a mode without history (W = 0) reads the zero row after class 0's rows
-    const W *rowp = wl > 0 ? table + cls_off[cl] : table + cls_off[0] + cls_w0;
+    const W *rowp = wl > 0 ? table + a.cls_off[cl] : table + a.cls_off[0] + a.cls_w0;
     W ra[S], rb[S];
     load_rows<R, S>(ra, rowp, i0, wl);
     for (int it = 0; it < per; it += 2 * S) {
@@ -318,6 +320,25 @@ __global__ __launch_bounds__(kLanes) void sweep_kernel(
   }
 }
 
+// One launch per step of mode-space work before the epilogue: the sweep items
+// of the blocks whose turn it is, then one push item per (64-mode block,
+// plane).  The two kinds share no data (the sweep reads no slot the push
+// writes, see sweep_item), so the latency-bound push gathers run beside the
+// streaming sweep.
+template <typename R, int S, bool COMP>
+__global__ __launch_bounds__(kLanes) void step_kernel(SweepArgs sa, PushArgs pa,
+                                                      long long sweep_items, long long nblocks) {
+  const long long item = blockIdx.x;
+  if (item < sweep_items) {
+    sweep_item<R, S, COMP>(sa, item);
+    return;
+  }
+  const long long k = item - sweep_items;
+  const int p = static_cast<int>(k / nblocks);
+  const long long s = (k - p * nblocks) * kLanes + threadIdx.x;
+  if (s < pa.M) push_mode<R>(pa, p, s);
+}
+
 // Per (mode, plane): the pending sum of this step plus the lags newer than the
 // block's last sweep (compensated for the compensated form), damping and
 // instantaneous terms, rotation back to (x1, x2, x3), scatter into the natural
@@ -352,10 +373,11 @@ __global__ __launch_bounds__(256) void conv_epilogue_kernel(
   const long long stride = blk_stride[b];
   const int sl = static_cast<int>(step % depth);
   const int phi = static_cast<int>(b % depth);
-  // lags not in the pending sum: those newer than the block's last sweep, or
-  // all of them before its first sweep (step < phi < depth)
+  // lags not in the pending sum: those from the block's last sweep on (the
+  // sweep of step m covers lags of U^{m-1} and older), or all of them before
+  // its first sweep (step < phi < depth)
   const bool swept = step >= phi;
-  const int fresh = min(wl, swept ? (sl - phi + depth) % depth : static_cast<int>(step) + 1);
+  const int fresh = min(wl, swept ? (sl - phi + depth) % depth + 1 : static_cast<int>(step) + 1);
   const int x0 = cap > 0 ? static_cast<int>(step % cap) : 0;
   R cs[kSums];
   {
@@ -565,31 +587,29 @@ __global__ __launch_bounds__(256) void tabulate_kernel(
 }
 
 template <typename R, int S, bool COMP>
-hipError_t sweep_launch_s(const sbim_handle *h, const Group &g, const SweepLaunch &a,
-                          hipEvent_t ev0, hipEvent_t ev1) {
-  const int phase = static_cast<int>(a.step % S);
-  const long long nphase = g.nblocks > phase ? (g.nblocks - phase + S - 1) / S : 0;
-  const long long items = (nphase + 7) / 8 * 8 * kLagGroups * g.np;
+hipError_t step_launch_s(const sbim_handle *h, const Group &g, const SweepArgs &sa0,
+                         const PushArgs &pa, hipEvent_t ev0, hipEvent_t ev1) {
+  SweepArgs sa = sa0;
+  const int phase = static_cast<int>(sa.step % S);
+  sa.nphase = g.nblocks > phase ? (g.nblocks - phase + S - 1) / S : 0;
+  const long long sweep_items = (sa.nphase + 7) / 8 * 8 * kLagGroups * g.np;
+  const long long items = sweep_items + g.nblocks * g.np;
   if (ev0) (void)hipEventRecord(ev0, h->stream);
-  if (items > 0)
-    hipLaunchKernelGGL((sweep_kernel<R, S, COMP>), dim3(static_cast<unsigned>(items)), dim3(kLanes),
-                       0, h->stream, static_cast<const cplx<R> *>(a.ring),
-                       static_cast<const typename W4<R>::T *>(g.table),
-                       static_cast<R *>(a.pending), g.cls, g.win, g.blk_off, g.blk_cap,
-                       g.blk_stride, g.cls_off, g.wmax, g.M, a.step, g.np, nphase);
+  hipLaunchKernelGGL((step_kernel<R, S, COMP>), dim3(static_cast<unsigned>(items)), dim3(kLanes),
+                     0, h->stream, sa, pa, sweep_items, g.nblocks);
   if (ev1) (void)hipEventRecord(ev1, h->stream);
   return hipGetLastError();
 }
 
 template <typename R, bool COMP>
-hipError_t sweep_launch_r(const sbim_handle *h, const Group &g, const SweepLaunch &a,
-                          hipEvent_t ev0, hipEvent_t ev1) {
+hipError_t step_launch_r(const sbim_handle *h, const Group &g, const SweepArgs &sa,
+                         const PushArgs &pa, hipEvent_t ev0, hipEvent_t ev1) {
   switch (h->depth) {
-    case 1: return sweep_launch_s<R, 1, COMP>(h, g, a, ev0, ev1);
-    case 2: return sweep_launch_s<R, 2, COMP>(h, g, a, ev0, ev1);
-    case 4: return sweep_launch_s<R, 4, COMP>(h, g, a, ev0, ev1);
-    case 6: return sweep_launch_s<R, 6, COMP>(h, g, a, ev0, ev1);
-    case 8: return sweep_launch_s<R, 8, COMP>(h, g, a, ev0, ev1);
+    case 1: return step_launch_s<R, 1, COMP>(h, g, sa, pa, ev0, ev1);
+    case 2: return step_launch_s<R, 2, COMP>(h, g, sa, pa, ev0, ev1);
+    case 4: return step_launch_s<R, 4, COMP>(h, g, sa, pa, ev0, ev1);
+    case 6: return step_launch_s<R, 6, COMP>(h, g, sa, pa, ev0, ev1);
+    case 8: return step_launch_s<R, 8, COMP>(h, g, sa, pa, ev0, ev1);
     default: return hipErrorInvalidValue;
   }
 }
@@ -611,31 +631,46 @@ hipError_t conv_launch_r(const sbim_handle *h, const Group &g, const ConvLaunch 
 
 }  // namespace
 
-hipError_t launch_push(const sbim_handle *h, const Group &g, const PushLaunch &a) {
-  const unsigned grid = static_cast<unsigned>((g.M * g.np + 255) / 256);
-  const int p0 = g.pl[0].index;
-  const int p1 = g.np > 1 ? g.pl[1].index : p0;
-  if (h->fp64) {
-    hipLaunchKernelGGL(push_kernel<double>, dim3(grid), dim3(256), 0, h->stream,
-                       static_cast<const double2 *>(a.spec), static_cast<const double2 *>(a.spec_v),
-                       static_cast<double2 *>(a.ring), reinterpret_cast<double2 *>(a.state),
-                       static_cast<double2 *>(a.vel), g.nat, g.geom, g.blk_off, g.blk_cap, g.blk_stride, g.M,
-                       a.nh, g.np, p0, p1, a.step, 1.0 / a.dt, a.vel_rule, a.state_rule);
-  } else {
-    hipLaunchKernelGGL(push_kernel<float>, dim3(grid), dim3(256), 0, h->stream,
-                       static_cast<const double2 *>(a.spec), static_cast<const double2 *>(a.spec_v),
-                       static_cast<float2 *>(a.ring), reinterpret_cast<double2 *>(a.state),
-                       static_cast<float2 *>(a.vel), g.nat, g.geom, g.blk_off, g.blk_cap, g.blk_stride, g.M,
-                       a.nh, g.np, p0, p1, a.step, 1.0 / a.dt, a.vel_rule, a.state_rule);
-  }
-  return hipGetLastError();
-}
-
-hipError_t launch_sweep(const sbim_handle *h, const Group &g, const SweepLaunch &a,
-                        hipEvent_t ev0, hipEvent_t ev1) {
-  if (h->fp64) return sweep_launch_r<double, false>(h, g, a, ev0, ev1);
-  if (h->comp) return sweep_launch_r<float, true>(h, g, a, ev0, ev1);
-  return sweep_launch_r<float, false>(h, g, a, ev0, ev1);
+hipError_t launch_step(const sbim_handle *h, const Group &g, const PushLaunch &p,
+                       const SweepLaunch &w, hipEvent_t ev0, hipEvent_t ev1) {
+  PushArgs pa;
+  pa.spec = p.spec;
+  pa.spec_v = p.spec_v;
+  pa.ring = p.ring;
+  pa.state = reinterpret_cast<double2 *>(p.state);
+  pa.vel = p.vel;
+  pa.nat = g.nat;
+  pa.geom = g.geom;
+  pa.blk_off = g.blk_off;
+  pa.blk_cap = g.blk_cap;
+  pa.blk_stride = g.blk_stride;
+  pa.M = g.M;
+  pa.nh = p.nh;
+  pa.np = g.np;
+  pa.plane0 = g.pl[0].index;
+  pa.plane1 = g.np > 1 ? g.pl[1].index : pa.plane0;
+  pa.step = p.step;
+  pa.inv_dt = 1.0 / p.dt;
+  pa.vel_rule = p.vel_rule;
+  pa.state_rule = p.state_rule;
+  SweepArgs sa;
+  sa.ring = w.ring;
+  sa.table = g.table;
+  sa.pending = w.pending;
+  sa.cls = g.cls;
+  sa.win = g.win;
+  sa.blk_off = g.blk_off;
+  sa.blk_cap = g.blk_cap;
+  sa.blk_stride = g.blk_stride;
+  sa.cls_off = g.cls_off;
+  sa.cls_w0 = g.wmax;
+  sa.M = g.M;
+  sa.step = w.step;
+  sa.np = g.np;
+  sa.nphase = 0;
+  if (h->fp64) return step_launch_r<double, false>(h, g, sa, pa, ev0, ev1);
+  if (h->comp) return step_launch_r<float, true>(h, g, sa, pa, ev0, ev1);
+  return step_launch_r<float, false>(h, g, sa, pa, ev0, ev1);
 }
 
 hipError_t launch_conv(const sbim_handle *h, const Group &g, const ConvLaunch &a) {

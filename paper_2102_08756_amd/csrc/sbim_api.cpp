@@ -313,14 +313,14 @@ int ensure_adjoint(sbim_handle *h) {
   return SBIM_OK;
 }
 
-// The history sweep of step `step` for one group; bracketed by a pair of the
-// handle's reusable events while sbim_profile_conv is on.
-int sweep_group(sbim_handle *h, Group &g, const void *ring, void *pending, long long step,
-                bool timed) {
-  sbim::SweepLaunch a;
-  a.ring = ring;
-  a.pending = pending;
-  a.step = step;
+// The push and history sweep of step `p.step` for one group (one launch),
+// bracketed by a pair of the handle's reusable events while sbim_profile_conv
+// is on.
+int step_group(sbim_handle *h, Group &g, const sbim::PushLaunch &p, void *pending, bool timed) {
+  sbim::SweepLaunch w;
+  w.ring = p.ring;
+  w.pending = pending;
+  w.step = p.step;
   hipError_t e;
   if (timed && h->profile) {
     if (h->ev_used == h->ev_start.size()) {  // grow the reusable event pool
@@ -333,12 +333,12 @@ int sweep_group(sbim_handle *h, Group &g, const void *ring, void *pending, long 
       h->ev_start.push_back(e0);
       h->ev_stop.push_back(e1);
     }
-    e = sbim::launch_sweep(h, g, a, h->ev_start[h->ev_used], h->ev_stop[h->ev_used]);
+    e = sbim::launch_step(h, g, p, w, h->ev_start[h->ev_used], h->ev_stop[h->ev_used]);
     ++h->ev_used;
   } else {
-    e = sbim::launch_sweep(h, g, a);
+    e = sbim::launch_step(h, g, p, w);
   }
-  if (e != hipSuccess) return hip_fail(h, e, "history sweep kernel");
+  if (e != hipSuccess) return hip_fail(h, e, "push / history sweep kernel");
   return SBIM_OK;
 }
 
@@ -524,9 +524,7 @@ int sbim_push_displacement(sbim_handle *h, const void *u, const void *v) {
     a.dt = h->cfg.dt;
     a.state_rule = incr ? sbim::STATE_ACCUM : sbim::STATE_REPLACE;
     a.vel_rule = v ? sbim::VEL_INPUT : (incr ? sbim::VEL_SCALE : sbim::VEL_DIFF);
-    e = sbim::launch_push(h, g, a);
-    if (e != hipSuccess) return hip_fail(h, e, "push kernel");
-    rc = sweep_group(h, g, g.ring, g.pending, h->step, true);
+    rc = step_group(h, g, a, g.pending, true);
     if (rc) return rc;
   }
   h->step += 1;
@@ -584,9 +582,7 @@ int sbim_backward(sbim_handle *h, const void *g_tau, void *du, void *dv) {
     a.state_rule = sbim::STATE_REPLACE;
     // transpose of the velocity rule of the forward push
     a.vel_rule = dv ? sbim::VEL_COPY : (incr ? sbim::VEL_SCALE : sbim::VEL_DIFF);
-    e = sbim::launch_push(h, g, a);
-    if (e != hipSuccess) return hip_fail(h, e, "adjoint push kernel");
-    rc = sweep_group(h, g, g.ring_adj, g.pending_adj, h->bstep, false);
+    rc = step_group(h, g, a, g.pending_adj, false);
     if (rc) return rc;
     sbim::ConvLaunch c;
     c.ring = g.ring_adj;
@@ -753,24 +749,31 @@ int sbim_step_work(const sbim_handle *h, long long n, double *mode_lags, double 
     for (long long s = 0; s < g.M; ++s)
       mode_lag_g += static_cast<double>(std::min<long long>(g.h_win[s], n + 1));
     lags += mode_lag_g * g.np;
-    // the sweep of step n: blocks of phase n mod S read the history each of
-    // their modes needs, the kernel rows of each distinct class of the block
-    // (lags up to min(cap, n+1) + S - 2), the per-mode class/window indices
-    // and block descriptors, and write S pending sums per mode and plane
+    // the sweep of step n: blocks of phase n mod S read the history before
+    // step n that each of their modes needs (lags 1 .. W-1), the kernel rows of
+    // each distinct class of the block (lags 1 .. min(cap-1, n) + S - 1), the
+    // per-mode class/window indices and block descriptors, and write S
+    // pending sums per mode and plane
     for (long long b = n % S; b < g.nblocks; b += S) {
-      const long long imax = std::min<long long>(g.h_blk_cap[b], n + 1);
+      const long long nent = std::max(0LL, std::min<long long>(g.h_blk_cap[b] - 1, n));
       int last_cls = -1;
       for (long long s = b * sbim::kLanes; s < std::min(g.M, (b + 1) * sbim::kLanes); ++s) {
         const int w = g.h_win[s];
-        bytes += std::min<long long>(w, n + 1) * g.np * 3.0 * 2.0 * r;
+        bytes += std::max(0LL, std::min<long long>(w - 1, n)) * g.np * 3.0 * 2.0 * r;
         bytes += 8.0 + S * g.np * 10.0 * r;
-        if (w > 0 && g.h_cls[s] != last_cls) {
+        if (w > 1 && g.h_cls[s] != last_cls) {
           last_cls = g.h_cls[s];
-          bytes += std::min<long long>(w, imax + S - 1) * 4.0 * r;
+          bytes += std::min<long long>(w - 1, nent + S - 1) * 4.0 * r;
         }
       }
       bytes += 16.0;
     }
+    // the push of step n (same launch), per mode and plane: the three
+    // float64 spectrum values, the float64 state read and written, the ring
+    // slot and velocity written; per mode its bin and direction; per block
+    // its descriptors
+    bytes += g.M * g.np * (3.0 * 16.0 + 3.0 * 32.0 + 3.0 * 2.0 * 2.0 * r);
+    bytes += g.M * (4.0 + 16.0) + g.nblocks * 16.0;
   }
   *mode_lags = lags;
   *conv_bytes = bytes;

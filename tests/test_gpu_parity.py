@@ -159,7 +159,7 @@ def sweep_case():
     return u, oracle.forward(SWEEP_CFG, u)
 
 
-@pytest.mark.parametrize("depth", [1, 2, 4, 8])
+@pytest.mark.parametrize("depth", [1, 2, 4, 6, 8])
 @pytest.mark.parametrize("precision", ["fp64", "fp32_comp", "fp32"])
 def test_sweep_depths(sweep_case, depth, precision, monkeypatch):
     monkeypatch.setenv("SBIM_SWEEP_DEPTH", str(depth))
