@@ -9,8 +9,9 @@ evaluation (forward FFT, history update, convolution, inverse FFT); the timed
 region is the whole 2000-step job from an empty history, inputs resident in
 HBM.  Reported: mode-history-steps per second (sum over steps, planes and modes
 of min(W, n+1)) for the compensated float32 form (headline), plain float32 and
-float64, the float32-vs-float64 relative L2 error, the convolution kernel's
-HBM roofline fraction, and the float64 CPU oracle on a bounded sample.
+float64, the float32-vs-float64 relative L2 error, the HBM roofline fraction
+of the dominant kernel (the launch that pushes a step and runs the history
+sweep), and the float64 CPU oracle on a bounded sample.
 """
 from __future__ import annotations
 
@@ -42,9 +43,10 @@ def kernel_source_hash():
 
 
 def read_traffic(workload, precision):
-    """Per-dispatch HBM bytes of the convolution from the committed rocprofv3 counter summary,
-    scaled by the copy-kernel calibration; None if absent or taken on other kernel sources."""
-    path = os.path.join(PROFILES, "conv_traffic.txt")
+    """Per-dispatch HBM bytes of the push / history-sweep launch from the committed rocprofv3
+    counter summary, scaled by the copy-kernel calibration; None if absent or taken on other
+    kernel sources."""
+    path = os.path.join(PROFILES, "step_kernel_traffic.txt")
     if not os.path.exists(path):
         return None
     want = f"{workload} {precision} "
@@ -134,6 +136,7 @@ def measure_form(wl, precision, steps, warmup, device, inputs_cache):
         "init_s": t_init,
         "mode_lags": lags,
         "roofline": {
+            "kernel": f"step_kernel (push + history sweep, depth {info['sweep_depth']})",
             "bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": gbs / HBM_PEAK_GBS,
             "traffic": traffic,
@@ -277,7 +280,8 @@ def main():
     for f in forms:
         res[f] = measure_form(wl, f, steps, args.warmup, device, cache)
         print(f"[bench] {f}: {res[f]['value']:.4e} {UNIT}, {res[f]['ms_per_step']:.3f} ms/step, "
-              f"conv {res[f]['roofline']['achieved']:.0f} GB/s ({100 * res[f]['roofline']['frac']:.1f}% of HBM peak)",
+              f"step kernel {res[f]['roofline']['achieved']:.0f} GB/s "
+              f"({100 * res[f]['roofline']['frac']:.1f}% of HBM peak)",
               file=sys.stderr, flush=True)
     acc = None
     if not args.no_accuracy and "fp64" in forms and len(forms) > 1:
@@ -300,8 +304,9 @@ def main():
         "roofline": {k: v for k, v in r["roofline"].items()},
         "cpu_baseline": cpu,
         "forms": {f: {"value": res[f]["value"], "ms_per_step": res[f]["ms_per_step"],
-                      "conv_GBs": res[f]["roofline"]["achieved"],
-                      "conv_frac": res[f]["roofline"]["frac"], "init_s": res[f]["init_s"],
+                      "step_kernel_GBs": res[f]["roofline"]["achieved"],
+                      "step_kernel_frac": res[f]["roofline"]["frac"],
+                      "sweep_depth": res[f]["info"]["sweep_depth"], "init_s": res[f]["init_s"],
                       "ring_bytes": res[f]["info"]["ring_bytes"],
                       "table_bytes": res[f]["info"]["table_bytes"],
                       "kernel_classes": res[f]["info"]["kernel_classes"]} for f in forms},

@@ -66,7 +66,7 @@ extern "C" {
 /* precision */
 #define SBIM_FP64 0       /* double fields, FFTs, history, kernels, sums */
 #define SBIM_FP32 1       /* float fields, FFTs, history, kernels; plain float sums */
-#define SBIM_FP32_COMP 2  /* as SBIM_FP32 with compensated (Neumaier) history sums */
+#define SBIM_FP32_COMP 2  /* as SBIM_FP32 with compensated (Kahan) history sums */
 /* window_mode */
 #define SBIM_W_FIXED 0
 #define SBIM_W_PER_MODE 1
