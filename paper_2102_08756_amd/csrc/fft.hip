@@ -336,10 +336,20 @@ int ilog2(int n) {
   return l;
 }
 
-// Work-group shapes: about 1024 points per work-group (one radix-4 butterfly per
-// thread per pass) when the transform allows it; MAXV, the points a thread
-// stages in registers per pass, is the smallest power of two that covers it.
-int tile_rows(int n1, int Nh) { return max(1, min(min(8, n1), 1024 / Nh)); }
+// Work-group shapes.  The transposed kernels (r2c_t, c2r_t) take at least 4
+// rows where LDS allows (their transposed accesses are `rows` consecutive
+// points long, and shorter runs multiply the HBM traffic, measured), else
+// about 1024 points; the row kernels take about 1024 points.  MAXV, the points
+// a thread stages in registers per pass, is the smallest power of two that
+// covers the work-group's points.
+constexpr size_t kMaxLds = 64 * 1024;
+int tile_rows(int n1, int Nh, size_t point_bytes, int extra_per_row) {
+  int rows = max(4, 1024 / Nh);
+  while (rows > 1 && (rows > n1 || rows * Nh > kFftThreads * kFftPerThread ||
+                      static_cast<size_t>(rows) * (Nh + extra_per_row) * point_bytes > kMaxLds))
+    rows >>= 1;
+  return rows;
+}
 int rows_per_group(int n) { return max(1, 1024 / n); }
 
 template <typename F>
@@ -367,7 +377,7 @@ template <typename Rin, typename R>
 hipError_t forward_impl(const void *in, void *spec, int F, int n1, int n3, const void *tw,
                         hipStream_t st) {
   const int Nh = n3 / 2, h3 = Nh + 1;
-  const int rows = tile_rows(n1, Nh);
+  const int rows = tile_rows(n1, Nh, sizeof(cplx<R>), 0);
   hipError_t e = with_maxv(rows * Nh, [&](auto mv) {
     hipLaunchKernelGGL((r2c_t_kernel<Rin, R, decltype(mv)::value>),
                        dim3(static_cast<unsigned>(F * (n1 / rows))), dim3(kFftThreads),
@@ -386,7 +396,7 @@ hipError_t inverse_impl(void *spec, void *out, const void *add, int F, int n1, i
   const int Nh = n3 / 2, h3 = Nh + 1;
   hipError_t e = cfft_launch<R>(spec, static_cast<long long>(F) * h3, n1, +1, tw, st);
   if (e != hipSuccess) return e;
-  const int rows = tile_rows(n1, Nh);
+  const int rows = tile_rows(n1, Nh, sizeof(cplx<R>), 1);
   return with_maxv(rows * Nh, [&](auto mv) {
     hipLaunchKernelGGL((c2r_t_kernel<R, decltype(mv)::value>),
                        dim3(static_cast<unsigned>(F * (n1 / rows))), dim3(kFftThreads),

@@ -88,6 +88,9 @@ CASES = {
     "plane256_w300": (4, {}, None, ["fp64", "fp32"]),
     "two_planes2048_permode400": (3, {"bank": 8}, 450, ["fp32_comp"]),
     "two_planes1024_w2000": (5, {"slip_ramp": 10.0}, 2100, ["fp32_comp"]),
+    # the largest grid the library accepts (4096-point transforms along both axes)
+    "two_planes4096_permode8": (3, {"n1": 4096, "n3": 4096, "window_cap": 8, "bank": 2}, 12,
+                                ["fp64", "fp32_comp"]),
 }
 
 

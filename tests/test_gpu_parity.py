@@ -153,23 +153,35 @@ SWEEP_CFG = dict(n1=32, n3=64, dx1=1.0, dx3=0.8, dt=0.2, window_cap=40, window_m
                  eta_w=1.5, input_kind="increment", planes=[dict(side=1), dict(side=-1)])
 
 
+# Windows of one and two lags (blocks whose capacity is below the sweep depth)
+# next to windows up to the cap.
+TINYWIN_CFG = dict(n1=32, n3=16, dx1=1.0, dx3=1.0, dt=0.2, window_cap=5, window_mode="per_mode",
+                   eta_w=0.04, input_kind="absolute", planes=[dict(side=1), dict(side=-1)])
+SWEEP_CASES = {"ragged40": (SWEEP_CFG, 90, 7), "tinywin": (TINYWIN_CFG, 30, 9)}
+
+
 @pytest.fixture(scope="module")
-def sweep_case():
-    u, _, _ = _inputs(SWEEP_CFG, 90, 7)
-    return u, oracle.forward(SWEEP_CFG, u)
+def sweep_refs():
+    out = {}
+    for name, (cfg, steps, seed) in SWEEP_CASES.items():
+        u, _, _ = _inputs(cfg, steps, seed)
+        out[name] = (u, oracle.forward(cfg, u))
+    return out
 
 
+@pytest.mark.parametrize("case", sorted(SWEEP_CASES))
 @pytest.mark.parametrize("depth", [1, 2, 4, 6, 8])
 @pytest.mark.parametrize("precision", ["fp64", "fp32_comp", "fp32"])
-def test_sweep_depths(sweep_case, depth, precision, monkeypatch):
+def test_sweep_depths(sweep_refs, case, depth, precision, monkeypatch):
     monkeypatch.setenv("SBIM_SWEEP_DEPTH", str(depth))
-    u, ref = sweep_case
-    sb = SBIM(Config.from_dict(SWEEP_CFG, precision=precision), device=DEV)
+    cfg = SWEEP_CASES[case][0]
+    u, ref = sweep_refs[case]
+    sb = SBIM(Config.from_dict(cfg, precision=precision), device=DEV)
     assert sb.info()["sweep_depth"] == depth
     sb.close()
-    got = run_gpu(SWEEP_CFG, u, precision)
+    got = run_gpu(cfg, u, precision)
     err = rel_l2(got, ref)
-    print(f"sweep depth {depth} {precision}: rel-L2 {err:.3e}")
+    print(f"{case} sweep depth {depth} {precision}: rel-L2 {err:.3e}")
     assert err < TOL[precision]
 
 
