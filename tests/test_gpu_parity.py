@@ -208,3 +208,23 @@ def test_tractions_repeatable_and_snapshots_mid_rotation():
         sb.push(ut[n])
         assert torch.equal(sb.tractions(), first[n]), n
     sb.close()
+
+
+@pytest.mark.parametrize("depth", [1, 2, 6, 8])
+@pytest.mark.parametrize("kind", ["absolute", "increment"])
+def test_adjoint_sweep_depths(depth, kind, monkeypatch):
+    """The adjoint runs the same sweep on its own history: exact transpose at every depth."""
+    monkeypatch.setenv("SBIM_SWEEP_DEPTH", str(depth))
+    cfg_d = dict(SWEEP_CFG, input_kind=kind)
+    u, _, _ = _inputs(cfg_d, 30, 10)
+    g = np.random.default_rng(11).standard_normal(u.shape)
+    du_ref, _ = oracle.adjoint(cfg_d, g)
+    sb = SBIM(Config.from_dict(cfg_d, precision="fp64"), device=DEV)
+    assert sb.info()["sweep_depth"] == depth
+    ut = torch.tensor(u, device=DEV, requires_grad=True)
+    tau = SBIMRun.apply(sb, ut)
+    (tau * torch.tensor(g, device=DEV)).sum().backward()
+    err = rel_l2(ut.grad.cpu().numpy(), du_ref)
+    print(f"adjoint depth {depth} {kind}: rel-L2 {err:.3e}")
+    assert err < 1e-12
+    sb.close()
