@@ -17,7 +17,6 @@ constexpr int kTwiddleN = 1 << kTwiddleLog;
 constexpr int kFftThreads = 256;
 constexpr int kFftPerThread = 16;     // transform points per thread in the LDS FFT kernels
 constexpr int kGaussN = 32;           // Gauss-Legendre points per quadrature panel
-constexpr int kLagGroups = 4;         // lag chunks per sweep wavefront (16 lanes each)
 constexpr int kMaxSweep = 8;          // deepest sweep: steps served by one pass over a history
 
 // What push_kernel stores as "velocity" for the epilogue.

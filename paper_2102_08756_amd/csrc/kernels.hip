@@ -164,6 +164,14 @@ template <typename R, int S, bool COMP> constexpr int sweep_group() {
   return S % g == 0 ? g : (S % 2 == 0 ? 2 : 1);  // a divisor of the span
 }
 
+// Lag chunks per sweep wavefront (measured on gfx950, 512x512 x 2 planes,
+// W = 1000): four (16 modes x 4 chunks) where three wavefronts fit per SIMD
+// (float32), two (32 modes x 2 chunks, 256-byte segments, half the
+// wavefronts) where two fit (float64, compensated).
+template <typename R, int S, bool COMP> constexpr int sweep_lag_groups() {
+  return (COMP || sizeof(R) == 8) ? 2 : 4;
+}
+
 // Rows k0 .. k0+S-1 of a mode's kernel.  A class's W rows are followed by a
 // zero row, so clamping the lag to W gives zero from the window on.
 template <typename R, int S>
@@ -221,17 +229,17 @@ __device__ __forceinline__ void sweep_span(R (&sums)[S][kSums], const typename W
 // each row is loaded once and never moved.
 //
 // Lag chunks are whole spans long, so chunks never overlap and no lane needs a
-// mask: chunks reach past the last entry by less than 4 spans, and a lag
+// mask: chunks reach past the last entry by less than LG spans, and a lag
 // i > min(cap-1, n) either meets zero kernel rows (i + s >= cap >= W) or a
 // ring slot not written since the last reset, which holds zero (the slot that
 // the concurrent push writes is lag cap, whose rows are zero).
 //
-// Work item (one wavefront) = (block of the phase, plane, quarter of the
-// block's 64 modes).  Its 64 lanes are 16 modes x 4 lag chunks: lane l takes
-// mode l mod 16 of the quarter and chunk l / 16 of the lags, so each history
-// load fetches four 128-byte segments, one per chunk.  The chunks are then
-// summed by a butterfly over lanes l ^ 16, l ^ 32 (fixed order, so the result
-// is bitwise reproducible).
+// Work item (one wavefront) = (block of the phase, plane, group of Q of the
+// block's 64 modes).  Its 64 lanes are Q modes x LG lag chunks (Q = 64 / LG):
+// lane l takes mode l mod Q of the group and chunk l / Q of the lags, so each
+// history load fetches LG segments of Q x 8 bytes (float32), one per chunk.
+// The chunks are then summed by a butterfly over lanes l ^ Q, l ^ 2Q, ...
+// (fixed order, so the result is bitwise reproducible).
 template <typename R, int S, bool COMP>
 __device__ __forceinline__ void sweep_item(const SweepArgs &a, long long item) {
   using W = typename W4<R>::T;
@@ -240,18 +248,19 @@ __device__ __forceinline__ void sweep_item(const SweepArgs &a, long long item) {
   R *__restrict__ pending = static_cast<R *>(a.pending);
   const long long M = a.M, step = a.step;
   const int np = a.np;
-  constexpr int Q = kLanes / kLagGroups;  // modes per item
+  constexpr int LG = sweep_lag_groups<R, S, COMP>();
+  constexpr int Q = kLanes / LG;  // modes per item
   // Items of one block get ids congruent mod 8, so they run on one XCD and
   // share the block's kernel rows in its L2.
-  const int per_blk = kLagGroups * np;
+  const int per_blk = LG * np;
   const long long kb = (item / (8LL * per_blk)) * 8 + (item & 7);
   if (kb >= a.nphase) return;
   const int r = static_cast<int>((item >> 3) % per_blk);
-  const int p = r / kLagGroups;
+  const int p = r / LG;
   const long long b = step % S + S * kb;
   const int lane = threadIdx.x;
   const int lg = lane / Q;
-  const int col = (r % kLagGroups) * Q + lane % Q;  // lane of the mode in its block
+  const int col = (r % LG) * Q + lane % Q;  // lane of the mode in its block
   const long long sm = b * kLanes + col;
   const bool valid = sm < M;
   const int cap = a.blk_cap[b];
@@ -259,7 +268,7 @@ __device__ __forceinline__ void sweep_item(const SweepArgs &a, long long item) {
   const int nent = static_cast<int>(max(0LL, min(static_cast<long long>(cap) - 1, step)));
   const int wl = valid ? a.win[sm] : 0;
   const int cl = valid ? a.cls[sm] : 0;
-  const int per = (nent + kLagGroups * S - 1) / (kLagGroups * S) * S;  // lags per chunk
+  const int per = (nent + LG * S - 1) / (LG * S) * S;  // lags per chunk
   const int i0 = 1 + lg * per;
 
   constexpr int G = sweep_group<R, S, COMP>();
@@ -306,14 +315,14 @@ __device__ __forceinline__ void sweep_item(const SweepArgs &a, long long item) {
   for (int s = 0; s < S; ++s)
 #pragma unroll
     for (int k = 0; k < kSums; ++k) acc[s][k].fold(sums[s][k]);
-  // sum the four lag chunks of each mode; lanes of chunk 0 store
+  // sum the lag chunks of each mode; lanes of chunk 0 store
 #pragma unroll
   for (int s = 0; s < S; ++s) {
     const long long slot = (step + s) % S;
 #pragma unroll
     for (int k = 0; k < kSums; ++k) {
-      acc[s][k].fold_lane(Q);
-      acc[s][k].fold_lane(2 * Q);
+#pragma unroll
+      for (int off = Q; off < kLanes; off <<= 1) acc[s][k].fold_lane(off);
       if (lg == 0 && valid)
         pending[((slot * np + p) * kSums + k) * M + sm] = acc[s][k].value();
     }
@@ -592,7 +601,8 @@ hipError_t step_launch_s(const sbim_handle *h, const Group &g, const SweepArgs &
   SweepArgs sa = sa0;
   const int phase = static_cast<int>(sa.step % S);
   sa.nphase = g.nblocks > phase ? (g.nblocks - phase + S - 1) / S : 0;
-  const long long sweep_items = (sa.nphase + 7) / 8 * 8 * kLagGroups * g.np;
+  const long long sweep_items =
+      (sa.nphase + 7) / 8 * 8 * sweep_lag_groups<R, S, COMP>() * g.np;
   const long long items = sweep_items + g.nblocks * g.np;
   if (ev0) (void)hipEventRecord(ev0, h->stream);
   hipLaunchKernelGGL((step_kernel<R, S, COMP>), dim3(static_cast<unsigned>(items)), dim3(kLanes),
