@@ -105,7 +105,7 @@ typedef struct {
   long long kernel_classes;    /* distinct (q, W) rows of the kernel tables, all groups */
   long long ring_bytes;        /* forward history ring */
   long long table_bytes;       /* kernel tables */
-  long long state_bytes;       /* float64 running state + velocity spectra */
+  long long state_bytes;       /* float64 running state */
   long long step;              /* pushes since init / reset */
   long long backward_step;     /* sbim_backward calls since the last reset */
   int material_groups;         /* planes sharing (c_s, c_p) share one table and one pass */
@@ -129,12 +129,14 @@ int sbim_init(const sbim_config *cfg, sbim_handle **out);
  *              u^n - u^{n-1} (SBIM_INCREMENT)
  *   v_or_null  device [P][3][n1][n3] velocity prediction for the damping term
  *              of this step, or NULL to use (u^n - u^{n-1}) / dt
- * Exactly one push precedes each sbim_tractions call.  The push also runs the
- * history sweep of this step, in the same launch: the 64-mode blocks whose
- * turn it is (one in sweep_depth of them, in rotation) read their history
- * window before this step once and store the part of each of the next
- * sweep_depth steps' history sums that this history already fixes; every
- * step thus reads each history entry 1/sweep_depth times on average.
+ * Exactly one push precedes each sbim_tractions call.  The push computes
+ * the traction spectrum of this step (the inverse transform is left to
+ * sbim_tractions) and, in the same launch, the history sweep for the coming
+ * steps: the 64-mode blocks whose turn it is (one in sweep_depth of them, in
+ * rotation) read their history window up to the previous step once and store
+ * the part of each of the next sweep_depth steps' history sums that this
+ * history already fixes; every step thus reads each history entry
+ * 1/sweep_depth times on average.
  */
 int sbim_push_displacement(sbim_handle *h, const void *u, const void *v_or_null);
 
@@ -142,8 +144,8 @@ int sbim_push_displacement(sbim_handle *h, const void *u, const void *v_or_null)
  * sbim_tractions: tau^n of the last pushed step into device [P][3][n1][n3].
  *   tau_inf_or_null  device [P][3][n1][n3] far-field traction added to the
  *                    result, or NULL for zero.
- * It adds to each mode's pending sum the lags from its block's last sweep on,
- * so it reads no state that it changes: calling it again before the next push
+ * It applies the inverse transform to the traction spectrum that the last
+ * push completed and changes no state: calling it again before the next push
  * returns the same tractions.
  * SBIM_E_STATE if no step was pushed since init/reset.
  */
@@ -179,8 +181,8 @@ int sbim_get_info(const sbim_handle *h, sbim_info *out);
 
 /*
  * Snapshots for checkpointing: the full forward state (ring, running state,
- * velocity spectra, pending history sums of the coming steps, step counter)
- * is sbim_state_bytes() bytes.  save/load
+ * pending history sums of the coming steps, traction spectrum of the last
+ * step, step counter) is sbim_state_bytes() bytes.  save/load
  * copy it to/from a caller-owned device buffer of at least that size,
  * asynchronously on the handle's stream.
  */
@@ -192,12 +194,14 @@ int sbim_load_state(sbim_handle *h, const void *src_device);
  * Work of the step with index n (0-based): *mode_lags = the number of
  * (plane, mode, lag) products of that step's history sums, i.e. min(W(q), n+1)
  * summed over planes and modes; *conv_bytes = the bytes that the one launch
- * of that step's push must move: the history sweep (the history before step
- * n of the modes whose block sweeps at step n, phase n mod sweep_depth; the
- * kernel rows of each distinct row class in those blocks; their row/window
- * indices and block descriptors; the sweep_depth pending sums written per mode
- * and plane) and the push itself (spectrum gathered, float64 state read and
- * written, ring slot and velocity written, per-mode bin and direction).
+ * of that step's push must move: the history sweep (the history up to step
+ * n-1 of the modes whose block sweeps for steps n+1 .. n+sweep_depth, phase
+ * (n+1) mod sweep_depth; the kernel rows of each distinct row class in those
+ * blocks; their row/window indices and block descriptors; the sweep_depth
+ * pending sums written per mode and plane) and the mode items (spectrum
+ * gathered, float64 state read and written, ring slot written, pending sum
+ * read, newest lags and their kernel rows read, traction spectrum written,
+ * per-mode indices and geometry).
  */
 int sbim_step_work(const sbim_handle *h, long long n, double *mode_lags, double *conv_bytes);
 

@@ -245,20 +245,20 @@ __global__ __launch_bounds__(kFftThreads) void r2c_t_kernel(
   }
 }
 
-// Complex FFT along contiguous rows of length n (in place); `per` rows per work-group.
+// Complex FFT along contiguous rows of length n, from `src` into `dst` (the
+// same array for in place); `per` rows per work-group.
 template <typename R, int MAXV>
 __global__ __launch_bounds__(kFftThreads) void cfft_rows_kernel(
-    cplx<R> *__restrict__ data, long long nrows, int n, int logn, int per, int dir,
+    const cplx<R> *src, cplx<R> *dst, long long nrows, int n, int logn, int per, int dir,
     const cplx<R> *__restrict__ tw) {
   extern __shared__ unsigned char smem_raw[];
   cplx<R> *buf = reinterpret_cast<cplx<R> *>(smem_raw);
   const long long row0 = static_cast<long long>(blockIdx.x) * per;
   const int nb = static_cast<int>(min(static_cast<long long>(per), nrows - row0));
-  cplx<R> *base = data + row0 * n;
-  for (int e = threadIdx.x; e < nb * n; e += kFftThreads) buf[e] = base[e];
+  for (int e = threadIdx.x; e < nb * n; e += kFftThreads) buf[e] = src[row0 * n + e];
   __syncthreads();
   lds_fft<R, kFftThreads, MAXV>(buf, n, logn, nb, dir, tw);
-  for (int e = threadIdx.x; e < nb * n; e += kFftThreads) base[e] = buf[e];
+  for (int e = threadIdx.x; e < nb * n; e += kFftThreads) dst[row0 * n + e] = buf[e];
 }
 
 // Inverse, last step: rows x1 in [x0, x0 + R) of one field from the transposed
@@ -360,15 +360,15 @@ hipError_t with_maxv(int points, F &&launch) {
 }
 
 template <typename R>
-hipError_t cfft_launch(void *spec, long long nrows, int n, int dir, const void *tw,
-                       hipStream_t st) {
+hipError_t cfft_launch(const void *src, void *dst, long long nrows, int n, int dir,
+                       const void *tw, hipStream_t st) {
   const int per = rows_per_group(n);
   return with_maxv(per * n, [&](auto mv) {
     hipLaunchKernelGGL((cfft_rows_kernel<R, decltype(mv)::value>),
                        dim3(static_cast<unsigned>((nrows + per - 1) / per)), dim3(kFftThreads),
                        static_cast<size_t>(per) * n * sizeof(cplx<R>), st,
-                       static_cast<cplx<R> *>(spec), nrows, n, ilog2(n), per, dir,
-                       static_cast<const cplx<R> *>(tw));
+                       static_cast<const cplx<R> *>(src), static_cast<cplx<R> *>(dst), nrows, n,
+                       ilog2(n), per, dir, static_cast<const cplx<R> *>(tw));
     return hipGetLastError();
   });
 }
@@ -387,21 +387,21 @@ hipError_t forward_impl(const void *in, void *spec, int F, int n1, int n3, const
     return hipGetLastError();
   });
   if (e != hipSuccess) return e;
-  return cfft_launch<R>(spec, static_cast<long long>(F) * h3, n1, -1, tw, st);
+  return cfft_launch<R>(spec, spec, static_cast<long long>(F) * h3, n1, -1, tw, st);
 }
 
 template <typename R>
-hipError_t inverse_impl(void *spec, void *out, const void *add, int F, int n1, int n3,
-                        double scale, const void *tw, hipStream_t st) {
+hipError_t inverse_impl(const void *spec, void *scratch, void *out, const void *add, int F, int n1,
+                        int n3, double scale, const void *tw, hipStream_t st) {
   const int Nh = n3 / 2, h3 = Nh + 1;
-  hipError_t e = cfft_launch<R>(spec, static_cast<long long>(F) * h3, n1, +1, tw, st);
+  hipError_t e = cfft_launch<R>(spec, scratch, static_cast<long long>(F) * h3, n1, +1, tw, st);
   if (e != hipSuccess) return e;
   const int rows = tile_rows(n1, Nh, sizeof(cplx<R>), 1);
   return with_maxv(rows * Nh, [&](auto mv) {
     hipLaunchKernelGGL((c2r_t_kernel<R, decltype(mv)::value>),
                        dim3(static_cast<unsigned>(F * (n1 / rows))), dim3(kFftThreads),
                        static_cast<size_t>(rows) * (Nh + 1) * sizeof(cplx<R>), st,
-                       static_cast<const cplx<R> *>(spec), static_cast<R *>(out),
+                       static_cast<const cplx<R> *>(scratch), static_cast<R *>(out),
                        static_cast<const R *>(add), n1, n3, ilog2(Nh), rows,
                        static_cast<R>(scale), static_cast<const cplx<R> *>(tw));
     return hipGetLastError();
@@ -416,10 +416,11 @@ hipError_t launch_fft_forward(bool in_fp64, const void *in, void *spec, int F, i
                  : forward_impl<float, double>(in, spec, F, n1, n3, tw64, st);
 }
 
-hipError_t launch_fft_inverse(bool fp64, void *spec, void *out, const void *add, int F, int n1,
-                              int n3, double scale, const void *tw, hipStream_t st) {
-  return fp64 ? inverse_impl<double>(spec, out, add, F, n1, n3, scale, tw, st)
-              : inverse_impl<float>(spec, out, add, F, n1, n3, scale, tw, st);
+hipError_t launch_fft_inverse(bool fp64, const void *spec, void *scratch, void *out,
+                              const void *add, int F, int n1, int n3, double scale, const void *tw,
+                              hipStream_t st) {
+  return fp64 ? inverse_impl<double>(spec, scratch, out, add, F, n1, n3, scale, tw, st)
+              : inverse_impl<float>(spec, scratch, out, add, F, n1, n3, scale, tw, st);
 }
 
 // Twiddles exp(-2 pi i m / 4096), m = 0..4095, from long-double sin/cos on the host.

@@ -59,14 +59,12 @@ struct Group {
   void *table = nullptr;          // [table_rows] x 4 reals (w11, w12, w22, w33)
   void *ring = nullptr;           // [ring_records][np][3][64] complex
   double *state = nullptr;        // [np][3][M] complex double (rotated frame, sorted)
-  void *vel = nullptr;            // [np][3][M] complex real_t
-  void *pending = nullptr;        // [depth][np][10][M] real_t: history sums of coming steps
+  void *pending = nullptr;        // [depth+1][np][10][M] real_t: history sums of coming steps
   // adjoint (allocated on first use)
   void *ring_adj = nullptr;
   void *pending_adj = nullptr;
   double *state_adj = nullptr;    // previous g spectrum (float64)
   double *lam_adj = nullptr;      // reverse running sum (float64)
-  void *vel_adj = nullptr;
   // host copies for diagnostics / work accounting
   std::vector<int> h_nat, h_cls, h_win;
   std::vector<long long> h_cls_off;
@@ -88,13 +86,13 @@ struct sbim_handle {
   sbim::Group g[SBIM_MAX_PLANES];
   long long step = 0;             // pushes done
   long long bstep = 0;            // backward calls done
-  bool pushed_since_tractions = false;
   int depth = 1;                  // sweep depth: steps served by one pass over a block's history
   void *twiddle = nullptr;        // [4096] complex real_t, exp(-2 pi i m / 4096)
   void *twiddle64 = nullptr;      // the same in float64 (== twiddle for SBIM_FP64)
   void *spec = nullptr;           // [P][3][h3][n1] complex float64: spectrum of the pushed field
   void *spec_v = nullptr;         // same for the velocity; second traction output of backward
-  void *out_spec = nullptr;       // [P][3][h3][n1] complex: traction spectrum
+  void *out_spec = nullptr;       // [P][3][h3][n1] complex: traction spectrum of the last push
+  void *out_adj = nullptr;        // the same for the last sbim_backward (allocated on first use)
   bool profile = false;
   std::vector<hipEvent_t> ev_start, ev_stop;  // reusable pool
   size_t ev_used = 0;                          // pairs recorded since sbim_profile_conv
@@ -108,55 +106,59 @@ namespace sbim {
 // float64 running state); in_fp64 selects the type of the input field.
 hipError_t launch_fft_forward(bool in_fp64, const void *in, void *spec, int F, int n1, int n3,
                               const void *tw64, hipStream_t st);
-// (spec is overwritten) out = scale * inverse(spec) + add_or_null
-hipError_t launch_fft_inverse(bool fp64, void *spec, void *out, const void *add_or_null, int F,
-                              int n1, int n3, double scale, const void *tw, hipStream_t st);
+// out = scale * inverse(spec) + add_or_null; spec is left intact, `scratch`
+// (the size of spec) receives the intermediate transform.
+hipError_t launch_fft_inverse(bool fp64, const void *spec, void *scratch, void *out,
+                              const void *add_or_null, int F, int n1, int n3, double scale,
+                              const void *tw, hipStream_t st);
 hipError_t upload_twiddles(bool fp64, void *dst, hipStream_t st);
 
 // kernels.hip
-struct PushLaunch {
+//
+// The history sums are split over time.  Block b of 64 modes has phase
+// b mod depth.  The launch of step n sweeps the blocks of phase (n+1) mod
+// depth: each reads its history up to step n-1 once and stores, for each of
+// the steps n+1 .. n+depth, the part of that step's sum over that history
+// ("pending" sums, depth+1 slots).  The same launch pushes step n for every
+// mode and completes its traction: the pending sum of step n plus the lags
+// from the block's last sweep on (at most depth+1 of them), damping and
+// instantaneous terms.
+struct StepLaunch {
   const void *spec;       // [P][3][nh] complex float64 (spectrum layout)
   const void *spec_v;     // velocity spectrum (same type) or null
   void *ring;
   double *state;
-  void *vel;
+  void *pending;
+  double *lam;            // non-null: accumulate (conv + instantaneous) into this float64 state
+  void *out_a;            // [P][3][nh] complex: output spectrum
+  void *out_b;            // non-null: damping part written here instead of added to out_a
   long long nh;
   long long step;         // index of this push
   double dt;
   int vel_rule, state_rule;
 };
-
-// The history sums are split over time.  Block b of 64 modes has phase
-// b mod depth; at each step n the blocks of phase n mod depth sweep their
-// history before step n once and store, for each of the steps n .. n+depth-1,
-// the part of that step's sum over that history ("pending" sums).  The
-// epilogue of step n adds to the pending sum of each mode the lags from its
-// block's last sweep on (at most depth of them).
-struct SweepLaunch {
-  const void *ring;
-  void *pending;
-  long long step;
-};
-// One launch: the sweep of step `step` and the push of that step (bracketed
-// by ev0/ev1 when they are non-null).
-hipError_t launch_step(const sbim_handle *h, const Group &g, const PushLaunch &p,
-                       const SweepLaunch &w, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+// One launch, bracketed by ev0/ev1 when they are non-null.
+hipError_t launch_step(const sbim_handle *h, const Group &g, const StepLaunch &w,
+                       hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 
 // Kernel arguments (device pointers) of the two item kinds of that launch.
-struct PushArgs {
+struct ModeArgs {
   const void *spec, *spec_v;
   void *ring;
   double2 *state;
-  void *vel;
-  const int *nat;
+  const void *pending, *table;
+  const long long *cls_off;
+  const int *cls, *win, *nat;
   const double *geom;
   const long long *blk_off;
   const int *blk_cap, *blk_stride;
-  long long M, nh;
-  int np, plane0, plane1;
-  long long step;
+  double2 *lam;
+  void *out_a, *out_b;
+  long long M, nh, step;
+  int np, depth;
   double inv_dt;
   int vel_rule, state_rule;
+  PlaneParams p0, p1;
 };
 struct SweepArgs {
   const void *ring, *table;
@@ -168,22 +170,8 @@ struct SweepArgs {
   int cls_w0;             // rows of class 0 (its zero row follows them)
   long long M, step;
   int np;
-  long long nphase;       // blocks of this step's phase
+  long long nphase;       // blocks of this launch's sweep phase
 };
-
-struct ConvLaunch {
-  const void *ring;
-  const void *pending;
-  const void *vel;
-  double *lam;            // non-null: accumulate (conv + instantaneous) into this float64 state
-  void *out_a;            // [P][3][nh] complex: output spectrum
-  void *out_b;            // non-null: damping part written here instead of added to out_a
-  long long nh;
-  long long step;
-};
-// Per-mode epilogue: pending sum + newest lags, damping and instantaneous
-// terms, rotation back to (x1, x2, x3), scatter into the spectrum.
-hipError_t launch_conv(const sbim_handle *h, const Group &g, const ConvLaunch &a);
 
 hipError_t launch_tabulate(bool fp64, const Group &g, double dt, const double *gl_x,
                            const double *gl_w, hipStream_t st);

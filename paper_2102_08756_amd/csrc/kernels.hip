@@ -1,14 +1,15 @@
 // Mode-space kernels of the boundary-integral step on gfx950:
-//   step_kernel          two kinds of items in one launch: the push (rotate a new
-//                        spectrum into the wavevector frame, update the float64
-//                        running state, store the history ring slot and the
-//                        velocity spectrum used by the damping term) and the
-//                        history sweep (the truncated history convolution, the
-//                        nonlocal term of Eq. SBI, Sec. 2.3: one pass over a
-//                        block's history serving several steps);
-//   conv_epilogue_kernel the newest lags, damping and instantaneous terms and the
-//                        rotation back to (x1, x2, x3);
-//   tabulate_kernel      float64 quadrature of the per-lag kernel weights.
+//   step_kernel      two kinds of items in one launch per step:
+//                    mode items: the push (rotate the new spectrum into the
+//                    wavevector frame, update the float64 running state, store
+//                    the history ring slot) and, from the same registers, the
+//                    traction of the step (pending history sum plus the newest
+//                    lags, damping and instantaneous terms of Eq. SBI, Sec. 2.3,
+//                    rotation back to (x1, x2, x3));
+//                    sweep items: the truncated history convolution (the
+//                    nonlocal term of Eq. SBI), one pass over a block's history
+//                    serving the next several steps;
+//   tabulate_kernel  float64 quadrature of the per-lag kernel weights.
 //
 // Layouts (one material group; modes sorted by (W desc, q asc), 64 per block):
 //   ring    [record][plane][component L,N,T][64 lanes] complex.  Step n of
@@ -35,68 +36,6 @@ template <> struct W4<float> { using T = float4; };
 template <> struct W4<double> { using T = double4; };
 
 // ------------------------------------------------------------------ push
-
-// Push of one (mode, plane): rotate the new spectrum into the wavevector
-// frame, update the float64 running state, store the ring slot and the
-// velocity spectrum used by the damping term.
-template <typename R>
-__device__ __forceinline__ void push_mode(const PushArgs &a, int p, long long s) {
-  const double2 *__restrict__ spec = static_cast<const double2 *>(a.spec);
-  const double2 *__restrict__ spec_v = static_cast<const double2 *>(a.spec_v);
-  cplx<R> *__restrict__ ring = static_cast<cplx<R> *>(a.ring);
-  double2 *__restrict__ state = a.state;
-  cplx<R> *__restrict__ vel = static_cast<cplx<R> *>(a.vel);
-  const long long M = a.M, nh = a.nh;
-  const int np = a.np;
-  const long long natural = a.nat[s];
-  const double kh1 = a.geom[4 * s + 1];
-  const double kh3 = a.geom[4 * s + 2];
-  const long long b = s >> 6;
-  const int lane = static_cast<int>(s & 63);
-  const int cap = a.blk_cap[b];
-  const long long rec = cap > 0 ? a.blk_off[b] + (a.step % cap) * a.blk_stride[b] : 0;
-  const int pg = p == 0 ? a.plane0 : a.plane1;
-  double2 x[3];
-#pragma unroll
-  for (int c = 0; c < 3; ++c) x[c] = spec[(pg * 3 + c) * nh + natural];
-  // (1, 2, 3) -> (L, N, T)
-  const double2 xr[3] = {{kh1 * x[0].x + kh3 * x[2].x, kh1 * x[0].y + kh3 * x[2].y},
-                         x[1],
-                         {-kh3 * x[0].x + kh1 * x[2].x, -kh3 * x[0].y + kh1 * x[2].y}};
-  double2 vr[3];
-  if (a.vel_rule == VEL_INPUT) {
-    double2 y[3];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) y[c] = spec_v[(pg * 3 + c) * nh + natural];
-    vr[0] = double2{kh1 * y[0].x + kh3 * y[2].x, kh1 * y[0].y + kh3 * y[2].y};
-    vr[1] = y[1];
-    vr[2] = double2{-kh3 * y[0].x + kh1 * y[2].x, -kh3 * y[0].y + kh1 * y[2].y};
-  }
-#pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    const long long si = (static_cast<long long>(p) * 3 + c) * M + s;
-    const double2 prev = state[si];
-    double2 now;
-    if (a.state_rule == STATE_ACCUM)
-      now = double2{prev.x + xr[c].x, prev.y + xr[c].y};
-    else
-      now = xr[c];
-    state[si] = now;
-    double2 v;
-    if (a.vel_rule == VEL_DIFF)
-      v = double2{(now.x - prev.x) * a.inv_dt, (now.y - prev.y) * a.inv_dt};
-    else if (a.vel_rule == VEL_SCALE)
-      v = double2{xr[c].x * a.inv_dt, xr[c].y * a.inv_dt};
-    else if (a.vel_rule == VEL_INPUT)
-      v = vr[c];
-    else
-      v = xr[c];
-    vel[si] = cplx<R>{static_cast<R>(v.x), static_cast<R>(v.y)};
-    if (cap > 0)
-      ring[((rec * np + p) * 3 + c) * kLanes + lane] =
-          cplx<R>{static_cast<R>(now.x), static_cast<R>(now.y)};
-  }
-}
 
 // ------------------------------------------------------------------ conv
 
@@ -219,20 +158,23 @@ __device__ __forceinline__ void sweep_span(R (&sums)[S][kSums], const typename W
   }
 }
 
-// The sweep of step n.  Blocks of phase n mod S read their history before
-// step n once, U^{n-i} for i = 1 .. min(cap-1, n), and form for each coming
-// step n+s (s = 0 .. S-1) its sum over that history:
-//   pending[(n+s) mod S] = sum_{i>=1} w_{i+s} (x) U^{n-i}   (lags i+s inside the window).
-// It does not read U^n, so it runs in the same launch as the push of step n.
+// The sweep launched with step n serves steps t0 = n+1 .. n+S.  Blocks of
+// phase t0 mod S read their history up to step n-1 once, U^{t0-i} for
+// i = 2 .. min(cap-1, t0), and form for each of those steps t0+s its sum over
+// that history:
+//   pending[(t0+s) mod (S+1)] = sum_{i>=2} w_{i+s} (x) U^{t0-i}   (lags i+s inside the window).
+// It reads neither U^n nor the pending sum of step n, so it runs in the same
+// launch as the push and traction of step n (S+1 pending slots keep step n's
+// sum apart from the S being written).
 // Each history entry thus serves S steps.  The kernel rows i .. i+2S-2 that a
 // span of S entries needs are held in two register arrays used in turn, so
 // each row is loaded once and never moved.
 //
 // Lag chunks are whole spans long, so chunks never overlap and no lane needs a
 // mask: chunks reach past the last entry by less than LG spans, and a lag
-// i > min(cap-1, n) either meets zero kernel rows (i + s >= cap >= W) or a
+// i > min(cap-1, t0) either meets zero kernel rows (i + s >= cap >= W) or a
 // ring slot not written since the last reset, which holds zero (the slot that
-// the concurrent push writes is lag cap, whose rows are zero).
+// the concurrent push writes is lag 1 or cap+1, whose rows are unused or zero).
 //
 // Work item (one wavefront) = (block of the phase, plane, group of Q of the
 // block's 64 modes).  Its 64 lanes are Q modes x LG lag chunks (Q = 64 / LG):
@@ -257,19 +199,20 @@ __device__ __forceinline__ void sweep_item(const SweepArgs &a, long long item) {
   if (kb >= a.nphase) return;
   const int r = static_cast<int>((item >> 3) % per_blk);
   const int p = r / LG;
-  const long long b = step % S + S * kb;
+  const long long t0 = step + 1;
+  const long long b = t0 % S + S * kb;
   const int lane = threadIdx.x;
   const int lg = lane / Q;
   const int col = (r % LG) * Q + lane % Q;  // lane of the mode in its block
   const long long sm = b * kLanes + col;
   const bool valid = sm < M;
   const int cap = a.blk_cap[b];
-  // history entries before step n that any lag of the window can reach
-  const int nent = static_cast<int>(max(0LL, min(static_cast<long long>(cap) - 1, step)));
+  // history entries (lags 2 .. min(cap-1, t0) of step t0) that the window can reach
+  const int nent = static_cast<int>(max(0LL, min(static_cast<long long>(cap) - 1, t0) - 1));
   const int wl = valid ? a.win[sm] : 0;
   const int cl = valid ? a.cls[sm] : 0;
   const int per = (nent + LG * S - 1) / (LG * S) * S;  // lags per chunk
-  const int i0 = 1 + lg * per;
+  const int i0 = 2 + lg * per;
 
   constexpr int G = sweep_group<R, S, COMP>();
   // plain form: the running sums; compensated form: the products since the
@@ -280,12 +223,12 @@ __device__ __forceinline__ void sweep_item(const SweepArgs &a, long long item) {
 #pragma unroll
     for (int k = 0; k < kSums; ++k) sums[s][k] = R(0);
   Acc<R, COMP> acc[S][kSums];
-  if (per > 0) {  // then cap > 1, so the block has a mode with W > 0 and class 0 exists
+  if (per > 0) {  // then cap > 2, so the block has a mode with W > 0 and class 0 exists
     const long long rec_len = static_cast<long long>(np) * 3 * kLanes;
     const long long dstep = a.blk_stride[b] * rec_len;  // elements between consecutive slots
     const long long dwrap = static_cast<long long>(cap) * dstep;
-    // ring slot of lag i0 (i0 may pass step)
-    int x = static_cast<int>((((step - i0) % cap) + cap) % cap);
+    // ring slot of lag i0 of step t0 (i0 may pass t0)
+    int x = static_cast<int>((((t0 - i0) % cap) + cap) % cap);
     const cplx<R> *hp = ring +
                         (a.blk_off[b] + static_cast<long long>(x) * a.blk_stride[b]) * rec_len +
                         static_cast<long long>(p) * 3 * kLanes + col;
@@ -318,7 +261,7 @@ __device__ __forceinline__ void sweep_item(const SweepArgs &a, long long item) {
   // sum the lag chunks of each mode; lanes of chunk 0 store
 #pragma unroll
   for (int s = 0; s < S; ++s) {
-    const long long slot = (step + s) % S;
+    const long long slot = (t0 + s) % (S + 1);
 #pragma unroll
     for (int k = 0; k < kSums; ++k) {
 #pragma unroll
@@ -329,13 +272,200 @@ __device__ __forceinline__ void sweep_item(const SweepArgs &a, long long item) {
   }
 }
 
-// One launch per step of mode-space work before the epilogue: the sweep items
-// of the blocks whose turn it is, then one push item per (64-mode block,
-// plane).  The two kinds share no data (the sweep reads no slot the push
-// writes, see sweep_item), so the latency-bound push gathers run beside the
-// streaming sweep.
+// Mode item of step n for one (mode, plane): the push, then the traction of
+// the same step from the same registers.
+//   push:    rotate the new spectrum into the wavevector frame, update the
+//            float64 running state, store the ring slot of step n;
+//   traction: the pending history sum of step n plus the lags from the
+//            block's last sweep on (compensated for the compensated form),
+//            damping and instantaneous terms, rotation back to (x1, x2, x3),
+//            scatter into the natural half-spectrum layout.
+// The lag-0 history value and the velocity of the damping term are the ones
+// just computed (rounded to the working precision as the ring stores them).
+template <typename R, bool COMP>
+__device__ __forceinline__ void mode_step(const ModeArgs &a, int p, long long s) {
+  using W = typename W4<R>::T;
+  const double2 *__restrict__ spec = static_cast<const double2 *>(a.spec);
+  const double2 *__restrict__ spec_v = static_cast<const double2 *>(a.spec_v);
+  cplx<R> *__restrict__ ring = static_cast<cplx<R> *>(a.ring);
+  double2 *__restrict__ state = a.state;
+  const long long M = a.M, nh = a.nh, step = a.step;
+  const int np = a.np;
+  const long long natural = a.nat[s];
+  const double q = a.geom[4 * s + 0];
+  const double kh1 = a.geom[4 * s + 1];
+  const double kh3 = a.geom[4 * s + 2];
+  const long long b = s >> 6;
+  const int lane = static_cast<int>(s & 63);
+  const int cap = a.blk_cap[b];
+  const long long base = a.blk_off[b];
+  const long long stride = a.blk_stride[b];
+  const long long rec_len = static_cast<long long>(np) * 3 * kLanes;
+  const int x0 = cap > 0 ? static_cast<int>(step % cap) : 0;
+  const PlaneParams &pp = p == 0 ? a.p0 : a.p1;
+  const int pg = pp.index;
+
+  // ---- push
+  cplx<R> u0[3], v0[3];
+  {
+    double2 x[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) x[c] = spec[(pg * 3 + c) * nh + natural];
+    // (1, 2, 3) -> (L, N, T)
+    const double2 xr[3] = {{kh1 * x[0].x + kh3 * x[2].x, kh1 * x[0].y + kh3 * x[2].y},
+                           x[1],
+                           {-kh3 * x[0].x + kh1 * x[2].x, -kh3 * x[0].y + kh1 * x[2].y}};
+    double2 vr[3];
+    if (a.vel_rule == VEL_INPUT) {
+      double2 y[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) y[c] = spec_v[(pg * 3 + c) * nh + natural];
+      vr[0] = double2{kh1 * y[0].x + kh3 * y[2].x, kh1 * y[0].y + kh3 * y[2].y};
+      vr[1] = y[1];
+      vr[2] = double2{-kh3 * y[0].x + kh1 * y[2].x, -kh3 * y[0].y + kh1 * y[2].y};
+    }
+    cplx<R> *rp = ring + (base + static_cast<long long>(x0) * stride) * rec_len +
+                  static_cast<long long>(p) * 3 * kLanes + lane;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const long long si = (static_cast<long long>(p) * 3 + c) * M + s;
+      const double2 prev = state[si];
+      double2 now;
+      if (a.state_rule == STATE_ACCUM)
+        now = double2{prev.x + xr[c].x, prev.y + xr[c].y};
+      else
+        now = xr[c];
+      state[si] = now;
+      double2 v;
+      if (a.vel_rule == VEL_DIFF)
+        v = double2{(now.x - prev.x) * a.inv_dt, (now.y - prev.y) * a.inv_dt};
+      else if (a.vel_rule == VEL_SCALE)
+        v = double2{xr[c].x * a.inv_dt, xr[c].y * a.inv_dt};
+      else if (a.vel_rule == VEL_INPUT)
+        v = vr[c];
+      else
+        v = xr[c];
+      v0[c] = cplx<R>{static_cast<R>(v.x), static_cast<R>(v.y)};
+      u0[c] = cplx<R>{static_cast<R>(now.x), static_cast<R>(now.y)};
+      if (cap > 0) rp[c * kLanes] = u0[c];
+    }
+  }
+
+  // ---- history sums of step n
+  const int wl = a.win[s];
+  const int S = a.depth;
+  const int phi = static_cast<int>(b % S);
+  // The sweep launched with step m-1 covers steps m .. m+S-1 (m = phi mod S,
+  // m >= 1) over the history up to step m-2.  Lags not in the pending sum:
+  // those from step m-1 on, or all of them before the block's first sweep.
+  const bool swept = step >= (phi == 0 ? S : phi);
+  const int fresh =
+      min(wl, swept ? static_cast<int>((step - phi) % S) + 2 : static_cast<int>(step) + 1);
+  R cs[kSums];
+  {
+    Acc<R, COMP> acc[kSums];
+    if (swept) {
+      const R *__restrict__ pend = static_cast<const R *>(a.pending) +
+                                   ((step % (S + 1)) * np + p) * kSums * M + s;
+#pragma unroll
+      for (int k = 0; k < kSums; ++k) acc[k].s = pend[k * M];
+    }
+    if (fresh > 0) {
+      const W *__restrict__ rowp = static_cast<const W *>(a.table) + a.cls_off[a.cls[s]];
+      const cplx<R> *rp = ring + static_cast<long long>(p) * 3 * kLanes + lane;
+      for (int j = 0; j < fresh; ++j) {
+        cplx<R> u[3];
+        if (j == 0) {
+#pragma unroll
+          for (int c = 0; c < 3; ++c) u[c] = u0[c];
+        } else {
+          int x = x0 - j;
+          if (x < 0) x += cap;
+          const cplx<R> *qp = rp + (base + static_cast<long long>(x) * stride) * rec_len;
+          u[0] = qp[0];
+          u[1] = qp[kLanes];
+          u[2] = qp[2 * kLanes];
+        }
+        const W w = rowp[j];
+        R part[kSums];
+#pragma unroll
+        for (int k = 0; k < kSums; ++k) part[k] = COMP ? R(0) : acc[k].s;
+        fma_lag<R>(part, w, u);
+#pragma unroll
+        for (int k = 0; k < kSums; ++k) {
+          if constexpr (COMP)
+            acc[k].fold(part[k]);
+          else
+            acc[k].s = part[k];
+        }
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < kSums; ++k) cs[k] = acc[k].value();
+  }
+
+  // ---- traction of step n
+  const R sg = static_cast<R>(pp.side);
+  const R muq = static_cast<R>(pp.mu * q);
+  const R damp = static_cast<R>(pp.mu / pp.cs);
+  const R inst = static_cast<R>((2.0 - pp.eta) * pp.mu * q);
+  const R eta = static_cast<R>(pp.eta);
+  const R r1 = static_cast<R>(kh1), r3 = static_cast<R>(kh3);
+  cplx<R> u[3] = {{R(0), R(0)}, {R(0), R(0)}, {R(0), R(0)}};
+  if (cap > 0 && wl > 0) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) u[c] = u0[c];
+  }
+  // conv + instantaneous (rotated frame):
+  //   A_L = -sg mu q C11 + i (2-eta) mu q U_N - i mu q C12[U_N]
+  //   A_N = -sg mu q C22 - i (2-eta) mu q U_L + i mu q C12[U_L]
+  //   A_T = -sg mu q C33
+  cplx<R> t[3];
+  t[0] = cplx<R>{-sg * muq * cs[0] - inst * u[1].y + muq * cs[3],
+                 -sg * muq * cs[1] + inst * u[1].x - muq * cs[2]};
+  t[1] = cplx<R>{-sg * muq * cs[4] + inst * u[0].y - muq * cs[7],
+                 -sg * muq * cs[5] - inst * u[0].x + muq * cs[6]};
+  t[2] = cplx<R>{-sg * muq * cs[8], -sg * muq * cs[9]};
+  // damping: -sg (mu/c_s) diag(1, eta, 1) V
+  const cplx<R> d[3] = {{-sg * damp * v0[0].x, -sg * damp * v0[0].y},
+                        {-sg * damp * eta * v0[1].x, -sg * damp * eta * v0[1].y},
+                        {-sg * damp * v0[2].x, -sg * damp * v0[2].y}};
+  if (a.lam) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const long long si = (static_cast<long long>(p) * 3 + c) * M + s;
+      double2 l = a.lam[si];
+      l.x += static_cast<double>(t[c].x);
+      l.y += static_cast<double>(t[c].y);
+      a.lam[si] = l;
+      t[c] = cplx<R>{static_cast<R>(l.x), static_cast<R>(l.y)};
+    }
+  }
+  cplx<R> *__restrict__ out_a = static_cast<cplx<R> *>(a.out_a);
+  cplx<R> *__restrict__ out_b = static_cast<cplx<R> *>(a.out_b);
+  if (!out_b) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) t[c] = cplx<R>{t[c].x + d[c].x, t[c].y + d[c].y};
+  }
+  // (L, N, T) -> (1, 2, 3)
+  out_a[(pg * 3 + 0) * nh + natural] = cplx<R>{r1 * t[0].x - r3 * t[2].x, r1 * t[0].y - r3 * t[2].y};
+  out_a[(pg * 3 + 1) * nh + natural] = t[1];
+  out_a[(pg * 3 + 2) * nh + natural] = cplx<R>{r3 * t[0].x + r1 * t[2].x, r3 * t[0].y + r1 * t[2].y};
+  if (out_b) {
+    out_b[(pg * 3 + 0) * nh + natural] =
+        cplx<R>{r1 * d[0].x - r3 * d[2].x, r1 * d[0].y - r3 * d[2].y};
+    out_b[(pg * 3 + 1) * nh + natural] = d[1];
+    out_b[(pg * 3 + 2) * nh + natural] =
+        cplx<R>{r3 * d[0].x + r1 * d[2].x, r3 * d[0].y + r1 * d[2].y};
+  }
+}
+
+// One launch per step of mode-space work: the sweep items of the blocks whose
+// turn it is, then one mode item per (64-mode block, plane).  The two kinds
+// share no data (see sweep_item), so the latency-bound push gathers and
+// traction scatters run beside the streaming sweep.
 template <typename R, int S, bool COMP>
-__global__ __launch_bounds__(kLanes) void step_kernel(SweepArgs sa, PushArgs pa,
+__global__ __launch_bounds__(kLanes) void step_kernel(SweepArgs sa, ModeArgs ma,
                                                       long long sweep_items, long long nblocks) {
   const long long item = blockIdx.x;
   if (item < sweep_items) {
@@ -345,138 +475,7 @@ __global__ __launch_bounds__(kLanes) void step_kernel(SweepArgs sa, PushArgs pa,
   const long long k = item - sweep_items;
   const int p = static_cast<int>(k / nblocks);
   const long long s = (k - p * nblocks) * kLanes + threadIdx.x;
-  if (s < pa.M) push_mode<R>(pa, p, s);
-}
-
-// Per (mode, plane): the pending sum of this step plus the lags newer than the
-// block's last sweep (compensated for the compensated form), damping and
-// instantaneous terms, rotation back to (x1, x2, x3), scatter into the natural
-// half-spectrum layout.
-template <typename R, bool COMP>
-__global__ __launch_bounds__(256) void conv_epilogue_kernel(
-    const R *__restrict__ pending, const cplx<R> *__restrict__ ring,
-    const typename W4<R>::T *__restrict__ table, const long long *__restrict__ cls_off,
-    const int *__restrict__ cls, const cplx<R> *__restrict__ vel, double2 *__restrict__ lam,
-    cplx<R> *__restrict__ out_a, cplx<R> *__restrict__ out_b, const int *__restrict__ nat,
-    const int *__restrict__ win, const double *__restrict__ geom,
-    const long long *__restrict__ blk_off, const int *__restrict__ blk_cap,
-    const int *__restrict__ blk_stride, long long M, long long nh, long long step, int np,
-    int depth, PlaneParams p0, PlaneParams p1) {
-  // one thread per (mode, plane); consecutive threads take consecutive modes
-  const long long t = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (t >= M * np) return;
-  const int p = static_cast<int>(t / M);
-  const long long s = t - p * M;
-  const long long b = s >> 6;
-  const int lane = static_cast<int>(s & 63);
-  const int cap = blk_cap[b];
-  const int wl = win[s];
-  const int cl = cls[s];
-  const double q = geom[4 * s + 0];
-  const R kh1 = static_cast<R>(geom[4 * s + 1]);
-  const R kh3 = static_cast<R>(geom[4 * s + 2]);
-  const long long natural = nat[s];
-  const long long rec_len = static_cast<long long>(np) * 3 * kLanes;
-  const cplx<R> *rp = ring + static_cast<long long>(p) * 3 * kLanes + lane;
-  const long long base = blk_off[b];
-  const long long stride = blk_stride[b];
-  const int sl = static_cast<int>(step % depth);
-  const int phi = static_cast<int>(b % depth);
-  // lags not in the pending sum: those from the block's last sweep on (the
-  // sweep of step m covers lags of U^{m-1} and older), or all of them before
-  // its first sweep (step < phi < depth)
-  const bool swept = step >= phi;
-  const int fresh = min(wl, swept ? (sl - phi + depth) % depth + 1 : static_cast<int>(step) + 1);
-  const int x0 = cap > 0 ? static_cast<int>(step % cap) : 0;
-  R cs[kSums];
-  {
-    Acc<R, COMP> a[kSums];
-    if (swept) {
-#pragma unroll
-      for (int k = 0; k < kSums; ++k) a[k].s = pending[((sl * np + p) * kSums + k) * M + s];
-    }
-    for (int j = 0; j < fresh; ++j) {
-      int x = x0 - j;
-      if (x < 0) x += cap;
-      const cplx<R> *qp = rp + (base + static_cast<long long>(x) * stride) * rec_len;
-      const cplx<R> u[3] = {qp[0], qp[kLanes], qp[2 * kLanes]};
-      const typename W4<R>::T w = table[cls_off[cl] + j];
-      R part[kSums];
-#pragma unroll
-      for (int k = 0; k < kSums; ++k) part[k] = COMP ? R(0) : a[k].s;
-      fma_lag<R>(part, w, u);
-#pragma unroll
-      for (int k = 0; k < kSums; ++k) {
-        if constexpr (COMP)
-          a[k].fold(part[k]);
-        else
-          a[k].s = part[k];
-      }
-    }
-#pragma unroll
-    for (int k = 0; k < kSums; ++k) cs[k] = a[k].value();
-  }
-  {
-    const PlaneParams &pp = p == 0 ? p0 : p1;
-    const R sg = static_cast<R>(pp.side);
-    const R muq = static_cast<R>(pp.mu * q);
-    const R damp = static_cast<R>(pp.mu / pp.cs);
-    const R inst = static_cast<R>((2.0 - pp.eta) * pp.mu * q);
-    const R eta = static_cast<R>(pp.eta);
-    cplx<R> u[3] = {{R(0), R(0)}, {R(0), R(0)}, {R(0), R(0)}};
-    if (cap > 0 && wl > 0) {
-      const cplx<R> *qp = rp + (base + static_cast<long long>(x0) * stride) * rec_len;
-      u[0] = qp[0];
-      u[1] = qp[kLanes];
-      u[2] = qp[2 * kLanes];
-    }
-    cplx<R> v[3];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) v[c] = vel[(static_cast<long long>(p) * 3 + c) * M + s];
-    // conv + instantaneous (rotated frame):
-    //   A_L = -sg mu q C11 + i (2-eta) mu q U_N - i mu q C12[U_N]
-    //   A_N = -sg mu q C22 - i (2-eta) mu q U_L + i mu q C12[U_L]
-    //   A_T = -sg mu q C33
-    cplx<R> a[3];
-    a[0] = cplx<R>{-sg * muq * cs[0] - inst * u[1].y + muq * cs[3],
-                   -sg * muq * cs[1] + inst * u[1].x - muq * cs[2]};
-    a[1] = cplx<R>{-sg * muq * cs[4] + inst * u[0].y - muq * cs[7],
-                   -sg * muq * cs[5] - inst * u[0].x + muq * cs[6]};
-    a[2] = cplx<R>{-sg * muq * cs[8], -sg * muq * cs[9]};
-    // damping: -sg (mu/c_s) diag(1, eta, 1) V
-    cplx<R> d[3] = {{-sg * damp * v[0].x, -sg * damp * v[0].y},
-                    {-sg * damp * eta * v[1].x, -sg * damp * eta * v[1].y},
-                    {-sg * damp * v[2].x, -sg * damp * v[2].y}};
-    if (lam) {
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        const long long si = (static_cast<long long>(p) * 3 + c) * M + s;
-        double2 l = lam[si];
-        l.x += static_cast<double>(a[c].x);
-        l.y += static_cast<double>(a[c].y);
-        lam[si] = l;
-        a[c] = cplx<R>{static_cast<R>(l.x), static_cast<R>(l.y)};
-      }
-    }
-    if (!out_b) {
-#pragma unroll
-      for (int c = 0; c < 3; ++c) a[c] = cplx<R>{a[c].x + d[c].x, a[c].y + d[c].y};
-    }
-    const int pg = pp.index;
-    // (L, N, T) -> (1, 2, 3)
-    out_a[(pg * 3 + 0) * nh + natural] =
-        cplx<R>{kh1 * a[0].x - kh3 * a[2].x, kh1 * a[0].y - kh3 * a[2].y};
-    out_a[(pg * 3 + 1) * nh + natural] = a[1];
-    out_a[(pg * 3 + 2) * nh + natural] =
-        cplx<R>{kh3 * a[0].x + kh1 * a[2].x, kh3 * a[0].y + kh1 * a[2].y};
-    if (out_b) {
-      out_b[(pg * 3 + 0) * nh + natural] =
-          cplx<R>{kh1 * d[0].x - kh3 * d[2].x, kh1 * d[0].y - kh3 * d[2].y};
-      out_b[(pg * 3 + 1) * nh + natural] = d[1];
-      out_b[(pg * 3 + 2) * nh + natural] =
-          cplx<R>{kh3 * d[0].x + kh1 * d[2].x, kh3 * d[0].y + kh1 * d[2].y};
-    }
-  }
+  if (s < ma.M) mode_step<R, COMP>(ma, p, s);
 }
 
 // -------------------------------------------------------------- tabulate
@@ -597,72 +596,65 @@ __global__ __launch_bounds__(256) void tabulate_kernel(
 
 template <typename R, int S, bool COMP>
 hipError_t step_launch_s(const sbim_handle *h, const Group &g, const SweepArgs &sa0,
-                         const PushArgs &pa, hipEvent_t ev0, hipEvent_t ev1) {
+                         const ModeArgs &ma, hipEvent_t ev0, hipEvent_t ev1) {
   SweepArgs sa = sa0;
-  const int phase = static_cast<int>(sa.step % S);
+  const int phase = static_cast<int>((sa.step + 1) % S);
   sa.nphase = g.nblocks > phase ? (g.nblocks - phase + S - 1) / S : 0;
   const long long sweep_items =
       (sa.nphase + 7) / 8 * 8 * sweep_lag_groups<R, S, COMP>() * g.np;
   const long long items = sweep_items + g.nblocks * g.np;
   if (ev0) (void)hipEventRecord(ev0, h->stream);
   hipLaunchKernelGGL((step_kernel<R, S, COMP>), dim3(static_cast<unsigned>(items)), dim3(kLanes),
-                     0, h->stream, sa, pa, sweep_items, g.nblocks);
+                     0, h->stream, sa, ma, sweep_items, g.nblocks);
   if (ev1) (void)hipEventRecord(ev1, h->stream);
   return hipGetLastError();
 }
 
 template <typename R, bool COMP>
 hipError_t step_launch_r(const sbim_handle *h, const Group &g, const SweepArgs &sa,
-                         const PushArgs &pa, hipEvent_t ev0, hipEvent_t ev1) {
+                         const ModeArgs &ma, hipEvent_t ev0, hipEvent_t ev1) {
   switch (h->depth) {
-    case 1: return step_launch_s<R, 1, COMP>(h, g, sa, pa, ev0, ev1);
-    case 2: return step_launch_s<R, 2, COMP>(h, g, sa, pa, ev0, ev1);
-    case 4: return step_launch_s<R, 4, COMP>(h, g, sa, pa, ev0, ev1);
-    case 6: return step_launch_s<R, 6, COMP>(h, g, sa, pa, ev0, ev1);
-    case 8: return step_launch_s<R, 8, COMP>(h, g, sa, pa, ev0, ev1);
+    case 1: return step_launch_s<R, 1, COMP>(h, g, sa, ma, ev0, ev1);
+    case 2: return step_launch_s<R, 2, COMP>(h, g, sa, ma, ev0, ev1);
+    case 4: return step_launch_s<R, 4, COMP>(h, g, sa, ma, ev0, ev1);
+    case 6: return step_launch_s<R, 6, COMP>(h, g, sa, ma, ev0, ev1);
+    case 8: return step_launch_s<R, 8, COMP>(h, g, sa, ma, ev0, ev1);
     default: return hipErrorInvalidValue;
   }
 }
 
-template <typename R, bool COMP>
-hipError_t conv_launch_r(const sbim_handle *h, const Group &g, const ConvLaunch &a) {
-  const PlaneParams p1 = g.np > 1 ? g.pl[1] : g.pl[0];
-  hipLaunchKernelGGL((conv_epilogue_kernel<R, COMP>),
-                     dim3(static_cast<unsigned>((g.M * g.np + 255) / 256)), dim3(256), 0,
-                     h->stream, static_cast<const R *>(a.pending),
-                     static_cast<const cplx<R> *>(a.ring),
-                     static_cast<const typename W4<R>::T *>(g.table), g.cls_off, g.cls,
-                     static_cast<const cplx<R> *>(a.vel), reinterpret_cast<double2 *>(a.lam),
-                     static_cast<cplx<R> *>(a.out_a), static_cast<cplx<R> *>(a.out_b), g.nat,
-                     g.win, g.geom, g.blk_off, g.blk_cap, g.blk_stride, g.M, a.nh, a.step, g.np,
-                     h->depth, g.pl[0], p1);
-  return hipGetLastError();
-}
-
 }  // namespace
 
-hipError_t launch_step(const sbim_handle *h, const Group &g, const PushLaunch &p,
-                       const SweepLaunch &w, hipEvent_t ev0, hipEvent_t ev1) {
-  PushArgs pa;
-  pa.spec = p.spec;
-  pa.spec_v = p.spec_v;
-  pa.ring = p.ring;
-  pa.state = reinterpret_cast<double2 *>(p.state);
-  pa.vel = p.vel;
-  pa.nat = g.nat;
-  pa.geom = g.geom;
-  pa.blk_off = g.blk_off;
-  pa.blk_cap = g.blk_cap;
-  pa.blk_stride = g.blk_stride;
-  pa.M = g.M;
-  pa.nh = p.nh;
-  pa.np = g.np;
-  pa.plane0 = g.pl[0].index;
-  pa.plane1 = g.np > 1 ? g.pl[1].index : pa.plane0;
-  pa.step = p.step;
-  pa.inv_dt = 1.0 / p.dt;
-  pa.vel_rule = p.vel_rule;
-  pa.state_rule = p.state_rule;
+hipError_t launch_step(const sbim_handle *h, const Group &g, const StepLaunch &w,
+                       hipEvent_t ev0, hipEvent_t ev1) {
+  ModeArgs ma;
+  ma.spec = w.spec;
+  ma.spec_v = w.spec_v;
+  ma.ring = w.ring;
+  ma.state = reinterpret_cast<double2 *>(w.state);
+  ma.pending = w.pending;
+  ma.table = g.table;
+  ma.cls_off = g.cls_off;
+  ma.cls = g.cls;
+  ma.win = g.win;
+  ma.nat = g.nat;
+  ma.geom = g.geom;
+  ma.blk_off = g.blk_off;
+  ma.blk_cap = g.blk_cap;
+  ma.blk_stride = g.blk_stride;
+  ma.lam = reinterpret_cast<double2 *>(w.lam);
+  ma.out_a = w.out_a;
+  ma.out_b = w.out_b;
+  ma.M = g.M;
+  ma.nh = w.nh;
+  ma.step = w.step;
+  ma.np = g.np;
+  ma.depth = h->depth;
+  ma.inv_dt = 1.0 / w.dt;
+  ma.vel_rule = w.vel_rule;
+  ma.state_rule = w.state_rule;
+  ma.p0 = g.pl[0];
+  ma.p1 = g.np > 1 ? g.pl[1] : g.pl[0];
   SweepArgs sa;
   sa.ring = w.ring;
   sa.table = g.table;
@@ -678,15 +670,9 @@ hipError_t launch_step(const sbim_handle *h, const Group &g, const PushLaunch &p
   sa.step = w.step;
   sa.np = g.np;
   sa.nphase = 0;
-  if (h->fp64) return step_launch_r<double, false>(h, g, sa, pa, ev0, ev1);
-  if (h->comp) return step_launch_r<float, true>(h, g, sa, pa, ev0, ev1);
-  return step_launch_r<float, false>(h, g, sa, pa, ev0, ev1);
-}
-
-hipError_t launch_conv(const sbim_handle *h, const Group &g, const ConvLaunch &a) {
-  if (h->fp64) return conv_launch_r<double, false>(h, g, a);
-  if (h->comp) return conv_launch_r<float, true>(h, g, a);
-  return conv_launch_r<float, false>(h, g, a);
+  if (h->fp64) return step_launch_r<double, false>(h, g, sa, ma, ev0, ev1);
+  if (h->comp) return step_launch_r<float, true>(h, g, sa, ma, ev0, ev1);
+  return step_launch_r<float, false>(h, g, sa, ma, ev0, ev1);
 }
 
 hipError_t launch_tabulate(bool fp64, const Group &g, double dt, const double *gl_x,

@@ -97,8 +97,8 @@ hipError_t dev_alloc_bytes(void **p, size_t bytes) {
 
 void free_group(Group &g) {
   void *ptrs[] = {g.nat,   g.cls,   g.win,   g.geom,      g.blk_off,   g.blk_cap, g.blk_stride, g.cls_off,
-                  g.cls_q, g.cls_w, g.table, g.ring,      g.state,     g.vel,     g.pending,
-                  g.ring_adj, g.state_adj, g.lam_adj, g.vel_adj, g.pending_adj};
+                  g.cls_q, g.cls_w, g.table, g.ring,      g.state,     g.pending,
+                  g.ring_adj, g.state_adj, g.lam_adj, g.pending_adj};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   g = Group();
@@ -109,7 +109,7 @@ void free_handle(sbim_handle *h) {
   (void)hipStreamSynchronize(h->stream);
   for (int i = 0; i < h->ngroups; ++i) free_group(h->g[i]);
   if (h->twiddle64 && h->twiddle64 != h->twiddle) (void)hipFree(h->twiddle64);
-  void *ptrs[] = {h->twiddle, h->spec, h->spec_v, h->out_spec};
+  void *ptrs[] = {h->twiddle, h->spec, h->spec_v, h->out_spec, h->out_adj};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   for (auto e : h->ev_start) (void)hipEventDestroy(e);
@@ -123,12 +123,12 @@ long long ring_bytes(const sbim_handle *h, const Group &g) {
 long long table_bytes(const sbim_handle *h, const Group &g) {
   return g.table_rows * 4LL * static_cast<long long>(h->rsize);
 }
-long long vel_bytes(const sbim_handle *h, const Group &g) {
-  return g.np * 3LL * g.M * 2 * static_cast<long long>(h->rsize);
-}
 long long state_bytes_g(const Group &g) { return g.np * 3LL * g.M * 16; }
 long long pending_bytes(const sbim_handle *h, const Group &g) {
-  return static_cast<long long>(h->depth) * g.np * 10LL * g.M * static_cast<long long>(h->rsize);
+  return (h->depth + 1LL) * g.np * 10LL * g.M * static_cast<long long>(h->rsize);
+}
+long long out_spec_bytes(const sbim_handle *h) {
+  return static_cast<long long>(h->cfg.nplanes) * 3 * h->nh * 2 * static_cast<long long>(h->rsize);
 }
 
 int validate(const sbim_config *c) {
@@ -279,8 +279,10 @@ hipError_t fft_forward(sbim_handle *h, const void *field, void *spec) {
 }
 
 // Inverse of a traction spectrum (destroyed) into a [P][3][n1][n3] field.
-hipError_t fft_inverse(sbim_handle *h, void *spec, void *field, const void *add) {
-  return sbim::launch_fft_inverse(h->fp64, spec, field, add, h->cfg.nplanes * 3, h->n1, h->n3,
+hipError_t fft_inverse(sbim_handle *h, const void *spec, void *scratch, void *field,
+                       const void *add) {
+  return sbim::launch_fft_inverse(h->fp64, spec, scratch, field, add, h->cfg.nplanes * 3, h->n1,
+                                  h->n3,
                                   1.0 / (static_cast<double>(h->n1) * h->n3), h->twiddle,
                                   h->stream);
 }
@@ -291,9 +293,8 @@ int ensure_adjoint(sbim_handle *h) {
     if (g.state_adj) continue;
     const size_t rb = static_cast<size_t>(ring_bytes(h, g));
     const size_t sb = static_cast<size_t>(state_bytes_g(g));
-    const size_t vb = static_cast<size_t>(vel_bytes(h, g));
     size_t free_b = 0, total_b = 0;
-    const size_t need = rb + 2 * sb + vb + static_cast<size_t>(pending_bytes(h, g));
+    const size_t need = rb + 2 * sb + static_cast<size_t>(pending_bytes(h, g) + out_spec_bytes(h));
     if (hipMemGetInfo(&free_b, &total_b) == hipSuccess && need > free_b)
       return fail(h, SBIM_E_OOM, "adjoint buffers need %zu bytes, %zu free", need, free_b);
     hipError_t e;
@@ -302,25 +303,21 @@ int ensure_adjoint(sbim_handle *h) {
         (e = dev_alloc_bytes(&g.pending_adj, pb)) != hipSuccess ||
         (e = dev_alloc(&g.state_adj, sb / 8)) != hipSuccess ||
         (e = dev_alloc(&g.lam_adj, sb / 8)) != hipSuccess ||
-        (e = dev_alloc_bytes(&g.vel_adj, vb)) != hipSuccess) {
+        (!h->out_adj &&
+         (e = dev_alloc_bytes(&h->out_adj, out_spec_bytes(h))) != hipSuccess)) {
       return fail(h, SBIM_E_OOM, "adjoint allocation failed: %s", hipGetErrorString(e));
     }
     if (rb) (void)hipMemsetAsync(g.ring_adj, 0, rb, h->stream);
     (void)hipMemsetAsync(g.state_adj, 0, sb, h->stream);
     (void)hipMemsetAsync(g.lam_adj, 0, sb, h->stream);
-    (void)hipMemsetAsync(g.vel_adj, 0, vb, h->stream);
   }
   return SBIM_OK;
 }
 
-// The push and history sweep of step `p.step` for one group (one launch),
-// bracketed by a pair of the handle's reusable events while sbim_profile_conv
-// is on.
-int step_group(sbim_handle *h, Group &g, const sbim::PushLaunch &p, void *pending, bool timed) {
-  sbim::SweepLaunch w;
-  w.ring = p.ring;
-  w.pending = pending;
-  w.step = p.step;
+// The launch of step `w.step` for one group (push, traction spectrum and the
+// sweep for the coming steps), bracketed by a pair of the handle's reusable
+// events while sbim_profile_conv is on.
+int step_group(sbim_handle *h, Group &g, const sbim::StepLaunch &w, bool timed) {
   hipError_t e;
   if (timed && h->profile) {
     if (h->ev_used == h->ev_start.size()) {  // grow the reusable event pool
@@ -333,12 +330,12 @@ int step_group(sbim_handle *h, Group &g, const sbim::PushLaunch &p, void *pendin
       h->ev_start.push_back(e0);
       h->ev_stop.push_back(e1);
     }
-    e = sbim::launch_step(h, g, p, w, h->ev_start[h->ev_used], h->ev_stop[h->ev_used]);
+    e = sbim::launch_step(h, g, w, h->ev_start[h->ev_used], h->ev_stop[h->ev_used]);
     ++h->ev_used;
   } else {
-    e = sbim::launch_step(h, g, p, w);
+    e = sbim::launch_step(h, g, w);
   }
-  if (e != hipSuccess) return hip_fail(h, e, "push / history sweep kernel");
+  if (e != hipSuccess) return hip_fail(h, e, "step kernel");
   return SBIM_OK;
 }
 
@@ -405,7 +402,7 @@ int sbim_init(const sbim_config *cfg, sbim_handle **out) {
     Group &g = h->g[i];
     plan_group(*cfg, h->depth, g, plan[i].geom, plan[i].blk_off, plan[i].blk_cap,
                plan[i].blk_stride, plan[i].cls_q);
-    need += ring_bytes(h, g) + table_bytes(h, g) + state_bytes_g(g) + vel_bytes(h, g);
+    need += ring_bytes(h, g) + table_bytes(h, g) + state_bytes_g(g);
     need += pending_bytes(h, g);
     need += g.M * (4 * 3 + 32) + g.nblocks * 16 + g.nclasses * 20;
   }
@@ -472,7 +469,6 @@ int sbim_init(const sbim_config *cfg, sbim_handle **out) {
     TRY(dev_alloc_bytes(&g.table, table_bytes(h, g)));
     TRY(dev_alloc_bytes(&g.ring, ring_bytes(h, g)));
     TRY(dev_alloc(&g.state, state_bytes_g(g) / 8));
-    TRY(dev_alloc_bytes(&g.vel, vel_bytes(h, g)));
     TRY(dev_alloc_bytes(&g.pending, pending_bytes(h, g)));
     TRY(upload(g.nat, g.h_nat.data(), g.M * sizeof(int), h->stream));
     TRY(upload(g.cls, g.h_cls.data(), g.M * sizeof(int), h->stream));
@@ -486,7 +482,6 @@ int sbim_init(const sbim_config *cfg, sbim_handle **out) {
     TRY(upload(g.cls_w, g.h_cls_w.data(), g.h_cls_w.size() * sizeof(int), h->stream));
     if (ring_bytes(h, g)) TRY(hipMemsetAsync(g.ring, 0, ring_bytes(h, g), h->stream));
     TRY(hipMemsetAsync(g.state, 0, state_bytes_g(g), h->stream));
-    TRY(hipMemsetAsync(g.vel, 0, vel_bytes(h, g), h->stream));
     TRY(hipMemsetAsync(g.pending, 0, pending_bytes(h, g), h->stream));
     TRY(sbim::launch_tabulate(h->fp64, g, cfg->dt, d_glx, d_glw, h->stream));
     // the host vectors must outlive the asynchronous copies
@@ -513,22 +508,24 @@ int sbim_push_displacement(sbim_handle *h, const void *u, const void *v) {
   const bool incr = h->cfg.input_kind == SBIM_INCREMENT;
   for (int i = 0; i < h->ngroups; ++i) {
     Group &g = h->g[i];
-    sbim::PushLaunch a;
-    a.spec = h->spec;
-    a.spec_v = v ? h->spec_v : nullptr;
-    a.ring = g.ring;
-    a.state = g.state;
-    a.vel = g.vel;
-    a.nh = h->nh;
-    a.step = h->step;
-    a.dt = h->cfg.dt;
-    a.state_rule = incr ? sbim::STATE_ACCUM : sbim::STATE_REPLACE;
-    a.vel_rule = v ? sbim::VEL_INPUT : (incr ? sbim::VEL_SCALE : sbim::VEL_DIFF);
-    rc = step_group(h, g, a, g.pending, true);
+    sbim::StepLaunch w;
+    w.spec = h->spec;
+    w.spec_v = v ? h->spec_v : nullptr;
+    w.ring = g.ring;
+    w.state = g.state;
+    w.pending = g.pending;
+    w.lam = nullptr;
+    w.out_a = h->out_spec;
+    w.out_b = nullptr;
+    w.nh = h->nh;
+    w.step = h->step;
+    w.dt = h->cfg.dt;
+    w.state_rule = incr ? sbim::STATE_ACCUM : sbim::STATE_REPLACE;
+    w.vel_rule = v ? sbim::VEL_INPUT : (incr ? sbim::VEL_SCALE : sbim::VEL_DIFF);
+    rc = step_group(h, g, w, true);
     if (rc) return rc;
   }
   h->step += 1;
-  h->pushed_since_tractions = true;
   return SBIM_OK;
 }
 
@@ -537,23 +534,10 @@ int sbim_tractions(sbim_handle *h, const void *tau_inf, void *tau) {
   int rc = check_ptr(h, tau, "tau");
   if (rc) return rc;
   if (h->step == 0) return fail(h, SBIM_E_STATE, "sbim_tractions before any push");
-  for (int i = 0; i < h->ngroups; ++i) {
-    Group &g = h->g[i];
-    sbim::ConvLaunch a;
-    a.ring = g.ring;
-    a.pending = g.pending;
-    a.vel = g.vel;
-    a.lam = nullptr;
-    a.out_a = h->out_spec;
-    a.out_b = nullptr;
-    a.nh = h->nh;
-    a.step = h->step - 1;
-    const hipError_t e = sbim::launch_conv(h, g, a);
-    if (e != hipSuccess) return hip_fail(h, e, "convolution epilogue kernel");
-  }
-  hipError_t e = fft_inverse(h, h->out_spec, tau, tau_inf);
+  // the traction spectrum of the last step was completed by its push; the
+  // forward spectrum buffer serves as scratch until the next push
+  hipError_t e = fft_inverse(h, h->out_spec, h->spec, tau, tau_inf);
   if (e != hipSuccess) return hip_fail(h, e, "inverse FFT");
-  h->pushed_since_tractions = false;
   return SBIM_OK;
 }
 
@@ -570,36 +554,28 @@ int sbim_backward(sbim_handle *h, const void *g_tau, void *du, void *dv) {
   const bool incr = h->cfg.input_kind == SBIM_INCREMENT;
   for (int i = 0; i < h->ngroups; ++i) {
     Group &g = h->g[i];
-    sbim::PushLaunch a;
-    a.spec = h->spec;
-    a.spec_v = nullptr;
-    a.ring = g.ring_adj;
-    a.state = g.state_adj;
-    a.vel = g.vel_adj;
-    a.nh = h->nh;
-    a.step = h->bstep;
-    a.dt = h->cfg.dt;
-    a.state_rule = sbim::STATE_REPLACE;
+    sbim::StepLaunch w;
+    w.spec = h->spec;
+    w.spec_v = nullptr;
+    w.ring = g.ring_adj;
+    w.state = g.state_adj;
+    w.pending = g.pending_adj;
+    w.lam = incr ? g.lam_adj : nullptr;
+    w.out_a = h->out_adj;
+    w.out_b = dv ? h->spec_v : nullptr;
+    w.nh = h->nh;
+    w.step = h->bstep;
+    w.dt = h->cfg.dt;
+    w.state_rule = sbim::STATE_REPLACE;
     // transpose of the velocity rule of the forward push
-    a.vel_rule = dv ? sbim::VEL_COPY : (incr ? sbim::VEL_SCALE : sbim::VEL_DIFF);
-    rc = step_group(h, g, a, g.pending_adj, false);
+    w.vel_rule = dv ? sbim::VEL_COPY : (incr ? sbim::VEL_SCALE : sbim::VEL_DIFF);
+    rc = step_group(h, g, w, false);
     if (rc) return rc;
-    sbim::ConvLaunch c;
-    c.ring = g.ring_adj;
-    c.pending = g.pending_adj;
-    c.vel = g.vel_adj;
-    c.lam = incr ? g.lam_adj : nullptr;
-    c.out_a = h->out_spec;
-    c.out_b = dv ? h->spec_v : nullptr;
-    c.nh = h->nh;
-    c.step = h->bstep;
-    e = sbim::launch_conv(h, g, c);
-    if (e != hipSuccess) return hip_fail(h, e, "adjoint convolution epilogue kernel");
   }
-  e = fft_inverse(h, h->out_spec, du, nullptr);
+  e = fft_inverse(h, h->out_adj, h->spec, du, nullptr);
   if (e != hipSuccess) return hip_fail(h, e, "inverse FFT of dL/du");
   if (dv) {
-    e = fft_inverse(h, h->spec_v, dv, nullptr);
+    e = fft_inverse(h, h->spec_v, h->spec, dv, nullptr);
     if (e != hipSuccess) return hip_fail(h, e, "inverse FFT of dL/dv");
   }
   h->bstep += 1;
@@ -616,7 +592,6 @@ int sbim_backward_reset(sbim_handle *h) {
     if (rb) e = hipMemsetAsync(g.ring_adj, 0, rb, h->stream);
     if (e == hipSuccess) e = hipMemsetAsync(g.state_adj, 0, state_bytes_g(g), h->stream);
     if (e == hipSuccess) e = hipMemsetAsync(g.lam_adj, 0, state_bytes_g(g), h->stream);
-    if (e == hipSuccess) e = hipMemsetAsync(g.vel_adj, 0, vel_bytes(h, g), h->stream);
     if (e != hipSuccess) return hip_fail(h, e, "clearing adjoint state");
   }
   h->bstep = 0;
@@ -630,11 +605,9 @@ int sbim_reset(sbim_handle *h) {
     hipError_t e = hipSuccess;
     if (ring_bytes(h, g)) e = hipMemsetAsync(g.ring, 0, ring_bytes(h, g), h->stream);
     if (e == hipSuccess) e = hipMemsetAsync(g.state, 0, state_bytes_g(g), h->stream);
-    if (e == hipSuccess) e = hipMemsetAsync(g.vel, 0, vel_bytes(h, g), h->stream);
     if (e != hipSuccess) return hip_fail(h, e, "clearing state");
   }
   h->step = 0;
-  h->pushed_since_tractions = false;
   return sbim_backward_reset(h);
 }
 
@@ -663,7 +636,7 @@ int sbim_get_info(const sbim_handle *h, sbim_info *out) {
     out->kernel_classes += g.nclasses;
     out->ring_bytes += ring_bytes(h, g);
     out->table_bytes += table_bytes(h, g);
-    out->state_bytes += state_bytes_g(g) + vel_bytes(h, g);
+    out->state_bytes += state_bytes_g(g);
   }
   out->step = h->step;
   out->backward_step = h->bstep;
@@ -674,10 +647,10 @@ int sbim_get_info(const sbim_handle *h, sbim_info *out) {
 
 long long sbim_state_bytes(const sbim_handle *h) {
   if (!h) return -1;
-  long long b = 256;  // header: step counter
+  long long b = 256 + out_spec_bytes(h);  // header (step counter), last traction spectrum
   for (int i = 0; i < h->ngroups; ++i) {
     const Group &g = h->g[i];
-    b += ring_bytes(h, g) + state_bytes_g(g) + vel_bytes(h, g) + pending_bytes(h, g);
+    b += ring_bytes(h, g) + state_bytes_g(g) + pending_bytes(h, g);
   }
   return b;
 }
@@ -690,15 +663,16 @@ int sbim_save_state(sbim_handle *h, void *dst) {
   hipError_t e = hipMemcpyAsync(d, &h->step, sizeof(long long), hipMemcpyHostToDevice, h->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(h->stream);  // &h->step may change after return
   d += 256;
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(d, h->out_spec, out_spec_bytes(h), hipMemcpyDeviceToDevice, h->stream);
+  d += out_spec_bytes(h);
   for (int i = 0; i < h->ngroups && e == hipSuccess; ++i) {
     Group &g = h->g[i];
-    const size_t rb = ring_bytes(h, g), sb = state_bytes_g(g), vb = vel_bytes(h, g);
+    const size_t rb = ring_bytes(h, g), sb = state_bytes_g(g);
     if (rb) e = hipMemcpyAsync(d, g.ring, rb, hipMemcpyDeviceToDevice, h->stream);
     d += rb;
     if (e == hipSuccess) e = hipMemcpyAsync(d, g.state, sb, hipMemcpyDeviceToDevice, h->stream);
     d += sb;
-    if (e == hipSuccess) e = hipMemcpyAsync(d, g.vel, vb, hipMemcpyDeviceToDevice, h->stream);
-    d += vb;
     const size_t pb = pending_bytes(h, g);
     if (e == hipSuccess) e = hipMemcpyAsync(d, g.pending, pb, hipMemcpyDeviceToDevice, h->stream);
     d += pb;
@@ -718,22 +692,21 @@ int sbim_load_state(sbim_handle *h, const void *src) {
   if (e != hipSuccess) return hip_fail(h, e, "sbim_load_state header");
   if (step < 0) return fail(h, SBIM_E_INVALID, "snapshot header is corrupt");
   s += 256;
+  e = hipMemcpyAsync(h->out_spec, s, out_spec_bytes(h), hipMemcpyDeviceToDevice, h->stream);
+  s += out_spec_bytes(h);
   for (int i = 0; i < h->ngroups && e == hipSuccess; ++i) {
     Group &g = h->g[i];
-    const size_t rb = ring_bytes(h, g), sb = state_bytes_g(g), vb = vel_bytes(h, g);
+    const size_t rb = ring_bytes(h, g), sb = state_bytes_g(g);
     if (rb) e = hipMemcpyAsync(g.ring, s, rb, hipMemcpyDeviceToDevice, h->stream);
     s += rb;
     if (e == hipSuccess) e = hipMemcpyAsync(g.state, s, sb, hipMemcpyDeviceToDevice, h->stream);
     s += sb;
-    if (e == hipSuccess) e = hipMemcpyAsync(g.vel, s, vb, hipMemcpyDeviceToDevice, h->stream);
-    s += vb;
     const size_t pb = pending_bytes(h, g);
     if (e == hipSuccess) e = hipMemcpyAsync(g.pending, s, pb, hipMemcpyDeviceToDevice, h->stream);
     s += pb;
   }
   if (e != hipSuccess) return hip_fail(h, e, "sbim_load_state");
   h->step = step;
-  h->pushed_since_tractions = false;
   return SBIM_OK;
 }
 
@@ -749,31 +722,42 @@ int sbim_step_work(const sbim_handle *h, long long n, double *mode_lags, double 
     for (long long s = 0; s < g.M; ++s)
       mode_lag_g += static_cast<double>(std::min<long long>(g.h_win[s], n + 1));
     lags += mode_lag_g * g.np;
-    // the sweep of step n: blocks of phase n mod S read the history before
-    // step n that each of their modes needs (lags 1 .. W-1), the kernel rows of
-    // each distinct class of the block (lags 1 .. min(cap-1, n) + S - 1), the
-    // per-mode class/window indices and block descriptors, and write S
-    // pending sums per mode and plane
-    for (long long b = n % S; b < g.nblocks; b += S) {
-      const long long nent = std::max(0LL, std::min<long long>(g.h_blk_cap[b] - 1, n));
+    // the sweep launched with step n (for steps n+1 .. n+S): blocks of phase
+    // (n+1) mod S read the history up to step n-1 that each of their modes
+    // needs (lags 2 .. W-1 of step n+1), the kernel rows of each distinct class
+    // of the block (lags 2 .. min(cap-1, n+1) + S - 1), the per-mode
+    // class/window indices and block descriptors, and write S pending sums per
+    // mode and plane
+    for (long long b = (n + 1) % S; b < g.nblocks; b += S) {
+      const long long last = std::min<long long>(g.h_blk_cap[b] - 1, n + 1);
       int last_cls = -1;
       for (long long s = b * sbim::kLanes; s < std::min(g.M, (b + 1) * sbim::kLanes); ++s) {
         const int w = g.h_win[s];
-        bytes += std::max(0LL, std::min<long long>(w - 1, n)) * g.np * 3.0 * 2.0 * r;
+        bytes += std::max(0LL, std::min<long long>(w - 1, n + 1) - 1) * g.np * 3.0 * 2.0 * r;
         bytes += 8.0 + S * g.np * 10.0 * r;
-        if (w > 1 && g.h_cls[s] != last_cls) {
+        if (w > 2 && g.h_cls[s] != last_cls) {
           last_cls = g.h_cls[s];
-          bytes += std::min<long long>(w - 1, nent + S - 1) * 4.0 * r;
+          bytes += std::max(0LL, std::min<long long>(w - 1, last + S - 1) - 1) * 4.0 * r;
         }
       }
       bytes += 16.0;
     }
-    // the push of step n (same launch), per mode and plane: the three
+    // the mode items of step n (same launch), per mode and plane: the three
     // float64 spectrum values, the float64 state read and written, the ring
-    // slot and velocity written; per mode its bin and direction; per block
-    // its descriptors
-    bytes += g.M * g.np * (3.0 * 16.0 + 3.0 * 32.0 + 3.0 * 2.0 * 2.0 * r);
-    bytes += g.M * (4.0 + 16.0) + g.nblocks * 16.0;
+    // slot written, the pending sum read, the newest lags (history from the
+    // ring beyond lag 0, kernel rows), the traction written; per mode its bin,
+    // q and direction, window, class and row offset; per block its descriptors
+    for (long long s = 0; s < g.M; ++s) {
+      const long long b = s / sbim::kLanes;
+      const int phi = static_cast<int>(b % S);
+      const bool swept = n >= (phi == 0 ? S : phi);
+      const long long fresh = std::min<long long>(g.h_win[s], swept ? (n - phi) % S + 2 : n + 1);
+      double per_plane = 3.0 * 16.0 + 3.0 * 32.0 + 3.0 * 2.0 * r + 3.0 * 2.0 * r;
+      if (swept) per_plane += 10.0 * r;
+      per_plane += std::max(0LL, fresh - 1) * 3.0 * 2.0 * r + fresh * 4.0 * r;
+      bytes += per_plane * g.np + 4.0 + 24.0 + 4.0 + 4.0 + (fresh > 0 ? 8.0 : 0.0);
+    }
+    bytes += g.nblocks * 16.0;
   }
   *mode_lags = lags;
   *conv_bytes = bytes;
