@@ -10,8 +10,9 @@ region is the whole 2000-step job from an empty history, inputs resident in
 HBM.  Reported: mode-history-steps per second (sum over steps, planes and modes
 of min(W, n+1)) for the compensated float32 form (headline), plain float32 and
 float64, the float32-vs-float64 relative L2 error, the HBM roofline fraction
-of the dominant kernel (the launch that pushes a step and runs the history
-sweep), and the float64 CPU oracle on a bounded sample.
+of the dominant kernel (the launch that pushes a step, completes its traction
+spectrum and runs the history sweep), and the float64 CPU oracle on a bounded
+sample.
 """
 from __future__ import annotations
 
@@ -43,8 +44,8 @@ def kernel_source_hash():
 
 
 def read_traffic(workload, precision):
-    """Per-dispatch HBM bytes of the push / history-sweep launch from the committed rocprofv3
-    counter summary, scaled by the copy-kernel calibration; None if absent or taken on other
+    """Per-dispatch HBM bytes of the step launch (push, traction, history sweep) from the
+    committed rocprofv3 counter summary, scaled by the copy-kernel calibration; None if absent or taken on other
     kernel sources."""
     path = os.path.join(PROFILES, "step_kernel_traffic.txt")
     if not os.path.exists(path):
@@ -136,7 +137,7 @@ def measure_form(wl, precision, steps, warmup, device, inputs_cache):
         "init_s": t_init,
         "mode_lags": lags,
         "roofline": {
-            "kernel": f"step_kernel (push + history sweep, depth {info['sweep_depth']})",
+            "kernel": f"step_kernel (push, traction and history sweep, depth {info['sweep_depth']})",
             "bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": gbs / HBM_PEAK_GBS,
             "traffic": traffic,
