@@ -36,10 +36,16 @@ PROFILES = os.path.join(ROOT, "profiles")
 
 
 def kernel_source_hash():
+    """Hash of the kernel sources with comments and blank lines stripped (a comment edit
+    does not invalidate recorded counters; any code change does)."""
+    import re
     h = hashlib.sha256()
     for f in ("kernels.hip", "internal.h"):
-        with open(os.path.join(ROOT, "paper_2102_08756_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_2102_08756_amd", "csrc", f)) as fh:
+            for line in fh:
+                code = re.sub(r"//.*", "", line).rstrip()
+                if code:
+                    h.update(code.encode() + b"\n")
     return h.hexdigest()[:16]
 
 

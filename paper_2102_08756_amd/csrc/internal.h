@@ -19,7 +19,7 @@ constexpr int kFftPerThread = 16;     // transform points per thread in the LDS 
 constexpr int kGaussN = 32;           // Gauss-Legendre points per quadrature panel
 constexpr int kMaxSweep = 8;          // deepest sweep: steps served by one pass over a history
 
-// What push_kernel stores as "velocity" for the epilogue.
+// How the push forms the velocity of the damping term.
 enum VelRule : int {
   VEL_DIFF = 0,   // (x_rot - previous state) / dt
   VEL_SCALE = 1,  // x_rot / dt
