@@ -190,3 +190,100 @@ def step_sources(wl: Workload):
             return special[m]
         return base + (7 * m) % wl.bank
     return fields, index, inc.uniform
+
+
+# ------------------------------------------------------------------ fault runs
+#
+# Stand-alone boundary-integral dynamic rupture on the plane between two
+# half-spaces, with the setup of the paper's TPV3 benchmark (Sec. 3.1): bulk
+# rho = 2670 kg/m^3, c_p = 6000 m/s, c_s = 3464 m/s; friction mu_s = 0.677,
+# mu_k = 0.525, d_c = 0.4 m; background shear 70 MPa along x1 and normal stress
+# 120 MPa (compressive); nucleation over a centred square patch of side 3 km;
+# rupture region 30 km x 15 km (Sec. 3.1 setup figure); dx = 50 m (Sec. 3.2).
+# Readings where the paper prints no number: the shear stress in the patch is
+# (mu_s + 0.005) sigma0, just above the static strength; outside the rupture
+# region the fault is locked (a static coefficient of 1e4); the time step is
+# c_s dt / dx = 0.25.  Cell centres sit at x = (i - n/2 + 1/2) dx, so the patch
+# and the region are symmetric about the grid centre.
+
+TPV3 = dict(rho=2670.0, cp=6000.0, cs=3464.0, mu_s=0.677, mu_k=0.525, d_c=0.4,
+            tau0=70.0e6, sigma0=120.0e6, patch=3000.0, region=(30000.0, 15000.0), dx=50.0)
+LOCKED_MU_S = 1.0e4
+
+
+@dataclass
+class FaultWorkload:
+    name: str
+    n1: int
+    n3: int
+    dx: float
+    steps: int
+    beta: float = 0.25                       # c_s dt / dx
+    region: tuple = TPV3["region"]           # (L1, L3) of the rupture region, m
+    patch: float = TPV3["patch"]             # side of the nucleation patch, m
+    lower: dict = None                       # material below the fault (None: mirror image)
+    window_cap: int = 0                      # 0: the whole run
+    window_mode: str = "fixed"
+    eta_w: float = 1.0
+    excess: float = 0.005                    # patch stress = (mu_s + excess) sigma0
+    tau0_3: float = 0.0                      # background shear along x3, Pa
+
+    def upper(self):
+        t = TPV3
+        return dict(side=1, mu=t["rho"] * t["cs"] ** 2, cs=t["cs"], cp=t["cp"])
+
+    @property
+    def dt(self):
+        return self.beta * self.dx / TPV3["cs"]
+
+    def planes(self):
+        if self.lower is None:
+            return [self.upper()]
+        return [self.upper(), dict(side=-1, **self.lower)]
+
+    def config_dict(self):
+        return dict(n1=self.n1, n3=self.n3, dx1=self.dx, dx3=self.dx, dt=self.dt,
+                    planes=self.planes(), window_cap=self.window_cap or self.steps,
+                    window_mode=self.window_mode, eta_w=self.eta_w)
+
+    def coords(self):
+        x1 = (np.arange(self.n1) - self.n1 / 2 + 0.5) * self.dx
+        x3 = (np.arange(self.n3) - self.n3 / 2 + 0.5) * self.dx
+        return np.meshgrid(x1, x3, indexing="ij")
+
+    def masks(self):
+        X1, X3 = self.coords()
+        h = self.patch / 2
+        patch = (np.abs(X1) < h) & (np.abs(X3) < h)
+        region = (np.abs(X1) < self.region[0] / 2) & (np.abs(X3) < self.region[1] / 2)
+        return patch, region
+
+    def params(self):
+        """(tau0 [3, n1, n3], mu_s, mu_k, d_c [n1, n3]) float64."""
+        t = TPV3
+        patch, region = self.masks()
+        tau0 = np.zeros((3, self.n1, self.n3))
+        tau0[0] = t["tau0"]
+        tau0[0][patch] = (t["mu_s"] + self.excess) * t["sigma0"]
+        tau0[1] = -t["sigma0"]
+        tau0[2] = self.tau0_3
+        mu_s = np.where(region, t["mu_s"], LOCKED_MU_S)
+        mu_k = np.full((self.n1, self.n3), t["mu_k"])
+        d_c = np.full((self.n1, self.n3), t["d_c"])
+        return tau0, mu_s, mu_k, d_c
+
+
+SLOWER = dict(mu=0.64 * TPV3["rho"] * TPV3["cs"] ** 2, cs=0.8 * TPV3["cs"], cp=0.8 * TPV3["cp"])
+
+FAULTS = {
+    # the paper's resolution and setup; the periodic images of the rupture
+    # region lie 21 km (x1) and 36 km (x3) beyond its edges
+    "tpv3_1024": FaultWorkload("tpv3_1024", 1024, 1024, 50.0, 2000),
+    # coarse grids for parity with the oracle
+    "tpv3_coarse16": FaultWorkload("tpv3_coarse16", 16, 16, 750.0, 80, region=(9000.0, 9000.0)),
+    "tpv3_coarse32": FaultWorkload("tpv3_coarse32", 32, 32, 375.0, 150, region=(9000.0, 9000.0)),
+    "tpv3_rect32x16": FaultWorkload("tpv3_rect32x16", 32, 16, 375.0, 120, region=(9000.0, 4500.0),
+                                    tau0_3=4.0e6),
+    "bimaterial32": FaultWorkload("bimaterial32", 32, 32, 375.0, 120, region=(9000.0, 9000.0),
+                                  lower=SLOWER),
+}
