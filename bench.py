@@ -12,7 +12,9 @@ of min(W, n+1)) for the compensated float32 form (headline), plain float32 and
 float64, the float32-vs-float64 relative L2 error, the HBM roofline fraction
 of the dominant kernel (the launch that pushes a step, completes its traction
 spectrum and runs the history sweep), and the float64 CPU oracle on a bounded
-sample.
+sample.  A second leg ("rupture") times the stand-alone dynamic rupture of the
+paper's TPV3 setup (1024 x 1024 cells of 50 m, 2000 steps) through the fault
+entry points.
 """
 from __future__ import annotations
 
@@ -203,6 +205,77 @@ def accuracy(wl, steps, device, inputs_cache, forms=("fp32_comp", "fp32"), block
     return out
 
 
+def measure_rupture(fw, precision, device, warmup=20):
+    """Stand-alone rupture on the fault between two half-spaces (the paper's TPV3 setup
+    at its resolution; the lower half-space is the mirror image of the upper one): the
+    whole run timed from rest, one library step (push without damping, inverse FFT,
+    interface solve) per time step."""
+    import torch
+    from paper_2102_08756_amd import SBIM, Config, Fault
+    cfg = Config.from_dict(fw.config_dict(), precision=precision, input_kind="increment")
+    t0 = time.time()
+    sb = SBIM(cfg, device=device)
+    prm = [torch.tensor(a, dtype=torch.float64, device=device).contiguous() for a in fw.params()]
+    flt = Fault(sb, *prm)
+    t_init = time.time() - t0
+    sb.profile_conv(True)
+    for _ in range(warmup):
+        flt.step()
+    flt.reset()
+    sb.profile_conv(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(fw.steps):
+        flt.step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    conv_ms, launches = sb.conv_timing()
+    sb.profile_conv(False)
+    lags = conv_bytes = 0.0
+    for n in range(fw.steps):
+        a, b = sb.step_work(n)
+        lags += a
+        conv_bytes += b
+    slip = flt.read("slip").cpu().numpy()
+    path = flt.read("slip_path")[0].cpu().numpy()
+    info = sb.info()
+    flt.close()
+    sb.close()
+    del sb, flt, prm
+    torch.cuda.empty_cache()
+    _, region = fw.masks()
+    gbs = conv_bytes / (conv_ms * 1e-3) / 1e9
+    return {
+        "ms_per_step": 1e3 * elapsed / fw.steps, "mode_lags_per_s": lags / elapsed,
+        "step_kernel_GBs": gbs, "step_kernel_frac": gbs / HBM_PEAK_GBS,
+        "sweep_depth": info["sweep_depth"], "init_s": t_init, "ring_bytes": info["ring_bytes"],
+        "region_slipped_frac": float((path[region] > 0).mean()),
+        "outside_slipped_cells": int((path[~region] > 0).sum()),
+        "max_slip_m": float(np.abs(slip).max()), "_slip": slip,
+    }
+
+
+def rupture_leg(fw, forms, device):
+    out = {"workload": fw.name, "n1": fw.n1, "n3": fw.n3, "dx_m": fw.dx, "dt_s": fw.dt,
+           "time_steps": fw.steps, "window_cap": fw.window_cap or fw.steps,
+           "lower_half_space": "mirror image" if fw.lower is None else "own material", "forms": {}}
+    slips = {}
+    for p in forms:
+        r = measure_rupture(fw, p, device)
+        slips[p] = r.pop("_slip")
+        out["forms"][p] = r
+        print(f"[bench] rupture {fw.name} {p}: {r['ms_per_step']:.3f} ms/step, "
+              f"{r['mode_lags_per_s']:.3e} mode-lags/s, step kernel {r['step_kernel_GBs']:.0f} GB/s; "
+              f"region slipped {100 * r['region_slipped_frac']:.1f}%, max slip {r['max_slip_m']:.3f} m",
+              file=sys.stderr, flush=True)
+    if "fp64" in slips:
+        for p in slips:
+            if p != "fp64":
+                out[f"{p}_vs_fp64_final_slip_rel_l2"] = float(
+                    np.linalg.norm(slips[p] - slips["fp64"]) / np.linalg.norm(slips["fp64"]))
+    return out
+
+
 def cpu_baseline(wl, sample_modes=64, seed=0):
     """float64 oracle on one steady-state step: full naive DFTs, convolution on sampled modes."""
     import oracle
@@ -258,6 +331,9 @@ def main():
     ap.add_argument("--forms", default="fp32_comp,fp32,fp64")
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--rupture-forms", default="fp32_comp,fp64",
+                    help="forms of the rupture leg on the fault workload (empty: skip it)")
+    ap.add_argument("--rupture", default="tpv3_1024", help="fault workload of the rupture leg")
     ap.add_argument("--calibrate-copy", type=float, default=0.0,
                     help="only run a torch device copy of this many GiB (counter calibration)")
     args = ap.parse_args()
@@ -297,6 +373,8 @@ def main():
                 cache[dt] = Inputs(wl, dt, device)
         acc = accuracy(wl, steps, device, cache, [f for f in forms if f != "fp64"])
         print(f"[bench] accuracy: {acc}", file=sys.stderr, flush=True)
+    rforms = [f for f in args.rupture_forms.split(",") if f]
+    rup = rupture_leg(workloads.FAULTS[args.rupture], rforms, device) if rforms else None
     cpu = None if args.no_cpu else cpu_baseline(wl)
     head = forms[0]
     r = res[head]
@@ -318,6 +396,7 @@ def main():
                       "table_bytes": res[f]["info"]["table_bytes"],
                       "kernel_classes": res[f]["info"]["kernel_classes"]} for f in forms},
         "accuracy": acc,
+        "rupture": rup,
         "kernel_source_hash": kernel_source_hash(),
     }
     print(json.dumps(line))

@@ -223,6 +223,94 @@ int sbim_mode_kernel(sbim_handle *h, int p, int i1, int i3, double *host_out, in
 int sbim_profile_conv(sbim_handle *h, int enable);
 int sbim_conv_timing(sbim_handle *h, double *total_ms, long long *launches);
 
+/*
+ * ---------------------------------------------------------------------------
+ * Frictional fault between two half-spaces (stand-alone boundary-integral
+ * dynamic rupture).
+ *
+ * The fault is the plane x2 = 0 of the grid.  Above it lies the half-space of
+ * plane 0 (side +1); below it the half-space of plane 1 (side -1) when the
+ * handle has two planes, otherwise the mirror image of plane 0 (same
+ * material, u-(x) = (-u1+, u2+, -u3+)): the fault is then a symmetry plane
+ * and its normal traction stays at tau0_2 (Sec. 3.1 uses this symmetry).
+ * Each side obeys its own boundary relation (Eq. SBI, two independent
+ * half-spaces).  The interface conditions are those of Sec. 2.2: the
+ * traction is continuous across the fault; per cell either stick (Eq. stick,
+ * zero slip rate, shear traction within the strength) or slip (Eq. slip,
+ * shear traction at the strength, slip rate along it), chosen as in
+ * Eq. stickslip; strength = normal stress x mu(delta), mu the linear
+ * slip-weakening coefficient of Eq. slipweak over the slip path delta.  The
+ * fault does not open: the normal velocity is continuous.
+ *
+ * One sbim_fault_step is the explicit step n (displacements u+ = u- = 0 and
+ * delta = 0 before step 0):
+ *   1. push each side's displacement u^n (u^n - u^{n-1} for an SBIM_INCREMENT
+ *      handle) with the damping term left out, and take that push's
+ *      tractions: s = the nonlocal and instantaneous parts of Eq. SBI;
+ *   2. f = tau0 + s per side; with Z_i = eta_ii mu / c_s per side (the
+ *      damping coefficients of Eq. SBI, eta_22 = c_p / c_s):
+ *        tau_2 = (Z2- f2+ + Z2+ f2-) / (Z2+ + Z2-)
+ *        t~    = (Z1- f+  + Z1+ f- ) / (Z1+ + Z1-)   for the shear pair (1, 3)
+ *        S     = max(-tau_2, 0) mu(delta^n)          (compression positive)
+ *        |t~| <= S: tau = t~, V = 0;  else tau = S t~ / |t~|,
+ *                   V = (t~ - tau)(1/Z1+ + 1/Z1-)
+ *   3. v+ = (f+ - tau) / Z+, v- = (tau - f-) / Z-; u^{n+1} = u^n + dt v;
+ *      slip D += dt V; delta += dt |V|.
+ * The fault's arithmetic and state are float64 for every precision; the
+ * traction functional s and the pushed displacement have the handle's
+ * precision.  Fault fields are device arrays [rows][n1][n3] of double
+ * (x3 fastest): traction rows (x1, x2, x3), slip and slip-rate rows (x1, x3).
+ *
+ * Ownership: the fault keeps copies of the parameters, its state, and two
+ * field buffers of the handle's precision.  It drives its handle: between
+ * sbim_fault_create and sbim_fault_destroy the handle must not be pushed,
+ * reset or destroyed by other calls (SBIM_E_STATE is returned when the step
+ * counts disagree).  Destroy the fault before its handle.
+ */
+typedef struct sbim_fault sbim_fault;
+
+typedef struct {
+  const double *tau0;  /* device [3][n1][n3]: background traction sigma_2i (i = 2: normal, tension > 0) */
+  const double *mu_s;  /* device [n1][n3]: static friction coefficient, >= mu_k */
+  const double *mu_k;  /* device [n1][n3]: kinetic friction coefficient, >= 0 */
+  const double *d_c;   /* device [n1][n3]: slip-weakening distance, > 0 */
+} sbim_fault_params;
+
+/* fields of sbim_fault_read */
+#define SBIM_FAULT_TRACTION 0     /* [3][n1][n3] tau of the last step */
+#define SBIM_FAULT_SLIP_RATE 1    /* [2][n1][n3] V of the last step (x1, x3) */
+#define SBIM_FAULT_SLIP 2         /* [2][n1][n3] D after the last step */
+#define SBIM_FAULT_SLIP_PATH 3    /* [n1][n3] delta after the last step */
+#define SBIM_FAULT_DISPLACEMENT 4 /* [2][3][n1][n3] u+ then u- after the last step */
+#define SBIM_FAULT_VELOCITY 5     /* [2][3][n1][n3] v+ then v- of the last step */
+
+/*
+ * sbim_fault_create: a fault on handle h (planes as described above, handle at
+ * step 0).  The parameter arrays are copied (the caller may free them
+ * afterwards) and checked on the device; synchronises the stream.
+ * SBIM_E_INVALID names the first offending cell (non-finite value, d_c <= 0,
+ * mu_k < 0 or mu_s < mu_k).  A cell can be locked (a bonded interface) by a
+ * static coefficient that no traction reaches.
+ */
+int sbim_fault_create(sbim_handle *h, const sbim_fault_params *prm, sbim_fault **out);
+
+/*
+ * sbim_fault_step: one explicit step (push, inverse transform, interface solve
+ * on the handle's stream).  tau_or_null / slip_rate_or_null: optional device
+ * [3][n1][n3] / [2][n1][n3] doubles that also receive the step's traction and
+ * slip rate.
+ */
+int sbim_fault_step(sbim_fault *f, double *tau_or_null, double *slip_rate_or_null);
+
+/* Copy one fault field (SBIM_FAULT_*) into device memory dst (asynchronous). */
+int sbim_fault_read(const sbim_fault *f, int field, double *dst);
+
+/* Zero the fault state and reset its handle (sbim_reset). */
+int sbim_fault_reset(sbim_fault *f);
+
+/* Synchronise the stream and free the fault (not its handle); NULL is accepted. */
+int sbim_fault_destroy(sbim_fault *f);
+
 #ifdef __cplusplus
 }
 #endif

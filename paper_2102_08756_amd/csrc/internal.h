@@ -24,7 +24,8 @@ enum VelRule : int {
   VEL_DIFF = 0,   // (x_rot - previous state) / dt
   VEL_SCALE = 1,  // x_rot / dt
   VEL_INPUT = 2,  // rotate(spectrum of the supplied velocity)
-  VEL_COPY = 3    // x_rot
+  VEL_COPY = 3,   // x_rot
+  VEL_ZERO = 4    // no damping term (the fault solve adds it)
 };
 enum StateRule : int { STATE_REPLACE = 0, STATE_ACCUM = 1 };
 
@@ -173,6 +174,26 @@ struct SweepArgs {
   long long nphase;       // blocks of this launch's sweep phase
 };
 
+// fault.hip: interface solve of a frictional fault between the two sides.
+// Fields are [component][cell] with cell = i1 * n3 + i3; u, v hold the upper
+// side in components 0..2 and the lower side in 3..5.
+struct FaultArgs {
+  const void *functional;     // [P][3][cells] working precision: tractions without damping
+  const double *tau0, *mu_s, *mu_k, *d_c;
+  double *u, *v;              // [2][3][cells]
+  double *slip, *rate;        // [2][cells]: components (x1, x3)
+  double *delta;              // [cells] slip path
+  double *tau;                // [3][cells]
+  double *tau_out, *rate_out; // optional copies for the caller
+  void *push;                 // [P][3][cells] working precision: input of the next push
+  long long cells;
+  double zp[3], zm[3];        // eta_ii mu / c_s of the upper and lower side
+  double dt;
+  int increment;              // the next push takes the increment dt v instead of u
+};
+hipError_t launch_fault_step(bool fp64, bool mirror, const FaultArgs &a, hipStream_t st);
+hipError_t launch_fault_check(const double *tau0, const double *mu_s, const double *mu_k,
+                              const double *d_c, long long cells, long long *bad, hipStream_t st);
 hipError_t launch_tabulate(bool fp64, const Group &g, double dt, const double *gl_x,
                            const double *gl_w, hipStream_t st);
 

@@ -343,6 +343,8 @@ __device__ __forceinline__ void mode_step(const ModeArgs &a, int p, long long s)
         v = double2{xr[c].x * a.inv_dt, xr[c].y * a.inv_dt};
       else if (a.vel_rule == VEL_INPUT)
         v = vr[c];
+      else if (a.vel_rule == VEL_ZERO)
+        v = double2{0.0, 0.0};
       else
         v = xr[c];
       v0[c] = cplx<R>{static_cast<R>(v.x), static_cast<R>(v.y)};

@@ -31,7 +31,11 @@ EXPORTS = (
     "sbim_backward_reset", "sbim_reset", "sbim_destroy", "sbim_last_error", "sbim_set_stream",
     "sbim_get_info", "sbim_state_bytes", "sbim_save_state", "sbim_load_state", "sbim_step_work",
     "sbim_mode_kernel", "sbim_profile_conv", "sbim_conv_timing",
+    "sbim_fault_create", "sbim_fault_step", "sbim_fault_read", "sbim_fault_reset",
+    "sbim_fault_destroy",
 )
+FAULT_FIELDS = {"traction": (0, 3), "slip_rate": (1, 2), "slip": (2, 2), "slip_path": (3, 1),
+                "displacement": (4, 6), "velocity": (5, 6)}
 
 
 class _Plane(ctypes.Structure):
@@ -53,6 +57,11 @@ class _Info(ctypes.Structure):
                 ("state_bytes", ctypes.c_longlong), ("step", ctypes.c_longlong),
                 ("backward_step", ctypes.c_longlong), ("material_groups", ctypes.c_int),
                 ("sweep_depth", ctypes.c_int)]
+
+
+class _FaultParams(ctypes.Structure):
+    _fields_ = [("tau0", ctypes.c_void_p), ("mu_s", ctypes.c_void_p), ("mu_k", ctypes.c_void_p),
+                ("d_c", ctypes.c_void_p)]
 
 
 _lib = None
@@ -86,6 +95,11 @@ def load_library(path=LIB_PATH):
         "sbim_mode_kernel": (i, [vp, i, i, i, ctypes.POINTER(d), i]),
         "sbim_profile_conv": (i, [vp, i]),
         "sbim_conv_timing": (i, [vp, ctypes.POINTER(d), ctypes.POINTER(ll)]),
+        "sbim_fault_create": (i, [vp, ctypes.POINTER(_FaultParams), ctypes.POINTER(vp)]),
+        "sbim_fault_step": (i, [vp, vp, vp]),
+        "sbim_fault_read": (i, [vp, i, vp]),
+        "sbim_fault_reset": (i, [vp]),
+        "sbim_fault_destroy": (i, [vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -281,6 +295,80 @@ class SBIM:
         if getattr(self, "_h", None):
             self._L.sbim_destroy(self._h)
             self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ------------------------------------------------------------------ fault
+
+class Fault:
+    """Frictional fault between plane 0 (above, side +1) and plane 1 (below,
+    side -1) of ``sbim``, or plane 0's mirror image when it has one plane.
+
+    tau0 [3, n1, n3], mu_s, mu_k, d_c [n1, n3]: float64 tensors on the handle's
+    device (copied).  Each ``step`` is one explicit step of the library's
+    interface solve (``sbim_fault_step``); fields are float64 [rows, n1, n3].
+    """
+
+    def __init__(self, sbim: SBIM, tau0, mu_s, mu_k, d_c):
+        self.sbim = sbim
+        n1, n3 = sbim.cfg.n1, sbim.cfg.n3
+        shapes = {"tau0": (3, n1, n3), "mu_s": (n1, n3), "mu_k": (n1, n3), "d_c": (n1, n3)}
+        args = {"tau0": tau0, "mu_s": mu_s, "mu_k": mu_k, "d_c": d_c}
+        for k, t in args.items():
+            if (not isinstance(t, torch.Tensor) or t.device != sbim.device or t.dtype != torch.float64
+                    or tuple(t.shape) != shapes[k] or not t.is_contiguous()):
+                raise ValueError(f"{k}: expected a contiguous float64 {shapes[k]} tensor on {sbim.device}")
+        self.cells = (n1, n3)
+        p = _FaultParams(*(ctypes.c_void_p(args[k].data_ptr()) for k in ("tau0", "mu_s", "mu_k", "d_c")))
+        sbim._sync_stream()
+        f = ctypes.c_void_p()
+        sbim._check(sbim._L.sbim_fault_create(sbim._h, ctypes.byref(p), ctypes.byref(f)))
+        self._f = f
+
+    def _out(self, t, rows, name):
+        if t is None:
+            return None
+        shape = (rows,) + self.cells
+        if (not isinstance(t, torch.Tensor) or t.device != self.sbim.device or t.dtype != torch.float64
+                or tuple(t.shape) != shape or not t.is_contiguous()):
+            raise ValueError(f"{name}: expected a contiguous float64 {shape} tensor")
+        return t
+
+    def step(self, tau=None, slip_rate=None):
+        self._out(tau, 3, "tau")
+        self._out(slip_rate, 2, "slip_rate")
+        self.sbim._sync_stream()
+        self.sbim._check(self.sbim._L.sbim_fault_step(self._f, _ptr(tau), _ptr(slip_rate)))
+
+    def read(self, name):
+        fid, rows = FAULT_FIELDS[name]
+        out = torch.empty((rows,) + self.cells, dtype=torch.float64, device=self.sbim.device)
+        self.sbim._sync_stream()
+        self.sbim._check(self.sbim._L.sbim_fault_read(self._f, fid, _ptr(out)))
+        return out
+
+    def run(self, steps):
+        """``steps`` steps; returns the traction [N, 3, n1, n3] and slip-rate
+        [N, 2, n1, n3] histories (device)."""
+        tau = torch.empty((steps, 3) + self.cells, dtype=torch.float64, device=self.sbim.device)
+        rate = torch.empty((steps, 2) + self.cells, dtype=torch.float64, device=self.sbim.device)
+        for n in range(steps):
+            self.step(tau[n], rate[n])
+        return tau, rate
+
+    def reset(self):
+        self.sbim._sync_stream()
+        self.sbim._check(self.sbim._L.sbim_fault_reset(self._f))
+
+    def close(self):
+        if getattr(self, "_f", None):
+            self.sbim._L.sbim_fault_destroy(self._f)
+            self._f = None
 
     def __del__(self):
         try:

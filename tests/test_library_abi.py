@@ -72,3 +72,11 @@ def test_null_arguments_rejected():
     assert lib.sbim_backward(None, None, None, None) == B.SBIM_E_INVALID
     assert lib.sbim_destroy(None) == B.SBIM_OK
     assert lib.sbim_state_bytes(None) == -1
+    assert lib.sbim_fault_create(None, None, None) == B.SBIM_E_INVALID
+    f = ctypes.c_void_p(123)
+    assert lib.sbim_fault_create(None, None, ctypes.byref(f)) == B.SBIM_E_INVALID
+    assert f.value is None
+    assert lib.sbim_fault_step(None, None, None) == B.SBIM_E_INVALID
+    assert lib.sbim_fault_read(None, 0, None) == B.SBIM_E_INVALID
+    assert lib.sbim_fault_reset(None) == B.SBIM_E_INVALID
+    assert lib.sbim_fault_destroy(None) == B.SBIM_OK
