@@ -239,11 +239,12 @@ int sbim_conv_timing(sbim_handle *h, double *total_ms, long long *launches);
  * zero slip rate, shear traction within the strength) or slip (Eq. slip,
  * shear traction at the strength, slip rate along it), chosen as in
  * Eq. stickslip; strength = normal stress x mu(delta), mu the linear
- * slip-weakening coefficient of Eq. slipweak over the slip path delta.  The
- * fault does not open: the normal velocity is continuous.
+ * slip-weakening coefficient of Eq. slipweak and delta the amplitude of the
+ * slip vector (Sec. 2.2).  The fault does not open: the normal velocity is
+ * continuous.
  *
  * One sbim_fault_step is the explicit step n (displacements u+ = u- = 0 and
- * delta = 0 before step 0):
+ * slip D = 0 before step 0):
  *   1. push each side's displacement u^n (u^n - u^{n-1} for an SBIM_INCREMENT
  *      handle) with the damping term left out, and take that push's
  *      tractions: s = the nonlocal and instantaneous parts of Eq. SBI;
@@ -251,11 +252,11 @@ int sbim_conv_timing(sbim_handle *h, double *total_ms, long long *launches);
  *      damping coefficients of Eq. SBI, eta_22 = c_p / c_s):
  *        tau_2 = (Z2- f2+ + Z2+ f2-) / (Z2+ + Z2-)
  *        t~    = (Z1- f+  + Z1+ f- ) / (Z1+ + Z1-)   for the shear pair (1, 3)
- *        S     = max(-tau_2, 0) mu(delta^n)          (compression positive)
+ *        S     = max(-tau_2, 0) mu(|D^n|)            (compression positive)
  *        |t~| <= S: tau = t~, V = 0;  else tau = S t~ / |t~|,
  *                   V = (t~ - tau)(1/Z1+ + 1/Z1-)
  *   3. v+ = (f+ - tau) / Z+, v- = (tau - f-) / Z-; u^{n+1} = u^n + dt v;
- *      slip D += dt V; delta += dt |V|.
+ *      slip D^{n+1} = D^n + dt V.
  * The fault's arithmetic and state are float64 for every precision; the
  * traction functional s and the pushed displacement have the handle's
  * precision.  Fault fields are device arrays [rows][n1][n3] of double
@@ -280,9 +281,8 @@ typedef struct {
 #define SBIM_FAULT_TRACTION 0     /* [3][n1][n3] tau of the last step */
 #define SBIM_FAULT_SLIP_RATE 1    /* [2][n1][n3] V of the last step (x1, x3) */
 #define SBIM_FAULT_SLIP 2         /* [2][n1][n3] D after the last step */
-#define SBIM_FAULT_SLIP_PATH 3    /* [n1][n3] delta after the last step */
-#define SBIM_FAULT_DISPLACEMENT 4 /* [2][3][n1][n3] u+ then u- after the last step */
-#define SBIM_FAULT_VELOCITY 5     /* [2][3][n1][n3] v+ then v- of the last step */
+#define SBIM_FAULT_DISPLACEMENT 3 /* [2][3][n1][n3] u+ then u- after the last step */
+#define SBIM_FAULT_VELOCITY 4     /* [2][3][n1][n3] v+ then v- of the last step */
 
 /*
  * sbim_fault_create: a fault on handle h (planes as described above, handle at

@@ -8,12 +8,13 @@ own boundary relation (Sec. 2.3, Eq. SBI; two independent half-spaces, as in the
 independent formulation the paper defers to).  The interface conditions are the
 ones of Sec. 2.2: traction continuity across the fault, the stick and slip
 conditions (Eqs. stick and slip) and linear slip-weakening strength (Eq.
-slipweak, strength = normal stress x friction coefficient).  The paper runs this
+slipweak, strength = normal stress x friction coefficient, with the slip delta
+of Eq. slipweak the amplitude of the slip vector, Sec. 2.2).  The paper runs this
 with its finite elements next to the fault (Sec. 2.4, items 5-7); here the two
 half-spaces touch the fault directly, which is the stand-alone boundary-integral
 rupture it compares against in Sec. 3.
 
-Explicit step n (u^{+,0} = u^{-,0} = 0, slip path delta^0 = 0):
+Explicit step n (u^{+,0} = u^{-,0} = 0, slip D^0 = 0):
 
 1. f^{+-} = tau0 + s^{+-}: background traction plus the traction that each
    half-space's boundary relation gives for its displacement history up to
@@ -28,12 +29,13 @@ Explicit step n (u^{+,0} = u^{-,0} = 0, slip path delta^0 = 0):
    Shear components (1, 3): the traction that keeps the slip rate zero is
        tau~ = (Z^- f^+ + Z^+ f^-) / (Z^+ + Z^-).
 3. Strength tau^s = sigma^n mu(delta^n) with sigma^n = max(-tau_2, 0)
-   (compression positive; tension gives zero strength) and mu of Eq. slipweak.
+   (compression positive; tension gives zero strength), mu of Eq. slipweak and
+   delta^n = |D^n| the amplitude of the slip before this step's update.
 4. Stick if |tau~| <= tau^s: tau = tau~, slip rate V = 0.  Otherwise slip:
    tau = tau^s tau~ / |tau~| and V = (tau~ - tau)(1/Z^+ + 1/Z^-), parallel to
    tau~ (so V >= 0 along the traction, as Eq. slip requires).
 5. v^+ = (f^+ - tau)/Z^+, v^- = (tau - f^-)/Z^-; u^{+-,n+1} = u^{+-,n} + dt v^{+-};
-   slip D^{n+1} = D^n + dt V, slip path delta^{n+1} = delta^n + dt |V|.
+   slip D^{n+1} = D^n + dt V.
 
 One plane only (side +1): the lower half-space is the mirror image of the upper
 one (same material, u^- = (-u1^+, u2^+, -u3^+)), so s^- = (s1^+, -s2^+, s3^+) and
@@ -74,19 +76,20 @@ def impedances(cfg):
 
 
 def friction_coefficient(delta, mu_s, mu_k, d_c):
-    """Eq. slipweak: linear weakening from mu_s to mu_k over the slip path d_c."""
+    """Eq. slipweak: linear weakening from mu_s to mu_k as the slip grows to d_c."""
     return np.where(delta < d_c, mu_s - (mu_s - mu_k) * delta / d_c, mu_k)
 
 
-def interface_solve(fp, fm, zp, zm, delta, prm):
+def interface_solve(fp, fm, zp, zm, D, prm):
     """Steps 2-4 on the grid.  fp, fm: [3, n1, n3] traction functionals of the two
-    sides (background included).  Returns (tau [3], V [2] for components (1, 3),
-    v^+ [3], v^- [3])."""
+    sides (background included); D [2, n1, n3]: slip before the step.  Returns
+    (tau [3], V [2] for components (1, 3), v^+ [3], v^- [3])."""
     tau = np.empty_like(fp)
     tau[1] = (zm[1] * fp[1] + zp[1] * fm[1]) / (zp[1] + zm[1])
     sh = [0, 2]
     stick = (zm[0] * fp[sh] + zp[0] * fm[sh]) / (zp[0] + zm[0])      # [2, n1, n3]
     mag = np.sqrt(stick[0] ** 2 + stick[1] ** 2)
+    delta = np.sqrt(D[0] * D[0] + D[1] * D[1])
     strength = np.maximum(-tau[1], 0.0) * friction_coefficient(delta, prm.mu_s, prm.mu_k, prm.d_c)
     slipping = mag > strength
     scale = np.where(slipping, strength / np.where(slipping, mag, 1.0), 1.0)
@@ -106,7 +109,6 @@ def rupture(cfg, prm: FaultParams, steps, weights_cache=None):
     traction [N, 3, n1, n3]   fault traction tau^n
     slip_rate [N, 2, n1, n3]  V^n, components (1, 3)
     slip [N, 2, n1, n3]       D^{n+1} (after the step's update)
-    delta [N, n1, n3]         slip path delta^{n+1}
     v_plus, v_minus [N, 3, n1, n3]  side velocities v^{+-,n}
     """
     if not isinstance(cfg, Config):
@@ -126,11 +128,10 @@ def rupture(cfg, prm: FaultParams, steps, weights_cache=None):
 
     u = np.zeros((P, 3, n1, n3))
     D = np.zeros((2, n1, n3))
-    delta = np.zeros((n1, n3))
     hist = [[] for _ in range(P)]
     out = {k: np.empty((steps,) + s) for k, s in (
         ("traction", (3, n1, n3)), ("slip_rate", (2, n1, n3)), ("slip", (2, n1, n3)),
-        ("delta", (n1, n3)), ("v_plus", (3, n1, n3)), ("v_minus", (3, n1, n3)))}
+        ("v_plus", (3, n1, n3)), ("v_minus", (3, n1, n3)))}
     for n in range(steps):
         s = np.empty((P, 3, n1, n3))
         for p in range(P):
@@ -143,16 +144,14 @@ def rupture(cfg, prm: FaultParams, steps, weights_cache=None):
             s[p] = dft.inverse_half(th.reshape(3, n1, h), n3)
         fp = tau0 + s[0]
         fm = tau0 + (MIRROR[:, None, None] * s[0] if P == 1 else s[1])
-        tau, V, vp, vm = interface_solve(fp, fm, zp, zm, delta, prm)
+        tau, V, vp, vm = interface_solve(fp, fm, zp, zm, D, prm)
         u[0] += cfg.dt * vp
         if P == 2:
             u[1] += cfg.dt * vm
         D += cfg.dt * V
-        delta += cfg.dt * np.sqrt(V[0] ** 2 + V[1] ** 2)
         out["traction"][n] = tau
         out["slip_rate"][n] = V
         out["slip"][n] = D
-        out["delta"][n] = delta
         out["v_plus"][n] = vp
         out["v_minus"][n] = vm
     return out

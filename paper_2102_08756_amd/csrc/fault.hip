@@ -4,7 +4,8 @@
 // (the boundary relation of Sec. 2.3 with its damping term left out); the
 // interface conditions are those of Sec. 2.2 (traction continuity, Eqs. stick
 // and slip chosen per cell as in Eq. stickslip, strength = normal stress x the
-// slip-weakening coefficient of Eq. slipweak), with the damping coefficients of
+// slip-weakening coefficient of Eq. slipweak at the amplitude of the slip
+// vector before the step), with the damping coefficients of
 // Eq. SBI as the impedances that tie each side's velocity to its traction.
 #include <hip/hip_runtime.h>
 
@@ -48,7 +49,8 @@ __global__ __launch_bounds__(kFaultThreads) void fault_step_kernel(FaultArgs a) 
   const double st2 = (a.zm[0] * fp[2] + a.zp[0] * fm[2]) / zs;
   const double mag = sqrt(st0 * st0 + st2 * st2);
 
-  const double delta = a.delta[c];
+  const double d0 = a.slip[c], d2 = a.slip[n + c];
+  const double delta = sqrt(d0 * d0 + d2 * d2);
   const double mus = a.mu_s[c], muk = a.mu_k[c], dc = a.d_c[c];
   const double mu = delta < dc ? mus - (mus - muk) * delta / dc : muk;
   const double strength = fmax(-tau[1], 0.0) * mu;
@@ -83,9 +85,8 @@ __global__ __launch_bounds__(kFaultThreads) void fault_step_kernel(FaultArgs a) 
     a.tau[i * n + c] = tau[i];
     if (a.tau_out) a.tau_out[i * n + c] = tau[i];
   }
-  a.slip[c] += dt * V0;
-  a.slip[n + c] += dt * V2;
-  a.delta[c] = delta + dt * sqrt(V0 * V0 + V2 * V2);
+  a.slip[c] = d0 + dt * V0;
+  a.slip[n + c] = d2 + dt * V2;
   a.rate[c] = V0;
   a.rate[n + c] = V2;
   if (a.rate_out) {

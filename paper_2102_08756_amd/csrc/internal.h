@@ -182,7 +182,6 @@ struct FaultArgs {
   const double *tau0, *mu_s, *mu_k, *d_c;
   double *u, *v;              // [2][3][cells]
   double *slip, *rate;        // [2][cells]: components (x1, x3)
-  double *delta;              // [cells] slip path
   double *tau;                // [3][cells]
   double *tau_out, *rate_out; // optional copies for the caller
   void *push;                 // [P][3][cells] working precision: input of the next push

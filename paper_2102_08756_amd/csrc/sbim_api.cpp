@@ -842,7 +842,7 @@ int sbim_conv_timing(sbim_handle *h, double *total_ms, long long *launches) {
 // Frictional fault between the half-space of plane 0 (above) and the one below
 // it (plane 1, or the mirror image of plane 0).  Float64 state in one block of
 // [kFaultRows][cells]: u (6 rows: upper side x1..x3, lower side x1..x3), v (6),
-// slip (2), slip rate (2), slip path (1), traction (3).
+// slip (2), slip rate (2), traction (3).
 struct sbim_fault {
   sbim_handle *h = nullptr;
   long long cells = 0;
@@ -858,8 +858,8 @@ struct sbim_fault {
 
 namespace {
 
-constexpr int kFaultRows = 20;
-constexpr int kRowU = 0, kRowV = 6, kRowSlip = 12, kRowRate = 14, kRowDelta = 16, kRowTau = 17;
+constexpr int kFaultRows = 19;
+constexpr int kRowU = 0, kRowV = 6, kRowSlip = 12, kRowRate = 14, kRowTau = 16;
 
 void free_fault(sbim_fault *f) {
   if (!f) return;
@@ -977,7 +977,6 @@ int sbim_fault_step(sbim_fault *f, double *tau_out, double *rate_out) {
   a.v = f->st + kRowV * n;
   a.slip = f->st + kRowSlip * n;
   a.rate = f->st + kRowRate * n;
-  a.delta = f->st + kRowDelta * n;
   a.tau = f->st + kRowTau * n;
   a.tau_out = tau_out;
   a.rate_out = rate_out;
@@ -1004,7 +1003,6 @@ int sbim_fault_read(const sbim_fault *f, int field, double *dst) {
     case SBIM_FAULT_TRACTION: row = kRowTau, rows = 3; break;
     case SBIM_FAULT_SLIP_RATE: row = kRowRate, rows = 2; break;
     case SBIM_FAULT_SLIP: row = kRowSlip, rows = 2; break;
-    case SBIM_FAULT_SLIP_PATH: row = kRowDelta, rows = 1; break;
     case SBIM_FAULT_DISPLACEMENT: row = kRowU, rows = 6; break;
     case SBIM_FAULT_VELOCITY: row = kRowV, rows = 6; break;
     default: return fail(h, SBIM_E_INVALID, "unknown fault field %d", field);

@@ -34,8 +34,8 @@ EXPORTS = (
     "sbim_fault_create", "sbim_fault_step", "sbim_fault_read", "sbim_fault_reset",
     "sbim_fault_destroy",
 )
-FAULT_FIELDS = {"traction": (0, 3), "slip_rate": (1, 2), "slip": (2, 2), "slip_path": (3, 1),
-                "displacement": (4, 6), "velocity": (5, 6)}
+FAULT_FIELDS = {"traction": (0, 3), "slip_rate": (1, 2), "slip": (2, 2), "displacement": (3, 6),
+                "velocity": (4, 6)}
 
 
 class _Plane(ctypes.Structure):

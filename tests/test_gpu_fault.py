@@ -3,7 +3,7 @@
 Every case runs the library's explicit step (push without damping, inverse
 transform, interface solve) and ``oracle.fault.rupture`` on the same seeded
 workload and compares, per step and cell, the fault traction, the slip rate,
-the slip, the slip path and both sides' displacement and velocity.  Bars,
+the slip and both sides' displacement and velocity.  Bars,
 relative to each field's largest magnitude over the run: float64 1e-9 (the
 transforms and history sums agree to ~1e-13; the stick/slip choice and the
 weakening amplify that by the ratio of shear modulus to strength drop), and
@@ -53,13 +53,12 @@ def gpu_run(name, precision, kind, steps=None):
     wl = workloads.FAULTS[name]
     steps = steps or wl.steps
     sb, f = make_fault(wl, precision, kind)
-    out = {k: [] for k in ("traction", "slip_rate", "slip", "delta", "v_plus", "v_minus", "u_plus")}
+    out = {k: [] for k in ("traction", "slip_rate", "slip", "v_plus", "v_minus", "u_plus")}
     for n in range(steps):
         f.step()
         out["traction"].append(f.read("traction"))
         out["slip_rate"].append(f.read("slip_rate"))
         out["slip"].append(f.read("slip"))
-        out["delta"].append(f.read("slip_path")[0])
         v = f.read("velocity")
         out["v_plus"].append(v[:3])
         out["v_minus"].append(v[3:])
@@ -86,7 +85,7 @@ def test_fault_fp64_matches_oracle(name, kind):
     ref = oracle_run(name)
     got = gpu_run(name, "fp64", kind)
     worst = {}
-    for key in ("traction", "slip_rate", "slip", "delta", "v_plus", "v_minus"):
+    for key in ("traction", "slip_rate", "slip", "v_plus", "v_minus"):
         scale = max(np.abs(ref[key]).max(), 1e-300)
         worst[key] = float(np.abs(got[key] - ref[key]).max() / scale)
     # displacement of the upper side: the running sum of dt v+
@@ -105,7 +104,7 @@ def test_fault_fp32_forms_against_oracle(name, precision):
     ref = oracle_run(name)
     got = gpu_run(name, precision, "increment")
     errs = {}
-    for key in ("traction", "slip_rate", "slip", "delta"):
+    for key in ("traction", "slip_rate", "slip"):
         errs[key] = float(np.linalg.norm(got[key] - ref[key]) / np.linalg.norm(ref[key]))
     fg, fr = first_slip(got["slip_rate"]), first_slip(ref["slip_rate"])
     both = (fg >= 0) & (fr >= 0)

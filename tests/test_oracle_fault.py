@@ -42,8 +42,8 @@ def _uniform_params(n, tau_sh, sigma, mu_s, mu_k, d_c, tau_3=0.0):
 @pytest.mark.parametrize("lower", [None, Plane(-1, 0.6, 0.8, 0.8 * math.sqrt(3.0))])
 def test_uniform_fault_closed_form(lower):
     """k = 0 only: V = (|tau0| - S(delta)) (1/Z+ + 1/Z-), Z = mu / c_s, so with
-    S linear in delta the slip path is delta^n = (A/B)((1 + B dt)^n - 1) until
-    it passes d_c, then grows by dt V_k per step."""
+    S linear in the slip amplitude delta, delta^n = (A/B)((1 + B dt)^n - 1) until
+    it passes d_c, then it grows by dt V_k per step."""
     planes = [Plane()] if lower is None else [Plane(), lower]
     dt, n, steps = 0.2, 4, 60
     cfg = Config(n1=n, n3=n, dt=dt, planes=planes, window_cap=steps)
@@ -59,12 +59,13 @@ def test_uniform_fault_closed_form(lower):
     k_star = int(np.argmax(delta >= d_c))     # first step that starts at or past d_c
     Vk = (tmag - sigma * mu_k) * cz
     expect = np.where(np.arange(steps) < k_star, delta, delta[k_star] + (np.arange(steps) - k_star) * dt * Vk)
-    # out["delta"][m] is the path after step m = delta^{m+1}
-    got = out["delta"][:, 0, 0]
+    # the slip after step m is delta^{m+1}
+    amp = np.hypot(out["slip"][:, 0], out["slip"][:, 1])
+    got = amp[:, 0, 0]
     np.testing.assert_allclose(got[:k_star], expect[1:k_star + 1], rtol=1e-12)
     np.testing.assert_allclose(got[k_star:], expect[k_star] + np.arange(1, steps - k_star + 1) * dt * Vk,
                                rtol=1e-12)
-    assert np.ptp(out["delta"][-1]) <= 1e-13 * out["delta"][-1].max()   # stays uniform
+    assert np.ptp(amp[-1]) <= 1e-13 * amp[-1].max()                 # stays uniform
     # slip along the background shear, side velocities split by impedance
     V = out["slip_rate"][:, :, 0, 0]
     np.testing.assert_allclose(V[:, 1] * t1, V[:, 0] * t3, atol=1e-15)
@@ -191,7 +192,8 @@ def test_nucleated_rupture_causal_and_confined():
     np.testing.assert_array_equal(out["traction"][:, 1], np.broadcast_to(tau0[1], out["traction"][:, 1].shape))
     # the shear traction never exceeds the strength of the step
     tau_sh = np.hypot(out["traction"][:, 0], out["traction"][:, 2])
-    delta_before = np.concatenate([np.zeros((1,) + mu_s.shape), out["delta"][:-1]])
+    amp = np.hypot(out["slip"][:, 0], out["slip"][:, 1])
+    delta_before = np.concatenate([np.zeros((1,) + mu_s.shape), amp[:-1]])
     mu = np.where(delta_before < d_c, mu_s - (mu_s - mu_k) * delta_before / d_c, mu_k)
     assert np.all(tau_sh <= -tau0[1] * mu * (1 + 1e-12))
 
