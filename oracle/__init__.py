@@ -13,6 +13,10 @@ Modules
            it defers to; derived from Eqs. consmoment and linelasticity)
   dft      naive forward / inverse transforms on the stored half spectrum
   sbim     the per-step traction update and its exact transpose (adjoint)
+  fault    a frictional fault between two half-spaces: stand-alone rupture
+           (Sec. 2.2 friction and stick-slip, Eq. SBI on each side)
+  hybrid   the hybrid scheme: a strip of hexahedral finite elements on the
+           fault, closed at S+ by the boundary relation (Secs. 2.2-2.4)
 
 Every function is pinned by ``tests/test_oracle_*.py`` against closed forms,
 library routines (numpy.fft, scipy.special, mpmath inverse Laplace) and

@@ -1,0 +1,167 @@
+"""Pins of the oracle's hybrid finite-element / boundary-integral rupture (``oracle.hybrid``).
+
+Fixed by facts outside the oracle's own formulas:
+  * the hexahedral element stiffness is symmetric, has exactly the six rigid-
+    body motions as null space, and passes the patch test: a uniform strain
+    gives the face forces sigma . n h^2 of linear elasticity (Eq. linelasticity);
+  * in the periodic strip a displacement linear in x2 loads only the two
+    boundary layers, with the stress times the node area;
+  * a spatially uniform fault (k = 0) settles at the slip rate of a plane shear
+    wave leaving each side, 2 (tau0 - tau_k) c_s / mu, once the strip's
+    transients have passed through S+ (the boundary relation absorbs them);
+  * a fault below strength everywhere never moves;
+  * moving the S+ boundary away from the fault (two versus four element
+    layers) leaves the rupture unchanged to within a few percent (the paper's
+    strip-width independence test, Secs. 4-6);
+  * with mesh refinement the hybrid rupture approaches the stand-alone
+    boundary-integral rupture on the same grid (Sec. 3.2: TPV3 agreement,
+    error decreasing with the mesh size).
+"""
+import numpy as np
+import pytest
+
+import workloads
+from oracle import fault, hybrid
+from oracle.hybrid import CORNERS, Layer, StripConfig, hex8_stiffness
+from oracle.sbim import Config, Plane
+
+T = workloads.TPV3
+RHO, CP, CS = T["rho"], T["cp"], T["cs"]
+MU = RHO * CS * CS
+
+
+def test_hex8_stiffness_symmetry_and_rigid_modes():
+    h, lam, mu = 2.0, 1.3, 0.7
+    K = hex8_stiffness(h, lam, mu)
+    assert np.abs(K - K.T).max() < 1e-14 * np.abs(K).max()
+    w = np.linalg.eigvalsh(K)
+    assert np.all(np.abs(w[:6]) < 1e-12 * w[-1]) and w[6] > 1e-3 * w[-1]
+    X = CORNERS * h
+    rigid = []
+    for c in range(3):
+        t = np.zeros((8, 3))
+        t[:, c] = 1.0
+        rigid.append(t)
+    for a, b in ((0, 1), (1, 2), (0, 2)):
+        r = np.zeros((8, 3))
+        r[:, a], r[:, b] = -X[:, b], X[:, a]
+        rigid.append(r)
+    for r in rigid:
+        assert np.abs(K @ r.ravel()).max() < 1e-13 * np.abs(K).max()
+
+
+@pytest.mark.parametrize("grad", [(0, 0), (1, 1), (2, 2), (0, 1), (1, 2), (0, 2)])
+def test_hex8_patch_test(grad):
+    """u_i = x_j (one displacement gradient entry): nodal forces summed over each
+    face equal sigma . n h^2 with sigma from Eq. linelasticity."""
+    h, lam, mu = 1.5, 0.8, 1.1
+    i, j = grad
+    K = hex8_stiffness(h, lam, mu)
+    X = CORNERS * h
+    u = np.zeros((8, 3))
+    u[:, i] = X[:, j]
+    f = (K @ u.ravel()).reshape(8, 3)
+    G = np.zeros((3, 3))
+    G[i, j] = 1.0
+    eps = 0.5 * (G + G.T)
+    sigma = lam * np.trace(eps) * np.eye(3) + 2 * mu * eps
+    # each corner collects a quarter of the traction sigma . n h^2 of each of its
+    # three faces (a uniform stress has a bilinear-exact consistent load)
+    expect = np.zeros((8, 3))
+    for a in range(8):
+        for axis in range(3):
+            n = np.zeros(3)
+            n[axis] = 1.0 if CORNERS[a, axis] else -1.0
+            expect[a] += sigma @ n * h * h / 4.0
+    np.testing.assert_allclose(f, expect, rtol=1e-12, atol=1e-12 * np.abs(expect).max())
+
+
+def test_strip_linear_field_loads_only_boundary_layers():
+    cfg = StripConfig(4, 8, 2.0, 0.1, [Layer(1.0, 2.0, 1.1)] * 3, Plane())
+    strip = hybrid.Strip(cfg)
+    L = cfg.layers[0]
+    eps = 1e-3
+    u = np.zeros(strip.shape)
+    x2 = np.arange(cfg.n2 + 1) * cfg.h
+    u[0] = eps * x2[:, None, None]                   # u1 = eps x2: shear strain eps/2
+    f = strip.internal_force(u)
+    sigma12 = L.mu * eps
+    A = cfg.h ** 2
+    np.testing.assert_allclose(f[0, 0], -sigma12 * A, rtol=1e-12)
+    np.testing.assert_allclose(f[0, -1], sigma12 * A, rtol=1e-12)
+    assert np.abs(f[0, 1:-1]).max() < 1e-12 * sigma12 * A
+    assert np.abs(f[1:]).max() < 1e-12 * sigma12 * A
+
+
+def _uniform(n, t1, mus, muk, dc=0.4):
+    tau0 = np.zeros((3, n, n))
+    tau0[0], tau0[1] = t1, -120e6
+    full = lambda x: np.full((n, n), float(x))  # noqa: E731
+    return tau0, full(mus), full(muk), full(dc)
+
+
+@pytest.mark.parametrize("n2", [1, 2])
+def test_uniform_fault_reaches_plane_wave_slip_rate(n2):
+    n, h = 4, 375.0
+    dt = 0.25 * h / CS
+    cfg = StripConfig(n, n, h, dt, [Layer(RHO, CP, CS)] * n2, Plane(1, MU, CS, CP), window_cap=4)
+    tau0, mus, muk, dc = _uniform(n, 80e6, 0.6, 0.6)
+    out = hybrid.hybrid_rupture(cfg, tau0, mus, muk, dc, 400)
+    V = out["slip_rate"][:, 0]
+    expect = 2 * (80e6 - 0.6 * 120e6) * CS / MU
+    assert np.abs(V[-50:] / expect - 1).max() < 2e-3
+    assert out["sliding"][-50:].all()
+    assert np.abs(out["slip_rate"][:, 1]).max() < 1e-9 * expect
+
+
+def test_fault_below_strength_never_moves():
+    n, h = 8, 375.0
+    cfg = StripConfig(n, n, h, 0.25 * h / CS, [Layer(RHO, CP, CS)] * 2, Plane(1, MU, CS, CP),
+                      window_cap=10)
+    rng = np.random.default_rng(5)
+    tau0, mus, muk, dc = _uniform(n, 0.0, 0.6, 0.5)
+    tau0[0] = rng.uniform(-50e6, 50e6, (n, n))
+    out = hybrid.hybrid_rupture(cfg, tau0, mus, muk, dc, 20)
+    assert not out["sliding"].any()
+    assert np.abs(out["slip_rate"]).max() == 0.0 and np.abs(out["top_u"]).max() == 0.0
+    np.testing.assert_array_equal(out["traction"][-1], tau0)
+
+
+def _strip_for(wl, n2):
+    return StripConfig(wl.n1, wl.n3, wl.dx, wl.dt, [Layer(RHO, CP, CS)] * n2, Plane(1, MU, CS, CP),
+                       window_cap=wl.steps)
+
+
+def _onset(sliding):
+    return np.where(sliding.any(0), np.argmax(sliding, axis=0), -1)
+
+
+def test_strip_width_independence():
+    wl = workloads.FAULTS["tpv3_coarse16"]
+    prm = wl.params()
+    a = hybrid.hybrid_rupture(_strip_for(wl, 2), *prm, wl.steps)
+    b = hybrid.hybrid_rupture(_strip_for(wl, 4), *prm, wl.steps)
+    oa, ob = _onset(a["sliding"]), _onset(b["sliding"])
+    np.testing.assert_array_equal(oa >= 0, ob >= 0)
+    assert np.abs(oa - ob).max() <= 1                  # rupture onset within one step
+    rel = np.linalg.norm(a["slip"][-1] - b["slip"][-1]) / np.linalg.norm(b["slip"][-1])
+    assert rel < 0.03
+    patch, region = wl.masks()
+    assert (_onset(a["sliding"])[region & ~patch] > 0).mean() > 0.5
+
+
+def test_hybrid_converges_to_boundary_integral_rupture():
+    errs = []
+    for n in (16, 32):
+        dx = 12000.0 / n
+        wl = workloads.FaultWorkload(f"conv{n}", n, n, dx, int(round(72 * 750 / dx)),
+                                     region=(9000.0, 9000.0))
+        prm = wl.params()
+        ref = fault.rupture(Config.from_dict(dict(wl.config_dict(), input_kind="absolute")),
+                            fault.FaultParams(*prm), wl.steps)
+        hyb = hybrid.hybrid_rupture(_strip_for(wl, 2), *prm, wl.steps)
+        errs.append(np.linalg.norm(hyb["slip"][-1] - ref["slip"][-1]) / np.linalg.norm(ref["slip"][-1]))
+        # no slip outside the rupture region, the same locked cells
+        patch, region = wl.masks()
+        assert not hyb["sliding"][:, ~region].any()
+    assert errs[1] < 0.5 * errs[0] and errs[1] < 0.15, errs
