@@ -255,6 +255,44 @@ def measure_rupture(fw, precision, device, warmup=20):
     }
 
 
+def measure_hybrid(fw, precision, device, layers=2, warmup=20):
+    """The hybrid scheme on the same setup: a strip of ``layers`` element layers of the
+    bulk material between the fault and S+ (two layers = the paper's strip width 4 dx
+    for the symmetric half), the whole run timed from rest."""
+    import torch
+    import workloads
+    from paper_2102_08756_amd import SBIM, Config, Strip
+    t = workloads.TPV3
+    cfg = Config.from_dict(fw.config_dict(), precision=precision, input_kind="increment")
+    t0 = time.time()
+    sb = SBIM(cfg, device=device)
+    prm = [torch.tensor(a, dtype=torch.float64, device=device).contiguous() for a in fw.params()]
+    st = Strip(sb, [(t["rho"], t["cp"], t["cs"])] * layers, *prm)
+    t_init = time.time() - t0
+    for _ in range(warmup):
+        st.step()
+    st.reset()
+    sb.profile_conv(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(fw.steps):
+        st.step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    conv_ms, launches = sb.conv_timing()
+    sb.profile_conv(False)
+    slip = st.read("slip").cpu().numpy()
+    st.close()
+    sb.close()
+    del sb, st, prm
+    torch.cuda.empty_cache()
+    nodes = (layers + 1) * fw.n1 * fw.n3
+    return {"layers": layers, "ms_per_step": 1e3 * elapsed / fw.steps,
+            "node_steps_per_s": nodes * fw.steps / elapsed,
+            "step_kernel_ms_per_step": conv_ms / launches if launches else None,
+            "init_s": t_init, "_slip": slip}
+
+
 def rupture_leg(fw, forms, device):
     out = {"workload": fw.name, "n1": fw.n1, "n3": fw.n3, "dx_m": fw.dx, "dt_s": fw.dt,
            "time_steps": fw.steps, "window_cap": fw.window_cap or fw.steps,
@@ -273,6 +311,17 @@ def rupture_leg(fw, forms, device):
             if p != "fp64":
                 out[f"{p}_vs_fp64_final_slip_rel_l2"] = float(
                     np.linalg.norm(slips[p] - slips["fp64"]) / np.linalg.norm(slips["fp64"]))
+    # hybrid: finite-element strip on the fault, closed by the boundary relation at S+
+    p = forms[0]
+    hy = measure_hybrid(fw, p, device)
+    hs = hy.pop("_slip")
+    hy["precision"] = p
+    hy["final_slip_rel_l2_vs_boundary_integral"] = float(
+        np.linalg.norm(hs - slips[p]) / np.linalg.norm(slips[p]))
+    out["hybrid"] = hy
+    print(f"[bench] hybrid {fw.name} {p}: {hy['ms_per_step']:.3f} ms/step "
+          f"({hy['layers']} element layers), final slip vs boundary integral "
+          f"{hy['final_slip_rel_l2_vs_boundary_integral']:.2e}", file=sys.stderr, flush=True)
     return out
 
 

@@ -311,6 +311,77 @@ int sbim_fault_reset(sbim_fault *f);
 /* Synchronise the stream and free the fault (not its handle); NULL is accepted. */
 int sbim_fault_destroy(sbim_fault *f);
 
+/*
+ * ---------------------------------------------------------------------------
+ * Hybrid finite-element / boundary-integral rupture (Sec. 2.4).
+ *
+ * A strip of 8-node hexahedral finite elements (Sec. 2.2, FEM) of side
+ * h = dx1 = dx3 lies on the fault: `layers` element layers between the fault
+ * (node layer 0) and the virtual boundary S+ (node layer `layers`), periodic
+ * in x1 and x3 on the handle's n1 x n3 grid.  The handle has one plane (side
+ * +1): the half-space above S+, whose boundary relation (Eq. SBI) closes the
+ * strip.  The fault plane is a symmetry plane (Sec. 3.1): the lower half of
+ * the strip is the mirror image, the slip is twice the tangential
+ * displacement of the fault nodes, and the fault normal traction keeps its
+ * background value.  Elements: trilinear shape functions, 2x2x2 Gauss points,
+ * isotropic elasticity per element layer (Eq. linelasticity), lumped mass
+ * rho h^3/8 per element corner.
+ *
+ * One sbim_strip_step advances t -> t+1 (Sec. 2.2 predictor-corrector,
+ * Sec. 2.4 items 1-7; dt = the handle's dt):
+ *   1. v_{t+1/2} = v_t + dt/2 a_t, u_{t+1} = u_t + dt v_{t+1/2},
+ *      v^pred = v_t + dt a_t (Eq. fepred; the displacement advances with the
+ *      half-step velocity, the form under which the stick condition after
+ *      Eq. freeslip keeps the slip fixed);
+ *   2. push the S+ layer's u_{t+1} (or its increment) with v^pred as the
+ *      velocity of the damping term; the tractions of that push act on the S+
+ *      nodes with area h^2;
+ *   3. r = -K u_{t+1} + S+ forces; at a fault node the stick traction is
+ *      tau~ = tau0 + M v* / (dt h^2) with v* = v_{t+1/2} + dt r / M the next
+ *      half-step velocity without fault traction (Eqs. freeslip,
+ *      sticktraction for two mirrored sides); strength S = max(-tau0_2, 0)
+ *      mu(|slip|) (Eq. slipweak); tau = tau~ if |tau~| <= S, else
+ *      S tau~/|tau~| (Eq. stickslip); the fault adds -h^2 (tau - tau0);
+ *   4. a_{t+1} = r / M, v_{t+1} = v_{t+1/2} + dt/2 a_{t+1} (Eqs. tintf, fecorr).
+ * All strip arithmetic is float64; the S+ push has the handle's precision.
+ * Fault fields are device [rows][n1][n3] doubles; node fields
+ * [3][layers+1][n1][n3].  Ownership rules as for sbim_fault.  The scheme is
+ * explicit: dt must satisfy the elements' CFL limit (the highest frequency of
+ * the lumped-mass hexahedra is 2 c_p / h, so c_p dt / h < 1).
+ */
+typedef struct sbim_strip sbim_strip;
+
+typedef struct {
+  int layers;           /* element layers between the fault and S+, 1..4096 */
+  const double *rho;    /* host [layers]: density of each element layer (fault side first) */
+  const double *cp;     /* host [layers]: pressure wave speed, > cs sqrt(4/3) */
+  const double *cs;     /* host [layers]: shear wave speed, > 0 */
+} sbim_strip_config;
+
+/* fields of sbim_strip_read */
+#define SBIM_STRIP_TRACTION 0     /* [3][n1][n3] fault traction of the last step */
+#define SBIM_STRIP_SLIP_RATE 1    /* [2][n1][n3] 2 v_{t+1} of the fault nodes (x1, x3) */
+#define SBIM_STRIP_SLIP 2         /* [2][n1][n3] 2 u_{t+1} of the fault nodes */
+#define SBIM_STRIP_SLIDING 3      /* [n1][n3] 1 where the slip branch was taken, else 0 */
+#define SBIM_STRIP_DISPLACEMENT 4 /* [3][layers+1][n1][n3] */
+#define SBIM_STRIP_VELOCITY 5     /* [3][layers+1][n1][n3] */
+
+/*
+ * sbim_strip_create: a strip on handle h (one plane of side +1, dx1 == dx3,
+ * at step 0) with the fault parameters of sbim_fault_params (copied and
+ * checked on the device; synchronises the stream).
+ */
+int sbim_strip_create(sbim_handle *h, const sbim_strip_config *cfg, const sbim_fault_params *prm,
+                      sbim_strip **out);
+/* One step; tau_or_null / slip_rate_or_null as in sbim_fault_step. */
+int sbim_strip_step(sbim_strip *s, double *tau_or_null, double *slip_rate_or_null);
+/* Copy one strip field (SBIM_STRIP_*) into device memory dst (asynchronous). */
+int sbim_strip_read(const sbim_strip *s, int field, double *dst);
+/* Zero the strip state and reset its handle. */
+int sbim_strip_reset(sbim_strip *s);
+/* Synchronise the stream and free the strip (not its handle); NULL is accepted. */
+int sbim_strip_destroy(sbim_strip *s);
+
 #ifdef __cplusplus
 }
 #endif

@@ -193,6 +193,25 @@ struct FaultArgs {
 hipError_t launch_fault_step(bool fp64, bool mirror, const FaultArgs &a, hipStream_t st);
 hipError_t launch_fault_check(const double *tau0, const double *mu_s, const double *mu_k,
                               const double *d_c, long long cells, long long *bad, hipStream_t st);
+// strip.hip: finite-element strip of the hybrid scheme.  Node fields are
+// float64 [3][n2+1][n1][n3]; cell fields [rows][n1][n3].
+struct StripArgs {
+  double *u, *v, *a;          // displacement, velocity (half-step between the kernels), acceleration
+  const double *stencil;      // [n2+1][27][3][3]: stiffness block of each neighbour offset
+                              // (o1, o2, o3), index (o1+1) + 3 (o2+1) + 9 (o3+1)
+  const double *mass;         // [n2+1] lumped mass of a node of each layer
+  const void *tau_sbi;        // [3][cells] working precision: traction of the half-space above S+
+  void *push_u, *push_v;      // [3][cells] working precision: S+ displacement (or increment), velocity
+  const double *tau0, *mu_s, *mu_k, *d_c;
+  double *tau, *rate, *slip, *sliding;   // fault outputs [3], [2], [2], [1] x cells
+  double *tau_out, *rate_out;            // optional caller copies
+  long long nodes, cells;
+  int n1, n3, n2;
+  double dt, area;
+  int increment;
+};
+hipError_t launch_strip_predict(bool fp64, const StripArgs &a, hipStream_t st);
+hipError_t launch_strip_correct(bool fp64, const StripArgs &a, hipStream_t st);
 hipError_t launch_tabulate(bool fp64, const Group &g, double dt, const double *gl_x,
                            const double *gl_w, hipStream_t st);
 

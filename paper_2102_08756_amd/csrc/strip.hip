@@ -1,0 +1,164 @@
+// Finite-element strip of the hybrid scheme: 8-node hexahedra on a regular grid
+// between the fault (node layer 0) and the boundary S+ (node layer N2), periodic
+// in x1 and x3 with the boundary-integral grid; explicit central differences in
+// the predictor-corrector form of Sec. 2.2 (Eqs. fepred, feintdisp, tintf,
+// fecorr); the traction of the half-space above S+ from the boundary relation
+// (Eq. SBI, Sec. 2.4 items 2-4); the fault as a symmetry plane with the stick
+// traction of the forward Lagrange multiplier (Eqs. freeslip, sticktraction)
+// limited by the slip-weakening strength (Eqs. stickslip, slipweak).
+//
+// Fields are float64 [component][node layer][x1][x3] (x3 fastest); one thread
+// per node.  The stiffness is applied node by node as a 27-point stencil of 3x3
+// blocks, one stencil per node layer (the element layers above and below it may
+// differ), precomputed on the host from the element stiffness.
+#include <hip/hip_runtime.h>
+
+#include "internal.h"
+
+// Plain float64 rounding of each product and sum, as in the interface solve of
+// the fault kernel: the stick/slip choice compares two such results.
+#pragma clang fp contract(off)
+
+namespace sbim {
+namespace {
+
+constexpr int kStripThreads = 256;
+
+template <typename R>
+__global__ __launch_bounds__(kStripThreads) void strip_predict_kernel(StripArgs a) {
+  const long long nodes = a.nodes;
+  const long long id = static_cast<long long>(blockIdx.x) * kStripThreads + threadIdx.x;
+  if (id >= nodes) return;
+  const double dt = a.dt;
+  const long long cells = a.cells;
+  const long long top0 = nodes - cells;          // first node of the S+ layer
+  R *__restrict__ pu = static_cast<R *>(a.push_u);
+  R *__restrict__ pv = static_cast<R *>(a.push_v);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const long long k = c * nodes + id;
+    const double v = a.v[k], acc = a.a[k];
+    const double vh = v + 0.5 * dt * acc;
+    const double un = a.u[k] + dt * vh;
+    a.u[k] = un;
+    a.v[k] = vh;                                  // the half-step velocity until the corrector
+    if (id >= top0) {
+      const long long t = c * cells + (id - top0);
+      pu[t] = static_cast<R>(a.increment ? dt * vh : un);
+      pv[t] = static_cast<R>(v + dt * acc);      // predicted velocity of Eq. fepred
+    }
+  }
+}
+
+template <typename R>
+__global__ __launch_bounds__(kStripThreads) void strip_correct_kernel(StripArgs a) {
+  const long long nodes = a.nodes;
+  const long long id = static_cast<long long>(blockIdx.x) * kStripThreads + threadIdx.x;
+  if (id >= nodes) return;
+  const int n1 = a.n1, n3 = a.n3;
+  const long long cells = a.cells;
+  const int layer = static_cast<int>(id / cells);
+  const long long cell = id - layer * cells;
+  const int i1 = static_cast<int>(cell / n3);
+  const int i3 = static_cast<int>(cell - static_cast<long long>(i1) * n3);
+  const double *__restrict__ C = a.stencil + static_cast<long long>(layer) * 27 * 9;
+
+  // r = -K u over the 27 neighbours (periodic in x1, x3; layers beyond the
+  // strip carry zero blocks and are skipped)
+  double r[3] = {0.0, 0.0, 0.0};
+  for (int o2 = -1; o2 <= 1; ++o2) {
+    const int l = layer + o2;
+    if (l < 0 || l > a.n2) continue;
+    for (int o1 = -1; o1 <= 1; ++o1) {
+      const int j1 = i1 + o1 < 0 ? i1 + o1 + n1 : (i1 + o1 >= n1 ? i1 + o1 - n1 : i1 + o1);
+      for (int o3 = -1; o3 <= 1; ++o3) {
+        const int j3 = i3 + o3 < 0 ? i3 + o3 + n3 : (i3 + o3 >= n3 ? i3 + o3 - n3 : i3 + o3);
+        const long long nb = (static_cast<long long>(l) * n1 + j1) * n3 + j3;
+        const double u0 = a.u[nb], u1 = a.u[nodes + nb], u2 = a.u[2 * nodes + nb];
+        const double *B = C + ((o1 + 1) + 3 * (o2 + 1) + 9 * (o3 + 1)) * 9;
+#pragma unroll
+        for (int p = 0; p < 3; ++p) r[p] -= B[3 * p] * u0 + B[3 * p + 1] * u1 + B[3 * p + 2] * u2;
+      }
+    }
+  }
+  const double A = a.area;
+  if (layer == a.n2) {                           // S+: traction of the half-space above
+    const R *__restrict__ ts = static_cast<const R *>(a.tau_sbi);
+#pragma unroll
+    for (int p = 0; p < 3; ++p) r[p] += A * static_cast<double>(ts[p * cells + cell]);
+  }
+  const double M = a.mass[layer];
+  const double dt = a.dt;
+  if (layer == 0) {                              // fault node: stick traction and strength
+    const double t00 = a.tau0[cell], t01 = a.tau0[cells + cell], t02 = a.tau0[2 * cells + cell];
+    const double vs0 = a.v[id] + dt * r[0] / M;
+    const double vs2 = a.v[2 * nodes + id] + dt * r[2] / M;
+    const double st0 = t00 + M * vs0 / (dt * A);
+    const double st2 = t02 + M * vs2 / (dt * A);
+    const double mag = sqrt(st0 * st0 + st2 * st2);
+    const double s0 = 2.0 * a.u[id], s2 = 2.0 * a.u[2 * nodes + id];
+    const double delta = sqrt(s0 * s0 + s2 * s2);
+    const double mus = a.mu_s[cell], muk = a.mu_k[cell], dc = a.d_c[cell];
+    const double mu = delta < dc ? mus - (mus - muk) * delta / dc : muk;
+    const double strength = fmax(-t01, 0.0) * mu;
+    double tau0 = st0, tau2 = st2;
+    const bool sliding = mag > strength;
+    if (sliding) {
+      const double sc = strength / mag;
+      tau0 = st0 * sc;
+      tau2 = st2 * sc;
+    }
+    r[0] -= A * (tau0 - t00);
+    r[2] -= A * (tau2 - t02);
+    a.tau[cell] = tau0;
+    a.tau[cells + cell] = t01;
+    a.tau[2 * cells + cell] = tau2;
+    a.slip[cell] = s0;
+    a.slip[cells + cell] = s2;
+    a.sliding[cell] = sliding ? 1.0 : 0.0;
+    if (a.tau_out) {
+      a.tau_out[cell] = tau0;
+      a.tau_out[cells + cell] = t01;
+      a.tau_out[2 * cells + cell] = tau2;
+    }
+  }
+  double vn[3];
+#pragma unroll
+  for (int p = 0; p < 3; ++p) {
+    const long long k = p * nodes + id;
+    const double acc = r[p] / M;
+    vn[p] = a.v[k] + 0.5 * dt * acc;
+    a.a[k] = acc;
+    a.v[k] = vn[p];
+  }
+  if (layer == 0) {
+    a.rate[cell] = 2.0 * vn[0];
+    a.rate[cells + cell] = 2.0 * vn[2];
+    if (a.rate_out) {
+      a.rate_out[cell] = 2.0 * vn[0];
+      a.rate_out[cells + cell] = 2.0 * vn[2];
+    }
+  }
+}
+
+}  // namespace
+
+hipError_t launch_strip_predict(bool fp64, const StripArgs &a, hipStream_t st) {
+  const unsigned blocks = static_cast<unsigned>((a.nodes + kStripThreads - 1) / kStripThreads);
+  if (fp64)
+    strip_predict_kernel<double><<<blocks, kStripThreads, 0, st>>>(a);
+  else
+    strip_predict_kernel<float><<<blocks, kStripThreads, 0, st>>>(a);
+  return hipGetLastError();
+}
+
+hipError_t launch_strip_correct(bool fp64, const StripArgs &a, hipStream_t st) {
+  const unsigned blocks = static_cast<unsigned>((a.nodes + kStripThreads - 1) / kStripThreads);
+  if (fp64)
+    strip_correct_kernel<double><<<blocks, kStripThreads, 0, st>>>(a);
+  else
+    strip_correct_kernel<float><<<blocks, kStripThreads, 0, st>>>(a);
+  return hipGetLastError();
+}
+
+}  // namespace sbim

@@ -32,8 +32,11 @@ EXPORTS = (
     "sbim_get_info", "sbim_state_bytes", "sbim_save_state", "sbim_load_state", "sbim_step_work",
     "sbim_mode_kernel", "sbim_profile_conv", "sbim_conv_timing",
     "sbim_fault_create", "sbim_fault_step", "sbim_fault_read", "sbim_fault_reset",
-    "sbim_fault_destroy",
+    "sbim_fault_destroy", "sbim_strip_create", "sbim_strip_step", "sbim_strip_read",
+    "sbim_strip_reset", "sbim_strip_destroy",
 )
+STRIP_FIELDS = {"traction": (0, 3), "slip_rate": (1, 2), "slip": (2, 2), "sliding": (3, 1),
+                "displacement": (4, None), "velocity": (5, None)}
 FAULT_FIELDS = {"traction": (0, 3), "slip_rate": (1, 2), "slip": (2, 2), "displacement": (3, 6),
                 "velocity": (4, 6)}
 
@@ -62,6 +65,11 @@ class _Info(ctypes.Structure):
 class _FaultParams(ctypes.Structure):
     _fields_ = [("tau0", ctypes.c_void_p), ("mu_s", ctypes.c_void_p), ("mu_k", ctypes.c_void_p),
                 ("d_c", ctypes.c_void_p)]
+
+
+class _StripConfig(ctypes.Structure):
+    _fields_ = [("layers", ctypes.c_int), ("rho", ctypes.POINTER(ctypes.c_double)),
+                ("cp", ctypes.POINTER(ctypes.c_double)), ("cs", ctypes.POINTER(ctypes.c_double))]
 
 
 _lib = None
@@ -100,6 +108,12 @@ def load_library(path=LIB_PATH):
         "sbim_fault_read": (i, [vp, i, vp]),
         "sbim_fault_reset": (i, [vp]),
         "sbim_fault_destroy": (i, [vp]),
+        "sbim_strip_create": (i, [vp, ctypes.POINTER(_StripConfig), ctypes.POINTER(_FaultParams),
+                                  ctypes.POINTER(vp)]),
+        "sbim_strip_step": (i, [vp, vp, vp]),
+        "sbim_strip_read": (i, [vp, i, vp]),
+        "sbim_strip_reset": (i, [vp]),
+        "sbim_strip_destroy": (i, [vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -375,6 +389,54 @@ class Fault:
             self.close()
         except Exception:
             pass
+
+
+class Strip(Fault):
+    """Hybrid scheme: a finite-element strip of ``layers`` (list of (rho, c_p, c_s),
+    fault side first) on the fault, closed at S+ by the single plane of ``sbim``
+    (``sbim_strip_*``).  Fault parameters as for ``Fault``."""
+
+    def __init__(self, sbim: SBIM, layers, tau0, mu_s, mu_k, d_c):
+        self.sbim = sbim
+        n1, n3 = sbim.cfg.n1, sbim.cfg.n3
+        self.cells = (n1, n3)
+        self.n2 = len(layers)
+        args = {"tau0": tau0, "mu_s": mu_s, "mu_k": mu_k, "d_c": d_c}
+        shapes = {"tau0": (3, n1, n3), "mu_s": (n1, n3), "mu_k": (n1, n3), "d_c": (n1, n3)}
+        for k, t in args.items():
+            if (not isinstance(t, torch.Tensor) or t.device != sbim.device or t.dtype != torch.float64
+                    or tuple(t.shape) != shapes[k] or not t.is_contiguous()):
+                raise ValueError(f"{k}: expected a contiguous float64 {shapes[k]} tensor on {sbim.device}")
+        arr = [(ctypes.c_double * max(self.n2, 1))(*[float(L[i]) for L in layers]) for i in range(3)]
+        sc = _StripConfig(self.n2, *(ctypes.cast(a, ctypes.POINTER(ctypes.c_double)) for a in arr))
+        p = _FaultParams(*(ctypes.c_void_p(args[k].data_ptr()) for k in ("tau0", "mu_s", "mu_k", "d_c")))
+        sbim._sync_stream()
+        f = ctypes.c_void_p()
+        sbim._check(sbim._L.sbim_strip_create(sbim._h, ctypes.byref(sc), ctypes.byref(p), ctypes.byref(f)))
+        self._f = f
+
+    def step(self, tau=None, slip_rate=None):
+        self._out(tau, 3, "tau")
+        self._out(slip_rate, 2, "slip_rate")
+        self.sbim._sync_stream()
+        self.sbim._check(self.sbim._L.sbim_strip_step(self._f, _ptr(tau), _ptr(slip_rate)))
+
+    def read(self, name):
+        fid, rows = STRIP_FIELDS[name]
+        shape = (rows,) + self.cells if rows else (3, self.n2 + 1) + self.cells
+        out = torch.empty(shape, dtype=torch.float64, device=self.sbim.device)
+        self.sbim._sync_stream()
+        self.sbim._check(self.sbim._L.sbim_strip_read(self._f, fid, _ptr(out)))
+        return out
+
+    def reset(self):
+        self.sbim._sync_stream()
+        self.sbim._check(self.sbim._L.sbim_strip_reset(self._f))
+
+    def close(self):
+        if getattr(self, "_f", None):
+            self.sbim._L.sbim_strip_destroy(self._f)
+            self._f = None
 
 
 # ------------------------------------------------------------------ autograd

@@ -80,3 +80,8 @@ def test_null_arguments_rejected():
     assert lib.sbim_fault_read(None, 0, None) == B.SBIM_E_INVALID
     assert lib.sbim_fault_reset(None) == B.SBIM_E_INVALID
     assert lib.sbim_fault_destroy(None) == B.SBIM_OK
+    assert lib.sbim_strip_create(None, None, None, None) == B.SBIM_E_INVALID
+    assert lib.sbim_strip_step(None, None, None) == B.SBIM_E_INVALID
+    assert lib.sbim_strip_read(None, 0, None) == B.SBIM_E_INVALID
+    assert lib.sbim_strip_reset(None) == B.SBIM_E_INVALID
+    assert lib.sbim_strip_destroy(None) == B.SBIM_OK
