@@ -16,7 +16,8 @@
 #include "internal.h"
 
 // Plain float64 rounding of each product and sum, as in the interface solve of
-// the fault kernel: the stick/slip choice compares two such results.
+// the fault kernel: the stick/slip choice compares two such results.  The
+// stencil sums alone are contracted into fused multiply-adds.
 #pragma clang fp contract(off)
 
 namespace sbim {
@@ -50,34 +51,48 @@ __global__ __launch_bounds__(kStripThreads) void strip_predict_kernel(StripArgs 
   }
 }
 
-template <typename R>
+// UNIFORM: every wavefront lies in one node layer (cells a multiple of 64), so
+// the layer's stencil is read through the scalar cache once per wavefront.
+template <typename R, bool UNIFORM>
 __global__ __launch_bounds__(kStripThreads) void strip_correct_kernel(StripArgs a) {
   const long long nodes = a.nodes;
   const long long id = static_cast<long long>(blockIdx.x) * kStripThreads + threadIdx.x;
   if (id >= nodes) return;
   const int n1 = a.n1, n3 = a.n3;
   const long long cells = a.cells;
-  const int layer = static_cast<int>(id / cells);
+  const int layer = UNIFORM ? __builtin_amdgcn_readfirstlane(static_cast<int>(id / cells))
+                            : static_cast<int>(id / cells);
   const long long cell = id - layer * cells;
   const int i1 = static_cast<int>(cell / n3);
   const int i3 = static_cast<int>(cell - static_cast<long long>(i1) * n3);
   const double *__restrict__ C = a.stencil + static_cast<long long>(layer) * 27 * 9;
+  // periodic neighbour rows and columns
+  const long long row[3] = {static_cast<long long>(i1 == 0 ? n1 - 1 : i1 - 1) * n3,
+                            static_cast<long long>(i1) * n3,
+                            static_cast<long long>(i1 == n1 - 1 ? 0 : i1 + 1) * n3};
+  const int col[3] = {i3 == 0 ? n3 - 1 : i3 - 1, i3, i3 == n3 - 1 ? 0 : i3 + 1};
 
-  // r = -K u over the 27 neighbours (periodic in x1, x3; layers beyond the
-  // strip carry zero blocks and are skipped)
+  // r = -K u over the 27 neighbours (layers beyond the strip carry zero blocks
+  // and are skipped)
   double r[3] = {0.0, 0.0, 0.0};
   for (int o2 = -1; o2 <= 1; ++o2) {
+#pragma clang fp contract(fast)
     const int l = layer + o2;
     if (l < 0 || l > a.n2) continue;
-    for (int o1 = -1; o1 <= 1; ++o1) {
-      const int j1 = i1 + o1 < 0 ? i1 + o1 + n1 : (i1 + o1 >= n1 ? i1 + o1 - n1 : i1 + o1);
-      for (int o3 = -1; o3 <= 1; ++o3) {
-        const int j3 = i3 + o3 < 0 ? i3 + o3 + n3 : (i3 + o3 >= n3 ? i3 + o3 - n3 : i3 + o3);
-        const long long nb = (static_cast<long long>(l) * n1 + j1) * n3 + j3;
-        const double u0 = a.u[nb], u1 = a.u[nodes + nb], u2 = a.u[2 * nodes + nb];
-        const double *B = C + ((o1 + 1) + 3 * (o2 + 1) + 9 * (o3 + 1)) * 9;
+    const long long base = static_cast<long long>(l) * cells;
 #pragma unroll
-        for (int p = 0; p < 3; ++p) r[p] -= B[3 * p] * u0 + B[3 * p + 1] * u1 + B[3 * p + 2] * u2;
+    for (int o1 = 0; o1 < 3; ++o1) {
+#pragma unroll
+      for (int o3 = 0; o3 < 3; ++o3) {
+        const long long nb = base + row[o1] + col[o3];
+        const double u0 = a.u[nb], u1 = a.u[nodes + nb], u2 = a.u[2 * nodes + nb];
+        const double *B = C + (o1 + 3 * (o2 + 1) + 9 * o3) * 9;
+#pragma unroll
+        for (int p = 0; p < 3; ++p) {
+          r[p] -= B[3 * p] * u0;
+          r[p] -= B[3 * p + 1] * u1;
+          r[p] -= B[3 * p + 2] * u2;
+        }
       }
     }
   }
@@ -154,10 +169,18 @@ hipError_t launch_strip_predict(bool fp64, const StripArgs &a, hipStream_t st) {
 
 hipError_t launch_strip_correct(bool fp64, const StripArgs &a, hipStream_t st) {
   const unsigned blocks = static_cast<unsigned>((a.nodes + kStripThreads - 1) / kStripThreads);
-  if (fp64)
-    strip_correct_kernel<double><<<blocks, kStripThreads, 0, st>>>(a);
-  else
-    strip_correct_kernel<float><<<blocks, kStripThreads, 0, st>>>(a);
+  const bool uniform = a.cells % 64 == 0;
+  if (fp64) {
+    if (uniform)
+      strip_correct_kernel<double, true><<<blocks, kStripThreads, 0, st>>>(a);
+    else
+      strip_correct_kernel<double, false><<<blocks, kStripThreads, 0, st>>>(a);
+  } else {
+    if (uniform)
+      strip_correct_kernel<float, true><<<blocks, kStripThreads, 0, st>>>(a);
+    else
+      strip_correct_kernel<float, false><<<blocks, kStripThreads, 0, st>>>(a);
+  }
   return hipGetLastError();
 }
 
