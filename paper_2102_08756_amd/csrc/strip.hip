@@ -8,7 +8,7 @@
 // limited by the slip-weakening strength (Eqs. stickslip, slipweak).
 //
 // Fields are float64 [component][node layer][x1][x3] (x3 fastest); one thread
-// per node.  The stiffness is applied node by node as a 27-point stencil of 3x3
+// per node in the predictor, per four nodes along x1 in the corrector.  The stiffness is applied node by node as a 27-point stencil of 3x3
 // blocks, one stencil per node layer (the element layers above and below it may
 // differ), precomputed on the host from the element stiffness.
 #include <hip/hip_runtime.h>
@@ -24,6 +24,7 @@ namespace sbim {
 namespace {
 
 constexpr int kStripThreads = 256;
+constexpr int kStripRows = 4;        // nodes along x1 per thread of the corrector (divides n1)
 
 template <typename R>
 __global__ __launch_bounds__(kStripThreads) void strip_predict_kernel(StripArgs a) {
@@ -51,51 +52,12 @@ __global__ __launch_bounds__(kStripThreads) void strip_predict_kernel(StripArgs 
   }
 }
 
-// UNIFORM: every wavefront lies in one node layer (cells a multiple of 64), so
-// the layer's stencil is read through the scalar cache once per wavefront.
-template <typename R, bool UNIFORM>
-__global__ __launch_bounds__(kStripThreads) void strip_correct_kernel(StripArgs a) {
-  const long long nodes = a.nodes;
-  const long long id = static_cast<long long>(blockIdx.x) * kStripThreads + threadIdx.x;
-  if (id >= nodes) return;
-  const int n1 = a.n1, n3 = a.n3;
-  const long long cells = a.cells;
-  const int layer = UNIFORM ? __builtin_amdgcn_readfirstlane(static_cast<int>(id / cells))
-                            : static_cast<int>(id / cells);
-  const long long cell = id - layer * cells;
-  const int i1 = static_cast<int>(cell / n3);
-  const int i3 = static_cast<int>(cell - static_cast<long long>(i1) * n3);
-  const double *__restrict__ C = a.stencil + static_cast<long long>(layer) * 27 * 9;
-  // periodic neighbour rows and columns
-  const long long row[3] = {static_cast<long long>(i1 == 0 ? n1 - 1 : i1 - 1) * n3,
-                            static_cast<long long>(i1) * n3,
-                            static_cast<long long>(i1 == n1 - 1 ? 0 : i1 + 1) * n3};
-  const int col[3] = {i3 == 0 ? n3 - 1 : i3 - 1, i3, i3 == n3 - 1 ? 0 : i3 + 1};
-
-  // r = -K u over the 27 neighbours (layers beyond the strip carry zero blocks
-  // and are skipped)
-  double r[3] = {0.0, 0.0, 0.0};
-  for (int o2 = -1; o2 <= 1; ++o2) {
-#pragma clang fp contract(fast)
-    const int l = layer + o2;
-    if (l < 0 || l > a.n2) continue;
-    const long long base = static_cast<long long>(l) * cells;
-#pragma unroll
-    for (int o1 = 0; o1 < 3; ++o1) {
-#pragma unroll
-      for (int o3 = 0; o3 < 3; ++o3) {
-        const long long nb = base + row[o1] + col[o3];
-        const double u0 = a.u[nb], u1 = a.u[nodes + nb], u2 = a.u[2 * nodes + nb];
-        const double *B = C + (o1 + 3 * (o2 + 1) + 9 * o3) * 9;
-#pragma unroll
-        for (int p = 0; p < 3; ++p) {
-          r[p] -= B[3 * p] * u0;
-          r[p] -= B[3 * p + 1] * u1;
-          r[p] -= B[3 * p + 2] * u2;
-        }
-      }
-    }
-  }
+// Everything after the stiffness forces for one node: the S+ traction, the
+// fault solve on layer 0, the corrector and the fault outputs.
+template <typename R>
+__device__ __forceinline__ void strip_finish(const StripArgs &a, int layer, long long id,
+                                             long long cell, double r[3]) {
+  const long long nodes = a.nodes, cells = a.cells;
   const double A = a.area;
   if (layer == a.n2) {                           // S+: traction of the half-space above
     const R *__restrict__ ts = static_cast<const R *>(a.tau_sbi);
@@ -156,6 +118,73 @@ __global__ __launch_bounds__(kStripThreads) void strip_correct_kernel(StripArgs 
   }
 }
 
+// One thread per kStripRows consecutive nodes along x1 (same layer, same x3):
+// each neighbour row of u is loaded once and serves up to three of them.
+// UNIFORM: every wavefront lies in one node layer, so the layer's stencil is
+// read through the scalar cache once per wavefront.
+template <typename R, bool UNIFORM>
+__global__ __launch_bounds__(kStripThreads) void strip_correct_kernel(StripArgs a) {
+  const long long nodes = a.nodes, cells = a.cells;
+  const int n1 = a.n1, n3 = a.n3;
+  const long long tid = static_cast<long long>(blockIdx.x) * kStripThreads + threadIdx.x;
+  const long long per_layer = cells / kStripRows;
+  if (tid >= nodes / kStripRows) return;
+  const int layer = UNIFORM ? __builtin_amdgcn_readfirstlane(static_cast<int>(tid / per_layer))
+                            : static_cast<int>(tid / per_layer);
+  const long long g = tid - layer * per_layer;
+  const int ib = static_cast<int>(g / n3);
+  const int i3 = static_cast<int>(g - static_cast<long long>(ib) * n3);
+  const int i10 = ib * kStripRows;
+  const double *__restrict__ C = a.stencil + static_cast<long long>(layer) * 27 * 9;
+  const int col[3] = {i3 == 0 ? n3 - 1 : i3 - 1, i3, i3 == n3 - 1 ? 0 : i3 + 1};
+
+  double r[kStripRows][3];
+#pragma unroll
+  for (int k = 0; k < kStripRows; ++k) r[k][0] = r[k][1] = r[k][2] = 0.0;
+  for (int o2 = -1; o2 <= 1; ++o2) {
+#pragma clang fp contract(fast)
+    const int l = layer + o2;
+    if (l < 0 || l > a.n2) continue;
+    const long long base = static_cast<long long>(l) * cells;
+    const double *__restrict__ Cl = C + 3 * (o2 + 1) * 9;
+#pragma unroll
+    for (int q = 0; q < kStripRows + 2; ++q) {     // neighbour row i10 - 1 + q
+      int jr = i10 - 1 + q;
+      jr = jr < 0 ? jr + n1 : (jr >= n1 ? jr - n1 : jr);
+      const long long rb = base + static_cast<long long>(jr) * n3;
+      double u[3][3];
+#pragma unroll
+      for (int o3 = 0; o3 < 3; ++o3) {
+        const long long nb = rb + col[o3];
+        u[o3][0] = a.u[nb];
+        u[o3][1] = a.u[nodes + nb];
+        u[o3][2] = a.u[2 * nodes + nb];
+      }
+      // row q is the neighbour at offset o1 = q - 1 - k of node k
+#pragma unroll
+      for (int k = 0; k < kStripRows; ++k) {
+        const int o1 = q - 1 - k;
+        if (o1 < -1 || o1 > 1) continue;
+#pragma unroll
+        for (int o3 = 0; o3 < 3; ++o3) {
+          const double *B = Cl + ((o1 + 1) + 9 * o3) * 9;
+#pragma unroll
+          for (int p = 0; p < 3; ++p) {
+            r[k][p] -= B[3 * p] * u[o3][0];
+            r[k][p] -= B[3 * p + 1] * u[o3][1];
+            r[k][p] -= B[3 * p + 2] * u[o3][2];
+          }
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < kStripRows; ++k) {
+    const long long cell = static_cast<long long>(i10 + k) * n3 + i3;
+    strip_finish<R>(a, layer, layer * cells + cell, cell, r[k]);
+  }
+}
+
 }  // namespace
 
 hipError_t launch_strip_predict(bool fp64, const StripArgs &a, hipStream_t st) {
@@ -168,8 +197,9 @@ hipError_t launch_strip_predict(bool fp64, const StripArgs &a, hipStream_t st) {
 }
 
 hipError_t launch_strip_correct(bool fp64, const StripArgs &a, hipStream_t st) {
-  const unsigned blocks = static_cast<unsigned>((a.nodes + kStripThreads - 1) / kStripThreads);
-  const bool uniform = a.cells % 64 == 0;
+  const long long threads = a.nodes / kStripRows;
+  const unsigned blocks = static_cast<unsigned>((threads + kStripThreads - 1) / kStripThreads);
+  const bool uniform = (a.cells / kStripRows) % 64 == 0;
   if (fp64) {
     if (uniform)
       strip_correct_kernel<double, true><<<blocks, kStripThreads, 0, st>>>(a);

@@ -6,7 +6,7 @@ loop, naive transforms, direct history sums) on the same workload, and
 compares per step: fault traction, slip rate, slip, the set of sliding nodes,
 and the S+ layer's displacement.  Bars relative to each field's largest value
 over the run: float64 1e-9 with identical sliding sets; float32 forms
-(boundary relation in float32, strip in float64) 1e-3 relative L2 with rupture
+(boundary relation in float32, strip in float64) 1e-5 relative L2 with rupture
 onset within one step.  At full size (1024 x 1024 cells of 50 m) the hybrid
 rupture is compared with the stand-alone boundary-integral rupture of the same
 setup: they are different discretisations that the paper shows agree (Sec. 3.2).
@@ -31,6 +31,7 @@ CASES = {
     "coarse16_two_layers": ("tpv3_coarse16", [BULK, BULK]),
     "rect32x16_slow_layer": ("tpv3_rect32x16", [SLOW, BULK, BULK]),
     "coarse32_one_layer": ("tpv3_coarse32", [BULK]),
+    "tiny8_two_layers": ("tpv3_tiny8", [BULK, SLOW]),
 }
 _REF = {}
 
@@ -105,7 +106,7 @@ def test_strip_fp32_forms_against_oracle(precision):
     np.testing.assert_array_equal(og >= 0, orf >= 0)
     assert np.abs(og - orf)[both].max() <= 1
     for k, e in errs.items():
-        assert e < 1e-3, (k, e)
+        assert e < 1e-5, (k, e)
 
 
 def test_strip_reset_and_errors():

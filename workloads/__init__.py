@@ -286,4 +286,7 @@ FAULTS = {
                                     tau0_3=4.0e6),
     "bimaterial32": FaultWorkload("bimaterial32", 32, 32, 375.0, 120, region=(9000.0, 9000.0),
                                   lower=SLOWER),
+    # fewer cells than one 64-wide wavefront per strip row block
+    "tpv3_tiny8": FaultWorkload("tpv3_tiny8", 8, 8, 750.0, 40, region=(4500.0, 4500.0),
+                                patch=1500.0),
 }
