@@ -103,8 +103,11 @@ def interface_solve(fp, fm, zp, zm, D, prm):
 MIRROR = np.array([1.0, -1.0, 1.0])      # s^- of the mirrored lower half-space
 
 
-def rupture(cfg, prm: FaultParams, steps, weights_cache=None):
-    """Run ``steps`` explicit steps; returns a dict of float64 histories:
+def rupture(cfg, prm: FaultParams, steps, weights_cache=None, dts=None):
+    """Run ``steps`` explicit steps; returns a dict of float64 histories.
+
+    ``dts``: per-step time steps, allowed in the quasi-dynamic limit
+    (window_mode "static"), whose boundary relation does not depend on dt.
 
     traction [N, 3, n1, n3]   fault traction tau^n
     slip_rate [N, 2, n1, n3]  V^n, components (1, 3)
@@ -119,6 +122,9 @@ def rupture(cfg, prm: FaultParams, steps, weights_cache=None):
         raise ValueError(f"fault needs planes with sides [+1] or [+1, -1], got {sides}")
     if cfg.input_kind != "absolute":
         raise ValueError("the fault oracle pushes absolute displacements")
+    if dts is not None and cfg.window_mode != "static":
+        raise ValueError("variable time steps need the quasi-dynamic (static) boundary relation")
+    dts = [cfg.dt] * steps if dts is None else [float(x) for x in dts]
     n1, n3 = cfg.n1, cfg.n3
     h = n3 // 2 + 1
     cache = {} if weights_cache is None else weights_cache
@@ -145,10 +151,11 @@ def rupture(cfg, prm: FaultParams, steps, weights_cache=None):
         fp = tau0 + s[0]
         fm = tau0 + (MIRROR[:, None, None] * s[0] if P == 1 else s[1])
         tau, V, vp, vm = interface_solve(fp, fm, zp, zm, D, prm)
-        u[0] += cfg.dt * vp
+        dt = dts[n]
+        u[0] += dt * vp
         if P == 2:
-            u[1] += cfg.dt * vm
-        D += cfg.dt * V
+            u[1] += dt * vm
+        D += dt * V
         out["traction"][n] = tau
         out["slip_rate"][n] = V
         out["slip"][n] = D

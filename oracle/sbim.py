@@ -34,7 +34,7 @@ from dataclasses import dataclass, field
 import numpy as np
 
 from . import dft
-from .kernels import lag_weights
+from .kernels import kernel_laplace, lag_weights
 
 
 @dataclass
@@ -54,7 +54,7 @@ class Config:
     dt: float = 0.2
     planes: list = field(default_factory=lambda: [Plane()])
     window_cap: int = 100
-    window_mode: str = "fixed"        # "fixed" | "per_mode"
+    window_mode: str = "fixed"        # "fixed" | "per_mode" | "static"
     eta_w: float = 1.0
     input_kind: str = "absolute"      # "absolute" | "increment"
 
@@ -90,10 +90,13 @@ def mode_geometry(cfg):
 
 
 def mode_window(q, cs, dt, cfg):
-    """History length W(q) per mode: fixed cap, or min(cap, ceil(2 pi eta_w / (q c_s dt)))."""
+    """History length W(q) per mode: fixed cap, or min(cap, ceil(2 pi eta_w / (q c_s dt))),
+    or 1 in the quasi-dynamic limit ("static")."""
     q = np.asarray(q, dtype=np.float64)
     if cfg.window_mode == "fixed":
         w = np.full(q.shape, cfg.window_cap, dtype=np.int64)
+    elif cfg.window_mode == "static":
+        w = np.ones(q.shape, dtype=np.int64)
     elif cfg.window_mode == "per_mode":
         with np.errstate(divide="ignore"):
             x = (2.0 * math.pi * cfg.eta_w) / (q * cs * dt)
@@ -160,9 +163,16 @@ class PlaneOperator:
             Wq = int(self.W[idx])
             if Wq == 0:
                 continue
-            key = (float(q[idx]), cs, cfg.dt, Wq, eta)
-            if key not in cache:
-                cache[key] = lag_weights(q[idx], cs, cfg.dt, Wq, eta)
+            if cfg.window_mode == "static":
+                # quasi-dynamic limit: the whole kernel acts on the current
+                # displacement, w_ab,0 = G_ab(infinity) = F_ab(s = 0)
+                key = ("static", eta)
+                if key not in cache:
+                    cache[key] = np.real(np.array(kernel_laplace(0.0, eta)))[:, None]
+            else:
+                key = (float(q[idx]), cs, cfg.dt, Wq, eta)
+                if key not in cache:
+                    cache[key] = lag_weights(q[idx], cs, cfg.dt, Wq, eta)
             w[:, :Wq, idx] = cache[key]
         self.K = np.zeros((self.Wmax, nm, 3, 3), dtype=complex)
         if self.Wmax:
