@@ -205,14 +205,17 @@ def accuracy(wl, steps, device, inputs_cache, forms=("fp32_comp", "fp32"), block
     return out
 
 
-def measure_rupture(fw, precision, device, warmup=20):
+def measure_rupture(fw, precision, device, warmup=20, window_mode=None):
     """Stand-alone rupture on the fault between two half-spaces (the paper's TPV3 setup
     at its resolution; the lower half-space is the mirror image of the upper one): the
     whole run timed from rest, one library step (push without damping, inverse FFT,
     interface solve) per time step."""
     import torch
     from paper_2102_08756_amd import SBIM, Config, Fault
-    cfg = Config.from_dict(fw.config_dict(), precision=precision, input_kind="increment")
+    cd = fw.config_dict()
+    if window_mode:
+        cd["window_mode"] = window_mode
+    cfg = Config.from_dict(cd, precision=precision, input_kind="increment")
     t0 = time.time()
     sb = SBIM(cfg, device=device)
     prm = [torch.tensor(a, dtype=torch.float64, device=device).contiguous() for a in fw.params()]
@@ -319,6 +322,14 @@ def rupture_leg(fw, forms, device):
     hy["final_slip_rel_l2_vs_boundary_integral"] = float(
         np.linalg.norm(hs - slips[p]) / np.linalg.norm(slips[p]))
     out["hybrid"] = hy
+    # quasi-dynamic limit of the same rupture (static kernel plus radiation damping)
+    qd = measure_rupture(fw, p, device, window_mode="static")
+    qd.pop("_slip")
+    out["quasi_dynamic"] = {k: qd[k] for k in ("ms_per_step", "init_s", "ring_bytes",
+                                               "region_slipped_frac", "max_slip_m")}
+    out["quasi_dynamic"]["precision"] = p
+    print(f"[bench] quasi-dynamic {fw.name} {p}: {qd['ms_per_step']:.3f} ms/step, "
+          f"max slip {qd['max_slip_m']:.3f} m", file=sys.stderr, flush=True)
     print(f"[bench] hybrid {fw.name} {p}: {hy['ms_per_step']:.3f} ms/step "
           f"({hy['layers']} element layers), final slip vs boundary integral "
           f"{hy['final_slip_rel_l2_vs_boundary_integral']:.2e}", file=sys.stderr, flush=True)

@@ -70,6 +70,12 @@ extern "C" {
 /* window_mode */
 #define SBIM_W_FIXED 0
 #define SBIM_W_PER_MODE 1
+/* quasi-dynamic limit (Sec. 7 pairs it with the dynamic relation for cycle
+ * simulations): each mode keeps only the step just pushed and the kernels act
+ * through their static integrals G_ab(infinity), i.e. the half-space's static
+ * surface stiffness; the damping term is kept.  window_cap is ignored and dt
+ * may change between pushes (sbim_set_dt). */
+#define SBIM_W_STATIC 2
 /* input_kind */
 #define SBIM_ABSOLUTE 0   /* push receives u^n - u^0 */
 #define SBIM_INCREMENT 1  /* push receives u^n - u^{n-1} */
@@ -90,7 +96,7 @@ typedef struct {
   int nplanes;           /* 1 or 2 */
   sbim_plane plane[SBIM_MAX_PLANES];
   int window_cap;        /* >= 1: longest history kept per mode */
-  int window_mode;       /* SBIM_W_FIXED or SBIM_W_PER_MODE */
+  int window_mode;       /* SBIM_W_FIXED, SBIM_W_PER_MODE or SBIM_W_STATIC */
   double eta_w;          /* > 0, used by SBIM_W_PER_MODE */
   int precision;         /* SBIM_FP64, SBIM_FP32 or SBIM_FP32_COMP */
   int input_kind;        /* SBIM_ABSOLUTE or SBIM_INCREMENT */
@@ -175,6 +181,15 @@ const char *sbim_last_error(const sbim_handle *h);
 
 /* Use another HIP stream for subsequent calls (the previous one is not synchronised). */
 int sbim_set_stream(sbim_handle *h, void *stream);
+
+/*
+ * sbim_set_dt: the time step of the following pushes (the velocity of the
+ * damping term when none is pushed, and the updates of a fault or strip on
+ * this handle).  Only for SBIM_W_STATIC handles, whose boundary relation does
+ * not depend on dt (variable time stepping); SBIM_E_STATE otherwise, since the
+ * dynamic kernels are integrated over the step of sbim_init.
+ */
+int sbim_set_dt(sbim_handle *h, double dt);
 
 /* Fill *out (host memory). */
 int sbim_get_info(const sbim_handle *h, sbim_info *out);

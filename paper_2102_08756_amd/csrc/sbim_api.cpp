@@ -153,7 +153,8 @@ int validate(const sbim_config *c) {
   }
   if (c->window_cap < 1 || c->window_cap > (1 << 20))
     return fail(nullptr, SBIM_E_INVALID, "window_cap=%d: must be in [1, 2^20]", c->window_cap);
-  if (c->window_mode != SBIM_W_FIXED && c->window_mode != SBIM_W_PER_MODE)
+  if (c->window_mode != SBIM_W_FIXED && c->window_mode != SBIM_W_PER_MODE &&
+      c->window_mode != SBIM_W_STATIC)
     return fail(nullptr, SBIM_E_INVALID, "window_mode=%d unknown", c->window_mode);
   if (c->window_mode == SBIM_W_PER_MODE && !finite_pos(c->eta_w))
     return fail(nullptr, SBIM_E_INVALID, "eta_w must be finite and > 0");
@@ -181,7 +182,9 @@ void plan_group(const sbim_config &c, int depth, Group &g, std::vector<double> &
       const double q = std::sqrt(k1 * k1 + k3 * k3);
       int w = 0;
       if (q > 0) {
-        if (c.window_mode == SBIM_W_FIXED) {
+        if (c.window_mode == SBIM_W_STATIC) {
+          w = 1;
+        } else if (c.window_mode == SBIM_W_FIXED) {
           w = c.window_cap;
         } else {
           const double x = (two_pi * c.eta_w) / (q * g.cs * c.dt);
@@ -516,7 +519,27 @@ int sbim_init(const sbim_config *cfg, sbim_handle **out) {
     if (ring_bytes(h, g)) TRY(hipMemsetAsync(g.ring, 0, ring_bytes(h, g), h->stream));
     TRY(hipMemsetAsync(g.state, 0, state_bytes_g(g), h->stream));
     TRY(hipMemsetAsync(g.pending, 0, pending_bytes(h, g), h->stream));
-    TRY(sbim::launch_tabulate(h->fp64, g, cfg->dt, d_glx, d_glw, h->stream));
+    if (cfg->window_mode == SBIM_W_STATIC) {
+      // one row per class: the static integrals G_ab(infinity) of the kernels,
+      // i.e. the static surface stiffness K_ab(0) less the instantaneous L-N
+      // coupling, (w11, w12, w22, w33); then the zero row
+      const double e2 = g.eta * g.eta;
+      const double row[4] = {2.0 * e2 / (e2 + 1.0), -2.0 / (e2 + 1.0) - (g.eta - 2.0),
+                             2.0 * e2 / (e2 + 1.0), 1.0};
+      std::vector<double> t64(static_cast<size_t>(g.table_rows) * 4, 0.0);
+      for (long long c = 0; c < g.nclasses; ++c)
+        for (int k = 0; k < 4; ++k) t64[static_cast<size_t>(g.h_cls_off[c]) * 4 + k] = row[k];
+      if (h->fp64) {
+        TRY(upload(g.table, t64.data(), t64.size() * sizeof(double), h->stream));
+        TRY(hipStreamSynchronize(h->stream));
+      } else {
+        std::vector<float> t32(t64.begin(), t64.end());
+        TRY(upload(g.table, t32.data(), t32.size() * sizeof(float), h->stream));
+        TRY(hipStreamSynchronize(h->stream));
+      }
+    } else {
+      TRY(sbim::launch_tabulate(h->fp64, g, cfg->dt, d_glx, d_glw, h->stream));
+    }
     // the host vectors must outlive the asynchronous copies
     TRY(hipStreamSynchronize(h->stream));
   }
@@ -631,6 +654,15 @@ int sbim_set_stream(sbim_handle *h, void *stream) {
   if (!h) return fail(nullptr, SBIM_E_INVALID, "handle is NULL");
   h->stream = static_cast<hipStream_t>(stream);
   h->cfg.stream = stream;
+  return SBIM_OK;
+}
+
+int sbim_set_dt(sbim_handle *h, double dt) {
+  if (!h) return fail(nullptr, SBIM_E_INVALID, "handle is NULL");
+  if (!(dt > 0) || !std::isfinite(dt)) return fail(h, SBIM_E_INVALID, "dt must be finite and > 0");
+  if (h->cfg.window_mode != SBIM_W_STATIC)
+    return fail(h, SBIM_E_STATE, "the time step of a dynamic handle is fixed at sbim_init");
+  h->cfg.dt = dt;
   return SBIM_OK;
 }
 

@@ -20,7 +20,7 @@ LIB_PATH = os.environ.get("SBIM_LIBRARY") or os.path.join(_HERE, "_lib", "libsbi
 
 SBIM_OK, SBIM_E_INVALID, SBIM_E_OOM, SBIM_E_STATE, SBIM_E_DEVICE = 0, -1, -2, -3, -4
 PRECISIONS = {"fp64": 0, "fp32": 1, "fp32_comp": 2}
-WINDOW_MODES = {"fixed": 0, "per_mode": 1}
+WINDOW_MODES = {"fixed": 0, "per_mode": 1, "static": 2}
 INPUT_KINDS = {"absolute": 0, "increment": 1}
 ERROR_NAMES = {SBIM_E_INVALID: "SBIM_E_INVALID", SBIM_E_OOM: "SBIM_E_OOM",
                SBIM_E_STATE: "SBIM_E_STATE", SBIM_E_DEVICE: "SBIM_E_DEVICE"}
@@ -29,6 +29,7 @@ ERROR_NAMES = {SBIM_E_INVALID: "SBIM_E_INVALID", SBIM_E_OOM: "SBIM_E_OOM",
 EXPORTS = (
     "sbim_init", "sbim_push_displacement", "sbim_tractions", "sbim_backward",
     "sbim_backward_reset", "sbim_reset", "sbim_destroy", "sbim_last_error", "sbim_set_stream",
+    "sbim_set_dt",
     "sbim_get_info", "sbim_state_bytes", "sbim_save_state", "sbim_load_state", "sbim_step_work",
     "sbim_mode_kernel", "sbim_profile_conv", "sbim_conv_timing",
     "sbim_fault_create", "sbim_fault_step", "sbim_fault_read", "sbim_fault_reset",
@@ -95,6 +96,7 @@ def load_library(path=LIB_PATH):
         "sbim_destroy": (i, [vp]),
         "sbim_last_error": (ctypes.c_char_p, [vp]),
         "sbim_set_stream": (i, [vp, vp]),
+        "sbim_set_dt": (i, [vp, d]),
         "sbim_get_info": (i, [vp, ctypes.POINTER(_Info)]),
         "sbim_state_bytes": (ll, [vp]),
         "sbim_save_state": (i, [vp, vp]),
@@ -252,6 +254,10 @@ class SBIM:
         self._sync_stream()
         self._check(self._L.sbim_backward(self._h, _ptr(g), _ptr(du), _ptr(dv)))
         return (du, dv) if with_velocity else du
+
+    def set_dt(self, dt):
+        """Time step of the following pushes (quasi-dynamic handles only)."""
+        self._check(self._L.sbim_set_dt(self._h, float(dt)))
 
     def backward_reset(self):
         self._check(self._L.sbim_backward_reset(self._h))

@@ -85,3 +85,4 @@ def test_null_arguments_rejected():
     assert lib.sbim_strip_read(None, 0, None) == B.SBIM_E_INVALID
     assert lib.sbim_strip_reset(None) == B.SBIM_E_INVALID
     assert lib.sbim_strip_destroy(None) == B.SBIM_OK
+    assert lib.sbim_set_dt(None, 0.1) == B.SBIM_E_INVALID
