@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
 #include <new>
 #include <numeric>
 #include <string>
@@ -198,9 +199,15 @@ void plan_group(const sbim_config &c, int depth, Group &g, std::vector<double> &
       k3v[f] = k3;
     }
   }
-  std::sort(keys.begin(), keys.end(), [](const ModeKey &a, const ModeKey &b) {
+  // Blocks hold modes of equal window.  With one window for all modes, modes
+  // of equal q sit together so that a block's lanes share kernel rows.  With
+  // per-mode windows (short histories, where the push and traction gathers
+  // dominate) modes of equal window stay in spectrum order, so the gathers of
+  // the spectrum and the scatters of the traction spectrum are contiguous runs.
+  const bool by_q = c.window_mode != SBIM_W_PER_MODE;
+  std::sort(keys.begin(), keys.end(), [by_q](const ModeKey &a, const ModeKey &b) {
     if (a.w != b.w) return a.w > b.w;
-    if (a.q != b.q) return a.q < b.q;
+    if (by_q && a.q != b.q) return a.q < b.q;
     return a.nat < b.nat;
   });
   g.M = M;
@@ -211,16 +218,24 @@ void plan_group(const sbim_config &c, int depth, Group &g, std::vector<double> &
   geom.assign(4 * M, 0.0);
   cls_q.clear();
   g.h_cls_w.clear();
+  // a class per distinct (W, q): kernel rows are shared whatever the order
+  std::map<std::pair<int, double>, int> class_of;
   for (long long s = 0; s < M; ++s) {
     const ModeKey &k = keys[s];
-    if (s == 0 || k.w != keys[s - 1].w || k.q != keys[s - 1].q) {
-      if (k.w > 0) {
+    int cls = 0;
+    if (k.w > 0) {
+      auto it = class_of.find({k.w, k.q});
+      if (it == class_of.end()) {
+        cls = static_cast<int>(cls_q.size());
+        class_of.emplace(std::make_pair(k.w, k.q), cls);
         cls_q.push_back(k.q);
         g.h_cls_w.push_back(k.w);
+      } else {
+        cls = it->second;
       }
     }
     g.h_nat[s] = k.nat;
-    g.h_cls[s] = k.w > 0 ? static_cast<int>(cls_q.size()) - 1 : 0;
+    g.h_cls[s] = cls;
     g.h_win[s] = k.w;
     const double q = qv[k.nat];
     geom[4 * s + 0] = q;
