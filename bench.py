@@ -336,6 +336,53 @@ def rupture_leg(fw, forms, device):
     return out
 
 
+def scaling_sweep(device, sizes=(128, 256, 512, 1024, 2048), window=200, layers=(2, 6)):
+    """Cost of one step against the grid size n x n at a fixed history window: the
+    boundary relation with the fault's interface solve, and the hybrid scheme with
+    two and six element layers (their difference / 4 is the cost of one node layer of
+    the strip).  Steady state: the window is full when the timed steps start."""
+    import torch
+    import workloads
+    from paper_2102_08756_amd import SBIM, Config, Fault, Strip
+    t = workloads.TPV3
+    rows = []
+    for n in sizes:
+        fw = workloads.FaultWorkload(f"scaling{n}", n, n, 50.0 * 1024 / n, 2 * window,
+                                     window_cap=window)
+        prm = [torch.tensor(a, dtype=torch.float64, device=device).contiguous() for a in fw.params()]
+        row = {"n": n, "modes": n * (n // 2 + 1), "window": window}
+
+        def timed(make):
+            sb = SBIM(Config.from_dict(fw.config_dict(), precision="fp32_comp",
+                                       input_kind="increment"), device=device)
+            obj = make(sb)
+            for _ in range(window):
+                obj.step()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(window):
+                obj.step()
+            torch.cuda.synchronize()
+            ms = 1e3 * (time.perf_counter() - t0) / window
+            obj.close()
+            sb.close()
+            return ms
+        row["boundary_ms"] = timed(lambda sb: Fault(sb, *prm))
+        for L in layers:
+            row[f"hybrid{L}_ms"] = timed(lambda sb: Strip(sb, [(t["rho"], t["cp"], t["cs"])] * L, *prm))
+        row["fe_node_layer_ms"] = (row[f"hybrid{layers[1]}_ms"] - row[f"hybrid{layers[0]}_ms"]) / (
+            layers[1] - layers[0])
+        row["boundary_us_per_kmode"] = 1e3 * row["boundary_ms"] / (row["modes"] / 1e3)
+        rows.append(row)
+        print(f"[bench] scaling n={n}: boundary {row['boundary_ms']:.3f} ms/step, "
+              f"hybrid {layers[0]} layers {row[f'hybrid{layers[0]}_ms']:.3f} ms, "
+              f"{layers[1]} layers {row[f'hybrid{layers[1]}_ms']:.3f} ms, "
+              f"one node layer {row['fe_node_layer_ms']:.4f} ms", file=sys.stderr, flush=True)
+        del prm
+        torch.cuda.empty_cache()
+    return rows
+
+
 def cpu_baseline(wl, sample_modes=64, seed=0):
     """float64 oracle on one steady-state step: full naive DFTs, convolution on sampled
     modes; timed with the host's BLAS threads and again limited to one thread (the
@@ -410,6 +457,8 @@ def main():
     ap.add_argument("--rupture-forms", default="fp32_comp,fp64",
                     help="forms of the rupture leg on the fault workload (empty: skip it)")
     ap.add_argument("--rupture", default="tpv3_1024", help="fault workload of the rupture leg")
+    ap.add_argument("--scaling", action="store_true",
+                    help="only the step-cost sweep over grid sizes (boundary relation vs strip layers)")
     ap.add_argument("--calibrate-copy", type=float, default=0.0,
                     help="only run a torch device copy of this many GiB (counter calibration)")
     args = ap.parse_args()
@@ -422,6 +471,9 @@ def main():
         print(json.dumps({"error": "no GPU visible"}))
         sys.exit(1)
     device = "cuda:0"
+    if args.scaling:
+        print(json.dumps({"scaling": scaling_sweep(device)}))
+        return
     if args.calibrate_copy:
         n = int(args.calibrate_copy * 2 ** 30 / 4)
         a = torch.ones(n, dtype=torch.float32, device=device)
