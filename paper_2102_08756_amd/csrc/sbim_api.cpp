@@ -224,14 +224,20 @@ void plan_group(const sbim_config &c, int depth, Group &g, std::vector<double> &
     const ModeKey &k = keys[s];
     int cls = 0;
     if (k.w > 0) {
-      auto it = class_of.find({k.w, k.q});
-      if (it == class_of.end()) {
+      bool known = false;
+      if (by_q) {                    // sorted by (W, q): equal keys are neighbours
+        known = s > 0 && k.w == keys[s - 1].w && k.q == keys[s - 1].q;
+        if (known) cls = g.h_cls[s - 1];
+      } else {
+        auto it = class_of.find({k.w, k.q});
+        known = it != class_of.end();
+        if (known) cls = it->second;
+      }
+      if (!known) {
         cls = static_cast<int>(cls_q.size());
-        class_of.emplace(std::make_pair(k.w, k.q), cls);
+        if (!by_q) class_of.emplace(std::make_pair(k.w, k.q), cls);
         cls_q.push_back(k.q);
         g.h_cls_w.push_back(k.w);
-      } else {
-        cls = it->second;
       }
     }
     g.h_nat[s] = k.nat;

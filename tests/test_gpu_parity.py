@@ -228,3 +228,19 @@ def test_adjoint_sweep_depths(depth, kind, monkeypatch):
     print(f"adjoint depth {depth} {kind}: rel-L2 {err:.3e}")
     assert err < 1e-12
     sb.close()
+
+
+def test_oversize_ring_is_refused_before_allocating():
+    """A window whose ring cannot fit in device memory: SBIM_E_OOM from sbim_init, with
+    nothing allocated, and the device stays usable."""
+    from paper_2102_08756_amd import SBIMError
+    free0, _ = torch.cuda.mem_get_info()
+    cfg = Config.from_dict(dict(n1=4096, n3=4096, window_cap=1 << 20,
+                                planes=[dict(side=1), dict(side=-1)]), precision="fp64")
+    with pytest.raises(SBIMError, match="SBIM_E_OOM"):
+        SBIM(cfg, device=DEV)
+    free1, _ = torch.cuda.mem_get_info()
+    assert abs(free1 - free0) < 64 << 20
+    cfg_d = dict(SMALL["tiny4"], input_kind="absolute")
+    u, _, _ = _inputs(cfg_d, 3, 5)
+    np.testing.assert_allclose(run_gpu(cfg_d, u, "fp64"), oracle.forward(cfg_d, u), rtol=1e-10, atol=1e-12)
