@@ -8,9 +8,10 @@
 // limited by the slip-weakening strength (Eqs. stickslip, slipweak).
 //
 // Fields are float64 [component][node layer][x1][x3] (x3 fastest); one thread
-// per node in the predictor, per four nodes along x1 in the corrector.  The stiffness is applied node by node as a 27-point stencil of 3x3
-// blocks, one stencil per node layer (the element layers above and below it may
-// differ), precomputed on the host from the element stiffness.
+// per node in the predictor, per four nodes along x1 in the corrector.  The
+// stiffness is applied node by node as a 27-point stencil of 3x3 blocks, one
+// stencil per node layer (the element layers above and below it may differ),
+// precomputed on the host from the element stiffness.
 #include <hip/hip_runtime.h>
 
 #include "internal.h"
