@@ -5,10 +5,13 @@ Oracle module: test infrastructure only (see ``oracle/__init__.py``).
 A thin strip of 8-node hexahedral finite elements (Sec. 2.2, FEM) sits on the
 fault; its far boundary S+ is closed by the boundary relation of an elastic
 half-space (Sec. 2.3, Eq. SBI), which absorbs the waves that leave the strip.
-Only the upper half of the strip is modelled: the fault plane is a symmetry
-plane (Sec. 3.1), so the lower half moves as the mirror image, the slip is twice
-the upper side's tangential displacement, the fault normal traction keeps its
-background value and no normal constraint is needed.
+``hybrid_rupture`` models only the upper half of the strip: the fault plane is a
+symmetry plane (Sec. 3.1), so the lower half moves as the mirror image, the slip
+is twice the upper side's tangential displacement, the fault normal traction
+keeps its background value and no normal constraint is needed.
+``hybrid_rupture_two_sided`` models both halves with split fault nodes, each
+closed by its own boundary relation (S+ and S-), for different materials
+across the fault.
 
 Discretisation (the paper's regular hexahedral mesh with matching SBI grid,
 Sec. 2.4 and the closing remarks of Sec. 7):
@@ -230,4 +233,112 @@ def hybrid_rupture(cfg: StripConfig, tau0, mu_s, mu_k, d_c, steps, weights_cache
         out["slip"][n] = slip_now
         out["top_u"][n] = u[:, top]
         out["top_v"][n] = v_pred[:, top]
+    return out
+
+
+@dataclass
+class TwoSidedConfig:
+    """The strip on both sides of the fault: ``upper[j]`` fills x2 in [j h, (j+1) h]
+    above the fault and ``lower[j]`` fills [-(j+1) h, -j h] below it (both listed from
+    the fault outwards); ``plane_up`` (side +1) closes S+, ``plane_down`` (side -1) S-."""
+    n1: int
+    n3: int
+    h: float
+    dt: float
+    upper: list
+    lower: list
+    plane_up: Plane
+    plane_down: Plane
+    window_cap: int = 100
+    window_mode: str = "fixed"
+    eta_w: float = 1.0
+
+    def sbim_config(self):
+        return Config(n1=self.n1, n3=self.n3, dx1=self.h, dx3=self.h, dt=self.dt,
+                      planes=[self.plane_up, self.plane_down], window_cap=self.window_cap,
+                      window_mode=self.window_mode, eta_w=self.eta_w, input_kind="absolute")
+
+
+def hybrid_rupture_two_sided(cfg: TwoSidedConfig, tau0, mu_s, mu_k, d_c, steps,
+                             weights_cache=None):
+    """The hybrid scheme with the strip on both sides of a split-node fault.
+
+    Each side is its own block of elements (the fault nodes are split: the upper
+    copy belongs to the elements above, the lower copy to those below), closed by
+    its own boundary relation at S+ or S-.  Per step, as the one-sided scheme for
+    each block, and at the fault (Sec. 2.2, Eqs. freeslip, sticktraction,
+    stickslip): the half-step velocities the two copies would reach without fault
+    traction, v*+ and v*-, give the traction change that closes their jump,
+        dtau~ = (v*+ - v*-) / (dt h^2 (1/M+ + 1/M-))      (all three components),
+    the normal component is applied as it is (no opening or interpenetration),
+    the shear pair is limited by the strength max(-tau_2, 0) mu(delta), delta the
+    slip amplitude |u+ - u-| at t+1, and the copies receive -/+ h^2 (tau - tau0).
+
+    Returns float64 histories: traction [N, 3, n1, n3]; sliding [N, n1, n3];
+    slip_rate and slip [N, 2, n1, n3] (upper minus lower copy, components 1, 3, at
+    t+1); normal_jump [N, n1, n3] (v2 of the upper minus the lower copy).
+    """
+    up = Strip(StripConfig(cfg.n1, cfg.n3, cfg.h, cfg.dt, cfg.upper, cfg.plane_up))
+    lo = Strip(StripConfig(cfg.n1, cfg.n3, cfg.h, cfg.dt, cfg.lower[::-1], cfg.plane_down))
+    n1, n3, h, dt = cfg.n1, cfg.n3, cfg.h, cfg.dt
+    top, Lb = len(cfg.upper), len(cfg.lower)
+    scfg = cfg.sbim_config()
+    cache = {} if weights_cache is None else weights_cache
+    ops = [PlaneOperator(scfg, p, None, cache) for p in range(2)]
+    hh = n3 // 2 + 1
+    A = h * h
+    state = {k: [np.zeros(s.shape) for _ in range(3)] for k, s in (("up", up), ("lo", lo))}
+    hist = [[], []]
+    sh = [0, 2]
+    out = {k: np.empty((steps,) + s) for k, s in (
+        ("traction", (3, n1, n3)), ("slip_rate", (2, n1, n3)), ("slip", (2, n1, n3)),
+        ("normal_jump", (n1, n3)))}
+    out["sliding"] = np.zeros((steps, n1, n3), dtype=bool)
+    for n in range(steps):
+        pred = {}
+        for k in ("up", "lo"):
+            u, v, a = state[k]
+            v_half = v + 0.5 * dt * a
+            u = u + dt * v_half
+            pred[k] = (u, v_half, v + dt * a)
+        tau_sbi = []
+        for p, (k, layer) in enumerate((("up", top), ("lo", 0))):
+            u, _, v_pred = pred[k]
+            hist[p].append(dft.forward_half(u[:, layer]).reshape(3, -1))
+            if len(hist[p]) > max(ops[p].Wmax, 1):
+                hist[p] = hist[p][-ops[p].Wmax:]
+            Vh = dft.forward_half(v_pred[:, layer]).reshape(3, -1)
+            t_hat = ops[p].apply_last(np.stack(hist[p]), Vh)
+            tau_sbi.append(dft.inverse_half(t_hat.reshape(3, n1, hh), n3))
+        (uu, vhu, _), (ul, vhl, _) = pred["up"], pred["lo"]
+        ru = -up.internal_force(uu)
+        rl = -lo.internal_force(ul)
+        ru[:, top] += A * tau_sbi[0]          # S+: outward normal +e2
+        rl[:, 0] -= A * tau_sbi[1]            # S-: outward normal -e2
+        Mp, Mm = up.mass[0], lo.mass[Lb]
+        vsp = vhu[:, 0] + dt * ru[:, 0] / Mp
+        vsm = vhl[:, Lb] + dt * rl[:, Lb] / Mm
+        stick = tau0 + (vsp - vsm) / (dt * A * (1.0 / Mp + 1.0 / Mm))
+        tau = np.empty_like(stick)
+        tau[1] = stick[1]
+        mag = np.sqrt(stick[0] * stick[0] + stick[2] * stick[2])
+        slip_now = uu[sh, 0] - ul[sh, Lb]
+        delta = np.sqrt(slip_now[0] * slip_now[0] + slip_now[1] * slip_now[1])
+        strength = np.maximum(-tau[1], 0.0) * friction_coefficient(delta, mu_s, mu_k, d_c)
+        slipping = mag > strength
+        scale = np.where(slipping, strength / np.where(slipping, mag, 1.0), 1.0)
+        tau[sh] = stick[sh] * scale
+        ru[:, 0] -= A * (tau - tau0)
+        rl[:, Lb] += A * (tau - tau0)
+        au = ru / up.mass[None]
+        al = rl / lo.mass[None]
+        vu = vhu + 0.5 * dt * au
+        vl = vhl + 0.5 * dt * al
+        state["up"] = [uu, vu, au]
+        state["lo"] = [ul, vl, al]
+        out["traction"][n] = tau
+        out["sliding"][n] = slipping
+        out["slip"][n] = slip_now
+        out["slip_rate"][n] = vu[sh, 0] - vl[sh, Lb]
+        out["normal_jump"][n] = vu[1, 0] - vl[1, Lb]
     return out

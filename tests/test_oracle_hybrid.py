@@ -165,3 +165,66 @@ def test_hybrid_converges_to_boundary_integral_rupture():
         patch, region = wl.masks()
         assert not hyb["sliding"][:, ~region].any()
     assert errs[1] < 0.5 * errs[0] and errs[1] < 0.15, errs
+
+
+# ---------------------------------------------------------------- two-sided strip
+
+def _two_sided_materials():
+    lo = workloads.SLOWER
+    Bu = Layer(RHO, CP, CS)
+    Bl = Layer(lo["mu"] / lo["cs"] ** 2, lo["cp"], lo["cs"])
+    return Bu, Bl, Plane(1, MU, CS, CP), Plane(-1, lo["mu"], lo["cs"], lo["cp"])
+
+
+def test_two_sided_strip_with_equal_sides_is_the_symmetric_strip():
+    """Equal materials and widths on both sides: the split-node scheme must
+    reproduce the one-sided scheme that models the fault as a symmetry plane."""
+    from oracle.hybrid import TwoSidedConfig
+    wl = workloads.FAULTS["tpv3_coarse16"]
+    Bu = Layer(RHO, CP, CS)
+    a = hybrid.hybrid_rupture(_strip_for(wl, 2), *wl.params(), wl.steps)
+    b = hybrid.hybrid_rupture_two_sided(
+        TwoSidedConfig(wl.n1, wl.n3, wl.dx, wl.dt, [Bu] * 2, [Bu] * 2, Plane(1, MU, CS, CP),
+                       Plane(-1, MU, CS, CP), window_cap=wl.steps), *wl.params(), wl.steps)
+    for k in ("traction", "slip_rate", "slip"):
+        assert np.abs(a[k] - b[k]).max() < 1e-12 * np.abs(a[k]).max(), k
+    np.testing.assert_array_equal(a["sliding"], b["sliding"])
+    assert np.abs(b["normal_jump"]).max() < 1e-12
+
+
+def test_two_sided_uniform_bimaterial_fault_reaches_plane_wave_slip_rate():
+    """k = 0 between two materials: each side radiates its own plane shear wave,
+    V = (tau0 - tau_k)(c_s+/mu+ + c_s-/mu-), and the normal traction stays put."""
+    from oracle.hybrid import TwoSidedConfig
+    Bu, Bl, Pu, Pl = _two_sided_materials()
+    n, h = 4, 375.0
+    cfg = TwoSidedConfig(n, n, h, 0.25 * h / CS, [Bu] * 2, [Bl] * 2, Pu, Pl, window_cap=4)
+    tau0, mus, muk, dc = _uniform(n, 80e6, 0.6, 0.6)
+    out = hybrid.hybrid_rupture_two_sided(cfg, tau0, mus, muk, dc, 500)
+    expect = (80e6 - 0.6 * 120e6) * (CS / MU + Pl.cs / Pl.mu)
+    assert np.abs(out["slip_rate"][-50:, 0] / expect - 1).max() < 2e-3
+    np.testing.assert_allclose(out["traction"][:, 1], -120e6, rtol=1e-9)
+
+
+def test_two_sided_hybrid_converges_to_bimaterial_boundary_integral_rupture():
+    """Different materials across the fault (the lower one slower): with mesh
+    refinement the hybrid rupture approaches the stand-alone two-plane rupture, and
+    the fault never opens (equal normal velocities of the two copies)."""
+    from oracle.hybrid import TwoSidedConfig
+    Bu, Bl, Pu, Pl = _two_sided_materials()
+    errs = []
+    for n in (16, 32):
+        dx = 12000.0 / n
+        wl = workloads.FaultWorkload(f"bimat{n}", n, n, dx, int(round(72 * 750 / dx)),
+                                     region=(9000.0, 9000.0), lower=workloads.SLOWER)
+        prm = wl.params()
+        ref = fault.rupture(Config.from_dict(dict(wl.config_dict(), input_kind="absolute")),
+                            fault.FaultParams(*prm), wl.steps)
+        hyb = hybrid.hybrid_rupture_two_sided(
+            TwoSidedConfig(n, n, dx, wl.dt, [Bu] * 2, [Bl] * 2, Pu, Pl, window_cap=wl.steps),
+            *prm, wl.steps)
+        errs.append(np.linalg.norm(hyb["slip"][-1] - ref["slip"][-1]) / np.linalg.norm(ref["slip"][-1]))
+        v = np.abs(hyb["slip_rate"]).max()
+        assert np.abs(hyb["normal_jump"]).max() < 1e-9 * v
+        assert np.ptp(hyb["traction"][:, 1]) > 1e6          # the bimaterial normal-stress change
+    assert errs[1] < 0.5 * errs[0] and errs[1] < 0.15, errs
