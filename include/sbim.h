@@ -358,9 +358,26 @@ int sbim_fault_destroy(sbim_fault *f);
  *      mu(|slip|) (Eq. slipweak); tau = tau~ if |tau~| <= S, else
  *      S tau~/|tau~| (Eq. stickslip); the fault adds -h^2 (tau - tau0);
  *   4. a_{t+1} = r / M, v_{t+1} = v_{t+1/2} + dt/2 a_{t+1} (Eqs. tintf, fecorr).
- * All strip arithmetic is float64; the S+ push has the handle's precision.
+ *
+ * Two-sided strip (layers_below > 0; the handle has two planes, sides +1 and
+ * -1 in that order): elements on both sides of a split-node fault, each block
+ * closed by its own boundary relation (S+ above, S- below, whose tractions act
+ * on the S- nodes with outward normal -e2).  The fault nodes have an upper and
+ * a lower copy.  In step 3 the stick traction closes the jump of their next
+ * half-step velocities, tau~ = tau0 + (v*+ - v*-) / (dt h^2 (1/M+ + 1/M-))
+ * (Eqs. freeslip, sticktraction with two sides), its normal component is
+ * applied as it is (no opening), the shear pair is limited by
+ * S = max(-tau_2, 0) mu(|u+ - u-|) (Eqs. stickslip, slipweak), and the upper
+ * and lower copies receive -h^2 (tau - tau0) and +h^2 (tau - tau0).  Slip and
+ * slip rate are then the upper minus the lower copy.
+ *
+ * All strip arithmetic is float64; the S+/S- push has the handle's precision.
  * Fault fields are device [rows][n1][n3] doubles; node fields
- * [3][layers+1][n1][n3].  Ownership rules as for sbim_fault.  The scheme is
+ * [3][L][n1][n3] over the storage node layers: L = layers + 1 one-sided
+ * (0 = fault, layers = S+); two-sided L = layers_below + layers + 2, layers
+ * 0 .. layers_below the lower block (0 = S-, layers_below = lower fault
+ * copy), then the upper block from its fault copy to S+.  Ownership rules as
+ * for sbim_fault.  The scheme is
  * explicit: dt must satisfy the elements' CFL limit (the highest frequency of
  * the lumped-mass hexahedra is 2 c_p / h, so c_p dt / h < 1).
  */
@@ -371,19 +388,23 @@ typedef struct {
   const double *rho;    /* host [layers]: density of each element layer (fault side first) */
   const double *cp;     /* host [layers]: pressure wave speed, > cs sqrt(4/3) */
   const double *cs;     /* host [layers]: shear wave speed, > 0 */
+  int layers_below;     /* element layers between the fault and S-, 0 (one-sided) .. 4096 */
+  const double *rho_below;  /* host [layers_below], fault side first; NULL when one-sided */
+  const double *cp_below;
+  const double *cs_below;
 } sbim_strip_config;
 
 /* fields of sbim_strip_read */
 #define SBIM_STRIP_TRACTION 0     /* [3][n1][n3] fault traction of the last step */
-#define SBIM_STRIP_SLIP_RATE 1    /* [2][n1][n3] 2 v_{t+1} of the fault nodes (x1, x3) */
-#define SBIM_STRIP_SLIP 2         /* [2][n1][n3] 2 u_{t+1} of the fault nodes */
+#define SBIM_STRIP_SLIP_RATE 1    /* [2][n1][n3] slip rate v_{t+1} jump (x1, x3): 2 v one-sided */
+#define SBIM_STRIP_SLIP 2         /* [2][n1][n3] slip u_{t+1} jump: 2 u one-sided */
 #define SBIM_STRIP_SLIDING 3      /* [n1][n3] 1 where the slip branch was taken, else 0 */
-#define SBIM_STRIP_DISPLACEMENT 4 /* [3][layers+1][n1][n3] */
-#define SBIM_STRIP_VELOCITY 5     /* [3][layers+1][n1][n3] */
+#define SBIM_STRIP_DISPLACEMENT 4 /* [3][L][n1][n3], L storage node layers */
+#define SBIM_STRIP_VELOCITY 5     /* [3][L][n1][n3] */
 
 /*
- * sbim_strip_create: a strip on handle h (one plane of side +1, dx1 == dx3,
- * at step 0) with the fault parameters of sbim_fault_params (copied and
+ * sbim_strip_create: a strip on handle h (one plane of side +1, or planes of
+ * sides +1, -1 when layers_below > 0; dx1 == dx3; at step 0) with the fault parameters of sbim_fault_params (copied and
  * checked on the device; synchronises the stream).
  */
 int sbim_strip_create(sbim_handle *h, const sbim_strip_config *cfg, const sbim_fault_params *prm,

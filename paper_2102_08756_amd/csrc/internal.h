@@ -194,24 +194,32 @@ hipError_t launch_fault_step(bool fp64, bool mirror, const FaultArgs &a, hipStre
 hipError_t launch_fault_check(const double *tau0, const double *mu_s, const double *mu_k,
                               const double *d_c, long long cells, long long *bad, hipStream_t st);
 // strip.hip: finite-element strip of the hybrid scheme.  Node fields are
-// float64 [3][n2+1][n1][n3]; cell fields [rows][n1][n3].
+// float64 [3][n2+1][n1][n3] over the storage node layers; cell fields
+// [rows][n1][n3].  One-sided (the fault a symmetry plane): layer 0 is the
+// fault, layer n2 is S+.  Two-sided: layers 0..fault_lo are the block below the
+// fault (0 = S-, fault_lo = the lower copy of the split fault nodes), layers
+// fault_hi = fault_lo + 1 .. n2 the block above it (n2 = S+).
 struct StripArgs {
   double *u, *v, *a;          // displacement, velocity (half-step between the kernels), acceleration
   const double *stencil;      // [n2+1][27][3][3]: stiffness block of each neighbour offset
                               // (o1, o2, o3), index (o1+1) + 3 (o2+1) + 9 (o3+1)
   const double *mass;         // [n2+1] lumped mass of a node of each layer
-  const void *tau_sbi;        // [3][cells] working precision: traction of the half-space above S+
-  void *push_u, *push_v;      // [3][cells] working precision: S+ displacement (or increment), velocity
+  const void *tau_sbi;        // [P][3][cells] working precision: tractions at S+ (and S-)
+  void *push_u, *push_v;      // [P][3][cells] working precision: S+ (and S-) displacement
+                              // (or increment) and predicted velocity
+  double *r_fault;            // two-sided: [2][3][cells] forces on the upper, lower fault copy
   const double *tau0, *mu_s, *mu_k, *d_c;
   double *tau, *rate, *slip, *sliding;   // fault outputs [3], [2], [2], [1] x cells
   double *tau_out, *rate_out;            // optional caller copies
   long long nodes, cells;
   int n1, n3, n2;
+  int fault_lo;               // two-sided: storage layer of the lower fault copy; -1 one-sided
   double dt, area;
   int increment;
 };
 hipError_t launch_strip_predict(bool fp64, const StripArgs &a, hipStream_t st);
 hipError_t launch_strip_correct(bool fp64, const StripArgs &a, hipStream_t st);
+hipError_t launch_strip_fault2(const StripArgs &a, hipStream_t st);
 hipError_t launch_tabulate(bool fp64, const Group &g, double dt, const double *gl_x,
                            const double *gl_w, hipStream_t st);
 

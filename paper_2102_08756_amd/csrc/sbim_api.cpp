@@ -1088,14 +1088,16 @@ int sbim_fault_destroy(sbim_fault *f) {
 // each) and fault outputs [8][cells] (traction 3, slip rate 2, slip 2, sliding 1).
 struct sbim_strip {
   sbim_handle *h = nullptr;
-  int n2 = 0;
+  int n2 = 0;                 // index of the top storage node layer (S+)
+  int fault_lo = -1;          // two-sided: storage layer of the lower fault copy
   long long cells = 0, nodes = 0;
   double *node = nullptr;     // u, v, a
   double *cell = nullptr;     // fault outputs
   double *prm = nullptr;      // tau0 (3), mu_s, mu_k, d_c
   double *stencil = nullptr;  // [n2+1][27][9]
   double *mass = nullptr;     // [n2+1]
-  void *push_u = nullptr, *push_v = nullptr, *tau_sbi = nullptr;  // [3][cells] working precision
+  void *push_u = nullptr, *push_v = nullptr, *tau_sbi = nullptr;  // [P][3][cells] working precision
+  double *r_fault = nullptr;  // two-sided: [2][3][cells]
   long long *bad = nullptr;
   long long steps = 0;
 };
@@ -1160,7 +1162,7 @@ void free_strip(sbim_strip *s) {
   if (!s) return;
   if (s->h) (void)hipStreamSynchronize(s->h->stream);
   void *ptrs[] = {s->node, s->cell, s->prm, s->stencil, s->mass, s->push_u, s->push_v,
-                  s->tau_sbi, s->bad};
+                  s->tau_sbi, s->r_fault, s->bad};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   delete s;
@@ -1190,38 +1192,62 @@ int sbim_strip_create(sbim_handle *h, const sbim_strip_config *sc, const sbim_fa
   if (!prm || !prm->tau0 || !prm->mu_s || !prm->mu_k || !prm->d_c)
     return fail(h, SBIM_E_INVALID, "fault parameters: a pointer is NULL");
   const sbim_config &c = h->cfg;
-  if (c.nplanes != 1 || c.plane[0].side != 1)
+  const int La = sc->layers, Lb = sc->layers_below;
+  if (Lb == 0 && (c.nplanes != 1 || c.plane[0].side != 1))
     return fail(h, SBIM_E_INVALID, "a strip needs a handle with one plane of side +1 (S+)");
+  if (Lb > 0 && (c.nplanes != 2 || c.plane[0].side != 1 || c.plane[1].side != -1))
+    return fail(h, SBIM_E_INVALID,
+                "a two-sided strip needs a handle with planes of sides +1 (S+) and -1 (S-)");
   if (c.dx1 != c.dx3)
     return fail(h, SBIM_E_INVALID, "strip elements are cubes: dx1 must equal dx3");
-  if (sc->layers < 1 || sc->layers > 4096)
-    return fail(h, SBIM_E_INVALID, "strip layers must be in [1, 4096], got %d", sc->layers);
-  for (int l = 0; l < sc->layers; ++l) {
-    const double r = sc->rho[l], p = sc->cp[l], q = sc->cs[l];
-    if (!(r > 0 && q > 0 && p > q * std::sqrt(4.0 / 3.0)) || !std::isfinite(r) ||
-        !std::isfinite(p))
-      return fail(h, SBIM_E_INVALID,
-                  "strip layer %d: need rho > 0, cs > 0, cp > cs sqrt(4/3) (got %g, %g, %g)", l,
-                  r, p, q);
+  if (La < 1 || La > 4096 || Lb < 0 || Lb > 4096)
+    return fail(h, SBIM_E_INVALID, "strip layers must be in [1, 4096] above and [0, 4096] below, "
+                "got %d and %d", La, Lb);
+  if (Lb > 0 && (!sc->rho_below || !sc->cp_below || !sc->cs_below))
+    return fail(h, SBIM_E_INVALID, "strip configuration: a pointer of the lower side is NULL");
+  for (int side = 0; side < 2; ++side) {
+    const int L = side ? Lb : La;
+    const double *R = side ? sc->rho_below : sc->rho, *P = side ? sc->cp_below : sc->cp,
+                 *Q = side ? sc->cs_below : sc->cs;
+    for (int l = 0; l < L; ++l) {
+      const double r = R[l], p = P[l], q = Q[l];
+      if (!(r > 0 && q > 0 && p > q * std::sqrt(4.0 / 3.0)) || !std::isfinite(r) ||
+          !std::isfinite(p))
+        return fail(h, SBIM_E_INVALID,
+                    "strip layer %d%s: need rho > 0, cs > 0, cp > cs sqrt(4/3) (got %g, %g, %g)",
+                    l, side ? " below the fault" : "", r, p, q);
+    }
   }
   if (h->step != 0) return fail(h, SBIM_E_STATE, "a strip starts from a handle at step 0");
   sbim_strip *s = new (std::nothrow) sbim_strip;
   if (!s) return fail(h, SBIM_E_OOM, "host allocation failed");
   s->h = h;
-  s->n2 = sc->layers;
+  // storage node layers: [0, Lb] the block below the fault (S- first; empty when
+  // one-sided), then the block above it from the fault to S+
+  const int base = Lb > 0 ? Lb + 1 : 0;
+  s->fault_lo = Lb > 0 ? Lb : -1;
+  s->n2 = base + La;
   s->cells = static_cast<long long>(h->n1) * h->n3;
   s->nodes = (s->n2 + 1LL) * s->cells;
   const double hx = c.dx1;
-  // stencil and lumped mass per node layer
+  // element layers in storage order: (first storage node layer, material)
+  struct ELayer { int j0; double rho, cp, cs; };
+  std::vector<ELayer> el;
+  for (int l = 0; l < Lb; ++l) {      // listed from the fault outwards: storage bottom-up
+    const int k = Lb - 1 - l;
+    el.push_back({l, sc->rho_below[k], sc->cp_below[k], sc->cs_below[k]});
+  }
+  for (int l = 0; l < La; ++l) el.push_back({base + l, sc->rho[l], sc->cp[l], sc->cs[l]});
+  // stencil and lumped mass per node layer (no element crosses the split fault)
   std::vector<double> st(static_cast<size_t>(s->n2 + 1) * 27 * 9, 0.0), ms(s->n2 + 1, 0.0);
   std::vector<double> K;
-  for (int l = 0; l < s->n2; ++l) {
-    const double rho = sc->rho[l];
-    const double mu = rho * sc->cs[l] * sc->cs[l];
-    const double lam = rho * sc->cp[l] * sc->cp[l] - 2.0 * mu;
+  for (const ELayer &E : el) {
+    const double rho = E.rho;
+    const double mu = rho * E.cs * E.cs;
+    const double lam = rho * E.cp * E.cp - 2.0 * mu;
     cube_stiffness(hx, lam, mu, K);
     for (int a2 = 0; a2 < 2; ++a2) {
-      const int j = l + a2;                // node layer of the element's corners with this a2
+      const int j = E.j0 + a2;             // node layer of the element's corners with this a2
       ms[j] += 4.0 * rho * hx * hx * hx / 8.0;
       for (int a1 = 0; a1 < 2; ++a1)
         for (int a3 = 0; a3 < 2; ++a3) {
@@ -1237,9 +1263,10 @@ int sbim_strip_create(sbim_handle *h, const sbim_strip_config *sc, const sbim_fa
     }
   }
   const size_t n = static_cast<size_t>(s->cells);
-  const size_t fb = 3 * n * h->rsize;
+  const size_t fb = static_cast<size_t>(c.nplanes) * 3 * n * h->rsize;
   hipError_t e;
   if ((e = dev_alloc(&s->node, 9 * static_cast<size_t>(s->nodes))) != hipSuccess ||
+      (Lb > 0 && (e = dev_alloc(&s->r_fault, 6 * n)) != hipSuccess) ||
       (e = dev_alloc(&s->cell, kCellRows * n)) != hipSuccess ||
       (e = dev_alloc(&s->prm, 6 * n)) != hipSuccess ||
       (e = dev_alloc(&s->stencil, st.size())) != hipSuccess ||
@@ -1316,6 +1343,8 @@ int sbim_strip_step(sbim_strip *s, double *tau_out, double *rate_out) {
   a.n1 = h->n1;
   a.n3 = h->n3;
   a.n2 = s->n2;
+  a.fault_lo = s->fault_lo;
+  a.r_fault = s->r_fault;
   a.dt = h->cfg.dt;
   a.area = h->cfg.dx1 * h->cfg.dx3;
   a.increment = h->cfg.input_kind == SBIM_INCREMENT;
@@ -1324,9 +1353,13 @@ int sbim_strip_step(sbim_strip *s, double *tau_out, double *rate_out) {
   int rc = push_fields(h, s->push_u, s->push_v, sbim::VEL_INPUT);
   if (rc) return rc;
   e = fft_inverse(h, h->out_spec, h->spec, s->tau_sbi, nullptr);
-  if (e != hipSuccess) return hip_fail(h, e, "inverse FFT of the S+ tractions");
+  if (e != hipSuccess) return hip_fail(h, e, "inverse FFT of the S+ (and S-) tractions");
   e = sbim::launch_strip_correct(h->fp64, a, h->stream);
   if (e != hipSuccess) return hip_fail(h, e, "strip corrector");
+  if (s->fault_lo >= 0) {
+    e = sbim::launch_strip_fault2(a, h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "strip fault nodes");
+  }
   s->steps += 1;
   return SBIM_OK;
 }

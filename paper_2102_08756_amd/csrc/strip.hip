@@ -45,10 +45,14 @@ __global__ __launch_bounds__(kStripThreads) void strip_predict_kernel(StripArgs 
     const double un = a.u[k] + dt * vh;
     a.u[k] = un;
     a.v[k] = vh;                                  // the half-step velocity until the corrector
-    if (id >= top0) {
+    if (id >= top0) {                             // S+: plane 0 of the push
       const long long t = c * cells + (id - top0);
       pu[t] = static_cast<R>(a.increment ? dt * vh : un);
       pv[t] = static_cast<R>(v + dt * acc);      // predicted velocity of Eq. fepred
+    } else if (a.fault_lo >= 0 && id < cells) {   // S- (two-sided): plane 1
+      const long long t = (3 + c) * cells + id;
+      pu[t] = static_cast<R>(a.increment ? dt * vh : un);
+      pv[t] = static_cast<R>(v + dt * acc);
     }
   }
 }
@@ -60,14 +64,26 @@ __device__ __forceinline__ void strip_finish(const StripArgs &a, int layer, long
                                              long long cell, double r[3]) {
   const long long nodes = a.nodes, cells = a.cells;
   const double A = a.area;
+  const R *__restrict__ ts = static_cast<const R *>(a.tau_sbi);
   if (layer == a.n2) {                           // S+: traction of the half-space above
-    const R *__restrict__ ts = static_cast<const R *>(a.tau_sbi);
 #pragma unroll
     for (int p = 0; p < 3; ++p) r[p] += A * static_cast<double>(ts[p * cells + cell]);
   }
+  const bool two = a.fault_lo >= 0;
+  if (two && layer == 0) {                       // S-: outward normal -e2
+#pragma unroll
+    for (int p = 0; p < 3; ++p) r[p] -= A * static_cast<double>(ts[(3 + p) * cells + cell]);
+  }
+  if (two && (layer == a.fault_lo || layer == a.fault_lo + 1)) {
+    // split fault nodes: the two copies are solved together by strip_fault2
+    const int side = layer == a.fault_lo ? 1 : 0;
+#pragma unroll
+    for (int p = 0; p < 3; ++p) a.r_fault[(side * 3 + p) * cells + cell] = r[p];
+    return;
+  }
   const double M = a.mass[layer];
   const double dt = a.dt;
-  if (layer == 0) {                              // fault node: stick traction and strength
+  if (!two && layer == 0) {                      // fault node: stick traction and strength
     const double t00 = a.tau0[cell], t01 = a.tau0[cells + cell], t02 = a.tau0[2 * cells + cell];
     const double vs0 = a.v[id] + dt * r[0] / M;
     const double vs2 = a.v[2 * nodes + id] + dt * r[2] / M;
@@ -109,7 +125,7 @@ __device__ __forceinline__ void strip_finish(const StripArgs &a, int layer, long
     a.a[k] = acc;
     a.v[k] = vn[p];
   }
-  if (layer == 0) {
+  if (!two && layer == 0) {
     a.rate[cell] = 2.0 * vn[0];
     a.rate[cells + cell] = 2.0 * vn[2];
     if (a.rate_out) {
@@ -186,7 +202,79 @@ __global__ __launch_bounds__(kStripThreads) void strip_correct_kernel(StripArgs 
   }
 }
 
+// Split fault nodes (two-sided strip), one thread per cell: the traction change
+// that closes the jump of the next half-step velocities of the two copies
+// (Eqs. freeslip, sticktraction), applied in full to the normal component (no
+// opening) and limited on the shear pair by the slip-weakening strength at the
+// current normal traction (Eqs. stickslip, slipweak); then both copies' corrector.
+__global__ __launch_bounds__(kStripThreads) void strip_fault2_kernel(StripArgs a) {
+  const long long cell = static_cast<long long>(blockIdx.x) * kStripThreads + threadIdx.x;
+  const long long cells = a.cells, nodes = a.nodes;
+  if (cell >= cells) return;
+  const long long im = static_cast<long long>(a.fault_lo) * cells + cell;   // lower copy
+  const long long ip = im + cells;                                          // upper copy
+  const double Mm = a.mass[a.fault_lo], Mp = a.mass[a.fault_lo + 1];
+  const double dt = a.dt, A = a.area;
+  double rp[3], rm[3], t0[3], stick[3];
+#pragma unroll
+  for (int p = 0; p < 3; ++p) {
+    rp[p] = a.r_fault[p * cells + cell];
+    rm[p] = a.r_fault[(3 + p) * cells + cell];
+    t0[p] = a.tau0[p * cells + cell];
+  }
+  const double zinv = dt * A * (1.0 / Mp + 1.0 / Mm);
+#pragma unroll
+  for (int p = 0; p < 3; ++p) {
+    const double vsp = a.v[p * nodes + ip] + dt * rp[p] / Mp;
+    const double vsm = a.v[p * nodes + im] + dt * rm[p] / Mm;
+    stick[p] = t0[p] + (vsp - vsm) / zinv;
+  }
+  double tau[3] = {stick[0], stick[1], stick[2]};
+  const double mag = sqrt(stick[0] * stick[0] + stick[2] * stick[2]);
+  const double s0 = a.u[ip] - a.u[im], s2 = a.u[2 * nodes + ip] - a.u[2 * nodes + im];
+  const double delta = sqrt(s0 * s0 + s2 * s2);
+  const double mus = a.mu_s[cell], muk = a.mu_k[cell], dc = a.d_c[cell];
+  const double mu = delta < dc ? mus - (mus - muk) * delta / dc : muk;
+  const double strength = fmax(-tau[1], 0.0) * mu;
+  const bool sliding = mag > strength;
+  if (sliding) {
+    const double sc = strength / mag;
+    tau[0] = stick[0] * sc;
+    tau[2] = stick[2] * sc;
+  }
+  double vp[3], vm[3];
+#pragma unroll
+  for (int p = 0; p < 3; ++p) {
+    const double dtau = A * (tau[p] - t0[p]);
+    const double ap = (rp[p] - dtau) / Mp;
+    const double am = (rm[p] + dtau) / Mm;
+    vp[p] = a.v[p * nodes + ip] + 0.5 * dt * ap;
+    vm[p] = a.v[p * nodes + im] + 0.5 * dt * am;
+    a.a[p * nodes + ip] = ap;
+    a.a[p * nodes + im] = am;
+    a.v[p * nodes + ip] = vp[p];
+    a.v[p * nodes + im] = vm[p];
+    a.tau[p * cells + cell] = tau[p];
+    if (a.tau_out) a.tau_out[p * cells + cell] = tau[p];
+  }
+  a.slip[cell] = s0;
+  a.slip[cells + cell] = s2;
+  a.sliding[cell] = sliding ? 1.0 : 0.0;
+  a.rate[cell] = vp[0] - vm[0];
+  a.rate[cells + cell] = vp[2] - vm[2];
+  if (a.rate_out) {
+    a.rate_out[cell] = vp[0] - vm[0];
+    a.rate_out[cells + cell] = vp[2] - vm[2];
+  }
+}
+
 }  // namespace
+
+hipError_t launch_strip_fault2(const StripArgs &a, hipStream_t st) {
+  const unsigned blocks = static_cast<unsigned>((a.cells + kStripThreads - 1) / kStripThreads);
+  strip_fault2_kernel<<<blocks, kStripThreads, 0, st>>>(a);
+  return hipGetLastError();
+}
 
 hipError_t launch_strip_predict(bool fp64, const StripArgs &a, hipStream_t st) {
   const unsigned blocks = static_cast<unsigned>((a.nodes + kStripThreads - 1) / kStripThreads);

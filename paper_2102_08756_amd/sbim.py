@@ -70,7 +70,10 @@ class _FaultParams(ctypes.Structure):
 
 class _StripConfig(ctypes.Structure):
     _fields_ = [("layers", ctypes.c_int), ("rho", ctypes.POINTER(ctypes.c_double)),
-                ("cp", ctypes.POINTER(ctypes.c_double)), ("cs", ctypes.POINTER(ctypes.c_double))]
+                ("cp", ctypes.POINTER(ctypes.c_double)), ("cs", ctypes.POINTER(ctypes.c_double)),
+                ("layers_below", ctypes.c_int), ("rho_below", ctypes.POINTER(ctypes.c_double)),
+                ("cp_below", ctypes.POINTER(ctypes.c_double)),
+                ("cs_below", ctypes.POINTER(ctypes.c_double))]
 
 
 _lib = None
@@ -400,21 +403,30 @@ class Fault:
 class Strip(Fault):
     """Hybrid scheme: a finite-element strip of ``layers`` (list of (rho, c_p, c_s),
     fault side first) on the fault, closed at S+ by the single plane of ``sbim``
-    (``sbim_strip_*``).  Fault parameters as for ``Fault``."""
+    (``sbim_strip_*``).  With ``layers_below`` (same form, fault side first) the
+    strip is two-sided: a split-node fault between two blocks, closed at S+ and
+    S- by the two planes (sides +1, -1) of ``sbim``.  Fault parameters as for
+    ``Fault``."""
 
-    def __init__(self, sbim: SBIM, layers, tau0, mu_s, mu_k, d_c):
+    def __init__(self, sbim: SBIM, layers, tau0, mu_s, mu_k, d_c, layers_below=None):
         self.sbim = sbim
         n1, n3 = sbim.cfg.n1, sbim.cfg.n3
         self.cells = (n1, n3)
-        self.n2 = len(layers)
+        below = list(layers_below or [])
+        self.n2 = len(layers) + (len(below) + 1 if below else 0)   # top storage node layer
         args = {"tau0": tau0, "mu_s": mu_s, "mu_k": mu_k, "d_c": d_c}
         shapes = {"tau0": (3, n1, n3), "mu_s": (n1, n3), "mu_k": (n1, n3), "d_c": (n1, n3)}
         for k, t in args.items():
             if (not isinstance(t, torch.Tensor) or t.device != sbim.device or t.dtype != torch.float64
                     or tuple(t.shape) != shapes[k] or not t.is_contiguous()):
                 raise ValueError(f"{k}: expected a contiguous float64 {shapes[k]} tensor on {sbim.device}")
-        arr = [(ctypes.c_double * max(self.n2, 1))(*[float(L[i]) for L in layers]) for i in range(3)]
-        sc = _StripConfig(self.n2, *(ctypes.cast(a, ctypes.POINTER(ctypes.c_double)) for a in arr))
+        def host(rows):
+            return [ctypes.cast((ctypes.c_double * max(len(rows), 1))(*[float(L[i]) for L in rows]),
+                                ctypes.POINTER(ctypes.c_double)) for i in range(3)]
+        self._host = (host(layers), host(below))          # kept alive until the call returns
+        nul = ctypes.POINTER(ctypes.c_double)()
+        sc = _StripConfig(len(layers), *self._host[0], len(below),
+                          *(self._host[1] if below else (nul, nul, nul)))
         p = _FaultParams(*(ctypes.c_void_p(args[k].data_ptr()) for k in ("tau0", "mu_s", "mu_k", "d_c")))
         sbim._sync_stream()
         f = ctypes.c_void_p()

@@ -254,3 +254,120 @@ def test_tpv3_hybrid_error_decreases_with_mesh_refinement():
     # least 1.6 times smaller
     assert errs[1] < errs[0] / 1.6 and errs[2] < errs[1] / 1.6
     assert errs[2] < 0.05
+
+
+# ------------------------------------------------------------ two-sided strip
+
+_LO = workloads.SLOWER
+BULK_LO = (_LO["mu"] / _LO["cs"] ** 2, _LO["cp"], _LO["cs"])       # the slower lower material
+TWO_CASES = {
+    # (workload, lower half-space, layers above, layers below), both lists from the fault out
+    "bimaterial32_2up_2down": (workloads.FAULTS["bimaterial32"], [BULK, BULK], [BULK_LO, BULK_LO]),
+    "rect32x16_3up_1down": (workloads.FaultWorkload("rect32x16_bimat", 32, 16, 375.0, 120,
+                                                    region=(9000.0, 4500.0), tau0_3=4.0e6,
+                                                    lower=_LO), [SLOW, BULK, BULK], [BULK_LO]),
+    "tiny8_1up_3down": (workloads.FaultWorkload("tiny8_bimat", 8, 8, 750.0, 40,
+                                                region=(4500.0, 4500.0), patch=1500.0, lower=_LO),
+                        [BULK], [BULK_LO, SLOW, BULK_LO]),
+}
+_REF2 = {}
+
+
+def oracle_two_sided(case):
+    if case not in _REF2:
+        wl, up_l, lo_l = TWO_CASES[case]
+        up, lo = wl.planes()
+        cfg = ohybrid.TwoSidedConfig(wl.n1, wl.n3, wl.dx, wl.dt, [Layer(*L) for L in up_l],
+                                     [Layer(*L) for L in lo_l],
+                                     OPlane(1, up["mu"], up["cs"], up["cp"]),
+                                     OPlane(-1, lo["mu"], lo["cs"], lo["cp"]), window_cap=wl.steps)
+        _REF2[case] = ohybrid.hybrid_rupture_two_sided(cfg, *wl.params(), wl.steps)
+    return _REF2[case]
+
+
+def gpu_two_sided(wl, up_l, lo_l, precision, kind, planes=None):
+    d = wl.config_dict() if planes is None else dict(wl.config_dict(), planes=planes)
+    sb = SBIM(Config.from_dict(d, precision=precision, input_kind=kind), device=DEV)
+    t = [torch.tensor(a, dtype=torch.float64, device=DEV).contiguous() for a in wl.params()]
+    s = Strip(sb, up_l, *t, layers_below=lo_l)
+    fl = len(lo_l)                                    # storage layer of the lower fault copy
+    out = {k: [] for k in ("traction", "slip_rate", "slip", "sliding", "normal_jump")}
+    for n in range(wl.steps):
+        s.step()
+        for k in ("traction", "slip_rate", "slip", "sliding"):
+            out[k].append(s.read(k))
+        v = s.read("velocity")
+        out["normal_jump"].append(v[1, fl + 1] - v[1, fl])
+    res = {k: torch.stack(v).cpu().numpy() for k, v in out.items()}
+    res["sliding"] = res["sliding"][:, 0] > 0.5
+    assert s.read("displacement").shape == (3, len(up_l) + len(lo_l) + 2, wl.n1, wl.n3)
+    s.close()
+    sb.close()
+    return res
+
+
+@pytest.mark.parametrize("kind", ["absolute", "increment"])
+@pytest.mark.parametrize("case", sorted(TWO_CASES))
+def test_two_sided_strip_fp64_matches_oracle(case, kind):
+    ref = oracle_two_sided(case)
+    got = gpu_two_sided(*TWO_CASES[case], "fp64", kind)
+    worst = {k: float(np.abs(got[k] - ref[k]).max() / max(np.abs(ref[k]).max(), 1e-300))
+             for k in ("traction", "slip_rate", "slip")}
+    vmax = np.abs(ref["slip_rate"]).max()
+    print(f"[strip2] {case} fp64 {kind}: " + ", ".join(f"{k} {v:.2e}" for k, v in worst.items())
+          + f"; max normal jump / max slip rate {np.abs(got['normal_jump']).max() / vmax:.1e}",
+          flush=True)
+    np.testing.assert_array_equal(got["sliding"], ref["sliding"])
+    assert ref["sliding"].any()
+    for key, w in worst.items():
+        assert w < 1e-9, (key, w)
+    assert np.abs(got["normal_jump"]).max() < 1e-9 * vmax     # the fault never opens
+    assert np.ptp(ref["traction"][:, 1]) > 1e5                # the normal traction does change
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp32_comp"])
+def test_two_sided_strip_fp32_forms_against_oracle(precision):
+    case = "bimaterial32_2up_2down"
+    ref = oracle_two_sided(case)
+    got = gpu_two_sided(*TWO_CASES[case], precision, "increment")
+    errs = {k: float(np.linalg.norm(got[k] - ref[k]) / np.linalg.norm(ref[k]))
+            for k in ("traction", "slip_rate", "slip")}
+    og, orf = onset(got["sliding"]), onset(ref["sliding"])
+    both = (og >= 0) & (orf >= 0)
+    print(f"[strip2] {case} {precision}: rel-L2 " + ", ".join(f"{k} {v:.2e}" for k, v in errs.items())
+          + f"; onset differs at {int((og != orf).sum())} cells", flush=True)
+    np.testing.assert_array_equal(og >= 0, orf >= 0)
+    assert np.abs(og - orf)[both].max() <= 1
+    for k, e in errs.items():
+        assert e < 1e-5, (k, e)
+
+
+def test_two_sided_strip_with_equal_sides_is_the_symmetric_strip():
+    """Same material and width on both sides of the split fault: the library's
+    two-sided strip reproduces its one-sided strip (the fault a symmetry plane)."""
+    wl = workloads.FAULTS["tpv3_coarse16"]
+    one = gpu_run("coarse16_two_layers", "fp64", "increment")
+    up = wl.upper()
+    two = gpu_two_sided(wl, [BULK, BULK], [BULK, BULK], "fp64", "increment",
+                        planes=[up, dict(up, side=-1)])
+    for k in ("traction", "slip_rate", "slip"):
+        w = float(np.abs(one[k] - two[k]).max() / np.abs(one[k]).max())
+        assert w < 1e-11, (k, w)
+    np.testing.assert_array_equal(one["sliding"], two["sliding"])
+    assert np.abs(two["normal_jump"]).max() < 1e-9 * np.abs(one["slip_rate"]).max()
+
+
+def test_two_sided_strip_errors():
+    wl = TWO_CASES["bimaterial32_2up_2down"][0]
+    args = [torch.tensor(a, dtype=torch.float64, device=DEV) for a in wl.params()]
+    up = wl.upper()
+    sb = SBIM(Config.from_dict(dict(wl.config_dict(), planes=[up])), device=DEV)
+    with pytest.raises(SBIMError, match="planes of sides"):
+        Strip(sb, [BULK], *args, layers_below=[BULK_LO])
+    sb.close()
+    sb = SBIM(Config.from_dict(wl.config_dict()), device=DEV)
+    with pytest.raises(SBIMError, match="one plane of side"):
+        Strip(sb, [BULK], *args)
+    with pytest.raises(SBIMError, match="strip layer 1 below the fault"):
+        Strip(sb, [BULK], *args, layers_below=[BULK_LO, (T["rho"], T["cs"], T["cs"])])
+    sb.close()
