@@ -261,7 +261,9 @@ def measure_rupture(fw, precision, device, warmup=20, window_mode=None):
 def measure_hybrid(fw, precision, device, layers=2, warmup=20):
     """The hybrid scheme on the same setup: a strip of ``layers`` element layers of the
     bulk material between the fault and S+ (two layers = the paper's strip width 4 dx
-    for the symmetric half), the whole run timed from rest."""
+    for the symmetric half), the whole run timed from rest.  A workload with its own
+    lower half-space gets the two-sided strip: ``layers`` element layers of the lower
+    material between the fault and S- as well."""
     import torch
     import workloads
     from paper_2102_08756_amd import SBIM, Config, Strip
@@ -270,7 +272,11 @@ def measure_hybrid(fw, precision, device, layers=2, warmup=20):
     t0 = time.time()
     sb = SBIM(cfg, device=device)
     prm = [torch.tensor(a, dtype=torch.float64, device=device).contiguous() for a in fw.params()]
-    st = Strip(sb, [(t["rho"], t["cp"], t["cs"])] * layers, *prm)
+    below = None
+    if fw.lower is not None:
+        lo = fw.lower
+        below = [(lo["mu"] / lo["cs"] ** 2, lo["cp"], lo["cs"])] * layers
+    st = Strip(sb, [(t["rho"], t["cp"], t["cs"])] * layers, *prm, layers_below=below)
     t_init = time.time() - t0
     for _ in range(warmup):
         st.step()
@@ -289,8 +295,8 @@ def measure_hybrid(fw, precision, device, layers=2, warmup=20):
     sb.close()
     del sb, st, prm
     torch.cuda.empty_cache()
-    nodes = (layers + 1) * fw.n1 * fw.n3
-    return {"layers": layers, "ms_per_step": 1e3 * elapsed / fw.steps,
+    nodes = (layers + 1) * (1 if below is None else 2) * fw.n1 * fw.n3
+    return {"layers": layers, "two_sided": below is not None, "ms_per_step": 1e3 * elapsed / fw.steps,
             "node_steps_per_s": nodes * fw.steps / elapsed,
             "step_kernel_ms_per_step": conv_ms / launches if launches else None,
             "init_s": t_init, "_slip": slip}
@@ -333,6 +339,23 @@ def rupture_leg(fw, forms, device):
     print(f"[bench] hybrid {fw.name} {p}: {hy['ms_per_step']:.3f} ms/step "
           f"({hy['layers']} element layers), final slip vs boundary integral "
           f"{hy['final_slip_rel_l2_vs_boundary_integral']:.2e}", file=sys.stderr, flush=True)
+    if fw.lower is None:
+        # the same rupture between two materials (the lower one slower): the stand-alone
+        # two-plane rupture and the two-sided strip, two element layers on each side
+        import dataclasses
+        import workloads
+        bf = dataclasses.replace(fw, name=f"{fw.name}_bimaterial", lower=workloads.SLOWER)
+        br = measure_rupture(bf, p, device)
+        br.pop("_slip")
+        bh = measure_hybrid(bf, p, device)
+        bhs = bh.pop("_slip")
+        out["bimaterial"] = {
+            "workload": bf.name, "lower_half_space": "0.64 mu, 0.8 c_s, 0.8 c_p of the upper",
+            "precision": p, "boundary_integral": {k: br[k] for k in (
+                "ms_per_step", "init_s", "region_slipped_frac", "max_slip_m")},
+            "hybrid_two_sided": dict(bh, max_slip_m=float(np.abs(bhs).max()))}
+        print(f"[bench] bimaterial {bf.name} {p}: boundary integral {br['ms_per_step']:.3f} ms/step, "
+              f"two-sided hybrid {bh['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
     return out
 
 
