@@ -158,17 +158,21 @@ __device__ __forceinline__ void sweep_span(R (&sums)[S][kSums], const typename W
   }
 }
 
-// The sweep launched with step n serves steps t0 = n+1 .. n+S.  Blocks of
-// phase t0 mod S read their history up to step n-1 once, U^{t0-i} for
-// i = 2 .. min(cap-1, t0), and form for each of those steps t0+s its sum over
-// that history:
-//   pending[(t0+s) mod (S+1)] = sum_{i>=2} w_{i+s} (x) U^{t0-i}   (lags i+s inside the window).
+// The sweep launched with step n serves steps t0 = n+1 .. n+D (depth D = S T).
+// Blocks of phase t0 mod D read their history up to step n-1 once, U^{t0-i}
+// for i = 2 .. min(cap-1, t0), and form for each of those steps t0+u its sum
+// over that history:
+//   pending[(t0+u) mod (D+1)] = sum_{i>=2} w_{i+u} (x) U^{t0-i}   (lags i+u inside the window).
 // It reads neither U^n nor the pending sum of step n, so it runs in the same
-// launch as the push and traction of step n (S+1 pending slots keep step n's
-// sum apart from the S being written).
-// Each history entry thus serves S steps.  The kernel rows i .. i+2S-2 that a
-// span of S entries needs are held in two register arrays used in turn, so
-// each row is loaded once and never moved.
+// launch as the push and traction of step n (D+1 pending slots keep step n's
+// sum apart from the D being written).
+// Each history entry thus serves D steps.  A lane holds the sums of S of
+// them (registers bound S); T lanes per mode and lag chunk take the D steps
+// in groups u = g S + s, g < T.  They load the same history entries in the
+// same instructions, so each entry is fetched from memory once for all D
+// steps.  The kernel rows i+gS .. i+gS+2S-2 that a span of S entries needs are
+// held in two register arrays used in turn, so each row is loaded once per
+// lane and never moved.
 //
 // Lag chunks are whole spans long, so chunks never overlap and no lane needs a
 // mask: chunks reach past the last entry by less than LG spans, and a lag
@@ -177,12 +181,13 @@ __device__ __forceinline__ void sweep_span(R (&sums)[S][kSums], const typename W
 // the concurrent push writes is lag 1 or cap+1, whose rows are unused or zero).
 //
 // Work item (one wavefront) = (block of the phase, plane, group of Q of the
-// block's 64 modes).  Its 64 lanes are Q modes x LG lag chunks (Q = 64 / LG):
-// lane l takes mode l mod Q of the group and chunk l / Q of the lags, so each
-// history load fetches LG segments of Q x 8 bytes (float32), one per chunk.
-// The chunks are then summed by a butterfly over lanes l ^ Q, l ^ 2Q, ...
-// (fixed order, so the result is bitwise reproducible).
-template <typename R, int S, bool COMP>
+// block's 64 modes).  Its 64 lanes are Q modes x T step groups x LG lag
+// chunks (Q = 64 / (T LG)): lane l takes mode l mod Q of the group, step
+// group (l / Q) mod T and chunk l / (Q T) of the lags, so each history load
+// fetches LG segments of Q x 8 bytes (float32), one per chunk.  The chunks
+// are then summed by a butterfly over lanes l ^ QT, l ^ 2QT, ... (fixed
+// order, so the result is bitwise reproducible).
+template <typename R, int S, int T, bool COMP>
 __device__ __forceinline__ void sweep_item(const SweepArgs &a, long long item) {
   using W = typename W4<R>::T;
   const cplx<R> *__restrict__ ring = static_cast<const cplx<R> *>(a.ring);
@@ -191,19 +196,22 @@ __device__ __forceinline__ void sweep_item(const SweepArgs &a, long long item) {
   const long long M = a.M, step = a.step;
   const int np = a.np;
   constexpr int LG = sweep_lag_groups<R, S, COMP>();
-  constexpr int Q = kLanes / LG;  // modes per item
+  constexpr int Q = kLanes / (LG * T);  // modes per item
+  constexpr int NQ = kLanes / Q;        // items per block and plane
+  constexpr int D = S * T;
   // Items of one block get ids congruent mod 8, so they run on one XCD and
   // share the block's kernel rows in its L2.
-  const int per_blk = LG * np;
+  const int per_blk = NQ * np;
   const long long kb = (item / (8LL * per_blk)) * 8 + (item & 7);
   if (kb >= a.nphase) return;
   const int r = static_cast<int>((item >> 3) % per_blk);
-  const int p = r / LG;
+  const int p = r / NQ;
   const long long t0 = step + 1;
-  const long long b = t0 % S + S * kb;
+  const long long b = t0 % D + D * kb;
   const int lane = threadIdx.x;
-  const int lg = lane / Q;
-  const int col = (r % LG) * Q + lane % Q;  // lane of the mode in its block
+  const int lg = lane / (Q * T);
+  const int u0 = (lane / Q) % T * S;        // first of the lane's S steps (t0 + u0 ..)
+  const int col = (r % NQ) * Q + lane % Q;  // lane of the mode in its block
   const long long sm = b * kLanes + col;
   const bool valid = sm < M;
   const int cap = a.blk_cap[b];
@@ -235,9 +243,9 @@ __device__ __forceinline__ void sweep_item(const SweepArgs &a, long long item) {
     // a mode without history (W = 0) reads the zero row after class 0's rows
     const W *rowp = wl > 0 ? table + a.cls_off[cl] : table + a.cls_off[0] + a.cls_w0;
     W ra[S], rb[S];
-    load_rows<R, S>(ra, rowp, i0, wl);
+    load_rows<R, S>(ra, rowp, i0 + u0, wl);
     for (int it = 0; it < per; it += 2 * S) {
-      const int i = i0 + it;
+      const int i = i0 + u0 + it;
       load_rows<R, S>(rb, rowp, i + S, wl);
       sweep_span<R, S, G>(sums, ra, rb, hp, x, cap, dstep, dwrap);
       if (it + S >= per) break;
@@ -261,11 +269,11 @@ __device__ __forceinline__ void sweep_item(const SweepArgs &a, long long item) {
   // sum the lag chunks of each mode; lanes of chunk 0 store
 #pragma unroll
   for (int s = 0; s < S; ++s) {
-    const long long slot = (t0 + s) % (S + 1);
+    const long long slot = (t0 + u0 + s) % (D + 1);
 #pragma unroll
     for (int k = 0; k < kSums; ++k) {
 #pragma unroll
-      for (int off = Q; off < kLanes; off <<= 1) acc[s][k].fold_lane(off);
+      for (int off = Q * T; off < kLanes; off <<= 1) acc[s][k].fold_lane(off);
       if (lg == 0 && valid)
         pending[((slot * np + p) * kSums + k) * M + sm] = acc[s][k].value();
     }
@@ -466,12 +474,12 @@ __device__ __forceinline__ void mode_step(const ModeArgs &a, int p, long long s)
 // turn it is, then one mode item per (64-mode block, plane).  The two kinds
 // share no data (see sweep_item), so the latency-bound push gathers and
 // traction scatters run beside the streaming sweep.
-template <typename R, int S, bool COMP>
+template <typename R, int S, int T, bool COMP>
 __global__ __launch_bounds__(kLanes) void step_kernel(SweepArgs sa, ModeArgs ma,
                                                       long long sweep_items, long long nblocks) {
   const long long item = blockIdx.x;
   if (item < sweep_items) {
-    sweep_item<R, S, COMP>(sa, item);
+    sweep_item<R, S, T, COMP>(sa, item);
     return;
   }
   const long long k = item - sweep_items;
@@ -596,18 +604,19 @@ __global__ __launch_bounds__(256) void tabulate_kernel(
   }
 }
 
-template <typename R, int S, bool COMP>
+template <typename R, int S, int T, bool COMP>
 hipError_t step_launch_s(const sbim_handle *h, const Group &g, const SweepArgs &sa0,
                          const ModeArgs &ma, hipEvent_t ev0, hipEvent_t ev1) {
+  constexpr int D = S * T;
   SweepArgs sa = sa0;
-  const int phase = static_cast<int>((sa.step + 1) % S);
-  sa.nphase = g.nblocks > phase ? (g.nblocks - phase + S - 1) / S : 0;
+  const int phase = static_cast<int>((sa.step + 1) % D);
+  sa.nphase = g.nblocks > phase ? (g.nblocks - phase + D - 1) / D : 0;
   const long long sweep_items =
-      (sa.nphase + 7) / 8 * 8 * sweep_lag_groups<R, S, COMP>() * g.np;
+      (sa.nphase + 7) / 8 * 8 * (sweep_lag_groups<R, S, COMP>() * T) * g.np;
   const long long items = sweep_items + g.nblocks * g.np;
   if (ev0) (void)hipEventRecord(ev0, h->stream);
-  hipLaunchKernelGGL((step_kernel<R, S, COMP>), dim3(static_cast<unsigned>(items)), dim3(kLanes),
-                     0, h->stream, sa, ma, sweep_items, g.nblocks);
+  hipLaunchKernelGGL((step_kernel<R, S, T, COMP>), dim3(static_cast<unsigned>(items)),
+                     dim3(kLanes), 0, h->stream, sa, ma, sweep_items, g.nblocks);
   if (ev1) (void)hipEventRecord(ev1, h->stream);
   return hipGetLastError();
 }
@@ -616,11 +625,13 @@ template <typename R, bool COMP>
 hipError_t step_launch_r(const sbim_handle *h, const Group &g, const SweepArgs &sa,
                          const ModeArgs &ma, hipEvent_t ev0, hipEvent_t ev1) {
   switch (h->depth) {
-    case 1: return step_launch_s<R, 1, COMP>(h, g, sa, ma, ev0, ev1);
-    case 2: return step_launch_s<R, 2, COMP>(h, g, sa, ma, ev0, ev1);
-    case 4: return step_launch_s<R, 4, COMP>(h, g, sa, ma, ev0, ev1);
-    case 6: return step_launch_s<R, 6, COMP>(h, g, sa, ma, ev0, ev1);
-    case 8: return step_launch_s<R, 8, COMP>(h, g, sa, ma, ev0, ev1);
+    case 1: return step_launch_s<R, 1, 1, COMP>(h, g, sa, ma, ev0, ev1);
+    case 2: return step_launch_s<R, 2, 1, COMP>(h, g, sa, ma, ev0, ev1);
+    case 4: return step_launch_s<R, 4, 1, COMP>(h, g, sa, ma, ev0, ev1);
+    case 6: return step_launch_s<R, 6, 1, COMP>(h, g, sa, ma, ev0, ev1);
+    case 8: return step_launch_s<R, 8, 1, COMP>(h, g, sa, ma, ev0, ev1);
+    case 12: return step_launch_s<R, 6, 2, COMP>(h, g, sa, ma, ev0, ev1);
+    case 16: return step_launch_s<R, 8, 2, COMP>(h, g, sa, ma, ev0, ev1);
     default: return hipErrorInvalidValue;
   }
 }

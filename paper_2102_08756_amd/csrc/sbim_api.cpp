@@ -166,6 +166,28 @@ int validate(const sbim_config *c) {
   return SBIM_OK;
 }
 
+// Mean history window over the half-spectrum's modes of a plane with shear
+// wave speed cs (the per-mode window rule of plan_group).
+double mean_window(const sbim_config &c, double cs) {
+  if (c.window_mode == SBIM_W_STATIC) return 1.0;
+  if (c.window_mode == SBIM_W_FIXED) return c.window_cap;
+  const int n1 = c.n1, h3 = c.n3 / 2 + 1;
+  const double two_pi = 2.0 * M_PI;
+  double sum = 0;
+  for (int i1 = 0; i1 < n1; ++i1) {
+    const int m1 = i1 < n1 / 2 ? i1 : i1 - n1;
+    const double k1 = (two_pi * m1) / (n1 * c.dx1);
+    for (int i3 = 0; i3 < h3; ++i3) {
+      const double k3 = (two_pi * i3) / (c.n3 * c.dx3);
+      const double q = std::sqrt(k1 * k1 + k3 * k3);
+      if (q > 0)
+        sum += std::min(static_cast<double>(c.window_cap),
+                        std::ceil((two_pi * c.eta_w) / (q * cs * c.dt)));
+    }
+  }
+  return sum / (static_cast<double>(n1) * h3);
+}
+
 // Mode geometry, windows, ordering and classes of one material group (host).
 void plan_group(const sbim_config &c, int depth, Group &g, std::vector<double> &geom,
                 std::vector<long long> &blk_off, std::vector<int> &blk_cap,
@@ -444,14 +466,22 @@ int sbim_init(const sbim_config *cfg, sbim_handle **out) {
     std::vector<int> blk_cap, blk_stride;
   };
   // Sweep depth: steps served by one pass over a block's history.  Deeper
-  // sweeps divide the history traffic but hold depth x 10 sums per lane in
-  // registers (measured best on gfx950, two planes 512x512, W = 1000: 8 for
-  // float32, 6 for float64 and for the compensated form, whose sums take two
-  // registers each).
-  h->depth = h->comp || h->fp64 ? 6 : 8;
-  if (const char *env = std::getenv("SBIM_SWEEP_DEPTH")) {  // tuning override: 1, 2, 4, 6 or 8
+  // sweeps divide the history traffic, but the newest lags of each step (up
+  // to depth + 1 of them) are summed by the mode items.  A lane holds the 10
+  // sums of up to 8 steps (float32) or 6 (float64 and the compensated form,
+  // whose sums take two registers each); depths 12 and 16 give each mode two
+  // lanes, one per half of the steps.  Measured on gfx950 (two planes,
+  // 512^2 at W = 1000, 1024^2 at W = 2000, 2048^2 with per-mode windows of
+  // mean 18 lags): with long windows float64 and the compensated form run
+  // fastest at 12, float32 at 8 (16 moves half the bytes in the same time);
+  // with mean windows under 64 lags every form runs fastest at 6.
+  double wbar = 0;
+  for (int p = 0; p < cfg->nplanes; ++p)
+    wbar = std::max(wbar, mean_window(*cfg, cfg->plane[p].cs));
+  h->depth = wbar < 64 ? 6 : (h->comp || h->fp64 ? 12 : 8);
+  if (const char *env = std::getenv("SBIM_SWEEP_DEPTH")) {  // tuning override
     const int v = std::atoi(env);
-    if (v == 1 || v == 2 || v == 4 || v == 6 || v == 8) h->depth = v;
+    if (v == 1 || v == 2 || v == 4 || v == 6 || v == 8 || v == 12 || v == 16) h->depth = v;
   }
   std::vector<HostPlan> plan(h->ngroups);
   size_t need = 0;

@@ -170,7 +170,7 @@ def sweep_refs():
 
 
 @pytest.mark.parametrize("case", sorted(SWEEP_CASES))
-@pytest.mark.parametrize("depth", [1, 2, 4, 6, 8])
+@pytest.mark.parametrize("depth", [1, 2, 4, 6, 8, 12, 16])
 @pytest.mark.parametrize("precision", ["fp64", "fp32_comp", "fp32"])
 def test_sweep_depths(sweep_refs, case, depth, precision, monkeypatch):
     monkeypatch.setenv("SBIM_SWEEP_DEPTH", str(depth))
@@ -188,14 +188,15 @@ def test_sweep_depths(sweep_refs, case, depth, precision, monkeypatch):
 def test_tractions_repeatable_and_snapshots_mid_rotation():
     """tractions() changes no state; a snapshot taken at a step that is not a
     multiple of the sweep depth restores the pending sums exactly."""
-    u = _inputs(SWEEP_CFG, 40, 8)[0]
     sb = SBIM(Config.from_dict(SWEEP_CFG, precision="fp32"), device=DEV)
     depth = sb.info()["sweep_depth"]
+    steps = 3 * depth + 20
+    u = _inputs(SWEEP_CFG, steps, 8)[0]
     ut = torch.tensor(u, dtype=torch.float32, device=DEV)
     snap = torch.empty(sb.state_bytes(), dtype=torch.uint8, device=DEV)
-    cut = 3 * depth + 3
+    cut = 2 * depth + 3
     first = []
-    for n in range(40):
+    for n in range(steps):
         sb.push(ut[n])
         a = sb.tractions().clone()
         b = sb.tractions().clone()
@@ -204,13 +205,13 @@ def test_tractions_repeatable_and_snapshots_mid_rotation():
         if n == cut:
             sb.save_state(snap)
     sb.load_state(snap)
-    for n in range(cut + 1, 40):
+    for n in range(cut + 1, steps):
         sb.push(ut[n])
         assert torch.equal(sb.tractions(), first[n]), n
     sb.close()
 
 
-@pytest.mark.parametrize("depth", [1, 2, 6, 8])
+@pytest.mark.parametrize("depth", [1, 2, 6, 8, 12, 16])
 @pytest.mark.parametrize("kind", ["absolute", "increment"])
 def test_adjoint_sweep_depths(depth, kind, monkeypatch):
     """The adjoint runs the same sweep on its own history: exact transpose at every depth."""
