@@ -251,14 +251,18 @@ __device__ __forceinline__ void sweep_item(const SweepArgs &a, long long item) {
       if (it + S >= per) break;
       load_rows<R, S>(ra, rowp, i + 2 * S, wl);
       sweep_span<R, S, G>(sums, rb, ra, hp, x, cap, dstep, dwrap);
+      // compensated form: fold the plain partial sums of the last 4S lags
+      // (every other pass of this loop; the branch is uniform over the wavefront)
       if constexpr (COMP) {
+        if ((it / (2 * S)) & 1) {
 #pragma unroll
-        for (int s = 0; s < S; ++s)
+          for (int s = 0; s < S; ++s)
 #pragma unroll
-          for (int k = 0; k < kSums; ++k) {
-            acc[s][k].fold(sums[s][k]);
-            sums[s][k] = R(0);
-          }
+            for (int k = 0; k < kSums; ++k) {
+              acc[s][k].fold(sums[s][k]);
+              sums[s][k] = R(0);
+            }
+        }
       }
     }
   }
@@ -475,8 +479,8 @@ __device__ __forceinline__ void mode_step(const ModeArgs &a, int p, long long s)
 // share no data (see sweep_item), so the latency-bound push gathers and
 // traction scatters run beside the streaming sweep.
 template <typename R, int S, int T, bool COMP>
-__global__ __launch_bounds__(kLanes) void step_kernel(SweepArgs sa, ModeArgs ma,
-                                                      long long sweep_items, long long nblocks) {
+__device__ __forceinline__ void step_items(const SweepArgs &sa, const ModeArgs &ma,
+                                           long long sweep_items, long long nblocks) {
   const long long item = blockIdx.x;
   if (item < sweep_items) {
     sweep_item<R, S, T, COMP>(sa, item);
@@ -486,6 +490,21 @@ __global__ __launch_bounds__(kLanes) void step_kernel(SweepArgs sa, ModeArgs ma,
   const int p = static_cast<int>(k / nblocks);
   const long long s = (k - p * nblocks) * kLanes + threadIdx.x;
   if (s < ma.M) mode_step<R, COMP>(ma, p, s);
+}
+
+template <typename R, int S, int T, bool COMP>
+__global__ __launch_bounds__(kLanes) void step_kernel(SweepArgs sa, ModeArgs ma,
+                                                      long long sweep_items, long long nblocks) {
+  step_items<R, S, T, COMP>(sa, ma, sweep_items, nblocks);
+}
+
+// The compensated sweep at up to 6 steps per lane, held to two wavefronts per
+// SIMD: left to itself the compiler takes the whole register file (one
+// wavefront) for a couple of registers that it then keeps in scratch instead.
+template <typename R, int S, int T, bool COMP>
+__global__ __launch_bounds__(kLanes) __attribute__((amdgpu_waves_per_eu(2))) void step_kernel_w2(
+    SweepArgs sa, ModeArgs ma, long long sweep_items, long long nblocks) {
+  step_items<R, S, T, COMP>(sa, ma, sweep_items, nblocks);
 }
 
 // -------------------------------------------------------------- tabulate
@@ -615,8 +634,12 @@ hipError_t step_launch_s(const sbim_handle *h, const Group &g, const SweepArgs &
       (sa.nphase + 7) / 8 * 8 * (sweep_lag_groups<R, S, COMP>() * T) * g.np;
   const long long items = sweep_items + g.nblocks * g.np;
   if (ev0) (void)hipEventRecord(ev0, h->stream);
-  hipLaunchKernelGGL((step_kernel<R, S, T, COMP>), dim3(static_cast<unsigned>(items)),
-                     dim3(kLanes), 0, h->stream, sa, ma, sweep_items, g.nblocks);
+  if constexpr (COMP && S <= 6)
+    hipLaunchKernelGGL((step_kernel_w2<R, S, T, COMP>), dim3(static_cast<unsigned>(items)),
+                       dim3(kLanes), 0, h->stream, sa, ma, sweep_items, g.nblocks);
+  else
+    hipLaunchKernelGGL((step_kernel<R, S, T, COMP>), dim3(static_cast<unsigned>(items)),
+                       dim3(kLanes), 0, h->stream, sa, ma, sweep_items, g.nblocks);
   if (ev1) (void)hipEventRecord(ev1, h->stream);
   return hipGetLastError();
 }
