@@ -486,7 +486,7 @@ def main():
                     help="only run a torch device copy of this many GiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "one GPU per process: the boundary relation and its fault and strip run on one device; --gpus must be 1"}))
         sys.exit(2)
     import torch
     import workloads
