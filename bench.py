@@ -152,6 +152,11 @@ def measure_form(wl, precision, steps, warmup, device, inputs_cache):
             "algorithmic_bytes_per_launch": conv_bytes / launches if launches else None,
             "avg_launch_ms": conv_ms / launches if launches else None,
             "launches": launches,
+            # the history bytes alone that a per-step (direct) convolution would stream for
+            # the same work in the same launch time: the sweep reads each entry once per
+            # sweep_depth steps, so `achieved` counts far fewer bytes than this
+            "direct_equivalent_GBs": lags * 6 * (8 if precision == "fp64" else 4)
+                                     / (conv_ms * 1e-3) / 1e9,
         },
         "info": info,
     }
