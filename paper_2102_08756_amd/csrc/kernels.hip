@@ -514,8 +514,23 @@ __global__ __launch_bounds__(kLanes) __attribute__((amdgpu_waves_per_eu(2))) voi
 // branch-cut densities D_ab (see the oracle-independent derivation in the
 // library notes): the substituted integrands are analytic.
 struct Node {
-  double y, g11, g12, g22, g33, ph_hi, ph_lo;
+  double y, g11, g12, g22, g33, ph_hi, ph_lo, c_step, s_step;
 };
+
+// Lags a thread of tabulate_kernel sums, kTabThreads apart.
+constexpr int kTabThreads = 256;
+constexpr int kTabLags = 8;
+
+// x - 2 pi k for the double-double x = hi + lo, reduced in two parts
+// (Cody-Waite): accurate to ~1e-16 absolute however many periods x spans.
+__device__ __forceinline__ double reduce_two_pi(double hi, double lo) {
+  const double two_pi_hi = 6.283185307179586;      // nearest double to 2 pi
+  const double two_pi_lo = 2.4492935982947064e-16;  // 2 pi - two_pi_hi
+  const double inv_two_pi = 0.15915494309189535;
+  const double k = rint(hi * inv_two_pi);
+  const double r = fma(-k, two_pi_hi, hi);  // exact
+  return fma(-k, two_pi_lo, r) + lo;
+}
 
 __device__ Node make_node(int i, int npan, double eta, double dT, const double *gl_x,
                           const double *gl_w) {
@@ -562,18 +577,22 @@ __device__ Node make_node(int i, int npan, double eta, double dT, const double *
   n.g33 = f * d33;
   n.ph_hi = y * dT;                    // y dT = ph_hi + ph_lo exactly
   n.ph_lo = fma(y, dT, -n.ph_hi);
+  // the phase step between the lags of one thread, kTabThreads y dT (exact scaling)
+  sincos(reduce_two_pi(kTabThreads * n.ph_hi, kTabThreads * n.ph_lo), &n.s_step, &n.c_step);
   return n;
 }
 
-// w_ab,j = sum_nodes g_ab cos or sin((j + 1/2) y dT).  The phase is formed as a
-// double-double and reduced by 2 pi in two parts (Cody-Waite), so it is
-// accurate to ~1e-16 absolute however many periods it spans.
+// w_ab,j = sum_nodes g_ab cos or sin((j + 1/2) y dT).  A thread takes lags
+// j, j + kTabThreads, ..., j + (kTabLags-1) kTabThreads.  For the first the
+// phase is formed as a double-double and reduced by 2 pi (reduce_two_pi) and
+// its sine and cosine evaluated; each next one is that pair rotated by the
+// node's phase step (at most kTabLags-1 rotations, a few ulps).
 template <typename R>
-__global__ __launch_bounds__(256) void tabulate_kernel(
+__global__ __launch_bounds__(kTabThreads) void tabulate_kernel(
     typename W4<R>::T *__restrict__ table, const long long *__restrict__ cls_off,
     const double *__restrict__ cls_q, const int *__restrict__ cls_w, double cs, double dt,
     double eta, double rate, const double *__restrict__ gl_x, const double *__restrict__ gl_w) {
-  __shared__ Node nodes[256];
+  __shared__ Node nodes[kTabThreads];
   const int c = blockIdx.x;
   const int W = cls_w[c];
   const double q = cls_q[c];
@@ -581,45 +600,55 @@ __global__ __launch_bounds__(256) void tabulate_kernel(
   const double tmax = dT * W * rate;
   const int npan = max(1, static_cast<int>(ceil(tmax / 40.0)));
   const int nnodes = 2 * npan * kGaussN;
-  const double two_pi_hi = 6.283185307179586;      // nearest double to 2 pi
-  const double two_pi_lo = 2.4492935982947064e-16;  // 2 pi - two_pi_hi
-  const double inv_two_pi = 0.15915494309189535;
-  for (int jb = 0; jb <= W; jb += 256) {  // j = W: the zero row
-    const int j = jb + threadIdx.x;
-    const double m = j + 0.5;
-    double w11 = 0, w12 = 0, w22 = 0, w33 = 0;
-    for (int nb = 0; nb < nnodes; nb += 256) {
+  constexpr int span = kTabThreads * kTabLags;
+  for (int jb = 0; jb <= W; jb += span) {  // j = W: the zero row
+    const int j0 = jb + threadIdx.x;
+    // lags of this thread inside the window
+    const int nl = j0 < W ? min(kTabLags, (W - 1 - j0) / kTabThreads + 1) : 0;
+    const double m = j0 + 0.5;
+    double w[kTabLags][4];
+#pragma unroll
+    for (int t = 0; t < kTabLags; ++t) w[t][0] = w[t][1] = w[t][2] = w[t][3] = 0.0;
+    for (int nb = 0; nb < nnodes; nb += kTabThreads) {
       __syncthreads();
       if (nb + threadIdx.x < nnodes)
         nodes[threadIdx.x] = make_node(nb + threadIdx.x, npan, eta, dT, gl_x, gl_w);
       __syncthreads();
-      const int cnt = min(256, nnodes - nb);
-      if (j < W) {
+      const int cnt = min(kTabThreads, nnodes - nb);
+      if (nl > 0) {
         for (int i = 0; i < cnt; ++i) {
           const Node &nd = nodes[i];
           const double p_hi = m * nd.ph_hi;
           const double p_lo = fma(m, nd.ph_lo, fma(m, nd.ph_hi, -p_hi));
-          const double k = rint(p_hi * inv_two_pi);
-          double r = fma(-k, two_pi_hi, p_hi);  // exact
-          r = fma(-k, two_pi_lo, r) + p_lo;
           double sn, cn;
-          sincos(r, &sn, &cn);
-          w11 = fma(nd.g11, cn, w11);
-          w12 = fma(nd.g12, sn, w12);
-          w22 = fma(nd.g22, cn, w22);
-          w33 = fma(nd.g33, cn, w33);
+          sincos(reduce_two_pi(p_hi, p_lo), &sn, &cn);
+#pragma unroll
+          for (int t = 0; t < kTabLags; ++t) {
+            if (t >= nl) break;
+            w[t][0] = fma(nd.g11, cn, w[t][0]);
+            w[t][1] = fma(nd.g12, sn, w[t][1]);
+            w[t][2] = fma(nd.g22, cn, w[t][2]);
+            w[t][3] = fma(nd.g33, cn, w[t][3]);
+            const double c2 = fma(cn, nd.c_step, -sn * nd.s_step);
+            sn = fma(sn, nd.c_step, cn * nd.s_step);
+            cn = c2;
+          }
         }
       }
     }
-    if (j < W) {
-      typename W4<R>::T o;
-      o.x = static_cast<R>(w11);
-      o.y = static_cast<R>(w12);
-      o.z = static_cast<R>(w22);
-      o.w = static_cast<R>(w33);
-      table[cls_off[c] + j] = o;
+#pragma unroll
+    for (int t = 0; t < kTabLags; ++t) {
+      const int j = j0 + t * kTabThreads;
+      if (t < nl) {
+        typename W4<R>::T o;
+        o.x = static_cast<R>(w[t][0]);
+        o.y = static_cast<R>(w[t][1]);
+        o.z = static_cast<R>(w[t][2]);
+        o.w = static_cast<R>(w[t][3]);
+        table[cls_off[c] + j] = o;
+      }
+      if (j == W) table[cls_off[c] + W] = typename W4<R>::T{R(0), R(0), R(0), R(0)};
     }
-    if (j == W) table[cls_off[c] + W] = typename W4<R>::T{R(0), R(0), R(0), R(0)};
   }
 }
 
@@ -716,11 +745,11 @@ hipError_t launch_tabulate(bool fp64, const Group &g, double dt, const double *g
   if (g.nclasses == 0) return hipSuccess;
   const double rate = fmax(1.0, (g.eta * g.eta - 1.0) / 2.0);
   if (fp64) {
-    hipLaunchKernelGGL(tabulate_kernel<double>, dim3(static_cast<unsigned>(g.nclasses)), dim3(256),
+    hipLaunchKernelGGL(tabulate_kernel<double>, dim3(static_cast<unsigned>(g.nclasses)), dim3(kTabThreads),
                        0, st, static_cast<double4 *>(g.table), g.cls_off, g.cls_q, g.cls_w, g.cs, dt,
                        g.eta, rate, gl_x, gl_w);
   } else {
-    hipLaunchKernelGGL(tabulate_kernel<float>, dim3(static_cast<unsigned>(g.nclasses)), dim3(256),
+    hipLaunchKernelGGL(tabulate_kernel<float>, dim3(static_cast<unsigned>(g.nclasses)), dim3(kTabThreads),
                        0, st, static_cast<float4 *>(g.table), g.cls_off, g.cls_q, g.cls_w, g.cs, dt,
                        g.eta, rate, gl_x, gl_w);
   }
