@@ -3,12 +3,15 @@
 // in x1 and x3 with the boundary-integral grid; explicit central differences in
 // the predictor-corrector form of Sec. 2.2 (Eqs. fepred, feintdisp, tintf,
 // fecorr); the traction of the half-space above S+ from the boundary relation
-// (Eq. SBI, Sec. 2.4 items 2-4); the fault as a symmetry plane with the stick
-// traction of the forward Lagrange multiplier (Eqs. freeslip, sticktraction)
-// limited by the slip-weakening strength (Eqs. stickslip, slipweak).
+// (Eq. SBI, Sec. 2.4 items 2-4); the fault either as a symmetry plane or, in
+// the two-sided strip, as split nodes between two element blocks, with the
+// stick traction of the forward Lagrange multiplier (Eqs. freeslip,
+// sticktraction) limited by the slip-weakening strength (Eqs. stickslip,
+// slipweak).
 //
 // Fields are float64 [component][node layer][x1][x3] (x3 fastest); one thread
-// per node in the predictor, per four nodes along x1 in the corrector.  The
+// per node in the predictor, per four nodes along x1 in each of three node
+// layers in the corrector, per fault cell for the split nodes.  The
 // stiffness is applied node by node as a 27-point stencil of 3x3 blocks, one
 // stencil per node layer (the element layers above and below it may differ),
 // precomputed on the host from the element stiffness.
@@ -26,6 +29,7 @@ namespace {
 
 constexpr int kStripThreads = 256;
 constexpr int kStripRows = 4;        // nodes along x1 per thread of the corrector (divides n1)
+constexpr int kStripLayers = 3;      // node layers per thread of the corrector
 
 template <typename R>
 __global__ __launch_bounds__(kStripThreads) void strip_predict_kernel(StripArgs a) {
@@ -135,35 +139,40 @@ __device__ __forceinline__ void strip_finish(const StripArgs &a, int layer, long
   }
 }
 
-// One thread per kStripRows consecutive nodes along x1 (same layer, same x3):
-// each neighbour row of u is loaded once and serves up to three of them.
-// UNIFORM: every wavefront lies in one node layer, so the layer's stencil is
-// read through the scalar cache once per wavefront.
+// One thread per kStripRows consecutive nodes along x1 (same x3) in each of
+// kStripLayers consecutive node layers: each row of u that the 27-point
+// stencils of those nodes need (node layers l0-1 .. l0+kStripLayers) is loaded
+// once and serves up to three of the thread's layers and three of its rows.
+// UNIFORM: every wavefront lies in one layer chunk, so the stencils are read
+// through the scalar cache once per wavefront.
 template <typename R, bool UNIFORM>
 __global__ __launch_bounds__(kStripThreads) void strip_correct_kernel(StripArgs a) {
   const long long nodes = a.nodes, cells = a.cells;
-  const int n1 = a.n1, n3 = a.n3;
+  const int n1 = a.n1, n3 = a.n3, n2 = a.n2;
   const long long tid = static_cast<long long>(blockIdx.x) * kStripThreads + threadIdx.x;
-  const long long per_layer = cells / kStripRows;
-  if (tid >= nodes / kStripRows) return;
-  const int layer = UNIFORM ? __builtin_amdgcn_readfirstlane(static_cast<int>(tid / per_layer))
-                            : static_cast<int>(tid / per_layer);
-  const long long g = tid - layer * per_layer;
+  const long long per_chunk = cells / kStripRows;
+  const int nchunks = (n2 + kStripLayers) / kStripLayers;
+  if (tid >= per_chunk * nchunks) return;
+  const int chunk = UNIFORM ? __builtin_amdgcn_readfirstlane(static_cast<int>(tid / per_chunk))
+                            : static_cast<int>(tid / per_chunk);
+  const int l0 = chunk * kStripLayers;
+  const long long g = tid - chunk * per_chunk;
   const int ib = static_cast<int>(g / n3);
   const int i3 = static_cast<int>(g - static_cast<long long>(ib) * n3);
   const int i10 = ib * kStripRows;
-  const double *__restrict__ C = a.stencil + static_cast<long long>(layer) * 27 * 9;
   const int col[3] = {i3 == 0 ? n3 - 1 : i3 - 1, i3, i3 == n3 - 1 ? 0 : i3 + 1};
 
-  double r[kStripRows][3];
+  double r[kStripLayers][kStripRows][3];
 #pragma unroll
-  for (int k = 0; k < kStripRows; ++k) r[k][0] = r[k][1] = r[k][2] = 0.0;
-  for (int o2 = -1; o2 <= 1; ++o2) {
+  for (int lo = 0; lo < kStripLayers; ++lo)
+#pragma unroll
+    for (int k = 0; k < kStripRows; ++k) r[lo][k][0] = r[lo][k][1] = r[lo][k][2] = 0.0;
+#pragma unroll 1
+  for (int li = -1; li <= kStripLayers; ++li) {   // u of node layer l0 + li
 #pragma clang fp contract(fast)
-    const int l = layer + o2;
-    if (l < 0 || l > a.n2) continue;
+    const int l = l0 + li;
+    if (l < 0 || l > n2) continue;
     const long long base = static_cast<long long>(l) * cells;
-    const double *__restrict__ Cl = C + 3 * (o2 + 1) * 9;
 #pragma unroll
     for (int q = 0; q < kStripRows + 2; ++q) {     // neighbour row i10 - 1 + q
       int jr = i10 - 1 + q;
@@ -177,28 +186,41 @@ __global__ __launch_bounds__(kStripThreads) void strip_correct_kernel(StripArgs 
         u[o3][1] = a.u[nodes + nb];
         u[o3][2] = a.u[2 * nodes + nb];
       }
-      // row q is the neighbour at offset o1 = q - 1 - k of node k
+      // the row is the neighbour at offset o2 = li - lo of the thread's layer lo
 #pragma unroll
-      for (int k = 0; k < kStripRows; ++k) {
-        const int o1 = q - 1 - k;
-        if (o1 < -1 || o1 > 1) continue;
+      for (int lo = 0; lo < kStripLayers; ++lo) {
+        const int o2 = li - lo;
+        if (o2 < -1 || o2 > 1 || l0 + lo > n2) continue;
+        const double *__restrict__ Cl =
+            a.stencil + static_cast<long long>(l0 + lo) * 27 * 9 + 3 * (o2 + 1) * 9;
+        // row q is the neighbour at offset o1 = q - 1 - k of node k
 #pragma unroll
-        for (int o3 = 0; o3 < 3; ++o3) {
-          const double *B = Cl + ((o1 + 1) + 9 * o3) * 9;
+        for (int k = 0; k < kStripRows; ++k) {
+          const int o1 = q - 1 - k;
+          if (o1 < -1 || o1 > 1) continue;
 #pragma unroll
-          for (int p = 0; p < 3; ++p) {
-            r[k][p] -= B[3 * p] * u[o3][0];
-            r[k][p] -= B[3 * p + 1] * u[o3][1];
-            r[k][p] -= B[3 * p + 2] * u[o3][2];
+          for (int o3 = 0; o3 < 3; ++o3) {
+            const double *B = Cl + ((o1 + 1) + 9 * o3) * 9;
+#pragma unroll
+            for (int p = 0; p < 3; ++p) {
+              r[lo][k][p] -= B[3 * p] * u[o3][0];
+              r[lo][k][p] -= B[3 * p + 1] * u[o3][1];
+              r[lo][k][p] -= B[3 * p + 2] * u[o3][2];
+            }
           }
         }
       }
     }
   }
 #pragma unroll
-  for (int k = 0; k < kStripRows; ++k) {
-    const long long cell = static_cast<long long>(i10 + k) * n3 + i3;
-    strip_finish<R>(a, layer, layer * cells + cell, cell, r[k]);
+  for (int lo = 0; lo < kStripLayers; ++lo) {
+    const int layer = l0 + lo;
+    if (layer > n2) break;
+#pragma unroll
+    for (int k = 0; k < kStripRows; ++k) {
+      const long long cell = static_cast<long long>(i10 + k) * n3 + i3;
+      strip_finish<R>(a, layer, layer * cells + cell, cell, r[lo][k]);
+    }
   }
 }
 
@@ -286,7 +308,7 @@ hipError_t launch_strip_predict(bool fp64, const StripArgs &a, hipStream_t st) {
 }
 
 hipError_t launch_strip_correct(bool fp64, const StripArgs &a, hipStream_t st) {
-  const long long threads = a.nodes / kStripRows;
+  const long long threads = a.cells / kStripRows * ((a.n2 + kStripLayers) / kStripLayers);
   const unsigned blocks = static_cast<unsigned>((threads + kStripThreads - 1) / kStripThreads);
   const bool uniform = (a.cells / kStripRows) % 64 == 0;
   if (fp64) {
