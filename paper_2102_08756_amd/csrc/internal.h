@@ -200,13 +200,16 @@ hipError_t launch_fault_check(const double *tau0, const double *mu_s, const doub
 // fault (0 = S-, fault_lo = the lower copy of the split fault nodes), layers
 // fault_hi = fault_lo + 1 .. n2 the block above it (n2 = S+).
 struct StripArgs {
-  double *u, *v, *a;          // displacement, velocity (half-step between the kernels), acceleration
+  const double *u;            // [3][nodes] u_{t+1}, read by the stencil
+  double *u_next;             // [3][nodes] u_{t+2}, written (the other displacement buffer)
+  double *vh;                 // [3][nodes] in: v_{t+1/2}; out: v_{t+3/2}
+  double *v;                  // [3][nodes] out: v_{t+1}
   const double *stencil;      // [n2+1][27][3][3]: stiffness block of each neighbour offset
                               // (o1, o2, o3), index (o1+1) + 3 (o2+1) + 9 (o3+1)
   const double *mass;         // [n2+1] lumped mass of a node of each layer
   const void *tau_sbi;        // [P][3][cells] working precision: tractions at S+ (and S-)
   void *push_u, *push_v;      // [P][3][cells] working precision: S+ (and S-) displacement
-                              // (or increment) and predicted velocity
+                              // (or increment) and predicted velocity of the next step
   double *r_fault;            // two-sided: [2][3][cells] forces on the upper, lower fault copy
   const double *tau0, *mu_s, *mu_k, *d_c;
   double *tau, *rate, *slip, *sliding;   // fault outputs [3], [2], [2], [1] x cells
@@ -217,7 +220,6 @@ struct StripArgs {
   double dt, area;
   int increment;
 };
-hipError_t launch_strip_predict(bool fp64, const StripArgs &a, hipStream_t st);
 hipError_t launch_strip_correct(bool fp64, const StripArgs &a, hipStream_t st);
 hipError_t launch_strip_fault2(const StripArgs &a, hipStream_t st);
 hipError_t launch_tabulate(bool fp64, const Group &g, double dt, const double *gl_x,

@@ -1113,15 +1113,20 @@ int sbim_fault_destroy(sbim_fault *f) {
 
 // ---------------------------------------------------------------- strip
 
-// Finite-element strip of the hybrid scheme on the fault, closed at S+ by the
-// handle's single plane.  Float64 node state [9][nodes] (u, v, a; 3 components
-// each) and fault outputs [8][cells] (traction 3, slip rate 2, slip 2, sliding 1).
+// Finite-element strip of the hybrid scheme on the fault, closed at S+ (and
+// S-) by the handle's planes.  Float64 node state [12][nodes], 3 components
+// each: two displacement buffers (u_{t+1} read by the next step's stencil, the
+// other one written with u_{t+2}; `cur` names the first), the half-step velocity
+// and the velocity v_{t+1}; fault outputs [8][cells] (traction 3, slip rate 2,
+// slip 2, sliding 1).  Each step ends with the predictor of the next one, so
+// the push inputs of S+ (S-) are ready when the step begins.
 struct sbim_strip {
   sbim_handle *h = nullptr;
   int n2 = 0;                 // index of the top storage node layer (S+)
   int fault_lo = -1;          // two-sided: storage layer of the lower fault copy
   long long cells = 0, nodes = 0;
-  double *node = nullptr;     // u, v, a
+  double *node = nullptr;     // u (two buffers), half-step velocity, velocity
+  int cur = 0;                // displacement buffer the next step's stencil reads
   double *cell = nullptr;     // fault outputs
   double *prm = nullptr;      // tau0 (3), mu_s, mu_k, d_c
   double *stencil = nullptr;  // [n2+1][27][9]
@@ -1200,10 +1205,15 @@ void free_strip(sbim_strip *s) {
 
 int strip_clear(sbim_strip *s) {
   sbim_handle *h = s->h;
-  hipError_t e = hipMemsetAsync(s->node, 0, sizeof(double) * 9 * s->nodes, h->stream);
+  // at rest: u_1 = 0 and v_{1/2} = 0, so the first push inputs are zero too
+  const size_t fb = static_cast<size_t>(h->cfg.nplanes) * 3 * s->cells * h->rsize;
+  hipError_t e = hipMemsetAsync(s->node, 0, sizeof(double) * 12 * s->nodes, h->stream);
   if (e == hipSuccess)
     e = hipMemsetAsync(s->cell, 0, sizeof(double) * kCellRows * s->cells, h->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(s->push_u, 0, fb, h->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(s->push_v, 0, fb, h->stream);
   if (e != hipSuccess) return hip_fail(h, e, "clearing the strip state");
+  s->cur = 0;
   s->steps = 0;
   return SBIM_OK;
 }
@@ -1295,7 +1305,7 @@ int sbim_strip_create(sbim_handle *h, const sbim_strip_config *sc, const sbim_fa
   const size_t n = static_cast<size_t>(s->cells);
   const size_t fb = static_cast<size_t>(c.nplanes) * 3 * n * h->rsize;
   hipError_t e;
-  if ((e = dev_alloc(&s->node, 9 * static_cast<size_t>(s->nodes))) != hipSuccess ||
+  if ((e = dev_alloc(&s->node, 12 * static_cast<size_t>(s->nodes))) != hipSuccess ||
       (Lb > 0 && (e = dev_alloc(&s->r_fault, 6 * n)) != hipSuccess) ||
       (e = dev_alloc(&s->cell, kCellRows * n)) != hipSuccess ||
       (e = dev_alloc(&s->prm, 6 * n)) != hipSuccess ||
@@ -1350,9 +1360,10 @@ int sbim_strip_step(sbim_strip *s, double *tau_out, double *rate_out) {
                 h->step, s->steps);
   const long long n = s->cells;
   sbim::StripArgs a;
-  a.u = s->node;
-  a.v = s->node + 3 * s->nodes;
-  a.a = s->node + 6 * s->nodes;
+  a.u = s->node + 3 * s->cur * s->nodes;
+  a.u_next = s->node + 3 * (1 - s->cur) * s->nodes;
+  a.vh = s->node + 6 * s->nodes;
+  a.v = s->node + 9 * s->nodes;
   a.stencil = s->stencil;
   a.mass = s->mass;
   a.tau_sbi = s->tau_sbi;
@@ -1378,11 +1389,11 @@ int sbim_strip_step(sbim_strip *s, double *tau_out, double *rate_out) {
   a.dt = h->cfg.dt;
   a.area = h->cfg.dx1 * h->cfg.dx3;
   a.increment = h->cfg.input_kind == SBIM_INCREMENT;
-  hipError_t e = sbim::launch_strip_predict(h->fp64, a, h->stream);
-  if (e != hipSuccess) return hip_fail(h, e, "strip predictor");
+  // push of u_{t+1} (or its increment) and the predicted velocity, written by
+  // the previous step's predictor
   int rc = push_fields(h, s->push_u, s->push_v, sbim::VEL_INPUT);
   if (rc) return rc;
-  e = fft_inverse(h, h->out_spec, h->spec, s->tau_sbi, nullptr);
+  hipError_t e = fft_inverse(h, h->out_spec, h->spec, s->tau_sbi, nullptr);
   if (e != hipSuccess) return hip_fail(h, e, "inverse FFT of the S+ (and S-) tractions");
   e = sbim::launch_strip_correct(h->fp64, a, h->stream);
   if (e != hipSuccess) return hip_fail(h, e, "strip corrector");
@@ -1390,6 +1401,7 @@ int sbim_strip_step(sbim_strip *s, double *tau_out, double *rate_out) {
     e = sbim::launch_strip_fault2(a, h->stream);
     if (e != hipSuccess) return hip_fail(h, e, "strip fault nodes");
   }
+  s->cur = 1 - s->cur;
   s->steps += 1;
   return SBIM_OK;
 }
@@ -1405,8 +1417,10 @@ int sbim_strip_read(const sbim_strip *s, int field, double *dst) {
     case SBIM_STRIP_SLIP_RATE: src = s->cell + kCellRate * s->cells, count = 2 * s->cells; break;
     case SBIM_STRIP_SLIP: src = s->cell + kCellSlip * s->cells, count = 2 * s->cells; break;
     case SBIM_STRIP_SLIDING: src = s->cell + kCellSliding * s->cells, count = s->cells; break;
-    case SBIM_STRIP_DISPLACEMENT: src = s->node, count = 3 * s->nodes; break;
-    case SBIM_STRIP_VELOCITY: src = s->node + 3 * s->nodes, count = 3 * s->nodes; break;
+    case SBIM_STRIP_DISPLACEMENT:   // u_{t+1}: the buffer the last step's stencil read
+      src = s->node + 3 * (1 - s->cur) * s->nodes, count = 3 * s->nodes;
+      break;
+    case SBIM_STRIP_VELOCITY: src = s->node + 9 * s->nodes, count = 3 * s->nodes; break;
     default: return fail(h, SBIM_E_INVALID, "unknown strip field %d", field);
   }
   hipError_t e = hipMemcpyAsync(dst, src, sizeof(double) * count, hipMemcpyDeviceToDevice,

@@ -31,38 +31,30 @@ constexpr int kStripThreads = 256;
 constexpr int kStripRows = 4;        // nodes along x1 per thread of the corrector (divides n1)
 constexpr int kStripLayers = 3;      // node layers per thread of the corrector
 
+// The predictor of the next step from a node's new acceleration and velocity
+// (Eq. fepred and the displacement update), with the push inputs of S+ (plane
+// 0) or S- (plane 1) when the node lies on one of them.
 template <typename R>
-__global__ __launch_bounds__(kStripThreads) void strip_predict_kernel(StripArgs a) {
-  const long long nodes = a.nodes;
-  const long long id = static_cast<long long>(blockIdx.x) * kStripThreads + threadIdx.x;
-  if (id >= nodes) return;
+__device__ __forceinline__ void strip_predict(const StripArgs &a, long long k, int push_plane,
+                                              long long cell, int c, double vn, double acc) {
   const double dt = a.dt;
-  const long long cells = a.cells;
-  const long long top0 = nodes - cells;          // first node of the S+ layer
-  R *__restrict__ pu = static_cast<R *>(a.push_u);
-  R *__restrict__ pv = static_cast<R *>(a.push_v);
-#pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    const long long k = c * nodes + id;
-    const double v = a.v[k], acc = a.a[k];
-    const double vh = v + 0.5 * dt * acc;
-    const double un = a.u[k] + dt * vh;
-    a.u[k] = un;
-    a.v[k] = vh;                                  // the half-step velocity until the corrector
-    if (id >= top0) {                             // S+: plane 0 of the push
-      const long long t = c * cells + (id - top0);
-      pu[t] = static_cast<R>(a.increment ? dt * vh : un);
-      pv[t] = static_cast<R>(v + dt * acc);      // predicted velocity of Eq. fepred
-    } else if (a.fault_lo >= 0 && id < cells) {   // S- (two-sided): plane 1
-      const long long t = (3 + c) * cells + id;
-      pu[t] = static_cast<R>(a.increment ? dt * vh : un);
-      pv[t] = static_cast<R>(v + dt * acc);
-    }
+  const double vh = vn + 0.5 * dt * acc;        // v_{t+3/2}
+  const double un = a.u[k] + dt * vh;           // u_{t+2}
+  a.v[k] = vn;
+  a.vh[k] = vh;
+  a.u_next[k] = un;
+  if (push_plane >= 0) {
+    R *__restrict__ pu = static_cast<R *>(a.push_u);
+    R *__restrict__ pv = static_cast<R *>(a.push_v);
+    const long long t = (push_plane * 3 + c) * a.cells + cell;
+    pu[t] = static_cast<R>(a.increment ? dt * vh : un);
+    pv[t] = static_cast<R>(vn + dt * acc);      // predicted velocity of Eq. fepred
   }
 }
 
-// Everything after the stiffness forces for one node: the S+ traction, the
-// fault solve on layer 0, the corrector and the fault outputs.
+// Everything after the stiffness forces for one node: the S+ (S-) traction,
+// the fault solve on layer 0 of the one-sided strip, the corrector and the
+// fault outputs, then the predictor of the next step.
 template <typename R>
 __device__ __forceinline__ void strip_finish(const StripArgs &a, int layer, long long id,
                                              long long cell, double r[3]) {
@@ -89,8 +81,8 @@ __device__ __forceinline__ void strip_finish(const StripArgs &a, int layer, long
   const double dt = a.dt;
   if (!two && layer == 0) {                      // fault node: stick traction and strength
     const double t00 = a.tau0[cell], t01 = a.tau0[cells + cell], t02 = a.tau0[2 * cells + cell];
-    const double vs0 = a.v[id] + dt * r[0] / M;
-    const double vs2 = a.v[2 * nodes + id] + dt * r[2] / M;
+    const double vs0 = a.vh[id] + dt * r[0] / M;
+    const double vs2 = a.vh[2 * nodes + id] + dt * r[2] / M;
     const double st0 = t00 + M * vs0 / (dt * A);
     const double st2 = t02 + M * vs2 / (dt * A);
     const double mag = sqrt(st0 * st0 + st2 * st2);
@@ -120,14 +112,14 @@ __device__ __forceinline__ void strip_finish(const StripArgs &a, int layer, long
       a.tau_out[2 * cells + cell] = tau2;
     }
   }
+  const int push_plane = layer == a.n2 ? 0 : (two && layer == 0 ? 1 : -1);
   double vn[3];
 #pragma unroll
   for (int p = 0; p < 3; ++p) {
     const long long k = p * nodes + id;
     const double acc = r[p] / M;
-    vn[p] = a.v[k] + 0.5 * dt * acc;
-    a.a[k] = acc;
-    a.v[k] = vn[p];
+    vn[p] = a.vh[k] + 0.5 * dt * acc;            // v_{t+1} (Eqs. tintf, fecorr)
+    strip_predict<R>(a, k, push_plane, cell, p, vn[p], acc);
   }
   if (!two && layer == 0) {
     a.rate[cell] = 2.0 * vn[0];
@@ -228,7 +220,8 @@ __global__ __launch_bounds__(kStripThreads) void strip_correct_kernel(StripArgs 
 // that closes the jump of the next half-step velocities of the two copies
 // (Eqs. freeslip, sticktraction), applied in full to the normal component (no
 // opening) and limited on the shear pair by the slip-weakening strength at the
-// current normal traction (Eqs. stickslip, slipweak); then both copies' corrector.
+// current normal traction (Eqs. stickslip, slipweak); then both copies' corrector
+// and the predictor of the next step.
 __global__ __launch_bounds__(kStripThreads) void strip_fault2_kernel(StripArgs a) {
   const long long cell = static_cast<long long>(blockIdx.x) * kStripThreads + threadIdx.x;
   const long long cells = a.cells, nodes = a.nodes;
@@ -247,8 +240,8 @@ __global__ __launch_bounds__(kStripThreads) void strip_fault2_kernel(StripArgs a
   const double zinv = dt * A * (1.0 / Mp + 1.0 / Mm);
 #pragma unroll
   for (int p = 0; p < 3; ++p) {
-    const double vsp = a.v[p * nodes + ip] + dt * rp[p] / Mp;
-    const double vsm = a.v[p * nodes + im] + dt * rm[p] / Mm;
+    const double vsp = a.vh[p * nodes + ip] + dt * rp[p] / Mp;
+    const double vsm = a.vh[p * nodes + im] + dt * rm[p] / Mm;
     stick[p] = t0[p] + (vsp - vsm) / zinv;
   }
   double tau[3] = {stick[0], stick[1], stick[2]};
@@ -270,12 +263,11 @@ __global__ __launch_bounds__(kStripThreads) void strip_fault2_kernel(StripArgs a
     const double dtau = A * (tau[p] - t0[p]);
     const double ap = (rp[p] - dtau) / Mp;
     const double am = (rm[p] + dtau) / Mm;
-    vp[p] = a.v[p * nodes + ip] + 0.5 * dt * ap;
-    vm[p] = a.v[p * nodes + im] + 0.5 * dt * am;
-    a.a[p * nodes + ip] = ap;
-    a.a[p * nodes + im] = am;
-    a.v[p * nodes + ip] = vp[p];
-    a.v[p * nodes + im] = vm[p];
+    vp[p] = a.vh[p * nodes + ip] + 0.5 * dt * ap;
+    vm[p] = a.vh[p * nodes + im] + 0.5 * dt * am;
+    // the split copies lie on neither S+ nor S-
+    strip_predict<double>(a, p * nodes + ip, -1, cell, p, vp[p], ap);
+    strip_predict<double>(a, p * nodes + im, -1, cell, p, vm[p], am);
     a.tau[p * cells + cell] = tau[p];
     if (a.tau_out) a.tau_out[p * cells + cell] = tau[p];
   }
@@ -295,15 +287,6 @@ __global__ __launch_bounds__(kStripThreads) void strip_fault2_kernel(StripArgs a
 hipError_t launch_strip_fault2(const StripArgs &a, hipStream_t st) {
   const unsigned blocks = static_cast<unsigned>((a.cells + kStripThreads - 1) / kStripThreads);
   strip_fault2_kernel<<<blocks, kStripThreads, 0, st>>>(a);
-  return hipGetLastError();
-}
-
-hipError_t launch_strip_predict(bool fp64, const StripArgs &a, hipStream_t st) {
-  const unsigned blocks = static_cast<unsigned>((a.nodes + kStripThreads - 1) / kStripThreads);
-  if (fp64)
-    strip_predict_kernel<double><<<blocks, kStripThreads, 0, st>>>(a);
-  else
-    strip_predict_kernel<float><<<blocks, kStripThreads, 0, st>>>(a);
   return hipGetLastError();
 }
 
