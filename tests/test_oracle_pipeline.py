@@ -118,6 +118,33 @@ def test_uniform_velocity_pure_damping(side):
                                * np.ones_like(tau), atol=1e-12)
 
 
+@pytest.mark.parametrize("side", [1, -1])
+def test_instantaneous_term_is_a_local_operator(side):
+    """The instantaneous part of the boundary relation (the K12 -> eta - 2 limit) is, in
+    physical space, the local operator (2 - eta) mu (du2/dx1, -(du1/dx1 + du3/dx3), du2/dx3),
+    with the same sign on both sides.  At the first step with the damping velocity zero
+    the history weights vanish as dt -> 0 (w_0 = G(q c_s dt) -> 0), so the traction is that
+    operator alone.  The derivatives here: spectral differentiation with numpy FFTs of a
+    field without Nyquist content."""
+    n1, n3, dx1, dx3 = 16, 12, 0.7, 1.3
+    mu, cs, cp = 1.3, 1.0, 1.9
+    cfg = Config(n1=n1, n3=n3, dx1=dx1, dx3=dx3, dt=1e-10, window_cap=4,
+                 planes=[Plane(side, mu, cs, cp)], input_kind="absolute")
+    rng = np.random.default_rng(17)
+    spec = rng.standard_normal((3, n1, n3 // 2 + 1)) + 1j * rng.standard_normal((3, n1, n3 // 2 + 1))
+    spec[:, n1 // 2, :] = 0
+    spec[:, :, n3 // 2] = 0
+    u = np.fft.irfft2(spec, s=(n1, n3))
+    k1 = 2 * np.pi * np.fft.fftfreq(n1, dx1)[:, None]
+    k3 = 2 * np.pi * np.fft.rfftfreq(n3, dx3)[None, :]
+    d1 = lambda f: np.fft.irfft2(1j * k1 * np.fft.rfft2(f), s=(n1, n3))  # noqa: E731
+    d3 = lambda f: np.fft.irfft2(1j * k3 * np.fft.rfft2(f), s=(n1, n3))  # noqa: E731
+    exp = (2.0 - cp / cs) * mu * np.stack([d1(u[1]), -(d1(u[0]) + d3(u[2])), d3(u[1])])
+    tau = oracle.forward(cfg, u[None, None], np.zeros((1, 1, 3, n1, n3)))[0, 0]
+    np.testing.assert_allclose(tau, exp, atol=1e-8 * np.abs(exp).max())
+    assert np.abs(exp).max() > 1e-2                      # a non-trivial field
+
+
 def test_mirror_rule():
     """tau^-(u1, u2, u3) = diag(-1, 1, -1) tau^+(u1, -u2, u3)."""
     rng = np.random.default_rng(3)
