@@ -364,6 +364,76 @@ def rupture_leg(fw, forms, device):
     return out
 
 
+def adjoint_leg(device, forms, every=50, receivers=64, seed=4000):
+    """Differentiation on the 256^2 single-plane job (W = 300, 500 steps): the gradient of
+    a receiver misfit L = sum_n sum_r sum_i tau_i^n(x_r)^2 (64 receiver cells) with respect
+    to the whole displacement history, through SBIMRun (the forward keeps every traction;
+    the backward runs the library's transpose in reverse time) and through
+    checkpointed_loss (snapshots every ``every`` steps, tractions recomputed per segment in
+    the backward).  Each pass is timed whole, from a synchronised device, after one
+    untimed pass of each kind; the two gradients are compared."""
+    import torch
+    import workloads
+    from paper_2102_08756_amd import SBIM, Config, SBIMRun, checkpointed_loss
+    wl = workloads.WORKLOADS[4]
+    out = {"workload": wl.name, "n1": wl.n1, "n3": wl.n3, "window_cap": wl.window_cap,
+           "time_steps": wl.steps, "receivers": receivers, "checkpoint_every": every,
+           "forms": {}}
+    rec = torch.randperm(wl.n1 * wl.n3, generator=torch.Generator().manual_seed(seed))[:receivers]
+    for f in forms:
+        sb = SBIM(Config.from_dict(wl.config_dict(), precision=f), device=device)
+        gen = torch.Generator(device=device).manual_seed(seed + 1)
+        u = torch.randn((wl.steps,) + sb.shape, generator=gen, dtype=sb.dtype, device=device)
+        r = rec.to(device)
+        P = sb.shape[0]
+
+        def full():
+            x = u.clone().requires_grad_(True)
+            t0 = time.perf_counter()
+            tau = SBIMRun.apply(sb, x)
+            L = (tau.reshape(wl.steps, P, 3, -1)[..., r] ** 2).sum()
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            L.backward()
+            torch.cuda.synchronize()
+            return x.grad, t1 - t0, time.perf_counter() - t1
+
+        def ckpt():
+            x = u.clone().requires_grad_(True)
+            t0 = time.perf_counter()
+            L = checkpointed_loss(sb, x, lambda tau, n: (tau.reshape(P, 3, -1)[..., r] ** 2).sum(),
+                                  every=every)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            L.backward()
+            torch.cuda.synchronize()
+            return x.grad, t1 - t0, time.perf_counter() - t1
+
+        full()
+        ckpt()
+        torch.cuda.synchronize()
+        g1, f1, b1 = full()
+        g2, f2, b2 = ckpt()
+        N = wl.steps
+        out["forms"][f] = {
+            "forward_ms_per_step": 1e3 * f1 / N, "backward_ms_per_step": 1e3 * b1 / N,
+            "checkpointed_forward_ms_per_step": 1e3 * f2 / N,
+            "checkpointed_backward_ms_per_step": 1e3 * b2 / N,
+            "gradient_rel_l2_full_vs_checkpointed": float(
+                (g1 - g2).double().norm() / g1.double().norm()),
+        }
+        o = out["forms"][f]
+        print(f"[bench] adjoint {wl.name} {f}: forward {o['forward_ms_per_step']:.3f} ms/step, "
+              f"backward {o['backward_ms_per_step']:.3f} ms/step; checkpointed "
+              f"{o['checkpointed_forward_ms_per_step']:.3f} + {o['checkpointed_backward_ms_per_step']:.3f}"
+              f" ms/step; gradients agree to {o['gradient_rel_l2_full_vs_checkpointed']:.1e}",
+              file=sys.stderr, flush=True)
+        del u, g1, g2
+        sb.close()
+        torch.cuda.empty_cache()
+    return out
+
+
 def scaling_sweep(device, sizes=(128, 256, 512, 1024, 2048), window=200, layers=(2, 6)):
     """Cost of one step against the grid size n x n at a fixed history window: the
     boundary relation with the fault's interface solve, and the hybrid scheme with
@@ -485,6 +555,8 @@ def main():
     ap.add_argument("--rupture-forms", default="fp32_comp,fp64",
                     help="forms of the rupture leg on the fault workload (empty: skip it)")
     ap.add_argument("--rupture", default="tpv3_1024", help="fault workload of the rupture leg")
+    ap.add_argument("--adjoint-forms", default="fp64,fp32_comp",
+                    help="forms of the adjoint leg on the 256^2 job (empty: skip it)")
     ap.add_argument("--scaling", action="store_true",
                     help="only the step-cost sweep over grid sizes (boundary relation vs strip layers)")
     ap.add_argument("--calibrate-copy", type=float, default=0.0,
@@ -535,6 +607,8 @@ def main():
         acc = accuracy(wl, steps, device, cache, [f for f in forms if f != "fp64"])
         print(f"[bench] accuracy: {acc}", file=sys.stderr, flush=True)
     rup = rupture_leg(workloads.FAULTS[args.rupture], rforms, device) if rforms else None
+    aforms = [f for f in args.adjoint_forms.split(",") if f]
+    adj = adjoint_leg(device, aforms) if aforms else None
     cpu = None if args.no_cpu else cpu_baseline(wl)
     head = forms[0]
     r = res[head]
@@ -557,6 +631,7 @@ def main():
                       "kernel_classes": res[f]["info"]["kernel_classes"]} for f in forms},
         "accuracy": acc,
         "rupture": rup,
+        "adjoint": adj,
         "kernel_source_hash": kernel_source_hash(),
     }
     print(json.dumps(line))
