@@ -269,6 +269,10 @@ TWO_CASES = {
     "tiny8_1up_3down": (workloads.FaultWorkload("tiny8_bimat", 8, 8, 750.0, 40,
                                                 region=(4500.0, 4500.0), patch=1500.0, lower=_LO),
                         [BULK], [BULK_LO, SLOW, BULK_LO]),
+    # 7 node layers: the corrector's last chunk of three layers holds one
+    "tiny8_2up_3down": (workloads.FaultWorkload("tiny8_bimat", 8, 8, 750.0, 40,
+                                                region=(4500.0, 4500.0), patch=1500.0, lower=_LO),
+                        [SLOW, BULK], [BULK_LO, BULK_LO, BULK_LO]),
 }
 _REF2 = {}
 
