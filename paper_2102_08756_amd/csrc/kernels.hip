@@ -104,9 +104,10 @@ template <typename R, int S, bool COMP> constexpr int sweep_group() {
 }
 
 // Lag chunks per sweep wavefront (measured on gfx950, 512x512 x 2 planes,
-// W = 1000): four (16 modes x 4 chunks) where three wavefronts fit per SIMD
-// (float32), two (32 modes x 2 chunks, 256-byte segments, half the
-// wavefronts) where two fit (float64, compensated).
+// W = 1000): four where three wavefronts fit per SIMD (float32: 16 modes x 4
+// chunks with one lane per mode, 8 modes x 2 x 4 with two), two where two fit
+// (float64, compensated: 32 modes x 2 chunks, 256-byte segments of float32
+// pairs, or 16 modes x 2 x 2 with two lanes per mode).
 template <typename R, int S, bool COMP> constexpr int sweep_lag_groups() {
   return (COMP || sizeof(R) == 8) ? 2 : 4;
 }
