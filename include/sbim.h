@@ -116,8 +116,9 @@ typedef struct {
   long long backward_step;     /* sbim_backward calls since the last reset */
   int material_groups;         /* planes sharing (c_s, c_p) share one table and one pass */
   int sweep_depth;             /* steps served by one pass over a block's history: 6 when
-                                  the mean window is under 64 lags, else 8 (float32) or 12
-                                  (float64, compensated); the environment variable
+                                  the mean window is under 64 lags, else 12 (float64,
+                                  compensated, and float32 from a mean window of 1500
+                                  lags) or 8 (float32 below that); the environment variable
                                   SBIM_SWEEP_DEPTH (1, 2, 4, 6, 8, 12 or 16) overrides it
                                   at sbim_init, for tuning */
 } sbim_info;

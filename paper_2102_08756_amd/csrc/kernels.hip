@@ -103,13 +103,13 @@ template <typename R, int S, bool COMP> constexpr int sweep_group() {
   return S % g == 0 ? g : (S % 2 == 0 ? 2 : 1);  // a divisor of the span
 }
 
-// Lag chunks per sweep wavefront (measured on gfx950, 512x512 x 2 planes,
-// W = 1000): four where three wavefronts fit per SIMD (float32: 16 modes x 4
-// chunks with one lane per mode, 8 modes x 2 x 4 with two), two where two fit
-// (float64, compensated: 32 modes x 2 chunks, 256-byte segments of float32
-// pairs, or 16 modes x 2 x 2 with two lanes per mode).
-template <typename R, int S, bool COMP> constexpr int sweep_lag_groups() {
-  return (COMP || sizeof(R) == 8) ? 2 : 4;
+// Lag chunks per sweep wavefront (measured on gfx950, 512x512 and 1024x1024 x
+// 2 planes, W = 1000 and 2000): four for float32 with one lane per mode (16
+// modes x 4 chunks, three wavefronts per SIMD), two otherwise (float64 and the
+// compensated form: 32 modes x 2 chunks, 256-byte segments of float32 pairs;
+// with two lanes per mode 16 modes x 2 x 2 in every form).
+template <typename R, int S, int T, bool COMP> constexpr int sweep_lag_groups() {
+  return (COMP || sizeof(R) == 8 || T > 1) ? 2 : 4;
 }
 
 // Rows k0 .. k0+S-1 of a mode's kernel.  A class's W rows are followed by a
@@ -196,7 +196,7 @@ __device__ __forceinline__ void sweep_item(const SweepArgs &a, long long item) {
   R *__restrict__ pending = static_cast<R *>(a.pending);
   const long long M = a.M, step = a.step;
   const int np = a.np;
-  constexpr int LG = sweep_lag_groups<R, S, COMP>();
+  constexpr int LG = sweep_lag_groups<R, S, T, COMP>();
   constexpr int Q = kLanes / (LG * T);  // modes per item
   constexpr int NQ = kLanes / Q;        // items per block and plane
   constexpr int D = S * T;
@@ -499,6 +499,14 @@ __global__ __launch_bounds__(kLanes) void step_kernel(SweepArgs sa, ModeArgs ma,
   step_items<R, S, T, COMP>(sa, ma, sweep_items, nblocks);
 }
 
+// The float32 sweep at 6 steps per lane and two lanes per mode, held to four
+// wavefronts per SIMD (128 registers; the compiler alone takes 131, three).
+template <typename R, int S, int T, bool COMP>
+__global__ __launch_bounds__(kLanes) __attribute__((amdgpu_waves_per_eu(4))) void step_kernel_w4(
+    SweepArgs sa, ModeArgs ma, long long sweep_items, long long nblocks) {
+  step_items<R, S, T, COMP>(sa, ma, sweep_items, nblocks);
+}
+
 // The compensated sweep at up to 6 steps per lane, held to two wavefronts per
 // SIMD: left to itself the compiler takes the whole register file (one
 // wavefront) for a couple of registers that it then keeps in scratch instead.
@@ -661,10 +669,13 @@ hipError_t step_launch_s(const sbim_handle *h, const Group &g, const SweepArgs &
   const int phase = static_cast<int>((sa.step + 1) % D);
   sa.nphase = g.nblocks > phase ? (g.nblocks - phase + D - 1) / D : 0;
   const long long sweep_items =
-      (sa.nphase + 7) / 8 * 8 * (sweep_lag_groups<R, S, COMP>() * T) * g.np;
+      (sa.nphase + 7) / 8 * 8 * (sweep_lag_groups<R, S, T, COMP>() * T) * g.np;
   const long long items = sweep_items + g.nblocks * g.np;
   if (ev0) (void)hipEventRecord(ev0, h->stream);
-  if constexpr (COMP && S <= 6)
+  if constexpr (!COMP && sizeof(R) == 4 && S == 6 && T == 2)
+    hipLaunchKernelGGL((step_kernel_w4<R, S, T, COMP>), dim3(static_cast<unsigned>(items)),
+                       dim3(kLanes), 0, h->stream, sa, ma, sweep_items, g.nblocks);
+  else if constexpr (COMP && S <= 6)
     hipLaunchKernelGGL((step_kernel_w2<R, S, T, COMP>), dim3(static_cast<unsigned>(items)),
                        dim3(kLanes), 0, h->stream, sa, ma, sweep_items, g.nblocks);
   else

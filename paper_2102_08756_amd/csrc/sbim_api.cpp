@@ -473,12 +473,12 @@ int sbim_init(const sbim_config *cfg, sbim_handle **out) {
   // lanes, one per half of the steps.  Measured on gfx950 (two planes,
   // 512^2 at W = 1000, 1024^2 at W = 2000, 2048^2 with per-mode windows of
   // mean 18 lags): with long windows float64 and the compensated form run
-  // fastest at 12, float32 at 8 (16 moves half the bytes in the same time);
-  // with mean windows under 64 lags every form runs fastest at 6.
+  // fastest at 12; float32 at 8 for W = 1000 (by 5%) and at 12 for W = 2000
+  // (by 7%); with mean windows under 64 lags every form runs fastest at 6.
   double wbar = 0;
   for (int p = 0; p < cfg->nplanes; ++p)
     wbar = std::max(wbar, mean_window(*cfg, cfg->plane[p].cs));
-  h->depth = wbar < 64 ? 6 : (h->comp || h->fp64 ? 12 : 8);
+  h->depth = wbar < 64 ? 6 : (h->comp || h->fp64 || wbar >= 1500 ? 12 : 8);
   if (const char *env = std::getenv("SBIM_SWEEP_DEPTH")) {  // tuning override
     const int v = std::atoi(env);
     if (v == 1 || v == 2 || v == 4 || v == 6 || v == 8 || v == 12 || v == 16) h->depth = v;

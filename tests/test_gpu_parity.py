@@ -187,13 +187,15 @@ def test_sweep_depths(sweep_refs, case, depth, precision, monkeypatch):
 
 @pytest.mark.parametrize("precision,long_depth", [("fp32", 8), ("fp32_comp", 12), ("fp64", 12)])
 def test_default_sweep_depth(precision, long_depth, monkeypatch):
-    """Long windows: 8 steps per sweep for float32, 12 (two lanes per mode) for float64 and
-    the compensated form; per-mode windows averaging under 64 lags (here 18): 6."""
+    """Long windows: 8 steps per sweep for float32 (12 from 1500 lags), 12 (two lanes per
+    mode) for float64 and the compensated form; per-mode windows averaging under 64 lags
+    (here 18): 6."""
     monkeypatch.delenv("SBIM_SWEEP_DEPTH", raising=False)
     long_w = dict(n1=64, n3=64, window_cap=100, planes=[dict(side=1)])
     short_w = dict(n1=64, n3=64, window_cap=400, window_mode="per_mode", eta_w=1.0,
                    planes=[dict(side=1), dict(side=-1)])
-    for cfg, want in ((long_w, long_depth), (short_w, 6)):
+    longer_w = dict(n1=16, n3=16, window_cap=1600, planes=[dict(side=1)])
+    for cfg, want in ((long_w, long_depth), (short_w, 6), (longer_w, 12)):
         sb = SBIM(Config.from_dict(cfg, precision=precision), device=DEV)
         assert sb.info()["sweep_depth"] == want, (cfg["window_mode"] if "window_mode" in cfg else "fixed")
         sb.close()
