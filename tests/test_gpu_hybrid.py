@@ -431,3 +431,34 @@ def test_tpv3_bimaterial_two_sided_hybrid_agrees_with_boundary_integral_rupture(
     assert (oh[region] >= 0).mean() > 0.99
     assert np.median(rel_onset) < 0.03 and np.percentile(rel_onset, 99) < 0.1
     assert rel_slip < 0.05
+
+
+@pytest.mark.parametrize("kind", ["absolute", "increment"])
+def test_strip_on_quasi_dynamic_boundary_matches_oracle(kind):
+    """The strip closed at S+ by the quasi-dynamic boundary relation (the static response
+    of the half-space plus radiation damping, window mode "static"): float64 against the
+    oracle's hybrid scheme with the same static window."""
+    import dataclasses
+    wl = dataclasses.replace(workloads.FAULTS["tpv3_coarse16"], window_mode="static", window_cap=1)
+    up = wl.upper()
+    cfg = StripConfig(wl.n1, wl.n3, wl.dx, wl.dt, [Layer(*BULK), Layer(*BULK)],
+                      OPlane(1, up["mu"], up["cs"], up["cp"]), window_cap=1, window_mode="static")
+    ref = ohybrid.hybrid_rupture(cfg, *wl.params(), wl.steps)
+    sb, s = make_strip(wl, [BULK, BULK], "fp64", kind)
+    got = {k: [] for k in ("traction", "slip_rate", "slip", "sliding")}
+    for n in range(wl.steps):
+        s.step()
+        for k in got:
+            got[k].append(s.read(k))
+    got = {k: torch.stack(v).cpu().numpy() for k, v in got.items()}
+    got["sliding"] = got["sliding"][:, 0] > 0.5
+    s.close()
+    sb.close()
+    worst = {k: float(np.abs(got[k] - ref[k]).max() / max(np.abs(ref[k]).max(), 1e-300))
+             for k in ("traction", "slip_rate", "slip")}
+    print(f"[strip] quasi-dynamic boundary, coarse16 fp64 {kind}: "
+          + ", ".join(f"{k} {v:.2e}" for k, v in worst.items()), flush=True)
+    np.testing.assert_array_equal(got["sliding"], ref["sliding"])
+    assert ref["sliding"].any()
+    for k, w in worst.items():
+        assert w < 1e-9, (k, w)
