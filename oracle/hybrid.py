@@ -171,8 +171,23 @@ class Strip:
         return out.reshape(u.shape)
 
 
-def hybrid_rupture(cfg: StripConfig, tau0, mu_s, mu_k, d_c, steps, weights_cache=None):
-    """Run the hybrid scheme; returns float64 histories:
+def _step_sizes(cfg, steps, dts):
+    """Per-step time steps: allowed with the quasi-dynamic (static) boundary relation,
+    which does not depend on dt (Sec. 7, variable time stepping); each step of the
+    explicit scheme then runs with its own size in the predictor, the stick traction and
+    the corrector."""
+    if dts is None:
+        return [cfg.dt] * steps
+    if cfg.window_mode != "static":
+        raise ValueError("variable time steps need the quasi-dynamic (static) boundary relation")
+    if len(dts) < steps:
+        raise ValueError("fewer time steps than steps")
+    return [float(x) for x in dts]
+
+
+def hybrid_rupture(cfg: StripConfig, tau0, mu_s, mu_k, d_c, steps, weights_cache=None, dts=None):
+    """Run the hybrid scheme; returns float64 histories (``dts``: per-step time steps, for
+    the quasi-dynamic boundary relation only):
 
     traction [N, 3, n1, n3]   fault traction (shear from the friction solve, normal tau0_2)
     sliding [N, n1, n3]       the slip branch of Eq. stickslip was taken (bool)
@@ -182,7 +197,8 @@ def hybrid_rupture(cfg: StripConfig, tau0, mu_s, mu_k, d_c, steps, weights_cache
     top_u, top_v [N, 3, n1, n3]  S+ layer displacement u_{t+1} and predicted velocity
     """
     strip = Strip(cfg)
-    n1, n3, h, dt = cfg.n1, cfg.n3, cfg.h, cfg.dt
+    n1, n3, h = cfg.n1, cfg.n3, cfg.h
+    dts = _step_sizes(cfg, steps, dts)
     top = cfg.n2
     scfg = cfg.sbim_config()
     op = PlaneOperator(scfg, 0, None, {} if weights_cache is None else weights_cache)
@@ -199,6 +215,7 @@ def hybrid_rupture(cfg: StripConfig, tau0, mu_s, mu_k, d_c, steps, weights_cache
         ("top_u", (3, n1, n3)), ("top_v", (3, n1, n3)))}
     out["sliding"] = np.zeros((steps, n1, n3), dtype=bool)
     for n in range(steps):
+        dt = dts[n]
         v_half = v + 0.5 * dt * a
         u = u + dt * v_half
         v_pred = v + dt * a
@@ -260,7 +277,7 @@ class TwoSidedConfig:
 
 
 def hybrid_rupture_two_sided(cfg: TwoSidedConfig, tau0, mu_s, mu_k, d_c, steps,
-                             weights_cache=None):
+                             weights_cache=None, dts=None):
     """The hybrid scheme with the strip on both sides of a split-node fault.
 
     Each side is its own block of elements (the fault nodes are split: the upper
@@ -280,7 +297,8 @@ def hybrid_rupture_two_sided(cfg: TwoSidedConfig, tau0, mu_s, mu_k, d_c, steps,
     """
     up = Strip(StripConfig(cfg.n1, cfg.n3, cfg.h, cfg.dt, cfg.upper, cfg.plane_up))
     lo = Strip(StripConfig(cfg.n1, cfg.n3, cfg.h, cfg.dt, cfg.lower[::-1], cfg.plane_down))
-    n1, n3, h, dt = cfg.n1, cfg.n3, cfg.h, cfg.dt
+    n1, n3, h = cfg.n1, cfg.n3, cfg.h
+    dts = _step_sizes(cfg, steps, dts)
     top, Lb = len(cfg.upper), len(cfg.lower)
     scfg = cfg.sbim_config()
     cache = {} if weights_cache is None else weights_cache
@@ -295,6 +313,7 @@ def hybrid_rupture_two_sided(cfg: TwoSidedConfig, tau0, mu_s, mu_k, d_c, steps,
         ("normal_jump", (n1, n3)))}
     out["sliding"] = np.zeros((steps, n1, n3), dtype=bool)
     for n in range(steps):
+        dt = dts[n]
         pred = {}
         for k in ("up", "lo"):
             u, v, a = state[k]
