@@ -222,6 +222,10 @@ struct StripArgs {
 };
 hipError_t launch_strip_correct(bool fp64, const StripArgs &a, hipStream_t st);
 hipError_t launch_strip_fault2(const StripArgs &a, hipStream_t st);
+hipError_t launch_strip_repredict(bool fp64, double *u_pred, const double *u_prev, double *vh,
+                                  const double *v, void *push_u, void *push_v, long long nodes,
+                                  long long cells, bool two_sided, bool increment, double dt,
+                                  double dt_old, hipStream_t st);
 hipError_t launch_tabulate(bool fp64, const Group &g, double dt, const double *gl_x,
                            const double *gl_w, hipStream_t st);
 

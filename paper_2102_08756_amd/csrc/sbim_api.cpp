@@ -1127,6 +1127,7 @@ struct sbim_strip {
   long long cells = 0, nodes = 0;
   double *node = nullptr;     // u (two buffers), half-step velocity, velocity
   int cur = 0;                // displacement buffer the next step's stencil reads
+  double dt_pred = 0;         // step size of the prediction held for the next step
   double *cell = nullptr;     // fault outputs
   double *prm = nullptr;      // tau0 (3), mu_s, mu_k, d_c
   double *stencil = nullptr;  // [n2+1][27][9]
@@ -1214,6 +1215,7 @@ int strip_clear(sbim_strip *s) {
   if (e == hipSuccess) e = hipMemsetAsync(s->push_v, 0, fb, h->stream);
   if (e != hipSuccess) return hip_fail(h, e, "clearing the strip state");
   s->cur = 0;
+  s->dt_pred = h->cfg.dt;
   s->steps = 0;
   return SBIM_OK;
 }
@@ -1390,7 +1392,17 @@ int sbim_strip_step(sbim_strip *s, double *tau_out, double *rate_out) {
   a.area = h->cfg.dx1 * h->cfg.dx3;
   a.increment = h->cfg.input_kind == SBIM_INCREMENT;
   // push of u_{t+1} (or its increment) and the predicted velocity, written by
-  // the previous step's predictor
+  // the previous step's predictor, redone first if the step size has changed
+  // since (sbim_set_dt on a quasi-dynamic handle)
+  if (h->cfg.dt != s->dt_pred) {
+    hipError_t e0 = sbim::launch_strip_repredict(
+        h->fp64, s->node + 3 * s->cur * s->nodes, s->node + 3 * (1 - s->cur) * s->nodes,
+        s->node + 6 * s->nodes, s->node + 9 * s->nodes, s->push_u, s->push_v, s->nodes,
+        s->cells, s->fault_lo >= 0, h->cfg.input_kind == SBIM_INCREMENT, h->cfg.dt,
+        s->dt_pred, h->stream);
+    if (e0 != hipSuccess) return hip_fail(h, e0, "strip predictor for the new step size");
+    s->dt_pred = h->cfg.dt;
+  }
   int rc = push_fields(h, s->push_u, s->push_v, sbim::VEL_INPUT);
   if (rc) return rc;
   hipError_t e = fft_inverse(h, h->out_spec, h->spec, s->tau_sbi, nullptr);

@@ -282,7 +282,55 @@ __global__ __launch_bounds__(kStripThreads) void strip_fault2_kernel(StripArgs a
   }
 }
 
+// A new step size before a step (the quasi-dynamic boundary relation allows
+// one): the predictor that the last step ran with its own size dt_old is redone
+// with the new size dt, one thread per node, from u_{t+1}, v_{t+1} and the
+// stored half-step velocity v_{t+1} + dt_old/2 a_{t+1}; the push inputs of S+
+// (and S-) follow.
+template <typename R>
+__global__ __launch_bounds__(kStripThreads) void strip_repredict_kernel(
+    double *u_pred, const double *u_prev, double *vh, const double *v, R *push_u, R *push_v,
+    long long nodes, long long cells, int two_sided, int increment, double dt, double dt_old) {
+  const long long id = static_cast<long long>(blockIdx.x) * kStripThreads + threadIdx.x;
+  if (id >= nodes) return;
+  const long long top0 = nodes - cells;
+  const int plane = id >= top0 ? 0 : (two_sided && id < cells ? 1 : -1);
+  const long long cell = plane == 0 ? id - top0 : id;
+  const double ratio = dt / dt_old;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const long long k = c * nodes + id;
+    const double vn = v[k];
+    const double half = vh[k] - vn;             // dt_old/2 a_{t+1}
+    const double h2 = vn + ratio * half;        // v_{t+3/2} with the new size
+    const double un = u_prev[k] + dt * h2;
+    vh[k] = h2;
+    u_pred[k] = un;
+    if (plane >= 0) {
+      const long long t = (plane * 3 + c) * cells + cell;
+      push_u[t] = static_cast<R>(increment ? dt * h2 : un);
+      push_v[t] = static_cast<R>(vn + 2.0 * ratio * half);
+    }
+  }
+}
+
 }  // namespace
+
+hipError_t launch_strip_repredict(bool fp64, double *u_pred, const double *u_prev, double *vh,
+                                  const double *v, void *push_u, void *push_v, long long nodes,
+                                  long long cells, bool two_sided, bool increment, double dt,
+                                  double dt_old, hipStream_t st) {
+  const unsigned blocks = static_cast<unsigned>((nodes + kStripThreads - 1) / kStripThreads);
+  if (fp64)
+    strip_repredict_kernel<double><<<blocks, kStripThreads, 0, st>>>(
+        u_pred, u_prev, vh, v, static_cast<double *>(push_u), static_cast<double *>(push_v),
+        nodes, cells, two_sided, increment, dt, dt_old);
+  else
+    strip_repredict_kernel<float><<<blocks, kStripThreads, 0, st>>>(
+        u_pred, u_prev, vh, v, static_cast<float *>(push_u), static_cast<float *>(push_v),
+        nodes, cells, two_sided, increment, dt, dt_old);
+  return hipGetLastError();
+}
 
 hipError_t launch_strip_fault2(const StripArgs &a, hipStream_t st) {
   const unsigned blocks = static_cast<unsigned>((a.cells + kStripThreads - 1) / kStripThreads);

@@ -462,3 +462,58 @@ def test_strip_on_quasi_dynamic_boundary_matches_oracle(kind):
     assert ref["sliding"].any()
     for k, w in worst.items():
         assert w < 1e-9, (k, w)
+
+
+@pytest.mark.parametrize("two_sided", [False, True])
+@pytest.mark.parametrize("kind", ["absolute", "increment"])
+def test_strip_with_variable_steps_matches_oracle(two_sided, kind):
+    """The quasi-dynamic boundary relation with a new step size before most steps
+    (sbim_set_dt; every fourth step repeats the previous size): the strip redoes its
+    prediction for the new size.  Float64 against the oracle's strip with the same step
+    sequence, one-sided and two-sided."""
+    import dataclasses
+    if two_sided:
+        wl = workloads.FaultWorkload("bimat16_qd", 16, 16, 750.0, 60, region=(9000.0, 9000.0),
+                                     lower=_LO, window_mode="static", window_cap=1)
+        up_l, lo_l = [BULK, BULK], [BULK_LO, BULK_LO]
+    else:
+        wl = dataclasses.replace(workloads.FAULTS["tpv3_coarse16"], window_mode="static",
+                                 window_cap=1)
+        up_l, lo_l = [BULK, BULK], None
+    rng = np.random.default_rng(31)
+    dts = rng.uniform(0.1, 0.3, wl.steps) * wl.dx / T["cs"]
+    for k in range(4, wl.steps, 4):
+        dts[k] = dts[k - 1]
+    planes = wl.planes()
+    op = [OPlane(1, planes[0]["mu"], planes[0]["cs"], planes[0]["cp"])]
+    if two_sided:
+        op.append(OPlane(-1, planes[1]["mu"], planes[1]["cs"], planes[1]["cp"]))
+        cfg = ohybrid.TwoSidedConfig(wl.n1, wl.n3, wl.dx, wl.dt, [Layer(*L) for L in up_l],
+                                     [Layer(*L) for L in lo_l], op[0], op[1], window_cap=1,
+                                     window_mode="static")
+        ref = ohybrid.hybrid_rupture_two_sided(cfg, *wl.params(), wl.steps, dts=dts)
+    else:
+        cfg = StripConfig(wl.n1, wl.n3, wl.dx, wl.dt, [Layer(*L) for L in up_l], op[0],
+                          window_cap=1, window_mode="static")
+        ref = ohybrid.hybrid_rupture(cfg, *wl.params(), wl.steps, dts=dts)
+    sb = SBIM(Config.from_dict(wl.config_dict(), precision="fp64", input_kind=kind), device=DEV)
+    prm = [torch.tensor(a, dtype=torch.float64, device=DEV).contiguous() for a in wl.params()]
+    s = Strip(sb, up_l, *prm, layers_below=lo_l)
+    got = {k: [] for k in ("traction", "slip_rate", "slip", "sliding")}
+    for n in range(wl.steps):
+        sb.set_dt(float(dts[n]))
+        s.step()
+        for k in got:
+            got[k].append(s.read(k))
+    got = {k: torch.stack(v).cpu().numpy() for k, v in got.items()}
+    got["sliding"] = got["sliding"][:, 0] > 0.5
+    s.close()
+    sb.close()
+    worst = {k: float(np.abs(got[k] - ref[k]).max() / max(np.abs(ref[k]).max(), 1e-300))
+             for k in ("traction", "slip_rate", "slip")}
+    print(f"[strip] variable steps, {'two' if two_sided else 'one'}-sided fp64 {kind}: "
+          + ", ".join(f"{k} {v:.2e}" for k, v in worst.items()), flush=True)
+    np.testing.assert_array_equal(got["sliding"], ref["sliding"])
+    assert ref["sliding"].any()
+    for k, w in worst.items():
+        assert w < 1e-9, (k, w)
