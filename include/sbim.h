@@ -376,6 +376,10 @@ int sbim_fault_destroy(sbim_fault *f);
  * and lower copies receive -h^2 (tau - tau0) and +h^2 (tau - tau0).  Slip and
  * slip rate are then the upper minus the lower copy.
  *
+ * On a quasi-dynamic handle (SBIM_W_STATIC) the step size may change between
+ * strip steps (sbim_set_dt): each step then runs with the handle's current dt,
+ * and the prediction of step 1 made at the previous size is redone first.
+ *
  * All strip arithmetic is float64; the S+/S- push has the handle's precision.
  * Fault fields are device [rows][n1][n3] doubles; node fields
  * [3][L][n1][n3] over the storage node layers: L = layers + 1 one-sided
