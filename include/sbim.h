@@ -377,8 +377,9 @@ int sbim_fault_destroy(sbim_fault *f);
  * slip rate are then the upper minus the lower copy.
  *
  * On a quasi-dynamic handle (SBIM_W_STATIC) the step size may change between
- * strip steps (sbim_set_dt): each step then runs with the handle's current dt,
- * and the prediction of step 1 made at the previous size is redone first.
+ * strip steps (sbim_set_dt): each step then runs with the handle's current dt
+ * (the library evaluates item 1 of a step at the end of the previous one, and
+ * evaluates it again with the new size when the size has changed).
  *
  * All strip arithmetic is float64; the S+/S- push has the handle's precision.
  * Fault fields are device [rows][n1][n3] doubles; node fields
