@@ -157,6 +157,10 @@ def measure_form(wl, precision, steps, warmup, device, inputs_cache):
             # sweep_depth steps, so `achieved` counts far fewer bytes than this
             "direct_equivalent_GBs": lags * 6 * (8 if precision == "fp64" else 4)
                                      / (conv_ms * 1e-3) / 1e9,
+            "note": (f"achieved counts the bytes of the time-blocked sweep, which reads each "
+                     f"history entry once per {info['sweep_depth']} steps; "
+                     f"direct_equivalent_GBs is the history bandwidth a per-step convolution "
+                     f"would need for the same work in the same launch time"),
         },
         "info": info,
     }
