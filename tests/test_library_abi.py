@@ -86,3 +86,33 @@ def test_null_arguments_rejected():
     assert lib.sbim_strip_reset(None) == B.SBIM_E_INVALID
     assert lib.sbim_strip_destroy(None) == B.SBIM_OK
     assert lib.sbim_set_dt(None, 0.1) == B.SBIM_E_INVALID
+
+
+STRUCTS = {"sbim_plane": B._Plane, "sbim_config": B._Config, "sbim_info": B._Info,
+           "sbim_fault_params": B._FaultParams, "sbim_strip_config": B._StripConfig}
+
+
+def test_binding_structs_match_the_header_layout(tmp_path):
+    """The ctypes structures of the binding have the sizes and field offsets that a C
+    compiler gives the header's structs (a program built with gcc prints them)."""
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        pytest.skip("no C compiler")
+    body = []
+    for cname, cls in STRUCTS.items():
+        body.append(f'printf("{cname} %zu\\n", sizeof({cname}));')
+        for fname, _ in cls._fields_:
+            body.append(f'printf("{cname}.{fname} %zu\\n", offsetof({cname}, {fname}));')
+    src = tmp_path / "layout.c"
+    src.write_text("#include <stdio.h>\n#include <stddef.h>\n#include \"sbim.h\"\nint main(void) {\n"
+                   + "\n".join(body) + "\nreturn 0;\n}\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.dirname(HEADER), str(src), "-o", str(exe)],
+                   check=True)
+    got = dict(line.split() for line in subprocess.run([str(exe)], check=True, capture_output=True,
+                                                          text=True).stdout.splitlines())
+    for cname, cls in STRUCTS.items():
+        assert int(got[cname]) == ctypes.sizeof(cls), cname
+        for fname, _ in cls._fields_:
+            assert int(got[f"{cname}.{fname}"]) == getattr(cls, fname).offset, (cname, fname)
