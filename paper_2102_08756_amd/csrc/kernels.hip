@@ -252,10 +252,10 @@ __device__ __forceinline__ void sweep_item(const SweepArgs &a, long long item) {
       if (it + S >= per) break;
       load_rows<R, S>(ra, rowp, i + 2 * S, wl);
       sweep_span<R, S, G>(sums, rb, ra, hp, x, cap, dstep, dwrap);
-      // compensated form: fold the plain partial sums of the last 4S lags
-      // (every other pass of this loop; the branch is uniform over the wavefront)
+      // compensated form: fold the plain partial sums of the last 6S lags
+      // (every third pass of this loop; the branch is uniform over the wavefront)
       if constexpr (COMP) {
-        if ((it / (2 * S)) & 1) {
+        if ((it / (2 * S)) % 3 == 2) {
 #pragma unroll
           for (int s = 0; s < S; ++s)
 #pragma unroll
