@@ -1,0 +1,51 @@
+"""CPU checks of bench.py's host logic: the kernel-source hash that ties the recorded
+HBM-traffic counters to the kernels, the reading of those counters, and the one-GPU
+guard of the command line."""
+import json
+import os
+import shutil
+import subprocess
+import sys
+
+import bench
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _copy_sources(tmp_path):
+    src = os.path.join(ROOT, "paper_2102_08756_amd", "csrc")
+    dst = tmp_path / "paper_2102_08756_amd" / "csrc"
+    shutil.copytree(src, dst)
+    return dst
+
+
+def test_kernel_hash_ignores_comments_but_not_code(tmp_path, monkeypatch):
+    base = bench.kernel_source_hash()
+    dst = _copy_sources(tmp_path)
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    assert bench.kernel_source_hash() == base
+    k = dst / "kernels.hip"
+    k.write_text(k.read_text() + "\n// a comment only\n\n")
+    assert bench.kernel_source_hash() == base
+    k.write_text(k.read_text() + "\nconstexpr int kUnused = 1;\n")
+    assert bench.kernel_source_hash() != base
+
+
+def test_traffic_is_read_only_for_the_recorded_kernels(tmp_path, monkeypatch):
+    prof = tmp_path / "profiles"
+    prof.mkdir()
+    h = bench.kernel_source_hash()
+    line = "two_planes512_w1000 fp32_comp 6.4e+08 312500.0 52000.0 2000\n"
+    (prof / "step_kernel_traffic.txt").write_text(f"# header\nkernel_source_hash={h}\n{line}")
+    monkeypatch.setattr(bench, "PROFILES", str(prof))
+    assert bench.read_traffic("two_planes512_w1000", "fp32_comp") == 6.4e8
+    assert bench.read_traffic("two_planes512_w1000", "fp64") is None
+    (prof / "step_kernel_traffic.txt").write_text(f"kernel_source_hash=0000000000000000\n{line}")
+    assert bench.read_traffic("two_planes512_w1000", "fp32_comp") is None
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in json.loads(r.stdout.strip().splitlines()[-1])["error"]
