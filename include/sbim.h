@@ -200,6 +200,14 @@ int sbim_set_dt(sbim_handle *h, double dt);
 int sbim_get_info(const sbim_handle *h, sbim_info *out);
 
 /*
+ * sbim_count_nonfinite: the number of infinities and NaNs in a device field
+ * [P][3][n1][n3] of the handle's precision (a displacement or velocity before it
+ * is pushed, or a traction output) into *count (host).  Synchronises the
+ * stream.  A diagnostic beside the step: the step itself does not check values.
+ */
+int sbim_count_nonfinite(sbim_handle *h, const void *field, long long *count);
+
+/*
  * Snapshots for checkpointing: the full forward state (ring, running state,
  * pending history sums of the coming steps, traction spectrum of the last
  * step, step counter) is sbim_state_bytes() bytes.  save/load

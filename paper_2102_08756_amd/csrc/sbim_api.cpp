@@ -17,6 +17,7 @@
 #include <vector>
 
 #include "internal.h"
+#include "checks.h"
 
 using sbim::Group;
 
@@ -714,6 +715,27 @@ int sbim_set_dt(sbim_handle *h, double dt) {
   if (h->cfg.window_mode != SBIM_W_STATIC)
     return fail(h, SBIM_E_STATE, "the time step of a dynamic handle is fixed at sbim_init");
   h->cfg.dt = dt;
+  return SBIM_OK;
+}
+
+int sbim_count_nonfinite(sbim_handle *h, const void *field, long long *count) {
+  if (!h) return fail(nullptr, SBIM_E_INVALID, "handle is NULL");
+  if (!field || !count) return fail(h, SBIM_E_INVALID, "field or count is NULL");
+  const long long n = static_cast<long long>(h->cfg.nplanes) * 3 * h->n1 * h->n3;
+  long long *partial = nullptr;
+  hipError_t e = hipMalloc(&partial, sizeof(long long) * sbim::kCheckBlocks);
+  if (e != hipSuccess) return fail(h, SBIM_E_OOM, "count buffer: %s", hipGetErrorString(e));
+  std::vector<long long> part(sbim::kCheckBlocks, 0);
+  e = sbim::launch_count_nonfinite(h->fp64, field, n, partial, h->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(part.data(), partial, sizeof(long long) * part.size(),
+                       hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  (void)hipFree(partial);
+  if (e != hipSuccess) return hip_fail(h, e, "non-finite count");
+  long long c = 0;
+  for (long long v : part) c += v;
+  *count = c;
   return SBIM_OK;
 }
 

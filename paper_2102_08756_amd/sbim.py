@@ -29,7 +29,7 @@ ERROR_NAMES = {SBIM_E_INVALID: "SBIM_E_INVALID", SBIM_E_OOM: "SBIM_E_OOM",
 EXPORTS = (
     "sbim_init", "sbim_push_displacement", "sbim_tractions", "sbim_backward",
     "sbim_backward_reset", "sbim_reset", "sbim_destroy", "sbim_last_error", "sbim_set_stream",
-    "sbim_set_dt",
+    "sbim_set_dt", "sbim_count_nonfinite",
     "sbim_get_info", "sbim_state_bytes", "sbim_save_state", "sbim_load_state", "sbim_step_work",
     "sbim_mode_kernel", "sbim_profile_conv", "sbim_conv_timing",
     "sbim_fault_create", "sbim_fault_step", "sbim_fault_read", "sbim_fault_reset",
@@ -101,6 +101,7 @@ def load_library(path=LIB_PATH):
         "sbim_set_stream": (i, [vp, vp]),
         "sbim_set_dt": (i, [vp, d]),
         "sbim_get_info": (i, [vp, ctypes.POINTER(_Info)]),
+        "sbim_count_nonfinite": (i, [vp, vp, ctypes.POINTER(ll)]),
         "sbim_state_bytes": (ll, [vp]),
         "sbim_save_state": (i, [vp, vp]),
         "sbim_load_state": (i, [vp, vp]),
@@ -257,6 +258,15 @@ class SBIM:
         self._sync_stream()
         self._check(self._L.sbim_backward(self._h, _ptr(g), _ptr(du), _ptr(dv)))
         return (du, dv) if with_velocity else du
+
+    def count_nonfinite(self, field):
+        """Infinities and NaNs in a [P][3][n1][n3] field of the handle's dtype (library
+        kernel; synchronises)."""
+        self._field(field, "field")
+        n = ctypes.c_longlong(0)
+        self._sync_stream()
+        self._check(self._L.sbim_count_nonfinite(self._h, _ptr(field), ctypes.byref(n)))
+        return n.value
 
     def set_dt(self, dt):
         """Time step of the following pushes (quasi-dynamic handles only)."""

@@ -138,6 +138,27 @@ def test_adjoint_fp64(kind, with_v):
     sb.close()
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_count_nonfinite(precision):
+    """The library's non-finite count of a field: zero for finite values, the number of
+    planted infinities and NaNs otherwise, and a NaN pushed into the history shows up in
+    the tractions."""
+    cfg_d = SMALL["two_planes_shared"]
+    sb = SBIM(Config.from_dict(cfg_d, precision=precision), device=DEV)
+    u = torch.randn(sb.shape, dtype=sb.dtype, device=DEV)
+    assert sb.count_nonfinite(u) == 0
+    bad = u.clone()
+    flat = bad.view(-1)
+    flat[0], flat[17], flat[-1] = float("nan"), float("inf"), float("-inf")
+    flat[1000] = float("nan")
+    assert sb.count_nonfinite(bad) == 4
+    sb.push(u)
+    assert sb.count_nonfinite(sb.tractions()) == 0
+    sb.push(bad)
+    assert sb.count_nonfinite(sb.tractions()) > 0
+    sb.close()
+
+
 def test_deterministic_bitwise():
     cfg_d = dict(SMALL["two_planes_shared"], input_kind="increment")
     u, _, _ = _inputs(cfg_d, 15, 6)
