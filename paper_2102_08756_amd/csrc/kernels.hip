@@ -225,7 +225,7 @@ __device__ __forceinline__ void sweep_item(const SweepArgs &a, long long item) {
 
   constexpr int G = sweep_group<R, S, COMP>();
   // plain form: the running sums; compensated form: the products since the
-  // last fold into the compensated accumulators (2S lags, one span pair)
+  // last fold into the compensated accumulators (up to 6S lags, three span pairs)
   R sums[S][kSums];
 #pragma unroll
   for (int s = 0; s < S; ++s)
