@@ -2,19 +2,25 @@
 
 Workload (default): two boundary planes of 512 x 512, three displacement
 components, mu = 1, c_s = 1, c_p = sqrt(3), dx = 1, dt = 0.2, history window
-1000 steps, 2000 time steps; inputs are the seeded |k|^-2 increment fields
+1000 steps, a 2000-step job; inputs are the seeded |k|^-2 increment fields
 (bank of 64 per plane and component) plus a Gaussian ramp pulse of width 20
 cells on u1.  A "step" is one push of the displacement plus one traction
-evaluation (forward FFT, history update, convolution, inverse FFT); the timed
-region is the whole 2000-step job from an empty history, inputs resident in
-HBM.  Reported: mode-history-steps per second (sum over steps, planes and modes
-of min(W, n+1)) for the compensated float32 form (headline), plain float32 and
-float64, the float32-vs-float64 relative L2 error, the HBM roofline fraction
-of the dominant kernel (the launch that pushes a step, completes its traction
-spectrum and runs the history sweep), and the float64 CPU oracle on a bounded
-sample.  A second leg ("rupture") times the stand-alone dynamic rupture of the
-paper's TPV3 setup (1024 x 1024 cells of 50 m, 2000 steps) through the fault
-entry points.
+evaluation (forward FFT, history update, convolution, inverse FFT).
+
+The timed region is the steady state of the job: the steps run from an empty
+history, the first ones untimed until the window is full and only the last
+``--steps`` of the job are left (every timed step then sums its whole
+1000-lag window), and those are timed with the inputs resident in HBM.
+Reported: mode-history-steps per second (sum over the timed steps, planes and
+modes of min(W, n+1)) for the compensated float32 form (headline), plain
+float32 and float64; the float32-vs-float64 relative L2 error over the whole
+2000-step job; the HBM roofline fraction of the dominant kernel (the launch
+that pushes a step, completes its traction spectrum and runs the history
+sweep) over the same timed steps; and the float64 CPU oracle on a bounded
+sample.  Further legs time the stand-alone dynamic rupture of the paper's
+TPV3 setup (1024 x 1024 cells of 50 m, 2000 steps) through the fault entry
+points, the hybrid strip and the quasi-dynamic limit on it, and the adjoint
+on the 256^2 job.
 """
 from __future__ import annotations
 
@@ -51,25 +57,51 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def read_traffic(workload, precision):
-    """Per-dispatch HBM bytes of the step launch (push, traction, history sweep) from the
-    committed rocprofv3 counter summary, scaled by the copy-kernel calibration; None if absent or taken on other
-    kernel sources."""
+def read_traffic(workload, precision, regime="steady"):
+    """Per-dispatch HBM bytes of the step launch (push, traction, history sweep) in the
+    given regime from the committed rocprofv3 counter summary, scaled by the copy-kernel
+    calibration; None if absent or taken on other kernel sources."""
     path = os.path.join(PROFILES, "step_kernel_traffic.txt")
     if not os.path.exists(path):
         return None
-    want = f"{workload} {precision} "
+    want = f"{workload} {precision} {regime} "
     src = None
     val = None
     for line in open(path):
         if line.startswith("kernel_source_hash"):
             src = line.split("=", 1)[1].strip()
         if line.startswith(want):
-            parts = line.split()
-            val = float(parts[2])
+            val = float(line.split()[3])
     if src != kernel_source_hash() or val is None:
         return None
     return val
+
+
+def host_cpu():
+    """Cores this process may run on, the machine's logical CPU count and the CPU model."""
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        usable = os.cpu_count()
+    model = None
+    try:
+        import subprocess
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except Exception:
+        pass
+    if model is None:
+        try:
+            for line in open("/proc/cpuinfo"):
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+        except OSError:
+            pass
+    return {"nproc": usable, "logical_cpus": os.cpu_count(), "model": model}
 
 
 class Inputs:
@@ -97,12 +129,25 @@ class Inputs:
 
 
 def run_job(sb, inputs, steps, tau):
-    for n in range(steps):
+    for n in steps:
         sb.push(inputs(n))
         sb.tractions(out=tau)
 
 
+def steady_window(wl, timed):
+    """First timed step of the steady state: the last ``timed`` steps of the job, but never
+    before every mode's window is full (step W_cap - 1 on); a request for more steps than the
+    job has at a full window runs past its end (each step then costs the same)."""
+    return max(wl.steps - timed, wl.window_cap - 1, 0)
+
+
+def default_timed_steps(wl):
+    return max(1, wl.steps - wl.window_cap)
+
+
 def measure_form(wl, precision, steps, warmup, device, inputs_cache):
+    """Time ``steps`` steps of the job at a full history window: ``warmup`` steps and a
+    reset, the job's first steps untimed (the window fills), then the timed ones."""
     import torch
     from paper_2102_08756_amd import SBIM, Config
     cfg = Config.from_dict(wl.config_dict(), precision=precision)
@@ -114,21 +159,24 @@ def measure_form(wl, precision, steps, warmup, device, inputs_cache):
         inputs_cache[key] = Inputs(wl, cfg.dtype, device)
     inputs = inputs_cache[key]
     tau = sb.new_field()
-    # warmup (also grows the conv event pool), then reset to an empty history
+    n0 = steady_window(wl, steps)
+    # warmup, then the job from an empty history; the launches are bracketed by events
+    # from here on, so the event pool has grown before the timed steps
     sb.profile_conv(True)
-    run_job(sb, inputs, warmup, tau)
+    run_job(sb, inputs, range(warmup), tau)
     sb.reset()
-    sb.profile_conv(True)
+    run_job(sb, inputs, range(n0), tau)
+    sb.profile_conv(True)              # synchronises and restarts the launch timing
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    run_job(sb, inputs, steps, tau)
+    run_job(sb, inputs, range(n0, n0 + steps), tau)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     conv_ms, launches = sb.conv_timing()
     sb.profile_conv(False)
     lags = 0.0
     conv_bytes = 0.0
-    for n in range(steps):
+    for n in range(n0, n0 + steps):
         a, b = sb.step_work(n)
         lags += a
         conv_bytes += b
@@ -138,29 +186,40 @@ def measure_form(wl, precision, steps, warmup, device, inputs_cache):
     torch.cuda.empty_cache()
     gbs = conv_bytes / (conv_ms * 1e-3) / 1e9
     traffic = read_traffic(wl.name, precision)
+    r = 8 if precision == "fp64" else 4
+    P = len(wl.planes)
+    shared = 1 if P == 1 or any(p != wl.planes[0] for p in wl.planes[1:]) else P
+    # bytes a direct (per-step) convolution streams for the same work: the whole window of
+    # history (3 complex per plane, mode and lag) and the kernel rows (4 reals per mode and
+    # lag, read once for the planes that share them)
+    direct_bytes = lags * (6 * r + 4 * r / shared)
     return {
         "value": lags / elapsed,
         "ms_per_step": 1e3 * elapsed / steps,
         "elapsed_s": elapsed,
         "init_s": t_init,
         "mode_lags": lags,
+        "first_timed_step": n0,
         "roofline": {
             "kernel": f"step_kernel (push, traction and history sweep, depth {info['sweep_depth']})",
             "bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": gbs / HBM_PEAK_GBS,
             "traffic": traffic,
+            "regime": (f"steady state: steps {n0}..{n0 + steps - 1} of the job, every mode's "
+                       f"window full; achieved and traffic over these launches only"),
             "algorithmic_bytes_per_launch": conv_bytes / launches if launches else None,
+            "traffic_over_algorithmic": (traffic * launches / conv_bytes
+                                         if traffic and launches else None),
             "avg_launch_ms": conv_ms / launches if launches else None,
             "launches": launches,
-            # the history bytes alone that a per-step (direct) convolution would stream for
-            # the same work in the same launch time: the sweep reads each entry once per
-            # sweep_depth steps, so `achieved` counts far fewer bytes than this
-            "direct_equivalent_GBs": lags * 6 * (8 if precision == "fp64" else 4)
-                                     / (conv_ms * 1e-3) / 1e9,
-            "note": (f"achieved counts the bytes of the time-blocked sweep, which reads each "
-                     f"history entry once per {info['sweep_depth']} steps; "
-                     f"direct_equivalent_GBs is the history bandwidth a per-step convolution "
-                     f"would need for the same work in the same launch time"),
+            "direct_convolution_equivalent": {
+                "GBs": direct_bytes / (conv_ms * 1e-3) / 1e9,
+                "x_hbm_peak": direct_bytes / (conv_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                "note": (f"the history and kernel-row bytes a per-step convolution would stream "
+                         f"for the same work in the same launch time; the sweep reads each "
+                         f"history entry once per {info['sweep_depth']} steps, so it is not a "
+                         f"fraction of the HBM peak"),
+            },
         },
         "info": info,
     }
@@ -311,7 +370,7 @@ def measure_hybrid(fw, precision, device, layers=2, warmup=20):
             "init_s": t_init, "_slip": slip}
 
 
-def rupture_leg(fw, forms, device):
+def rupture_leg(fw, forms, device, bimaterial=False):
     out = {"workload": fw.name, "n1": fw.n1, "n3": fw.n3, "dx_m": fw.dx, "dt_s": fw.dt,
            "time_steps": fw.steps, "window_cap": fw.window_cap or fw.steps,
            "lower_half_space": "mirror image" if fw.lower is None else "own material", "forms": {}}
@@ -348,7 +407,7 @@ def rupture_leg(fw, forms, device):
     print(f"[bench] hybrid {fw.name} {p}: {hy['ms_per_step']:.3f} ms/step "
           f"({hy['layers']} element layers), final slip vs boundary integral "
           f"{hy['final_slip_rel_l2_vs_boundary_integral']:.2e}", file=sys.stderr, flush=True)
-    if fw.lower is None:
+    if bimaterial and fw.lower is None:
         # the same rupture between two materials (the lower one slower): the stand-alone
         # two-plane rupture and the two-sided strip, two element layers on each side
         import dataclasses
@@ -531,6 +590,7 @@ def cpu_baseline(wl, sample_modes=64, seed=0):
     t_dft, t_conv, step_s = one_step()
     out = {
         "value": lags / step_s, "unit": UNIT, "cores": cores, "kind": "oracle",
+        "host": host_cpu(),
         "sample": (f"one steady-state step (W={W}) of {wl.name}: naive DFT forward+inverse of all "
                    f"{P}x3 fields timed in full ({t_dft:.2f} s); direct convolution timed on "
                    f"{sample_modes} random modes per plane ({t_conv:.3f} s) and scaled to all "
@@ -550,7 +610,9 @@ def cpu_baseline(wl, sample_modes=64, seed=0):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=None, help="timed steps (default: the whole job)")
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed steps at the end of the job, every mode's window full "
+                         "(default: all steps of the job after the window has filled)")
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--workload", type=int, default=2)
     ap.add_argument("--forms", default="fp32_comp,fp32,fp64")
@@ -559,6 +621,8 @@ def main():
     ap.add_argument("--rupture-forms", default="fp32_comp,fp64",
                     help="forms of the rupture leg on the fault workload (empty: skip it)")
     ap.add_argument("--rupture", default="tpv3_1024", help="fault workload of the rupture leg")
+    ap.add_argument("--bimaterial", action="store_true",
+                    help="also time the rupture between two materials (stand-alone and two-sided strip)")
     ap.add_argument("--adjoint-forms", default="fp64,fp32_comp",
                     help="forms of the adjoint leg on the 256^2 job (empty: skip it)")
     ap.add_argument("--scaling", action="store_true",
@@ -588,12 +652,12 @@ def main():
         print(json.dumps({"copy_bytes_each_way": 4 * n, "dispatches": 5}))
         return
     wl = workloads.WORKLOADS[args.workload]
-    steps = args.steps or wl.steps
+    steps = args.steps or default_timed_steps(wl)
     forms = [f for f in args.forms.split(",") if f]
     rforms = [f for f in args.rupture_forms.split(",") if f]
     if not forms:                       # the rupture leg alone (profiling runs)
-        print(json.dumps({"rupture": rupture_leg(workloads.FAULTS[args.rupture], rforms, device)
-                          if rforms else None}))
+        print(json.dumps({"rupture": rupture_leg(workloads.FAULTS[args.rupture], rforms, device,
+                                                 args.bimaterial) if rforms else None}))
         return
     cache = {}
     res = {}
@@ -608,9 +672,10 @@ def main():
         for dt in (torch.float32, torch.float64):
             if dt not in cache:
                 cache[dt] = Inputs(wl, dt, device)
-        acc = accuracy(wl, steps, device, cache, [f for f in forms if f != "fp64"])
+        acc = accuracy(wl, wl.steps, device, cache, [f for f in forms if f != "fp64"])
         print(f"[bench] accuracy: {acc}", file=sys.stderr, flush=True)
-    rup = rupture_leg(workloads.FAULTS[args.rupture], rforms, device) if rforms else None
+    rup = (rupture_leg(workloads.FAULTS[args.rupture], rforms, device, args.bimaterial)
+           if rforms else None)
     aforms = [f for f in args.adjoint_forms.split(",") if f]
     adj = adjoint_leg(device, aforms) if aforms else None
     cpu = None if args.no_cpu else cpu_baseline(wl)
@@ -623,10 +688,14 @@ def main():
         "dtype": "f64" if head == "fp64" else "f32", "data": "synthetic",
         "config": {"workload": wl.name, "n1": wl.n1, "n3": wl.n3, "planes": len(wl.planes),
                    "window_cap": wl.window_cap, "window_mode": wl.window_mode,
-                   "time_steps": steps, "precision": head, "input_kind": wl.input_kind},
+                   "time_steps": wl.steps, "timed_steps": steps,
+                   "first_timed_step": r["first_timed_step"],
+                   "mode_lags_per_step": r["mode_lags"] / steps,
+                   "precision": head, "input_kind": wl.input_kind},
         "roofline": {k: v for k, v in r["roofline"].items()},
         "cpu_baseline": cpu,
         "forms": {f: {"value": res[f]["value"], "ms_per_step": res[f]["ms_per_step"],
+                      "mode_lags_per_step": res[f]["mode_lags"] / steps,
                       "step_kernel_GBs": res[f]["roofline"]["achieved"],
                       "step_kernel_frac": res[f]["roofline"]["frac"],
                       "sweep_depth": res[f]["info"]["sweep_depth"], "init_s": res[f]["init_s"],

@@ -184,7 +184,12 @@ int sbim_destroy(sbim_handle *h);
 /* Message of the last failure on h (or of the last failed sbim_init when h is NULL). */
 const char *sbim_last_error(const sbim_handle *h);
 
-/* Use another HIP stream for subsequent calls (the previous one is not synchronised). */
+/*
+ * Use another HIP stream for subsequent calls.  Work queued on the new stream
+ * is ordered after everything already queued on the old one (an event recorded
+ * there and waited on by the new stream); the host is not synchronised.
+ * SBIM_E_DEVICE if that ordering cannot be set up (the stream is then unchanged).
+ */
 int sbim_set_stream(sbim_handle *h, void *stream);
 
 /*

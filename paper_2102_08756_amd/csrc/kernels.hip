@@ -671,7 +671,10 @@ hipError_t step_launch_s(const sbim_handle *h, const Group &g, const SweepArgs &
   const long long sweep_items =
       (sa.nphase + 7) / 8 * 8 * (sweep_lag_groups<R, S, T, COMP>() * T) * g.np;
   const long long items = sweep_items + g.nblocks * g.np;
-  if (ev0) (void)hipEventRecord(ev0, h->stream);
+  if (ev0) {
+    const hipError_t e = hipEventRecord(ev0, h->stream);
+    if (e != hipSuccess) return e;
+  }
   if constexpr (!COMP && sizeof(R) == 4 && S == 6 && T == 2)
     hipLaunchKernelGGL((step_kernel_w4<R, S, T, COMP>), dim3(static_cast<unsigned>(items)),
                        dim3(kLanes), 0, h->stream, sa, ma, sweep_items, g.nblocks);
@@ -681,8 +684,9 @@ hipError_t step_launch_s(const sbim_handle *h, const Group &g, const SweepArgs &
   else
     hipLaunchKernelGGL((step_kernel<R, S, T, COMP>), dim3(static_cast<unsigned>(items)),
                        dim3(kLanes), 0, h->stream, sa, ma, sweep_items, g.nblocks);
-  if (ev1) (void)hipEventRecord(ev1, h->stream);
-  return hipGetLastError();
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess && ev1) e = hipEventRecord(ev1, h->stream);
+  return e;
 }
 
 template <typename R, bool COMP>

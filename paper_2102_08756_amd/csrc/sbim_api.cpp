@@ -334,29 +334,51 @@ hipError_t fft_inverse(sbim_handle *h, const void *spec, void *scratch, void *fi
                                   h->stream);
 }
 
+// Adjoint buffers of every group, allocated and cleared on first use.  A group
+// is complete once its state_adj is set; a failed allocation or clear frees
+// that group's partial buffers again, so a later call starts from scratch.
 int ensure_adjoint(sbim_handle *h) {
   for (int i = 0; i < h->ngroups; ++i) {
     Group &g = h->g[i];
     if (g.state_adj) continue;
     const size_t rb = static_cast<size_t>(ring_bytes(h, g));
     const size_t sb = static_cast<size_t>(state_bytes_g(g));
+    const size_t pb = static_cast<size_t>(pending_bytes(h, g));
     size_t free_b = 0, total_b = 0;
-    const size_t need = rb + 2 * sb + static_cast<size_t>(pending_bytes(h, g) + out_spec_bytes(h));
+    const size_t need = rb + 2 * sb + pb + (h->out_adj ? 0 : static_cast<size_t>(out_spec_bytes(h)));
     if (hipMemGetInfo(&free_b, &total_b) == hipSuccess && need > free_b)
       return fail(h, SBIM_E_OOM, "adjoint buffers need %zu bytes, %zu free", need, free_b);
+    void *ring = nullptr, *pending = nullptr;
+    double *state = nullptr, *lam = nullptr;
+    auto release = [&]() {
+      void *ptrs[] = {ring, pending, state, lam};
+      for (void *q : ptrs)
+        if (q) (void)hipFree(q);
+    };
     hipError_t e;
-    const size_t pb = static_cast<size_t>(pending_bytes(h, g));
-    if ((e = dev_alloc_bytes(&g.ring_adj, rb)) != hipSuccess ||
-        (e = dev_alloc_bytes(&g.pending_adj, pb)) != hipSuccess ||
-        (e = dev_alloc(&g.state_adj, sb / 8)) != hipSuccess ||
-        (e = dev_alloc(&g.lam_adj, sb / 8)) != hipSuccess ||
-        (!h->out_adj &&
-         (e = dev_alloc_bytes(&h->out_adj, out_spec_bytes(h))) != hipSuccess)) {
+    if ((e = dev_alloc_bytes(&ring, rb)) != hipSuccess ||
+        (e = dev_alloc_bytes(&pending, pb)) != hipSuccess ||
+        (e = dev_alloc(&state, sb / 8)) != hipSuccess ||
+        (e = dev_alloc(&lam, sb / 8)) != hipSuccess) {
+      release();
       return fail(h, SBIM_E_OOM, "adjoint allocation failed: %s", hipGetErrorString(e));
     }
-    if (rb) (void)hipMemsetAsync(g.ring_adj, 0, rb, h->stream);
-    (void)hipMemsetAsync(g.state_adj, 0, sb, h->stream);
-    (void)hipMemsetAsync(g.lam_adj, 0, sb, h->stream);
+    if (!h->out_adj && (e = dev_alloc_bytes(&h->out_adj, out_spec_bytes(h))) != hipSuccess) {
+      release();
+      return fail(h, SBIM_E_OOM, "adjoint allocation failed: %s", hipGetErrorString(e));
+    }
+    e = rb ? hipMemsetAsync(ring, 0, rb, h->stream) : hipSuccess;
+    if (e == hipSuccess) e = hipMemsetAsync(state, 0, sb, h->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(lam, 0, sb, h->stream);
+    if (e != hipSuccess) {
+      (void)hipStreamSynchronize(h->stream);
+      release();
+      return hip_fail(h, e, "clearing adjoint state");
+    }
+    g.ring_adj = ring;
+    g.pending_adj = pending;
+    g.lam_adj = lam;
+    g.state_adj = state;
   }
   return SBIM_OK;
 }
@@ -444,7 +466,6 @@ int sbim_init(const sbim_config *cfg, sbim_handle **out) {
     delete h;
     return fail(nullptr, SBIM_E_DEVICE, "hipGetDevice: %s", hipGetErrorString(e));
   }
-
   // material groups: planes with equal (c_s, c_p) share kernel tables and one pass
   for (int p = 0; p < cfg->nplanes; ++p) {
     const sbim_plane &pl = cfg->plane[p];
@@ -704,7 +725,18 @@ const char *sbim_last_error(const sbim_handle *h) {
 
 int sbim_set_stream(sbim_handle *h, void *stream) {
   if (!h) return fail(nullptr, SBIM_E_INVALID, "handle is NULL");
-  h->stream = static_cast<hipStream_t>(stream);
+  hipStream_t next = static_cast<hipStream_t>(stream);
+  if (next != h->stream) {
+    // work queued on the new stream starts after everything queued so far
+    hipEvent_t ev;
+    hipError_t e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    if (e != hipSuccess) return hip_fail(h, e, "sbim_set_stream: hipEventCreate");
+    e = hipEventRecord(ev, h->stream);
+    if (e == hipSuccess) e = hipStreamWaitEvent(next, ev, 0);
+    (void)hipEventDestroy(ev);
+    if (e != hipSuccess) return hip_fail(h, e, "sbim_set_stream: ordering after the old stream");
+  }
+  h->stream = next;
   h->cfg.stream = stream;
   return SBIM_OK;
 }

@@ -273,6 +273,7 @@ class SBIM:
         self._check(self._L.sbim_set_dt(self._h, float(dt)))
 
     def backward_reset(self):
+        self._sync_stream()
         self._check(self._L.sbim_backward_reset(self._h))
 
     def reset(self):
