@@ -213,6 +213,25 @@ int sbim_get_info(const sbim_handle *h, sbim_info *out);
 int sbim_count_nonfinite(sbim_handle *h, const void *field, long long *count);
 
 /*
+ * sbim_count_nonfinite_noalloc: the same count, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  It calls no hipMalloc, hipFree or other
+ * allocating routine: the per-work-group partial counts go to a static device
+ * array of the library (1024 counts, 8 KiB; each GPU the library runs on holds
+ * its own copy until the process ends, its address looked up once per device
+ * by sbim_init), and a second one-work-group kernel writes their sum to
+ * *count_dev, a caller-owned device int64.  Asynchronous on the handle's
+ * stream (no host synchronisation); the count is there once the stream has
+ * passed this call.  The scratch size does not depend on the field size, so
+ * every field the handle accepts fits.  Calls that overlap on one GPU (other
+ * streams, other handles, other threads) share the array and race: order them.
+ * Errors: SBIM_E_INVALID for a NULL handle, field or count_dev; SBIM_E_STATE
+ * when the current device is not the handle's; SBIM_E_DEVICE for a launch
+ * failure.
+ */
+int sbim_count_nonfinite_noalloc(sbim_handle *h, const void *field, long long *count_dev);
+
+/*
  * Snapshots for checkpointing: the full forward state (ring, running state,
  * pending history sums of the coming steps, traction spectrum of the last
  * step, step counter) is sbim_state_bytes() bytes.  save/load

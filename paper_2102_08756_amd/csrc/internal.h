@@ -94,6 +94,7 @@ struct sbim_handle {
   void *spec_v = nullptr;         // same for the velocity; second traction output of backward
   void *out_spec = nullptr;       // [P][3][h3][n1] complex: traction spectrum of the last push
   void *out_adj = nullptr;        // the same for the last sbim_backward (allocated on first use)
+  long long *count_scratch = nullptr;  // device address of the static partial counts (checks.hip)
   bool profile = false;
   std::vector<hipEvent_t> ev_start, ev_stop;  // reusable pool
   size_t ev_used = 0;                          // pairs recorded since sbim_profile_conv

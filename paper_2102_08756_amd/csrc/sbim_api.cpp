@@ -466,6 +466,14 @@ int sbim_init(const sbim_config *cfg, sbim_handle **out) {
     delete h;
     return fail(nullptr, SBIM_E_DEVICE, "hipGetDevice: %s", hipGetErrorString(e));
   }
+  // the device address of the allocation-free count's static scratch (once per device)
+  e = sbim::count_scratch_address(h->device, &h->count_scratch);
+  if (e != hipSuccess) {
+    delete h;
+    return fail(nullptr, SBIM_E_DEVICE, "hipGetSymbolAddress(scratch) on device %d: %s",
+                h->device, hipGetErrorString(e));
+  }
+
   // material groups: planes with equal (c_s, c_p) share kernel tables and one pass
   for (int p = 0; p < cfg->nplanes; ++p) {
     const sbim_plane &pl = cfg->plane[p];
@@ -768,6 +776,21 @@ int sbim_count_nonfinite(sbim_handle *h, const void *field, long long *count) {
   long long c = 0;
   for (long long v : part) c += v;
   *count = c;
+  return SBIM_OK;
+}
+
+int sbim_count_nonfinite_noalloc(sbim_handle *h, const void *field, long long *count_dev) {
+  if (!h) return fail(nullptr, SBIM_E_INVALID, "handle is NULL");
+  if (!field || !count_dev) return fail(h, SBIM_E_INVALID, "field or count_dev is NULL");
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(h, e, "hipGetDevice");
+  if (dev != h->device)
+    return fail(h, SBIM_E_STATE, "current device %d is not the handle's device %d", dev, h->device);
+  const long long n = static_cast<long long>(h->cfg.nplanes) * 3 * h->n1 * h->n3;
+  e = sbim::launch_count_nonfinite_static(h->fp64, field, n, h->count_scratch, count_dev,
+                                          h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "non-finite count (static scratch)");
   return SBIM_OK;
 }
 

@@ -29,7 +29,7 @@ ERROR_NAMES = {SBIM_E_INVALID: "SBIM_E_INVALID", SBIM_E_OOM: "SBIM_E_OOM",
 EXPORTS = (
     "sbim_init", "sbim_push_displacement", "sbim_tractions", "sbim_backward",
     "sbim_backward_reset", "sbim_reset", "sbim_destroy", "sbim_last_error", "sbim_set_stream",
-    "sbim_set_dt", "sbim_count_nonfinite",
+    "sbim_set_dt", "sbim_count_nonfinite", "sbim_count_nonfinite_noalloc",
     "sbim_get_info", "sbim_state_bytes", "sbim_save_state", "sbim_load_state", "sbim_step_work",
     "sbim_mode_kernel", "sbim_profile_conv", "sbim_conv_timing",
     "sbim_fault_create", "sbim_fault_step", "sbim_fault_read", "sbim_fault_reset",
@@ -102,6 +102,7 @@ def load_library(path=LIB_PATH):
         "sbim_set_dt": (i, [vp, d]),
         "sbim_get_info": (i, [vp, ctypes.POINTER(_Info)]),
         "sbim_count_nonfinite": (i, [vp, vp, ctypes.POINTER(ll)]),
+        "sbim_count_nonfinite_noalloc": (i, [vp, vp, vp]),
         "sbim_state_bytes": (ll, [vp]),
         "sbim_save_state": (i, [vp, vp]),
         "sbim_load_state": (i, [vp, vp]),
@@ -267,6 +268,17 @@ class SBIM:
         self._sync_stream()
         self._check(self._L.sbim_count_nonfinite(self._h, _ptr(field), ctypes.byref(n)))
         return n.value
+
+    def count_nonfinite_noalloc(self, field, out):
+        """The same count written to ``out`` (a one-element int64 tensor on the handle's
+        device) without any device allocation; asynchronous on the current stream."""
+        self._field(field, "field")
+        if (not isinstance(out, torch.Tensor) or out.device != self.device
+                or out.dtype != torch.int64 or out.numel() < 1):
+            raise ValueError(f"out: expected an int64 tensor of at least one element on {self.device}")
+        self._sync_stream()
+        self._check(self._L.sbim_count_nonfinite_noalloc(self._h, _ptr(field), _ptr(out)))
+        return out
 
     def set_dt(self, dt):
         """Time step of the following pushes (quasi-dynamic handles only)."""
