@@ -115,12 +115,20 @@ typedef struct {
   long long step;              /* pushes since init / reset */
   long long backward_step;     /* sbim_backward calls since the last reset */
   int material_groups;         /* planes sharing (c_s, c_p) share one table and one pass */
-  int sweep_depth;             /* steps served by one pass over a block's history: 6 when
-                                  the mean window is under 64 lags, else 12 (float64,
-                                  compensated, and float32 from a mean window of 1500
-                                  lags) or 8 (float32 below that); the environment variable
-                                  SBIM_SWEEP_DEPTH (1, 2, 4, 6, 8, 12 or 16) overrides it
-                                  at sbim_init, for tuning */
+  int sweep_depth;             /* steps served by one pass over a block's history: 32 on
+                                  the matrix cores (below); otherwise 6 when the mean
+                                  window is under 64 lags, else 12 (float64, compensated,
+                                  and float32 from a mean window of 1500 lags) or 8
+                                  (float32 below that); the environment variable
+                                  SBIM_SWEEP_DEPTH (1, 2, 4, 6, 8, 12 or 16; 16 or 32 on
+                                  the matrix cores) overrides it at sbim_init, for tuning */
+  int sweep_matrix_cores;      /* 1: the history sweep runs as 16x16x4 float32 matrix-core
+                                  products (float32 forms, one window for every mode, two
+                                  planes of one material, mean window of 64 lags or more);
+                                  SBIM_SWEEP_KIND=valu or mfma overrides it, for tuning */
+  int sweep_lag_chunks;        /* matrix-core sweep: wavefronts per group of four modes,
+                                  each summing a range of lags (1, 2 or 4; 0 otherwise);
+                                  SBIM_SWEEP_CHUNKS overrides it, for tuning */
 } sbim_info;
 
 /*

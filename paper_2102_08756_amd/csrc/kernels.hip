@@ -285,6 +285,198 @@ __device__ __forceinline__ void sweep_item(const SweepArgs &a, long long item) {
   }
 }
 
+// ------------------------------------------------------- matrix-core sweep
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+// Kernel-row blocks a compensated quad sweep sums in plain float32 (the
+// matrix-core accumulators) before folding them into its compensated sums:
+// 8 blocks of 4 lags.
+constexpr int kQuadFold = 8;
+
+// The sweep on the matrix cores, for float32 history of two planes that share
+// their kernel rows (one material group, one window for every mode).  Its
+// sums are the same as sweep_item's: the launch of step n serves steps
+// t0 = n+1 .. n+D (D = 16 G) from the history up to step n-1,
+//   pending[(t0+u) mod (D+1)] = sum_{i>=2} w_{i+u} (x) U^{t0-i},
+// but per class of modes the product over lags is a Toeplitz matrix times a
+// matrix of history columns:
+//   out[u][col] = sum_i w[i + u] U^{t0-i}[col],
+// done as 16x16x4 float32 products (one per 4 lags and 16 steps), each the
+// sequence of four fused multiply-adds of a lane's FMA chain in lag order.
+//
+// Classes are padded to multiples of 4 sorted positions, so the four lanes
+// 4j .. 4j+3 of a block ("quad" j) share one kernel row.  The 16 columns are
+// (plane p, mode mq of the quad, real/imaginary part): col = 8 p + 2 mq + reim.
+// Per 4 lags i0 .. i0+3 and 16-step group g the operands are
+//   A[s][k] = w_type[i0 + k + s + 16 g]   (lane s + 16 k; rows past the class's
+//                                          window clamp to its zero row),
+//   B[k][col] = U^{t0-i0-k}[col]          (lane col + 16 k, one float of the ring),
+// and the five products per group are (w11, U_L), (w12, U_N), (w22, U_N),
+// (w12, U_L), (w33, U_T) -> sums 2 tau + reim, tau = 0..4, as fma_lag orders
+// them.  Output lane l, register v of group g: step u = 16 g + 4 (l/16) + v,
+// column l mod 16.
+//
+// Work-group = one quad of a block of this launch's phase; its LG wavefronts
+// take consecutive ranges of the 4-lag blocks and are summed in LDS in a fixed
+// order (the compensated sums with Neumaier's rule), so results are bitwise
+// reproducible.  Work-group ids of one block are congruent mod 8, so the 16
+// quads of a block, which share the history's cache lines, run on one XCD.
+// Lags past min(cap-1, t0) meet zero rows or never-written (zero) ring slots,
+// as in sweep_item.
+template <bool COMP, int G>
+__device__ __forceinline__ void quad_sweep(const SweepArgs &a, long long wg, int LG,
+                                           float *__restrict__ lds) {
+  constexpr int D = 16 * G;
+  const long long kb = (wg >> 7) * 8 + (wg & 7);
+  if (kb >= a.nphase) return;                      // uniform over the work-group
+  const int j = static_cast<int>((wg >> 3) & 15);  // quad of the block
+  const long long M = a.M, step = a.step;
+  const long long t0 = step + 1;
+  const long long b = t0 % D + D * kb;
+  const int chunk = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int s_ = lane & 15;                 // A row (step in group) / B column
+  const int k_ = lane >> 4;                 // lag within a 4-lag block
+  const int p = s_ >> 3, mq = (s_ >> 1) & 3, reim = s_ & 1;
+  const long long sq = b * kLanes + 4 * j;  // first sorted position of the quad
+  if (sq >= M) return;                      // past the last mode (uniform); M is a multiple of 4
+  const int cap = a.blk_cap[b];
+  const int wl = a.win[sq];                 // the class's window (its first position is a mode)
+  const int nent = wl > 0 ? static_cast<int>(max(0LL, min(static_cast<long long>(cap) - 1, t0) - 1)) : 0;
+  const int nblk = (nent + 3) / 4;
+  const int per = (nblk + LG - 1) / LG;
+  const int beta0 = min(nblk, chunk * per);
+  const int beta1 = min(nblk, beta0 + per);
+
+  v4f C[G][5];
+#pragma unroll
+  for (int g = 0; g < G; ++g)
+#pragma unroll
+    for (int t = 0; t < 5; ++t) C[g][t] = v4f{0.f, 0.f, 0.f, 0.f};
+  Acc<float, COMP> acc[G][5][4];
+  if (beta1 > beta0) {
+    const float4 *__restrict__ rowp = static_cast<const float4 *>(a.table) + a.cls_off[a.cls[sq]];
+    const long long rec_len = 2LL * 3 * kLanes * 2;                    // floats per ring record
+    const long long dstep = static_cast<long long>(a.blk_stride[b]) * rec_len;
+    const long long dwrap = static_cast<long long>(cap) * dstep;
+    int i0 = 2 + 4 * beta0;                 // first lag of the block being summed
+    int x = static_cast<int>((((t0 - i0 - k_) % cap) + cap) % cap);  // ring slot of this lane's lag
+    const float *hp = static_cast<const float *>(a.ring) +
+                      (a.blk_off[b] + static_cast<long long>(x) * a.blk_stride[b]) * rec_len +
+                      ((p * 3) * kLanes + 4 * j + mq) * 2 + reim;
+    const int r0 = k_ + s_;
+    float bu[3];
+    float4 rw[G];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) bu[c] = hp[c * kLanes * 2];
+#pragma unroll
+    for (int g = 0; g < G; ++g) rw[g] = rowp[min(i0 + r0 + 16 * g, wl)];
+    int fold = 0;
+    for (int beta = beta0; beta < beta1; ++beta) {
+      // next block's operands, loaded while this block's products run
+      float nb[3] = {0.f, 0.f, 0.f};
+      float4 nr[G];
+      if (beta + 1 < beta1) {
+        x -= 4;
+        hp -= 4 * dstep;
+        if (x < 0) {
+          x += cap;
+          hp += dwrap;
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) nb[c] = hp[c * kLanes * 2];
+#pragma unroll
+        for (int g = 0; g < G; ++g) nr[g] = rowp[min(i0 + 4 + r0 + 16 * g, wl)];
+      }
+#pragma unroll
+      for (int g = 0; g < G; ++g) {
+        C[g][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(rw[g].x, bu[0], C[g][0], 0, 0, 0);
+        C[g][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(rw[g].y, bu[1], C[g][1], 0, 0, 0);
+        C[g][2] = __builtin_amdgcn_mfma_f32_16x16x4f32(rw[g].z, bu[1], C[g][2], 0, 0, 0);
+        C[g][3] = __builtin_amdgcn_mfma_f32_16x16x4f32(rw[g].y, bu[0], C[g][3], 0, 0, 0);
+        C[g][4] = __builtin_amdgcn_mfma_f32_16x16x4f32(rw[g].w, bu[2], C[g][4], 0, 0, 0);
+      }
+      if constexpr (COMP) {
+        // fold the plain partial sums of the last kQuadFold blocks (uniform branch)
+        if (++fold == kQuadFold) {
+          fold = 0;
+#pragma unroll
+          for (int g = 0; g < G; ++g)
+#pragma unroll
+            for (int t = 0; t < 5; ++t)
+#pragma unroll
+              for (int v = 0; v < 4; ++v) {
+                acc[g][t][v].fold(C[g][t][v]);
+                C[g][t][v] = 0.f;
+              }
+        }
+      }
+      i0 += 4;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) bu[c] = nb[c];
+#pragma unroll
+      for (int g = 0; g < G; ++g) rw[g] = nr[g];
+    }
+  }
+#pragma unroll
+  for (int g = 0; g < G; ++g)
+#pragma unroll
+    for (int t = 0; t < 5; ++t)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[g][t][v].fold(C[g][t][v]);
+  // lag ranges of the other wavefronts, added in chunk order by wavefront 0
+  if (LG > 1) {
+    constexpr int NV = G * 5 * 4;
+    constexpr int PER = COMP ? 2 : 1;
+    if (chunk > 0) {
+      float *dst = lds + static_cast<long long>(chunk - 1) * NV * PER * kLanes + lane;
+#pragma unroll
+      for (int g = 0; g < G; ++g)
+#pragma unroll
+        for (int t = 0; t < 5; ++t)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int idx = (g * 5 + t) * 4 + v;
+            dst[(idx * PER) * kLanes] = acc[g][t][v].s;
+            if constexpr (COMP) dst[(idx * PER + 1) * kLanes] = acc[g][t][v].c;
+          }
+    }
+    __syncthreads();
+    if (chunk == 0) {
+      for (int w = 1; w < LG; ++w) {
+        const float *src = lds + static_cast<long long>(w - 1) * NV * PER * kLanes + lane;
+#pragma unroll
+        for (int g = 0; g < G; ++g)
+#pragma unroll
+          for (int t = 0; t < 5; ++t)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              const int idx = (g * 5 + t) * 4 + v;
+              if constexpr (COMP) {
+                neumaier(acc[g][t][v].s, acc[g][t][v].c, src[(idx * PER) * kLanes]);
+                acc[g][t][v].c += src[(idx * PER + 1) * kLanes];
+              } else {
+                acc[g][t][v].s += src[(idx * PER) * kLanes];
+              }
+            }
+      }
+    }
+  }
+  if (chunk != 0) return;
+  float *__restrict__ pending = static_cast<float *>(a.pending);
+  const long long col_off = (static_cast<long long>(p) * kSums + reim) * M + sq + mq;
+#pragma unroll
+  for (int g = 0; g < G; ++g)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const long long slot = (t0 + 16 * g + 4 * k_ + v) % (D + 1);
+      float *dst = pending + slot * 2 * kSums * M + col_off;
+#pragma unroll
+      for (int t = 0; t < 5; ++t) dst[2 * t * M] = acc[g][t][v].value();
+    }
+}
+
 // Mode item of step n for one (mode, plane): the push, then the traction of
 // the same step from the same registers.
 //   push:    rotate the new spectrum into the wavevector frame, update the
@@ -305,6 +497,7 @@ __device__ __forceinline__ void mode_step(const ModeArgs &a, int p, long long s)
   const long long M = a.M, nh = a.nh, step = a.step;
   const int np = a.np;
   const long long natural = a.nat[s];
+  if (natural < 0) return;  // a padding position of the matrix-core layout: no mode
   const double q = a.geom[4 * s + 0];
   const double kh1 = a.geom[4 * s + 1];
   const double kh3 = a.geom[4 * s + 2];
@@ -516,6 +709,27 @@ __global__ __launch_bounds__(kLanes) __attribute__((amdgpu_waves_per_eu(2))) voi
   step_items<R, S, T, COMP>(sa, ma, sweep_items, nblocks);
 }
 
+// The launch of the matrix-core form: work-groups of LG wavefronts, first the
+// quad sweeps of this launch's phase, then the mode items (LG (block, plane)
+// items per work-group, one per wavefront).  LDS (dynamic) holds the partial
+// sums of wavefronts 1 .. LG-1 of a quad.
+template <bool COMP, int G>
+__global__ __launch_bounds__(4 * kLanes) __attribute__((amdgpu_waves_per_eu(2))) void step_kernel_mfma(SweepArgs sa, ModeArgs ma,
+                                                              long long sweep_wgs,
+                                                              long long nblocks, int LG) {
+  extern __shared__ float quad_lds[];
+  const long long wg = blockIdx.x;
+  if (wg < sweep_wgs) {
+    quad_sweep<COMP, G>(sa, wg, LG, quad_lds);
+    return;
+  }
+  const long long k = (wg - sweep_wgs) * LG + (threadIdx.x >> 6);
+  if (k >= nblocks * ma.np) return;
+  const int p = static_cast<int>(k / nblocks);
+  const long long s = (k - p * nblocks) * kLanes + (threadIdx.x & 63);
+  if (s < ma.M) mode_step<float, COMP>(ma, p, s);
+}
+
 // -------------------------------------------------------------- tabulate
 
 // Piece A (0 < y < 1): y = sin(t).  Piece B (1 < y < eta): y^2 = 1 + (eta^2-1) sin^2(t).
@@ -689,6 +903,29 @@ hipError_t step_launch_s(const sbim_handle *h, const Group &g, const SweepArgs &
   return e;
 }
 
+template <bool COMP, int G>
+hipError_t step_launch_q(const sbim_handle *h, const Group &g, const SweepArgs &sa0,
+                         const ModeArgs &ma, hipEvent_t ev0, hipEvent_t ev1) {
+  constexpr int D = 16 * G;
+  SweepArgs sa = sa0;
+  const int phase = static_cast<int>((sa.step + 1) % D);
+  sa.nphase = g.nblocks > phase ? (g.nblocks - phase + D - 1) / D : 0;
+  const int LG = h->lag_chunks;
+  const long long sweep_wgs = (sa.nphase + 7) / 8 * 8 * 16;
+  const long long mode_wgs = (g.nblocks * g.np + LG - 1) / LG;
+  const size_t lds =
+      static_cast<size_t>(LG - 1) * G * 5 * 4 * (COMP ? 2 : 1) * kLanes * sizeof(float);
+  if (ev0) {
+    const hipError_t e = hipEventRecord(ev0, h->stream);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL((step_kernel_mfma<COMP, G>), dim3(static_cast<unsigned>(sweep_wgs + mode_wgs)),
+                     dim3(LG * kLanes), lds, h->stream, sa, ma, sweep_wgs, g.nblocks, LG);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess && ev1) e = hipEventRecord(ev1, h->stream);
+  return e;
+}
+
 template <typename R, bool COMP>
 hipError_t step_launch_r(const sbim_handle *h, const Group &g, const SweepArgs &sa,
                          const ModeArgs &ma, hipEvent_t ev0, hipEvent_t ev1) {
@@ -751,6 +988,16 @@ hipError_t launch_step(const sbim_handle *h, const Group &g, const StepLaunch &w
   sa.step = w.step;
   sa.np = g.np;
   sa.nphase = 0;
+  if (h->mfma) {
+    if (g.np != 2 || h->fp64 || (h->depth != 16 && h->depth != 32) || h->lag_chunks < 1 ||
+        h->lag_chunks > 4)
+      return hipErrorInvalidValue;
+    if (h->comp)
+      return h->depth == 32 ? step_launch_q<true, 2>(h, g, sa, ma, ev0, ev1)
+                            : step_launch_q<true, 1>(h, g, sa, ma, ev0, ev1);
+    return h->depth == 32 ? step_launch_q<false, 2>(h, g, sa, ma, ev0, ev1)
+                          : step_launch_q<false, 1>(h, g, sa, ma, ev0, ev1);
+  }
   if (h->fp64) return step_launch_r<double, false>(h, g, sa, ma, ev0, ev1);
   if (h->comp) return step_launch_r<float, true>(h, g, sa, ma, ev0, ev1);
   return step_launch_r<float, false>(h, g, sa, ma, ev0, ev1);

@@ -190,7 +190,11 @@ double mean_window(const sbim_config &c, double cs) {
 }
 
 // Mode geometry, windows, ordering and classes of one material group (host).
-void plan_group(const sbim_config &c, int depth, Group &g, std::vector<double> &geom,
+// With `quads` (the matrix-core sweep) every class starts at a multiple of 4
+// sorted positions and is padded to a multiple of 4 with positions that hold
+// no mode (bin -1, window 0, the class's row set), so each aligned group of
+// four lanes shares one kernel row.
+void plan_group(const sbim_config &c, int depth, bool quads, Group &g, std::vector<double> &geom,
                 std::vector<long long> &blk_off, std::vector<int> &blk_cap,
                 std::vector<int> &blk_stride, std::vector<double> &cls_q) {
   const int n1 = c.n1, h3 = c.n3 / 2 + 1;
@@ -233,18 +237,40 @@ void plan_group(const sbim_config &c, int depth, Group &g, std::vector<double> &
     if (by_q && a.q != b.q) return a.q < b.q;
     return a.nat < b.nat;
   });
-  g.M = M;
-  g.nblocks = (M + sbim::kLanes - 1) / sbim::kLanes;
-  g.h_nat.resize(M);
-  g.h_cls.resize(M);
-  g.h_win.resize(M);
-  geom.assign(4 * M, 0.0);
+  if (quads) {
+    // pad each run of equal (W, q) (a class, sorted together) to a multiple of 4;
+    // a padding position carries nat = -1
+    std::vector<ModeKey> padded;
+    padded.reserve(M + M / 2);
+    for (long long s0 = 0; s0 < M;) {
+      long long s1 = s0;
+      while (s1 < M && keys[s1].w == keys[s0].w && keys[s1].q == keys[s0].q) ++s1;
+      for (long long s = s0; s < s1; ++s) padded.push_back(keys[s]);
+      for (long long r = (s1 - s0) % 4; r != 0 && r < 4; ++r)
+        padded.push_back(ModeKey{keys[s0].w, keys[s0].q, -1});
+      s0 = s1;
+    }
+    keys.swap(padded);
+  }
+  const long long Ms = static_cast<long long>(keys.size());  // sorted positions
+  g.M = Ms;
+  g.nblocks = (Ms + sbim::kLanes - 1) / sbim::kLanes;
+  g.h_nat.resize(Ms);
+  g.h_cls.resize(Ms);
+  g.h_win.resize(Ms);
+  geom.assign(4 * Ms, 0.0);
   cls_q.clear();
   g.h_cls_w.clear();
   // a class per distinct (W, q): kernel rows are shared whatever the order
   std::map<std::pair<int, double>, int> class_of;
-  for (long long s = 0; s < M; ++s) {
+  for (long long s = 0; s < Ms; ++s) {
     const ModeKey &k = keys[s];
+    if (k.nat < 0) {  // padding: the class of the position before it, no window, no bin
+      g.h_nat[s] = -1;
+      g.h_cls[s] = g.h_cls[s - 1];
+      g.h_win[s] = 0;
+      continue;
+    }
     int cls = 0;
     if (k.w > 0) {
       bool known = false;
@@ -272,12 +298,16 @@ void plan_group(const sbim_config &c, int depth, Group &g, std::vector<double> &
     geom[4 * s + 2] = q > 0 ? k3v[k.nat] / q : 0.0;
   }
   g.nclasses = static_cast<long long>(cls_q.size());
-  g.wmax = M > 0 ? keys[0].w : 0;
+  g.wmax = Ms > 0 ? keys[0].w : 0;
   blk_off.resize(g.nblocks);
   blk_cap.resize(g.nblocks);
   blk_stride.resize(g.nblocks);
-  for (long long b = 0; b < g.nblocks; ++b)
-    blk_cap[b] = g.h_win[b * sbim::kLanes];  // sorted by W desc: first lane has the block maximum
+  for (long long b = 0; b < g.nblocks; ++b) {  // the largest window of the block's modes
+    int cap = 0;
+    for (long long s = b * sbim::kLanes; s < std::min(Ms, (b + 1) * sbim::kLanes); ++s)
+      cap = std::max(cap, g.h_win[s]);
+    blk_cap[b] = cap;
+  }
   g.h_blk_cap = blk_cap;
   // Blocks of one sweep phase (b mod depth) are stored together; within a
   // phase, runs of consecutive blocks with equal capacity are stored slot-major.
@@ -509,19 +539,51 @@ int sbim_init(const sbim_config *cfg, sbim_handle **out) {
   for (int p = 0; p < cfg->nplanes; ++p)
     wbar = std::max(wbar, mean_window(*cfg, cfg->plane[p].cs));
   h->depth = wbar < 64 ? 6 : (h->comp || h->fp64 || wbar >= 1500 ? 12 : 8);
+  // Matrix-core sweep: float32 history, one window for every mode, both planes
+  // in one material group (their kernel rows shared), windows long enough for
+  // the deep sweep to pay.  Its depth is 16 or 32 (one or two 16-step groups of
+  // the 16x16x4 products); measured on gfx950 (two planes 512^2 at W = 1000,
+  // 1024^2 at W = 2000): 32 for both float32 forms.
+  const bool mfma_able = !h->fp64 && cfg->window_mode == SBIM_W_FIXED && h->ngroups == 1 &&
+                         h->g[0].np == 2;
+  h->mfma = mfma_able && wbar >= 64;
+  if (const char *env = std::getenv("SBIM_SWEEP_KIND")) {  // tuning override
+    if (std::strcmp(env, "valu") == 0) h->mfma = false;
+    if (std::strcmp(env, "mfma") == 0) h->mfma = mfma_able;
+  }
+  if (h->mfma) h->depth = 32;
   if (const char *env = std::getenv("SBIM_SWEEP_DEPTH")) {  // tuning override
     const int v = std::atoi(env);
-    if (v == 1 || v == 2 || v == 4 || v == 6 || v == 8 || v == 12 || v == 16) h->depth = v;
+    if (h->mfma) {
+      if (v == 16 || v == 32) h->depth = v;
+    } else if (v == 1 || v == 2 || v == 4 || v == 6 || v == 8 || v == 12 || v == 16) {
+      h->depth = v;
+    }
   }
   std::vector<HostPlan> plan(h->ngroups);
   size_t need = 0;
   for (int i = 0; i < h->ngroups; ++i) {
     Group &g = h->g[i];
-    plan_group(*cfg, h->depth, g, plan[i].geom, plan[i].blk_off, plan[i].blk_cap,
+    plan_group(*cfg, h->depth, h->mfma, g, plan[i].geom, plan[i].blk_off, plan[i].blk_cap,
                plan[i].blk_stride, plan[i].cls_q);
     need += ring_bytes(h, g) + table_bytes(h, g) + state_bytes_g(g);
     need += pending_bytes(h, g);
     need += g.M * (4 * 3 + 32) + g.nblocks * 16 + g.nclasses * 20;
+  }
+  if (h->mfma) {
+    // Wavefronts per quad (lag ranges): enough work-groups for about two
+    // wavefronts per SIMD (1024 SIMDs) when a phase has few quads, each range
+    // at least 8 blocks of 4 lags.
+    const Group &g = h->g[0];
+    const long long quads = (g.nblocks + h->depth - 1) / h->depth * 16;
+    const int nblk = (std::max(0, g.wmax - 2) + 3) / 4;
+    h->lag_chunks = 1;
+    while (h->lag_chunks < 4 && quads * h->lag_chunks < 2048 && nblk >= 16 * h->lag_chunks)
+      h->lag_chunks *= 2;
+    if (const char *env = std::getenv("SBIM_SWEEP_CHUNKS")) {  // tuning override
+      const int v = std::atoi(env);
+      if (v == 1 || v == 2 || v == 4) h->lag_chunks = v;
+    }
   }
   // input spectra are float64 in every form; the traction spectrum is real_t
   const size_t spec_bytes = static_cast<size_t>(cfg->nplanes) * 3 * h->nh * 2 * sizeof(double);
@@ -809,6 +871,8 @@ int sbim_get_info(const sbim_handle *h, sbim_info *out) {
   out->backward_step = h->bstep;
   out->material_groups = h->ngroups;
   out->sweep_depth = h->depth;
+  out->sweep_matrix_cores = h->mfma ? 1 : 0;
+  out->sweep_lag_chunks = h->mfma ? h->lag_chunks : 0;
   return SBIM_OK;
 }
 
@@ -899,6 +963,7 @@ int sbim_step_work(const sbim_handle *h, long long n, double *mode_lags, double 
       const long long last = std::min<long long>(g.h_blk_cap[b] - 1, n + 1);
       int last_cls = -1;
       for (long long s = b * sbim::kLanes; s < std::min(g.M, (b + 1) * sbim::kLanes); ++s) {
+        if (g.h_nat[s] < 0) continue;  // padding position of the matrix-core layout
         const int w = g.h_win[s];
         bytes += std::max(0LL, std::min<long long>(w - 1, n + 1) - 1) * g.np * 3.0 * 2.0 * r;
         bytes += 8.0 + S * g.np * 10.0 * r;
@@ -915,6 +980,7 @@ int sbim_step_work(const sbim_handle *h, long long n, double *mode_lags, double 
     // ring beyond lag 0, kernel rows), the traction written; per mode its bin,
     // q and direction, window, class and row offset; per block its descriptors
     for (long long s = 0; s < g.M; ++s) {
+      if (g.h_nat[s] < 0) continue;
       const long long b = s / sbim::kLanes;
       const int phi = static_cast<int>(b % S);
       const bool swept = n >= (phi == 0 ? S : phi);

@@ -1,0 +1,156 @@
+"""GPU parity of the matrix-core history sweep (16x16x4 float32 products over
+groups of four modes that share a kernel row) against the float64 oracle.
+
+The matrix-core form runs for float32 history of two planes of one material
+with one window for every mode.  On these small grids it is switched on with
+the tuning override SBIM_SWEEP_KIND=mfma; the depth (16 or 32 steps per pass)
+and the wavefronts per quad (lag ranges summed separately, then in LDS) are
+set the same way.  Cases: square grids (classes of 4 and 8 modes), an
+anisotropic grid (classes of 2: half of each quad is padding), a window
+shorter than the sweep depth, a window that is not a multiple of 4 lags, and
+a grid whose sorted positions end inside a 64-lane block.  Bars: relative L2
+1e-5 over all planes, components, cells and steps (the float32 bar), and the
+adjoint against the oracle's transpose at the same bar.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2102_08756_amd import SBIM, Config, SBIMRun
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+TWO = [dict(side=1), dict(side=-1)]
+
+CASES = {
+    # 32 x 17 = 544 modes: classes of 4 and 8, the last block ragged
+    "square32_w40": (dict(n1=32, n3=32, window_cap=40, planes=TWO), 110),
+    # anisotropic spacing: only (+-m1, m3) share q, so classes of 2 padded to 4
+    "aniso16x32_w37": (dict(n1=16, n3=32, dx1=0.7, dx3=1.3, window_cap=37, planes=TWO), 100),
+    # a window shorter than either sweep depth
+    "square16_w5": (dict(n1=16, n3=16, window_cap=5, planes=TWO), 50),
+    # two planes of one material with different shear moduli and sides (shared rows)
+    "mu_differs_w21": (dict(n1=32, n3=16, window_cap=21,
+                            planes=[dict(side=1, mu=1.0), dict(side=-1, mu=2.5)]), 80),
+}
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
+
+
+def _inputs(cfg_d, steps, seed):
+    rng = np.random.default_rng(seed)
+    P = len(cfg_d["planes"])
+    return rng.standard_normal((steps, P, 3, cfg_d["n1"], cfg_d["n3"]))
+
+
+@pytest.fixture(scope="module")
+def refs():
+    out = {}
+    for name, (cfg, steps) in CASES.items():
+        for kind in ("absolute", "increment"):
+            c = dict(cfg, input_kind=kind)
+            u = _inputs(c, steps, 31 + len(name))
+            out[name, kind] = (u, oracle.forward(c, u))
+    return out
+
+
+def run_gpu(cfg_d, u, precision):
+    sb = SBIM(Config.from_dict(cfg_d, precision=precision), device=DEV)
+    info = sb.info()
+    ut = torch.tensor(u, dtype=sb.dtype, device=DEV)
+    out = np.empty(u.shape)
+    for n in range(u.shape[0]):
+        sb.push(ut[n])
+        out[n] = sb.tractions().double().cpu().numpy()
+    sb.close()
+    return out, info
+
+
+@pytest.mark.parametrize("chunks", [1, 2, 4])
+@pytest.mark.parametrize("depth", [16, 32])
+@pytest.mark.parametrize("precision", ["fp32", "fp32_comp"])
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_matrix_core_sweep_matches_oracle(refs, case, precision, depth, chunks, monkeypatch):
+    monkeypatch.setenv("SBIM_SWEEP_KIND", "mfma")
+    monkeypatch.setenv("SBIM_SWEEP_DEPTH", str(depth))
+    monkeypatch.setenv("SBIM_SWEEP_CHUNKS", str(chunks))
+    kind = "increment" if (depth + chunks) % 2 else "absolute"
+    cfg = dict(CASES[case][0], input_kind=kind)
+    u, ref = refs[case, kind]
+    got, info = run_gpu(cfg, u, precision)
+    assert info["sweep_matrix_cores"] == 1
+    assert info["sweep_depth"] == depth and info["sweep_lag_chunks"] == chunks
+    err = rel_l2(got, ref)
+    print(f"[mfma] {case} {kind} {precision} depth {depth} chunks {chunks}: rel-L2 {err:.3e}",
+          flush=True)
+    assert err < 1e-5
+
+
+def test_matrix_core_sweep_is_the_default_for_long_windows(monkeypatch):
+    monkeypatch.delenv("SBIM_SWEEP_KIND", raising=False)
+    monkeypatch.delenv("SBIM_SWEEP_DEPTH", raising=False)
+    monkeypatch.delenv("SBIM_SWEEP_CHUNKS", raising=False)
+    long_w = dict(n1=64, n3=64, window_cap=100, planes=TWO)
+    for precision, want in (("fp32", 1), ("fp32_comp", 1), ("fp64", 0)):
+        sb = SBIM(Config.from_dict(long_w, precision=precision), device=DEV)
+        info = sb.info()
+        sb.close()
+        assert info["sweep_matrix_cores"] == want, precision
+        if want:
+            assert info["sweep_depth"] == 32 and info["sweep_lag_chunks"] in (1, 2, 4)
+    # one plane, or planes of two materials: the vector-unit sweep
+    for planes in ([dict(side=1)], [dict(side=1), dict(side=-1, cs=1.2, cp=2.5)]):
+        sb = SBIM(Config.from_dict(dict(long_w, planes=planes), precision="fp32"), device=DEV)
+        assert sb.info()["sweep_matrix_cores"] == 0
+        sb.close()
+
+
+def test_matrix_core_sweep_deterministic_and_snapshot(monkeypatch):
+    """Bitwise run-to-run repeatability (fixed LDS summation order) and a snapshot taken
+    in the middle of a sweep rotation restoring the pending sums exactly."""
+    monkeypatch.setenv("SBIM_SWEEP_KIND", "mfma")
+    monkeypatch.setenv("SBIM_SWEEP_CHUNKS", "4")
+    cfg = dict(CASES["square32_w40"][0], input_kind="increment")
+    u = _inputs(cfg, 90, 5)
+    a, _ = run_gpu(cfg, u, "fp32_comp")
+    b, _ = run_gpu(cfg, u, "fp32_comp")
+    assert np.array_equal(a, b)
+    sb = SBIM(Config.from_dict(cfg, precision="fp32_comp"), device=DEV)
+    ut = torch.tensor(u, dtype=sb.dtype, device=DEV)
+    snap = torch.empty(sb.state_bytes(), dtype=torch.uint8, device=DEV)
+    cut = 45
+    first = []
+    for n in range(70):
+        sb.push(ut[n])
+        first.append(sb.tractions().clone())
+        if n == cut:
+            sb.save_state(snap)
+    sb.load_state(snap)
+    for n in range(cut + 1, 70):
+        sb.push(ut[n])
+        assert torch.equal(sb.tractions(), first[n]), n
+    sb.close()
+
+
+@pytest.mark.parametrize("kind", ["absolute", "increment"])
+def test_matrix_core_adjoint_matches_oracle(kind, monkeypatch):
+    """The adjoint runs the same launch on its own history: float32 transpose against
+    the oracle's at the float32 bar."""
+    monkeypatch.setenv("SBIM_SWEEP_KIND", "mfma")
+    monkeypatch.setenv("SBIM_SWEEP_CHUNKS", "2")
+    cfg = dict(CASES["square32_w40"][0], input_kind=kind)
+    u = _inputs(cfg, 60, 12)
+    g = np.random.default_rng(13).standard_normal(u.shape)
+    du_ref, _ = oracle.adjoint(cfg, g)
+    sb = SBIM(Config.from_dict(cfg, precision="fp32_comp"), device=DEV)
+    assert sb.info()["sweep_matrix_cores"] == 1
+    ut = torch.tensor(u, dtype=torch.float32, device=DEV, requires_grad=True)
+    tau = SBIMRun.apply(sb, ut)
+    (tau * torch.tensor(g, dtype=torch.float32, device=DEV)).sum().backward()
+    err = rel_l2(ut.grad.double().cpu().numpy(), du_ref)
+    print(f"[mfma] adjoint {kind}: rel-L2 {err:.3e}", flush=True)
+    assert err < 1e-5
+    sb.close()
