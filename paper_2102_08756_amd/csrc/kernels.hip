@@ -293,6 +293,10 @@ typedef float v4f __attribute__((ext_vector_type(4)));
 // matrix-core accumulators) before folding them into its compensated sums:
 // 8 blocks of 4 lags.
 constexpr int kQuadFold = 8;
+// Blocks of 4 lags whose history and kernel rows the quad sweep has in flight
+// ahead of its products (measured on gfx950: 2 to 8 within 3%; 2 fits the
+// compensated form's register budget best).
+constexpr int kQuadAhead = 2;
 
 // The sweep on the matrix cores, for float32 history of two planes that share
 // their kernel rows (one material group, one window for every mode).  Its
@@ -324,6 +328,23 @@ constexpr int kQuadFold = 8;
 // quads of a block, which share the history's cache lines, run on one XCD.
 // Lags past min(cap-1, t0) meet zero rows or never-written (zero) ring slots,
 // as in sweep_item.
+// One component of the next block's Toeplitz operand of a 16-step group: lane
+// (s, k) = s + 16 k takes lane s + 4 of `cur` for s < 12 and lane s - 12 of
+// `above` (the group 16 steps later) for s >= 12 (DPP row shifts within rows of
+// 16 lanes).
+__device__ __forceinline__ float shift_row4(float cur, float above) {
+  const int t = __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, 0.f),
+                                            __builtin_bit_cast(int, above), 0x11C /* row_shr:12 */,
+                                            0xF, 0xF, false);
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(t, __builtin_bit_cast(int, cur),
+                                                               0x104 /* row_shl:4 */, 0xF, 0xF,
+                                                               false));
+}
+__device__ __forceinline__ float4 shift_rows4(float4 cur, float4 above) {
+  return float4{shift_row4(cur.x, above.x), shift_row4(cur.y, above.y),
+                shift_row4(cur.z, above.z), shift_row4(cur.w, above.w)};
+}
+
 template <bool COMP, int G>
 __device__ __forceinline__ void quad_sweep(const SweepArgs &a, long long wg, int LG,
                                            float *__restrict__ lds) {
@@ -334,7 +355,9 @@ __device__ __forceinline__ void quad_sweep(const SweepArgs &a, long long wg, int
   const long long M = a.M, step = a.step;
   const long long t0 = step + 1;
   const long long b = t0 % D + D * kb;
-  const int chunk = threadIdx.x >> 6;
+  // the lag range of this wavefront (uniform: kept in scalar registers, so the
+  // loop control below is scalar)
+  const int chunk = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
   const int lane = threadIdx.x & 63;
   const int s_ = lane & 15;                 // A row (step in group) / B column
   const int k_ = lane >> 4;                 // lag within a 4-lag block
@@ -342,7 +365,8 @@ __device__ __forceinline__ void quad_sweep(const SweepArgs &a, long long wg, int
   const long long sq = b * kLanes + 4 * j;  // first sorted position of the quad
   if (sq >= M) return;                      // past the last mode (uniform); M is a multiple of 4
   const int cap = a.blk_cap[b];
-  const int wl = a.win[sq];                 // the class's window (its first position is a mode)
+  const int wl = __builtin_amdgcn_readfirstlane(a.win[sq]);  // the class's window (its first
+                                                             // position is a mode)
   const int nent = wl > 0 ? static_cast<int>(max(0LL, min(static_cast<long long>(cap) - 1, t0) - 1)) : 0;
   const int nblk = (nent + 3) / 4;
   const int per = (nblk + LG - 1) / LG;
@@ -357,66 +381,87 @@ __device__ __forceinline__ void quad_sweep(const SweepArgs &a, long long wg, int
   Acc<float, COMP> acc[G][5][4];
   if (beta1 > beta0) {
     const float4 *__restrict__ rowp = static_cast<const float4 *>(a.table) + a.cls_off[a.cls[sq]];
-    const long long rec_len = 2LL * 3 * kLanes * 2;                    // floats per ring record
-    const long long dstep = static_cast<long long>(a.blk_stride[b]) * rec_len;
-    const long long dwrap = static_cast<long long>(cap) * dstep;
-    int i0 = 2 + 4 * beta0;                 // first lag of the block being summed
-    int x = static_cast<int>((((t0 - i0 - k_) % cap) + cap) % cap);  // ring slot of this lane's lag
-    const float *hp = static_cast<const float *>(a.ring) +
-                      (a.blk_off[b] + static_cast<long long>(x) * a.blk_stride[b]) * rec_len +
-                      ((p * 3) * kLanes + 4 * j + mq) * 2 + reim;
+    // History addresses: the block's slot 0 (uniform) plus a 32-bit offset per
+    // lane, slot x at x * dstep floats (the host keeps cap * dstep below 2^31).
+    const float *__restrict__ run =
+        static_cast<const float *>(a.ring) + a.blk_off[b] * (2LL * 3 * kLanes * 2);
+    const int dstep = a.blk_stride[b] * (2 * 3 * kLanes * 2);
+    const int col = ((p * 3) * kLanes + 4 * j + mq) * 2 + reim;
+    // The history loads run kQuadAhead blocks ahead of the products (they come
+    // from memory); xl is the ring slot of this lane's lag in the next block to load.
+    int xl = static_cast<int>((((t0 - (2 + 4 * beta0) - k_) % cap) + cap) % cap);
+    float bq[kQuadAhead][3];
+#pragma unroll
+    for (int q = 0; q < kQuadAhead; ++q) {
+      if (beta0 + q < beta1) {
+        const float *hl = run + (xl * dstep + col);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) bq[q][c] = hl[c * kLanes * 2];
+        // the next block's slot is 4 lags older; cap >= 4 whenever a chunk has
+        // a second block
+        xl -= 4;
+        if (xl < 0) xl += cap;
+      }
+    }
+    // Kernel-row operands: the top 16-step group's rows are loaded (as far ahead
+    // as the history, since the rows' leading edge comes from memory); the
+    // lower group's operand follows by a row shift of 4 lanes: lane (s, k) of
+    // the next block takes lane (s + 4, k) of its own group, or lane (s - 12, k)
+    // of the group above for s >= 12.
     const int r0 = k_ + s_;
-    float bu[3];
-    float4 rw[G];
+    float4 fq[kQuadAhead];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) bu[c] = hp[c * kLanes * 2];
-#pragma unroll
-    for (int g = 0; g < G; ++g) rw[g] = rowp[min(i0 + r0 + 16 * g, wl)];
+    for (int q = 0; q < kQuadAhead; ++q)
+      if (beta0 + q < beta1) fq[q] = rowp[min(2 + 4 * (beta0 + q) + r0 + 16 * (G - 1), wl)];
+    float4 a0 = G == 2 ? rowp[min(2 + 4 * beta0 + r0, wl)] : float4{0.f, 0.f, 0.f, 0.f};
     int fold = 0;
-    for (int beta = beta0; beta < beta1; ++beta) {
-      // next block's operands, loaded while this block's products run
-      float nb[3] = {0.f, 0.f, 0.f};
-      float4 nr[G];
-      if (beta + 1 < beta1) {
-        x -= 4;
-        hp -= 4 * dstep;
-        if (x < 0) {
-          x += cap;
-          hp += dwrap;
+    for (int base = beta0; base < beta1; base += kQuadAhead) {
+#pragma unroll
+      for (int q = 0; q < kQuadAhead; ++q) {
+        const int beta = base + q;
+        if (beta >= beta1) break;           // uniform over the wavefront
+        const float4 top = fq[q];
+        float4 rw[G];
+        if constexpr (G == 2) {
+          rw[0] = a0;
+          rw[1] = top;
+        } else {
+          rw[0] = top;
         }
 #pragma unroll
-        for (int c = 0; c < 3; ++c) nb[c] = hp[c * kLanes * 2];
+        for (int g = 0; g < G; ++g) {
+          C[g][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(rw[g].x, bq[q][0], C[g][0], 0, 0, 0);
+          C[g][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(rw[g].y, bq[q][1], C[g][1], 0, 0, 0);
+          C[g][2] = __builtin_amdgcn_mfma_f32_16x16x4f32(rw[g].z, bq[q][1], C[g][2], 0, 0, 0);
+          C[g][3] = __builtin_amdgcn_mfma_f32_16x16x4f32(rw[g].y, bq[q][0], C[g][3], 0, 0, 0);
+          C[g][4] = __builtin_amdgcn_mfma_f32_16x16x4f32(rw[g].w, bq[q][2], C[g][4], 0, 0, 0);
+        }
+        if constexpr (G == 2) a0 = shift_rows4(a0, top);
+        // this register set now takes block beta + kQuadAhead
+        if (beta + kQuadAhead < beta1) {
+          const float *hl = run + (xl * dstep + col);
 #pragma unroll
-        for (int g = 0; g < G; ++g) nr[g] = rowp[min(i0 + 4 + r0 + 16 * g, wl)];
-      }
+          for (int c = 0; c < 3; ++c) bq[q][c] = hl[c * kLanes * 2];
+          fq[q] = rowp[min(2 + 4 * (beta + kQuadAhead) + r0 + 16 * (G - 1), wl)];
+          xl -= 4;
+          if (xl < 0) xl += cap;
+        }
+        if constexpr (COMP) {
+          // fold the plain partial sums of the last kQuadFold blocks (uniform branch)
+          if (++fold == kQuadFold) {
+            fold = 0;
 #pragma unroll
-      for (int g = 0; g < G; ++g) {
-        C[g][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(rw[g].x, bu[0], C[g][0], 0, 0, 0);
-        C[g][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(rw[g].y, bu[1], C[g][1], 0, 0, 0);
-        C[g][2] = __builtin_amdgcn_mfma_f32_16x16x4f32(rw[g].z, bu[1], C[g][2], 0, 0, 0);
-        C[g][3] = __builtin_amdgcn_mfma_f32_16x16x4f32(rw[g].y, bu[0], C[g][3], 0, 0, 0);
-        C[g][4] = __builtin_amdgcn_mfma_f32_16x16x4f32(rw[g].w, bu[2], C[g][4], 0, 0, 0);
-      }
-      if constexpr (COMP) {
-        // fold the plain partial sums of the last kQuadFold blocks (uniform branch)
-        if (++fold == kQuadFold) {
-          fold = 0;
+            for (int g = 0; g < G; ++g)
 #pragma unroll
-          for (int g = 0; g < G; ++g)
+              for (int t = 0; t < 5; ++t)
 #pragma unroll
-            for (int t = 0; t < 5; ++t)
-#pragma unroll
-              for (int v = 0; v < 4; ++v) {
-                acc[g][t][v].fold(C[g][t][v]);
-                C[g][t][v] = 0.f;
-              }
+                for (int v = 0; v < 4; ++v) {
+                  acc[g][t][v].fold(C[g][t][v]);
+                  C[g][t][v] = 0.f;
+                }
+          }
         }
       }
-      i0 += 4;
-#pragma unroll
-      for (int c = 0; c < 3; ++c) bu[c] = nb[c];
-#pragma unroll
-      for (int g = 0; g < G; ++g) rw[g] = nr[g];
     }
   }
 #pragma unroll
@@ -579,33 +624,28 @@ __device__ __forceinline__ void mode_step(const ModeArgs &a, int p, long long s)
       for (int k = 0; k < kSums; ++k) acc[k].s = pend[k * M];
     }
     if (fresh > 0) {
+      // the newest lags: plain products (the compensated form folds their sum,
+      // at most depth + 1 lags, into the pending sum once)
       const W *__restrict__ rowp = static_cast<const W *>(a.table) + a.cls_off[a.cls[s]];
-      const cplx<R> *rp = ring + static_cast<long long>(p) * 3 * kLanes + lane;
-      for (int j = 0; j < fresh; ++j) {
-        cplx<R> u[3];
-        if (j == 0) {
+      R part[kSums];
 #pragma unroll
-          for (int c = 0; c < 3; ++c) u[c] = u0[c];
-        } else {
-          int x = x0 - j;
-          if (x < 0) x += cap;
-          const cplx<R> *qp = rp + (base + static_cast<long long>(x) * stride) * rec_len;
-          u[0] = qp[0];
-          u[1] = qp[kLanes];
-          u[2] = qp[2 * kLanes];
-        }
-        const W w = rowp[j];
-        R part[kSums];
+      for (int k = 0; k < kSums; ++k) part[k] = COMP ? R(0) : acc[k].s;
+      fma_lag<R>(part, rowp[0], u0);
+      const cplx<R> *rp = ring + base * rec_len + static_cast<long long>(p) * 3 * kLanes + lane;
+      int x = x0;
+#pragma unroll 2
+      for (int j = 1; j < fresh; ++j) {
+        x = (x == 0 ? cap : x) - 1;
+        const cplx<R> *qp = rp + static_cast<long long>(x) * stride * rec_len;
+        const cplx<R> u[3] = {qp[0], qp[kLanes], qp[2 * kLanes]};
+        fma_lag<R>(part, rowp[j], u);
+      }
 #pragma unroll
-        for (int k = 0; k < kSums; ++k) part[k] = COMP ? R(0) : acc[k].s;
-        fma_lag<R>(part, w, u);
-#pragma unroll
-        for (int k = 0; k < kSums; ++k) {
-          if constexpr (COMP)
-            acc[k].fold(part[k]);
-          else
-            acc[k].s = part[k];
-        }
+      for (int k = 0; k < kSums; ++k) {
+        if constexpr (COMP)
+          acc[k].fold(part[k]);
+        else
+          acc[k].s = part[k];
       }
     }
 #pragma unroll
@@ -713,10 +753,9 @@ __global__ __launch_bounds__(kLanes) __attribute__((amdgpu_waves_per_eu(2))) voi
 // quad sweeps of this launch's phase, then the mode items (LG (block, plane)
 // items per work-group, one per wavefront).  LDS (dynamic) holds the partial
 // sums of wavefronts 1 .. LG-1 of a quad.
-template <bool COMP, int G>
-__global__ __launch_bounds__(4 * kLanes) __attribute__((amdgpu_waves_per_eu(2))) void step_kernel_mfma(SweepArgs sa, ModeArgs ma,
-                                                              long long sweep_wgs,
-                                                              long long nblocks, int LG) {
+template <bool COMP, int G, int WAVES>
+__global__ __launch_bounds__(4 * kLanes) __attribute__((amdgpu_waves_per_eu(WAVES))) void
+step_kernel_mfma(SweepArgs sa, ModeArgs ma, long long sweep_wgs, long long nblocks, int LG) {
   extern __shared__ float quad_lds[];
   const long long wg = blockIdx.x;
   if (wg < sweep_wgs) {
@@ -919,7 +958,12 @@ hipError_t step_launch_q(const sbim_handle *h, const Group &g, const SweepArgs &
     const hipError_t e = hipEventRecord(ev0, h->stream);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL((step_kernel_mfma<COMP, G>), dim3(static_cast<unsigned>(sweep_wgs + mode_wgs)),
+  // Register budget: three wavefronts per SIMD (168 registers).  The compensated
+  // two-group form then keeps a few registers in scratch; measured on gfx950 it
+  // still runs 4-8% faster than at two wavefronts per SIMD, whose 1024 resident
+  // two-wavefront work-groups leave the 1040 quads of a 512^2 phase a second round.
+  constexpr int WAVES = 3;
+  hipLaunchKernelGGL((step_kernel_mfma<COMP, G, WAVES>), dim3(static_cast<unsigned>(sweep_wgs + mode_wgs)),
                      dim3(LG * kLanes), lds, h->stream, sa, ma, sweep_wgs, g.nblocks, LG);
   hipError_t e = hipGetLastError();
   if (e == hipSuccess && ev1) e = hipEventRecord(ev1, h->stream);

@@ -571,15 +571,44 @@ int sbim_init(const sbim_config *cfg, sbim_handle **out) {
     need += g.M * (4 * 3 + 32) + g.nblocks * 16 + g.nclasses * 20;
   }
   if (h->mfma) {
-    // Wavefronts per quad (lag ranges): enough work-groups for about two
-    // wavefronts per SIMD (1024 SIMDs) when a phase has few quads, each range
-    // at least 8 blocks of 4 lags.
+    // The quad sweep addresses a block's history with 32-bit offsets from its
+    // slot 0: every block's capacity times its slot stride must stay below 2^31
+    // floats, else the vector-unit sweep plans the group instead.
+    const Group &g0 = h->g[0];
+    bool fits = true;
+    for (long long b = 0; b < g0.nblocks; ++b)
+      if (static_cast<long long>(plan[0].blk_cap[b]) * plan[0].blk_stride[b] * 2 * 3 * sbim::kLanes * 2 >=
+          (1LL << 31))
+        fits = false;
+    if (!fits) {
+      h->mfma = false;
+      h->depth = wbar < 64 ? 6 : (h->comp || wbar >= 1500 ? 12 : 8);
+      need = 0;
+      Group &g = h->g[0];
+      const double cs = g.cs, cp = g.cp, eta = g.eta;
+      const int np = g.np;
+      sbim::PlaneParams pl[SBIM_MAX_PLANES] = {g.pl[0], g.pl[1]};
+      g = Group();
+      g.cs = cs, g.cp = cp, g.eta = eta, g.np = np;
+      for (int k = 0; k < np; ++k) g.pl[k] = pl[k];
+      plan[0] = HostPlan();
+      plan_group(*cfg, h->depth, false, g, plan[0].geom, plan[0].blk_off, plan[0].blk_cap,
+                 plan[0].blk_stride, plan[0].cls_q);
+      need += ring_bytes(h, g) + table_bytes(h, g) + state_bytes_g(g) + pending_bytes(h, g);
+      need += g.M * (4 * 3 + 32) + g.nblocks * 16 + g.nclasses * 20;
+    }
+  }
+  if (h->mfma) {
+    // Wavefronts per quad (lag ranges, each at least 16 blocks of 4 lags),
+    // measured on gfx950 (two planes 512^2 at W = 1000, 1024^2 at W = 2000):
+    // two for the compensated form; four for plain float32 when a phase has
+    // under 2048 quads, else two.
     const Group &g = h->g[0];
     const long long quads = (g.nblocks + h->depth - 1) / h->depth * 16;
     const int nblk = (std::max(0, g.wmax - 2) + 3) / 4;
+    const int want = h->comp ? 2 : (quads < 2048 ? 4 : 2);
     h->lag_chunks = 1;
-    while (h->lag_chunks < 4 && quads * h->lag_chunks < 2048 && nblk >= 16 * h->lag_chunks)
-      h->lag_chunks *= 2;
+    while (h->lag_chunks < want && nblk >= 16 * 2 * h->lag_chunks) h->lag_chunks *= 2;
     if (const char *env = std::getenv("SBIM_SWEEP_CHUNKS")) {  // tuning override
       const int v = std::atoi(env);
       if (v == 1 || v == 2 || v == 4) h->lag_chunks = v;
