@@ -209,6 +209,18 @@ int sbim_set_stream(sbim_handle *h, void *stream);
  */
 int sbim_set_dt(sbim_handle *h, double dt);
 
+/*
+ * sbim_traction_spectrum: copy the traction spectrum of the last push (the
+ * nonlocal, instantaneous and damping terms of Sec. 2.3, Eq. SBI, in the
+ * (x1, x2, x3) frame, before tau^infinity and the inverse transform) into dst:
+ * device memory of [P][3][n3/2+1][n1] complex values of the handle's precision
+ * (interleaved re, im; bin (i1, i3) at i3 * n1 + i1; forward transform
+ * exp(-i k.x), no 1/(n1 n3) factor).  Asynchronous on the handle's stream; a
+ * diagnostic for checking the step before the inverse transform.
+ * SBIM_E_STATE before the first push.
+ */
+int sbim_traction_spectrum(sbim_handle *h, void *dst);
+
 /* Fill *out (host memory). */
 int sbim_get_info(const sbim_handle *h, sbim_info *out);
 

@@ -885,6 +885,17 @@ int sbim_count_nonfinite_noalloc(sbim_handle *h, const void *field, long long *c
   return SBIM_OK;
 }
 
+int sbim_traction_spectrum(sbim_handle *h, void *dst) {
+  if (!h) return fail(nullptr, SBIM_E_INVALID, "handle is NULL");
+  int rc = check_ptr(h, dst, "dst");
+  if (rc) return rc;
+  if (h->step == 0) return fail(h, SBIM_E_STATE, "sbim_traction_spectrum before any push");
+  const hipError_t e =
+      hipMemcpyAsync(dst, h->out_spec, out_spec_bytes(h), hipMemcpyDeviceToDevice, h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "sbim_traction_spectrum");
+  return SBIM_OK;
+}
+
 int sbim_get_info(const sbim_handle *h, sbim_info *out) {
   if (!h || !out) return fail(nullptr, SBIM_E_INVALID, "handle or out is NULL");
   std::memset(out, 0, sizeof *out);

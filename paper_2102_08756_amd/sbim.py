@@ -29,7 +29,7 @@ ERROR_NAMES = {SBIM_E_INVALID: "SBIM_E_INVALID", SBIM_E_OOM: "SBIM_E_OOM",
 EXPORTS = (
     "sbim_init", "sbim_push_displacement", "sbim_tractions", "sbim_backward",
     "sbim_backward_reset", "sbim_reset", "sbim_destroy", "sbim_last_error", "sbim_set_stream",
-    "sbim_set_dt", "sbim_count_nonfinite", "sbim_count_nonfinite_noalloc",
+    "sbim_set_dt", "sbim_count_nonfinite", "sbim_count_nonfinite_noalloc", "sbim_traction_spectrum",
     "sbim_get_info", "sbim_state_bytes", "sbim_save_state", "sbim_load_state", "sbim_step_work",
     "sbim_mode_kernel", "sbim_profile_conv", "sbim_conv_timing",
     "sbim_fault_create", "sbim_fault_step", "sbim_fault_read", "sbim_fault_reset",
@@ -104,6 +104,7 @@ def load_library(path=LIB_PATH):
         "sbim_get_info": (i, [vp, ctypes.POINTER(_Info)]),
         "sbim_count_nonfinite": (i, [vp, vp, ctypes.POINTER(ll)]),
         "sbim_count_nonfinite_noalloc": (i, [vp, vp, vp]),
+        "sbim_traction_spectrum": (i, [vp, vp]),
         "sbim_state_bytes": (ll, [vp]),
         "sbim_save_state": (i, [vp, vp]),
         "sbim_load_state": (i, [vp, vp]),
@@ -279,6 +280,19 @@ class SBIM:
             raise ValueError(f"out: expected an int64 tensor of at least one element on {self.device}")
         self._sync_stream()
         self._check(self._L.sbim_count_nonfinite_noalloc(self._h, _ptr(field), _ptr(out)))
+        return out
+
+    def traction_spectrum(self, out=None):
+        """Traction spectrum of the last push: complex [P, 3, n3/2+1, n1] (complex64 for the
+        float32 forms), before tau_inf and the inverse transform."""
+        ct = torch.complex128 if self.dtype == torch.float64 else torch.complex64
+        shape = (self.P, 3, self.cfg.n3 // 2 + 1, self.cfg.n1)
+        if out is None:
+            out = torch.empty(shape, dtype=ct, device=self.device)
+        if tuple(out.shape) != shape or out.dtype != ct or not out.is_contiguous() or out.device != self.device:
+            raise ValueError(f"out: expected contiguous {ct} {shape} on {self.device}")
+        self._sync_stream()
+        self._check(self._L.sbim_traction_spectrum(self._h, _ptr(out)))
         return out
 
     def set_dt(self, dt):

@@ -88,6 +88,7 @@ def test_null_arguments_rejected():
     assert lib.sbim_set_dt(None, 0.1) == B.SBIM_E_INVALID
     assert lib.sbim_count_nonfinite(None, None, None) == B.SBIM_E_INVALID
     assert lib.sbim_count_nonfinite_noalloc(None, None, None) == B.SBIM_E_INVALID
+    assert lib.sbim_traction_spectrum(None, None) == B.SBIM_E_INVALID
 
 
 STRUCTS = {"sbim_plane": B._Plane, "sbim_config": B._Config, "sbim_info": B._Info,
