@@ -263,6 +263,23 @@ int sbim_save_state(sbim_handle *h, void *dst_device);
 int sbim_load_state(sbim_handle *h, const void *src_device);
 
 /*
+ * Light snapshots for checkpointing long runs: only the float64 running state
+ * (the accumulated displacement spectrum of every mode) and the step counter,
+ * sbim_running_state_bytes() bytes, copied to/from a caller-owned device buffer
+ * asynchronously on the handle's stream.  Loading one also empties the history
+ * ring and the pending sums.  The truncated convolution reads only the last
+ * W + sweep_depth + 1 pushes, so after loading the running state of step n0 and
+ * pushing steps n0 .. a-1 again with a - n0 >= W_cap + sweep_depth + 2, the
+ * handle is in the state of the original run at step a (bit for bit: the same
+ * history entries, summed by the same launches); tractions of the replayed
+ * steps before that are not the original ones.  SBIM_E_INVALID for NULL
+ * arguments or a corrupt header.
+ */
+long long sbim_running_state_bytes(const sbim_handle *h);
+int sbim_save_running_state(sbim_handle *h, void *dst_device);
+int sbim_load_running_state(sbim_handle *h, const void *src_device);
+
+/*
  * Work of the step with index n (0-based): *mode_lags = the number of
  * (plane, mode, lag) products of that step's history sums, i.e. min(W(q), n+1)
  * summed over planes and modes; *conv_bytes = the bytes that the one launch

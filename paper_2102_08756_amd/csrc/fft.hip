@@ -206,6 +206,15 @@ __device__ void lds_fft(cplx<R> *buf, int N, int logN, int nseq, int dir,
 
 static_assert(kFftThreads * kFftPerThread == 4096, "one work-group covers the longest transform");
 
+// Tile of a transposed kernel from its work-group id.  Work-groups are dispatched
+// round-robin over the 8 XCDs (id mod 8); a grid that is a multiple of 8 maps
+// ids id = 8 k + x to tile x * (grid / 8) + k, so the tiles of one XCD are
+// consecutive and the partial cache lines of their transposed runs meet in one L2.
+__device__ __forceinline__ int xcd_tile(int id, int grid) {
+  if (grid % 8) return id;
+  return (id & 7) * (grid >> 3) + (id >> 3);
+}
+
 // Forward, step 1: rows x1 in [x0, x0 + R) of one field; each row of n3 reals
 // becomes n3/2+1 bins.  Pairs (x[2m], x[2m+1]) form a half-length complex
 // sequence z; with Z = FFT(z)
@@ -221,8 +230,9 @@ __global__ __launch_bounds__(kFftThreads) void r2c_t_kernel(
   const int Nh = n3 >> 1;
   const int h3 = Nh + 1;
   const int tiles = n1 / rows;
-  const int f = blockIdx.x / tiles;
-  const int x0 = (blockIdx.x - f * tiles) * rows;
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int f = tile / tiles;
+  const int x0 = (tile - f * tiles) * rows;
   const cplx<Rin> *src =
       reinterpret_cast<const cplx<Rin> *>(in + (static_cast<long long>(f) * n1 + x0) * n3);
   for (int e = threadIdx.x; e < rows * Nh; e += kFftThreads) {
@@ -277,8 +287,9 @@ __global__ __launch_bounds__(kFftThreads) void c2r_t_kernel(
   const int h3 = Nh + 1;
   cplx<R> *nyq = buf + rows * Nh;  // bin k = Nh of each row
   const int tiles = n1 / rows;
-  const int f = blockIdx.x / tiles;
-  const int x0 = (blockIdx.x - f * tiles) * rows;
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int f = tile / tiles;
+  const int x0 = (tile - f * tiles) * rows;
   const cplx<R> *src = spec + static_cast<long long>(f) * h3 * n1 + x0;
   for (int e = threadIdx.x; e < rows * h3; e += kFftThreads) {
     const int k = e / rows;

@@ -981,6 +981,55 @@ int sbim_load_state(sbim_handle *h, const void *src) {
   return SBIM_OK;
 }
 
+long long sbim_running_state_bytes(const sbim_handle *h) {
+  if (!h) return -1;
+  long long b = 256;  // header (step counter)
+  for (int i = 0; i < h->ngroups; ++i) b += state_bytes_g(h->g[i]);
+  return b;
+}
+
+int sbim_save_running_state(sbim_handle *h, void *dst) {
+  if (!h) return fail(nullptr, SBIM_E_INVALID, "handle is NULL");
+  int rc = check_ptr(h, dst, "dst");
+  if (rc) return rc;
+  char *d = static_cast<char *>(dst);
+  hipError_t e = hipMemcpyAsync(d, &h->step, sizeof(long long), hipMemcpyHostToDevice, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);  // &h->step may change after return
+  d += 256;
+  for (int i = 0; i < h->ngroups && e == hipSuccess; ++i) {
+    const Group &g = h->g[i];
+    e = hipMemcpyAsync(d, g.state, state_bytes_g(g), hipMemcpyDeviceToDevice, h->stream);
+    d += state_bytes_g(g);
+  }
+  if (e != hipSuccess) return hip_fail(h, e, "sbim_save_running_state");
+  return SBIM_OK;
+}
+
+int sbim_load_running_state(sbim_handle *h, const void *src) {
+  if (!h) return fail(nullptr, SBIM_E_INVALID, "handle is NULL");
+  int rc = check_ptr(h, src, "src");
+  if (rc) return rc;
+  const char *s = static_cast<const char *>(src);
+  long long step = 0;
+  hipError_t e = hipMemcpyAsync(&step, s, sizeof(long long), hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "sbim_load_running_state header");
+  if (step < 0) return fail(h, SBIM_E_INVALID, "running-state snapshot header is corrupt");
+  s += 256;
+  for (int i = 0; i < h->ngroups && e == hipSuccess; ++i) {
+    Group &g = h->g[i];
+    e = hipMemcpyAsync(g.state, s, state_bytes_g(g), hipMemcpyDeviceToDevice, h->stream);
+    s += state_bytes_g(g);
+    // the history before the snapshot is gone: start from an empty ring and no pending sums
+    const size_t rb = static_cast<size_t>(ring_bytes(h, g));
+    if (e == hipSuccess && rb) e = hipMemsetAsync(g.ring, 0, rb, h->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(g.pending, 0, pending_bytes(h, g), h->stream);
+  }
+  if (e != hipSuccess) return hip_fail(h, e, "sbim_load_running_state");
+  h->step = step;
+  return SBIM_OK;
+}
+
 int sbim_step_work(const sbim_handle *h, long long n, double *mode_lags, double *conv_bytes) {
   if (!h || !mode_lags || !conv_bytes || n < 0)
     return fail(nullptr, SBIM_E_INVALID, "bad arguments to sbim_step_work");

@@ -30,7 +30,8 @@ EXPORTS = (
     "sbim_init", "sbim_push_displacement", "sbim_tractions", "sbim_backward",
     "sbim_backward_reset", "sbim_reset", "sbim_destroy", "sbim_last_error", "sbim_set_stream",
     "sbim_set_dt", "sbim_count_nonfinite", "sbim_count_nonfinite_noalloc", "sbim_traction_spectrum",
-    "sbim_get_info", "sbim_state_bytes", "sbim_save_state", "sbim_load_state", "sbim_step_work",
+    "sbim_get_info", "sbim_state_bytes", "sbim_save_state", "sbim_load_state",
+    "sbim_running_state_bytes", "sbim_save_running_state", "sbim_load_running_state", "sbim_step_work",
     "sbim_mode_kernel", "sbim_profile_conv", "sbim_conv_timing",
     "sbim_fault_create", "sbim_fault_step", "sbim_fault_read", "sbim_fault_reset",
     "sbim_fault_destroy", "sbim_strip_create", "sbim_strip_step", "sbim_strip_read",
@@ -106,6 +107,9 @@ def load_library(path=LIB_PATH):
         "sbim_count_nonfinite_noalloc": (i, [vp, vp, vp]),
         "sbim_traction_spectrum": (i, [vp, vp]),
         "sbim_state_bytes": (ll, [vp]),
+        "sbim_running_state_bytes": (ll, [vp]),
+        "sbim_save_running_state": (i, [vp, vp]),
+        "sbim_load_running_state": (i, [vp, vp]),
         "sbim_save_state": (i, [vp, vp]),
         "sbim_load_state": (i, [vp, vp]),
         "sbim_step_work": (i, [vp, ll, ctypes.POINTER(d), ctypes.POINTER(d)]),
@@ -330,6 +334,31 @@ class SBIM:
         self._sync_stream()
         self._check(self._L.sbim_load_state(self._h, _ptr(buf)))
 
+    def running_state_bytes(self):
+        return int(self._L.sbim_running_state_bytes(self._h))
+
+    def save_running_state(self, buf=None):
+        """Light snapshot: the float64 running state and the step counter only."""
+        if buf is None:
+            buf = torch.empty(self.running_state_bytes(), dtype=torch.uint8, device=self.device)
+        if buf.numel() < self.running_state_bytes() or buf.device != self.device:
+            raise ValueError("snapshot buffer too small or on the wrong device")
+        self._sync_stream()
+        self._check(self._L.sbim_save_running_state(self._h, _ptr(buf)))
+        return buf
+
+    def load_running_state(self, buf):
+        """Restore a light snapshot; the history ring and pending sums start empty, so the
+        next W_cap + sweep_depth + 2 pushes rebuild what the tractions need."""
+        if buf.numel() < self.running_state_bytes() or buf.device != self.device:
+            raise ValueError("snapshot buffer too small or on the wrong device")
+        self._sync_stream()
+        self._check(self._L.sbim_load_running_state(self._h, _ptr(buf)))
+
+    def replay_steps(self):
+        """Pushes that rebuild the history after load_running_state: W_cap + sweep_depth + 2."""
+        return int(self.cfg.window_cap) + int(self.info()["sweep_depth"]) + 2
+
     def step_work(self, n):
         a, b = ctypes.c_double(), ctypes.c_double()
         self._check(self._L.sbim_step_work(self._h, int(n), ctypes.byref(a), ctypes.byref(b)))
@@ -535,35 +564,45 @@ class _CheckpointedLoss(torch.autograd.Function):
     def forward(ctx, sbim, every, loss_fn, u_hist, v_hist):
         sbim.reset()
         N = u_hist.shape[0]
-        snaps = []
+        R = sbim.replay_steps()
+        nseg = (N + every - 1) // every
+        # segment [a, a + every) is recomputed from the running state of step max(0, a - R)
+        starts = sorted({max(0, seg * every - R) for seg in range(nseg)})
+        snaps = {}
         total = torch.zeros((), dtype=sbim.dtype, device=sbim.device)
         tau = sbim.new_field()
         for n in range(N):
-            if n % every == 0:
-                snaps.append(sbim.save_state())
+            if n in starts:
+                snaps[n] = sbim.save_running_state()
             sbim.push(u_hist[n].contiguous(), None if v_hist is None else v_hist[n].contiguous())
             sbim.tractions(out=tau)
             total = total + loss_fn(tau, n).detach()
-        ctx.sbim, ctx.every, ctx.loss_fn, ctx.snaps = sbim, every, loss_fn, snaps
+        ctx.sbim, ctx.every, ctx.loss_fn, ctx.snaps, ctx.R = sbim, every, loss_fn, snaps, R
         ctx.save_for_backward(u_hist, v_hist if v_hist is not None else torch.empty(0))
         ctx.with_v = v_hist is not None
         return total
 
     @staticmethod
     def backward(ctx, gout):
-        sbim, every, loss_fn = ctx.sbim, ctx.every, ctx.loss_fn
+        sbim, every, loss_fn, R = ctx.sbim, ctx.every, ctx.loss_fn, ctx.R
         u_hist, v_hist = ctx.saved_tensors
         v_hist = v_hist if ctx.with_v else None
         N = u_hist.shape[0]
         du = torch.empty_like(u_hist)
         dv = torch.empty_like(u_hist) if ctx.with_v else None
+
+        def push(n):
+            sbim.push(u_hist[n].contiguous(), None if v_hist is None else v_hist[n].contiguous())
         sbim.backward_reset()
         for seg in range((N - 1) // every, -1, -1):
             a, b = seg * every, min(N, (seg + 1) * every)
-            sbim.load_state(ctx.snaps[seg])      # recompute this segment's tractions
+            n0 = max(0, a - R)
+            sbim.load_running_state(ctx.snaps[n0])
+            for n in range(n0, a):               # rebuild the history the segment reads
+                push(n)
             taus = []
-            for n in range(a, b):
-                sbim.push(u_hist[n].contiguous(), None if v_hist is None else v_hist[n].contiguous())
+            for n in range(a, b):                # recompute this segment's tractions
+                push(n)
                 taus.append(sbim.tractions())
             for n in range(b - 1, a - 1, -1):
                 t = taus[n - a].detach().requires_grad_(True)
@@ -576,7 +615,17 @@ class _CheckpointedLoss(torch.autograd.Function):
 
 
 def checkpointed_loss(sbim: SBIM, u_hist, loss_fn, every=50, v_hist=None):
-    """L = sum_n loss_fn(tau^n, n) without keeping tau^n: snapshots every ``every``
-    steps in the forward, and per-segment recomputation of tau in the backward.
-    The handle's forward state is left at the end of the first segment afterwards."""
+    """L = sum_n loss_fn(tau^n, n) without keeping tau^n.
+
+    The forward keeps, per segment of ``every`` steps starting at step a, a light
+    snapshot of the running state of step max(0, a - R), R = W_cap + sweep_depth + 2
+    (``SBIM.replay_steps``): the float64 displacement spectrum and the step counter,
+    ``running_state_bytes()`` each.  The backward restores it, pushes steps
+    a - R .. a - 1 again to rebuild the history the truncated convolution reads, then
+    recomputes the segment's tractions (bit for bit the forward's) and runs the
+    library's transpose over them in reverse.  Memory: N / every snapshots of the
+    running state instead of N traction fields (SBIMRun); cost: up to R + every
+    pushes per segment in the backward, so ``every`` >= W_cap keeps the recomputation
+    within twice the forward.  The handle's forward state is left at the end of the
+    first segment afterwards."""
     return _CheckpointedLoss.apply(sbim, int(every), loss_fn, u_hist, v_hist)

@@ -125,3 +125,52 @@ def test_checkpointed_loss_matches_and_fp32_adjoint(setup):
     print(f"[adjoint] float32 vs float64 gradient: rel-L2 {rel32:.3e}; loss {abs(L32 - L64) / L64:.3e}",
           flush=True)
     assert rel32 < 1e-4
+
+
+@pytest.mark.parametrize("precision,kind", [("fp64", "increment"), ("fp32_comp", "increment"),
+                                            ("fp32", "absolute")])
+def test_running_state_snapshot_and_replay(precision, kind, monkeypatch):
+    """A light snapshot (float64 running state and step counter) of step n0, then the pushes
+    of steps n0 .. a-1 again (a - n0 = W_cap + sweep_depth + 2): from step a on the tractions
+    equal the original run's bit for bit.  Two planes of one material at W = 40 take the
+    matrix-core sweep in the float32 forms (forced), the float64 form the vector sweep."""
+    monkeypatch.setenv("SBIM_SWEEP_KIND", "mfma")
+    cfg = dict(n1=32, n3=32, window_cap=40, planes=[dict(side=1), dict(side=-1)], input_kind=kind)
+    sb = SBIM(Config.from_dict(cfg, precision=precision), device=DEV)
+    R = sb.replay_steps()
+    assert sb.running_state_bytes() * 20 < sb.state_bytes()
+    rng = np.random.default_rng(21)
+    steps = 2 * R + 30
+    u = torch.tensor(rng.standard_normal((steps, 2, 3, 32, 32)), dtype=sb.dtype, device=DEV)
+    n0 = 17
+    a = n0 + R
+    ref = []
+    for n in range(steps):
+        if n == n0:
+            snap = sb.save_running_state()
+        sb.push(u[n])
+        ref.append(sb.tractions().clone())
+    sb.load_running_state(snap)
+    assert sb.info()["step"] == n0
+    for n in range(n0, a):
+        sb.push(u[n])
+    for n in range(a, steps):
+        sb.push(u[n])
+        assert torch.equal(sb.tractions(), ref[n]), n
+    sb.close()
+
+
+def test_checkpointed_loss_memory_and_replay_cost(setup):
+    """The checkpoints of checkpointed_loss hold the running state only: on the 256^2,
+    W = 300 job they total a few MB against the whole traction history that SBIMRun
+    keeps (0.79 GB in float64)."""
+    wl, du, rec = setup
+    sb = SBIM(Config.from_dict(wl.config_dict(), precision="fp64"), device=DEV)
+    N = du.shape[0]
+    snaps = len({max(0, s * 50 - sb.replay_steps()) for s in range((N + 49) // 50)})
+    ckpt = snaps * sb.running_state_bytes()
+    full = N * 3 * wl.n1 * wl.n3 * 8
+    print(f"[adjoint] checkpoints {snaps} x {sb.running_state_bytes()} B = {ckpt / 1e6:.1f} MB "
+          f"against {full / 1e6:.0f} MB of tractions", flush=True)
+    assert ckpt * 50 < full
+    sb.close()
