@@ -17,7 +17,8 @@ CSRC = os.path.join(PKG, "csrc")
 OUT_DIR = os.path.join(PKG, "_lib")
 LIB = os.path.join(OUT_DIR, "libsbim.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
-SOURCES = ["fft.hip", "kernels.hip", "fault.hip", "strip.hip", "checks.hip", "sbim_api.cpp"]
+SOURCES = ["fft.hip", "kernels.hip", "fault.hip", "strip.hip", "checks.hip", "sbim_api.cpp",
+           "diagnostics_api.cpp", "fault_api.cpp", "strip_api.cpp"]
 
 ARCH = os.environ.get("SBIM_OFFLOAD_ARCH", "gfx950")
 COMMON = [

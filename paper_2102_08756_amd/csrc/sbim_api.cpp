@@ -16,12 +16,12 @@
 #include <string>
 #include <vector>
 
-#include "internal.h"
+#include "api_internal.h"
 #include "checks.h"
 
 using sbim::Group;
 
-namespace {
+namespace sbim_api {
 
 thread_local std::string g_init_error;
 
@@ -83,13 +83,6 @@ struct ModeKey {
   double q;
   int nat;
 };
-
-template <typename T>
-hipError_t dev_alloc(T **p, size_t count) {
-  *p = nullptr;
-  if (count == 0) return hipSuccess;
-  return hipMalloc(reinterpret_cast<void **>(p), count * sizeof(T));
-}
 
 hipError_t dev_alloc_bytes(void **p, size_t bytes) {
   *p = nullptr;
@@ -471,7 +464,9 @@ int push_fields(sbim_handle *h, const void *u, const void *v, int vel_rule) {
   return SBIM_OK;
 }
 
-}  // namespace
+}  // namespace sbim_api
+
+using namespace sbim_api;
 
 extern "C" {
 
@@ -846,842 +841,6 @@ int sbim_set_dt(sbim_handle *h, double dt) {
   if (h->cfg.window_mode != SBIM_W_STATIC)
     return fail(h, SBIM_E_STATE, "the time step of a dynamic handle is fixed at sbim_init");
   h->cfg.dt = dt;
-  return SBIM_OK;
-}
-
-int sbim_count_nonfinite(sbim_handle *h, const void *field, long long *count) {
-  if (!h) return fail(nullptr, SBIM_E_INVALID, "handle is NULL");
-  if (!field || !count) return fail(h, SBIM_E_INVALID, "field or count is NULL");
-  const long long n = static_cast<long long>(h->cfg.nplanes) * 3 * h->n1 * h->n3;
-  long long *partial = nullptr;
-  hipError_t e = hipMalloc(&partial, sizeof(long long) * sbim::kCheckBlocks);
-  if (e != hipSuccess) return fail(h, SBIM_E_OOM, "count buffer: %s", hipGetErrorString(e));
-  std::vector<long long> part(sbim::kCheckBlocks, 0);
-  e = sbim::launch_count_nonfinite(h->fp64, field, n, partial, h->stream);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(part.data(), partial, sizeof(long long) * part.size(),
-                       hipMemcpyDeviceToHost, h->stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
-  (void)hipFree(partial);
-  if (e != hipSuccess) return hip_fail(h, e, "non-finite count");
-  long long c = 0;
-  for (long long v : part) c += v;
-  *count = c;
-  return SBIM_OK;
-}
-
-int sbim_count_nonfinite_noalloc(sbim_handle *h, const void *field, long long *count_dev) {
-  if (!h) return fail(nullptr, SBIM_E_INVALID, "handle is NULL");
-  if (!field || !count_dev) return fail(h, SBIM_E_INVALID, "field or count_dev is NULL");
-  int dev = -1;
-  hipError_t e = hipGetDevice(&dev);
-  if (e != hipSuccess) return hip_fail(h, e, "hipGetDevice");
-  if (dev != h->device)
-    return fail(h, SBIM_E_STATE, "current device %d is not the handle's device %d", dev, h->device);
-  const long long n = static_cast<long long>(h->cfg.nplanes) * 3 * h->n1 * h->n3;
-  e = sbim::launch_count_nonfinite_static(h->fp64, field, n, h->count_scratch, count_dev,
-                                          h->stream);
-  if (e != hipSuccess) return hip_fail(h, e, "non-finite count (static scratch)");
-  return SBIM_OK;
-}
-
-int sbim_traction_spectrum(sbim_handle *h, void *dst) {
-  if (!h) return fail(nullptr, SBIM_E_INVALID, "handle is NULL");
-  int rc = check_ptr(h, dst, "dst");
-  if (rc) return rc;
-  if (h->step == 0) return fail(h, SBIM_E_STATE, "sbim_traction_spectrum before any push");
-  const hipError_t e =
-      hipMemcpyAsync(dst, h->out_spec, out_spec_bytes(h), hipMemcpyDeviceToDevice, h->stream);
-  if (e != hipSuccess) return hip_fail(h, e, "sbim_traction_spectrum");
-  return SBIM_OK;
-}
-
-int sbim_get_info(const sbim_handle *h, sbim_info *out) {
-  if (!h || !out) return fail(nullptr, SBIM_E_INVALID, "handle or out is NULL");
-  std::memset(out, 0, sizeof *out);
-  out->modes_per_plane = h->nh;
-  for (int i = 0; i < h->ngroups; ++i) {
-    const Group &g = h->g[i];
-    out->kernel_classes += g.nclasses;
-    out->ring_bytes += ring_bytes(h, g);
-    out->table_bytes += table_bytes(h, g);
-    out->state_bytes += state_bytes_g(g);
-  }
-  out->step = h->step;
-  out->backward_step = h->bstep;
-  out->material_groups = h->ngroups;
-  out->sweep_depth = h->depth;
-  out->sweep_matrix_cores = h->mfma ? 1 : 0;
-  out->sweep_lag_chunks = h->mfma ? h->lag_chunks : 0;
-  return SBIM_OK;
-}
-
-long long sbim_state_bytes(const sbim_handle *h) {
-  if (!h) return -1;
-  long long b = 256 + out_spec_bytes(h);  // header (step counter), last traction spectrum
-  for (int i = 0; i < h->ngroups; ++i) {
-    const Group &g = h->g[i];
-    b += ring_bytes(h, g) + state_bytes_g(g) + pending_bytes(h, g);
-  }
-  return b;
-}
-
-int sbim_save_state(sbim_handle *h, void *dst) {
-  if (!h) return fail(nullptr, SBIM_E_INVALID, "handle is NULL");
-  int rc = check_ptr(h, dst, "dst");
-  if (rc) return rc;
-  char *d = static_cast<char *>(dst);
-  hipError_t e = hipMemcpyAsync(d, &h->step, sizeof(long long), hipMemcpyHostToDevice, h->stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);  // &h->step may change after return
-  d += 256;
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(d, h->out_spec, out_spec_bytes(h), hipMemcpyDeviceToDevice, h->stream);
-  d += out_spec_bytes(h);
-  for (int i = 0; i < h->ngroups && e == hipSuccess; ++i) {
-    Group &g = h->g[i];
-    const size_t rb = ring_bytes(h, g), sb = state_bytes_g(g);
-    if (rb) e = hipMemcpyAsync(d, g.ring, rb, hipMemcpyDeviceToDevice, h->stream);
-    d += rb;
-    if (e == hipSuccess) e = hipMemcpyAsync(d, g.state, sb, hipMemcpyDeviceToDevice, h->stream);
-    d += sb;
-    const size_t pb = pending_bytes(h, g);
-    if (e == hipSuccess) e = hipMemcpyAsync(d, g.pending, pb, hipMemcpyDeviceToDevice, h->stream);
-    d += pb;
-  }
-  if (e != hipSuccess) return hip_fail(h, e, "sbim_save_state");
-  return SBIM_OK;
-}
-
-int sbim_load_state(sbim_handle *h, const void *src) {
-  if (!h) return fail(nullptr, SBIM_E_INVALID, "handle is NULL");
-  int rc = check_ptr(h, src, "src");
-  if (rc) return rc;
-  const char *s = static_cast<const char *>(src);
-  long long step = 0;
-  hipError_t e = hipMemcpyAsync(&step, s, sizeof(long long), hipMemcpyDeviceToHost, h->stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
-  if (e != hipSuccess) return hip_fail(h, e, "sbim_load_state header");
-  if (step < 0) return fail(h, SBIM_E_INVALID, "snapshot header is corrupt");
-  s += 256;
-  e = hipMemcpyAsync(h->out_spec, s, out_spec_bytes(h), hipMemcpyDeviceToDevice, h->stream);
-  s += out_spec_bytes(h);
-  for (int i = 0; i < h->ngroups && e == hipSuccess; ++i) {
-    Group &g = h->g[i];
-    const size_t rb = ring_bytes(h, g), sb = state_bytes_g(g);
-    if (rb) e = hipMemcpyAsync(g.ring, s, rb, hipMemcpyDeviceToDevice, h->stream);
-    s += rb;
-    if (e == hipSuccess) e = hipMemcpyAsync(g.state, s, sb, hipMemcpyDeviceToDevice, h->stream);
-    s += sb;
-    const size_t pb = pending_bytes(h, g);
-    if (e == hipSuccess) e = hipMemcpyAsync(g.pending, s, pb, hipMemcpyDeviceToDevice, h->stream);
-    s += pb;
-  }
-  if (e != hipSuccess) return hip_fail(h, e, "sbim_load_state");
-  h->step = step;
-  return SBIM_OK;
-}
-
-long long sbim_running_state_bytes(const sbim_handle *h) {
-  if (!h) return -1;
-  long long b = 256;  // header (step counter)
-  for (int i = 0; i < h->ngroups; ++i) b += state_bytes_g(h->g[i]);
-  return b;
-}
-
-int sbim_save_running_state(sbim_handle *h, void *dst) {
-  if (!h) return fail(nullptr, SBIM_E_INVALID, "handle is NULL");
-  int rc = check_ptr(h, dst, "dst");
-  if (rc) return rc;
-  char *d = static_cast<char *>(dst);
-  hipError_t e = hipMemcpyAsync(d, &h->step, sizeof(long long), hipMemcpyHostToDevice, h->stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);  // &h->step may change after return
-  d += 256;
-  for (int i = 0; i < h->ngroups && e == hipSuccess; ++i) {
-    const Group &g = h->g[i];
-    e = hipMemcpyAsync(d, g.state, state_bytes_g(g), hipMemcpyDeviceToDevice, h->stream);
-    d += state_bytes_g(g);
-  }
-  if (e != hipSuccess) return hip_fail(h, e, "sbim_save_running_state");
-  return SBIM_OK;
-}
-
-int sbim_load_running_state(sbim_handle *h, const void *src) {
-  if (!h) return fail(nullptr, SBIM_E_INVALID, "handle is NULL");
-  int rc = check_ptr(h, src, "src");
-  if (rc) return rc;
-  const char *s = static_cast<const char *>(src);
-  long long step = 0;
-  hipError_t e = hipMemcpyAsync(&step, s, sizeof(long long), hipMemcpyDeviceToHost, h->stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
-  if (e != hipSuccess) return hip_fail(h, e, "sbim_load_running_state header");
-  if (step < 0) return fail(h, SBIM_E_INVALID, "running-state snapshot header is corrupt");
-  s += 256;
-  for (int i = 0; i < h->ngroups && e == hipSuccess; ++i) {
-    Group &g = h->g[i];
-    e = hipMemcpyAsync(g.state, s, state_bytes_g(g), hipMemcpyDeviceToDevice, h->stream);
-    s += state_bytes_g(g);
-    // the history before the snapshot is gone: start from an empty ring and no pending sums
-    const size_t rb = static_cast<size_t>(ring_bytes(h, g));
-    if (e == hipSuccess && rb) e = hipMemsetAsync(g.ring, 0, rb, h->stream);
-    if (e == hipSuccess) e = hipMemsetAsync(g.pending, 0, pending_bytes(h, g), h->stream);
-  }
-  if (e != hipSuccess) return hip_fail(h, e, "sbim_load_running_state");
-  h->step = step;
-  return SBIM_OK;
-}
-
-int sbim_step_work(const sbim_handle *h, long long n, double *mode_lags, double *conv_bytes) {
-  if (!h || !mode_lags || !conv_bytes || n < 0)
-    return fail(nullptr, SBIM_E_INVALID, "bad arguments to sbim_step_work");
-  const double r = static_cast<double>(h->rsize);
-  const int S = h->depth;
-  double lags = 0, bytes = 0;
-  for (int i = 0; i < h->ngroups; ++i) {
-    const Group &g = h->g[i];
-    double mode_lag_g = 0;
-    for (long long s = 0; s < g.M; ++s)
-      mode_lag_g += static_cast<double>(std::min<long long>(g.h_win[s], n + 1));
-    lags += mode_lag_g * g.np;
-    // the sweep launched with step n (for steps n+1 .. n+S): blocks of phase
-    // (n+1) mod S read the history up to step n-1 that each of their modes
-    // needs (lags 2 .. W-1 of step n+1), the kernel rows of each distinct class
-    // of the block (lags 2 .. min(cap-1, n+1) + S - 1), the per-mode
-    // class/window indices and block descriptors, and write S pending sums per
-    // mode and plane
-    for (long long b = (n + 1) % S; b < g.nblocks; b += S) {
-      const long long last = std::min<long long>(g.h_blk_cap[b] - 1, n + 1);
-      int last_cls = -1;
-      for (long long s = b * sbim::kLanes; s < std::min(g.M, (b + 1) * sbim::kLanes); ++s) {
-        if (g.h_nat[s] < 0) continue;  // padding position of the matrix-core layout
-        const int w = g.h_win[s];
-        bytes += std::max(0LL, std::min<long long>(w - 1, n + 1) - 1) * g.np * 3.0 * 2.0 * r;
-        bytes += 8.0 + S * g.np * 10.0 * r;
-        if (w > 2 && g.h_cls[s] != last_cls) {
-          last_cls = g.h_cls[s];
-          bytes += std::max(0LL, std::min<long long>(w - 1, last + S - 1) - 1) * 4.0 * r;
-        }
-      }
-      bytes += 16.0;
-    }
-    // the mode items of step n (same launch), per mode and plane: the three
-    // float64 spectrum values, the float64 state read and written, the ring
-    // slot written, the pending sum read, the newest lags (history from the
-    // ring beyond lag 0, kernel rows), the traction written; per mode its bin,
-    // q and direction, window, class and row offset; per block its descriptors
-    for (long long s = 0; s < g.M; ++s) {
-      if (g.h_nat[s] < 0) continue;
-      const long long b = s / sbim::kLanes;
-      const int phi = static_cast<int>(b % S);
-      const bool swept = n >= (phi == 0 ? S : phi);
-      const long long fresh = std::min<long long>(g.h_win[s], swept ? (n - phi) % S + 2 : n + 1);
-      double per_plane = 3.0 * 16.0 + 3.0 * 32.0 + 3.0 * 2.0 * r + 3.0 * 2.0 * r;
-      if (swept) per_plane += 10.0 * r;
-      per_plane += std::max(0LL, fresh - 1) * 3.0 * 2.0 * r + fresh * 4.0 * r;
-      bytes += per_plane * g.np + 4.0 + 24.0 + 4.0 + 4.0 + (fresh > 0 ? 8.0 : 0.0);
-    }
-    bytes += g.nblocks * 16.0;
-  }
-  *mode_lags = lags;
-  *conv_bytes = bytes;
-  return SBIM_OK;
-}
-
-int sbim_mode_kernel(sbim_handle *h, int p, int i1, int i3, double *host_out, int max_lags) {
-  if (!h) return fail(nullptr, SBIM_E_INVALID, "handle is NULL");
-  if (p < 0 || p >= h->cfg.nplanes || i1 < 0 || i1 >= h->n1 || i3 < 0 || i3 >= h->h3 ||
-      max_lags < 0 || (max_lags > 0 && !host_out))
-    return fail(h, SBIM_E_INVALID, "bad arguments to sbim_mode_kernel");
-  const Group *gp = nullptr;
-  for (int i = 0; i < h->ngroups; ++i)
-    for (int k = 0; k < h->g[i].np; ++k)
-      if (h->g[i].pl[k].index == p) gp = &h->g[i];
-  const Group &g = *gp;
-  const int f = i3 * h->n1 + i1;
-  long long s = -1;
-  for (long long t = 0; t < g.M; ++t)
-    if (g.h_nat[t] == f) s = t;
-  const int w = g.h_win[s];
-  if (w == 0) return 0;
-  const int c = g.h_cls[s];
-  hipError_t e = hipStreamSynchronize(h->stream);
-  const int nl = std::min(w, max_lags);
-  std::vector<char> tmp(4 * h->rsize);
-  for (int j = 0; j < nl && e == hipSuccess; ++j) {
-    const char *src = static_cast<const char *>(g.table) + (g.h_cls_off[c] + j) * 4 * h->rsize;
-    e = hipMemcpy(tmp.data(), src, 4 * h->rsize, hipMemcpyDeviceToHost);
-    for (int k = 0; k < 4; ++k) {
-      double v;
-      if (h->fp64)
-        std::memcpy(&v, tmp.data() + 8 * k, 8);
-      else {
-        float fv;
-        std::memcpy(&fv, tmp.data() + 4 * k, 4);
-        v = fv;
-      }
-      host_out[static_cast<long long>(k) * max_lags + j] = v;
-    }
-  }
-  if (e != hipSuccess) return hip_fail(h, e, "sbim_mode_kernel copy");
-  return w;
-}
-
-int sbim_profile_conv(sbim_handle *h, int enable) {
-  if (!h) return fail(nullptr, SBIM_E_INVALID, "handle is NULL");
-  hipError_t e = hipStreamSynchronize(h->stream);
-  if (e != hipSuccess) return hip_fail(h, e, "sbim_profile_conv sync");
-  h->ev_used = 0;
-  h->profile = enable != 0;
-  return SBIM_OK;
-}
-
-int sbim_conv_timing(sbim_handle *h, double *total_ms, long long *launches) {
-  if (!h || !total_ms || !launches) return fail(nullptr, SBIM_E_INVALID, "bad arguments");
-  hipError_t e = hipStreamSynchronize(h->stream);
-  if (e != hipSuccess) return hip_fail(h, e, "sbim_conv_timing sync");
-  double tot = 0;
-  for (size_t i = 0; i < h->ev_used; ++i) {
-    float ms = 0;
-    e = hipEventElapsedTime(&ms, h->ev_start[i], h->ev_stop[i]);
-    if (e != hipSuccess) return hip_fail(h, e, "hipEventElapsedTime");
-    tot += ms;
-  }
-  *total_ms = tot;
-  *launches = static_cast<long long>(h->ev_used);
-  return SBIM_OK;
-}
-
-}  // extern "C"
-
-// ---------------------------------------------------------------- fault
-
-// Frictional fault between the half-space of plane 0 (above) and the one below
-// it (plane 1, or the mirror image of plane 0).  Float64 state in one block of
-// [kFaultRows][cells]: u (6 rows: upper side x1..x3, lower side x1..x3), v (6),
-// slip (2), slip rate (2), traction (3).
-struct sbim_fault {
-  sbim_handle *h = nullptr;
-  long long cells = 0;
-  bool mirror = false;
-  double zp[3] = {0, 0, 0}, zm[3] = {0, 0, 0};
-  double *prm = nullptr;     // tau0 (3 rows), mu_s, mu_k, d_c
-  double *st = nullptr;      // state rows as above
-  void *push = nullptr;      // [P][3][cells] working precision: input of the next push
-  void *func = nullptr;      // [P][3][cells] working precision: tractions without damping
-  long long *bad = nullptr;  // parameter check result
-  long long steps = 0;
-};
-
-namespace {
-
-constexpr int kFaultRows = 19;
-constexpr int kRowU = 0, kRowV = 6, kRowSlip = 12, kRowRate = 14, kRowTau = 16;
-
-void free_fault(sbim_fault *f) {
-  if (!f) return;
-  if (f->h) (void)hipStreamSynchronize(f->h->stream);
-  void *ptrs[] = {f->prm, f->st, f->push, f->func, f->bad};
-  for (void *p : ptrs)
-    if (p) (void)hipFree(p);
-  delete f;
-}
-
-int fault_clear(sbim_fault *f) {
-  sbim_handle *h = f->h;
-  const size_t field = static_cast<size_t>(h->cfg.nplanes) * 3 * f->cells * h->rsize;
-  hipError_t e = hipMemsetAsync(f->st, 0, sizeof(double) * kFaultRows * f->cells, h->stream);
-  if (e == hipSuccess) e = hipMemsetAsync(f->push, 0, field, h->stream);
-  if (e != hipSuccess) return hip_fail(h, e, "clearing the fault state");
-  f->steps = 0;
-  return SBIM_OK;
-}
-
-}  // namespace
-
-extern "C" {
-
-int sbim_fault_create(sbim_handle *h, const sbim_fault_params *prm, sbim_fault **out) {
-  if (!out) return fail(h, SBIM_E_INVALID, "out is NULL");
-  *out = nullptr;
-  if (!h) return fail(nullptr, SBIM_E_INVALID, "handle is NULL");
-  if (!prm || !prm->tau0 || !prm->mu_s || !prm->mu_k || !prm->d_c)
-    return fail(h, SBIM_E_INVALID, "fault parameters: a pointer is NULL");
-  const sbim_config &c = h->cfg;
-  const bool one = c.nplanes == 1 && c.plane[0].side == 1;
-  const bool two = c.nplanes == 2 && c.plane[0].side == 1 && c.plane[1].side == -1;
-  if (!one && !two)
-    return fail(h, SBIM_E_INVALID,
-                "a fault needs plane 0 with side +1 and, if present, plane 1 with side -1");
-  if (h->step != 0) return fail(h, SBIM_E_STATE, "a fault starts from a handle at step 0");
-  sbim_fault *f = new (std::nothrow) sbim_fault;
-  if (!f) return fail(h, SBIM_E_OOM, "host allocation failed");
-  f->h = h;
-  f->cells = static_cast<long long>(h->n1) * h->n3;
-  f->mirror = one;
-  const sbim_plane &pu = c.plane[0];
-  const sbim_plane &pl = one ? c.plane[0] : c.plane[1];
-  const double zu[3] = {pu.mu / pu.cs, (pu.cp / pu.cs) * pu.mu / pu.cs, pu.mu / pu.cs};
-  const double zl[3] = {pl.mu / pl.cs, (pl.cp / pl.cs) * pl.mu / pl.cs, pl.mu / pl.cs};
-  for (int i = 0; i < 3; ++i) {
-    f->zp[i] = zu[i];
-    f->zm[i] = zl[i];
-  }
-  const size_t n = static_cast<size_t>(f->cells);
-  const size_t field = static_cast<size_t>(c.nplanes) * 3 * n * h->rsize;
-  hipError_t e;
-  if ((e = dev_alloc(&f->prm, 6 * n)) != hipSuccess ||
-      (e = dev_alloc(&f->st, kFaultRows * n)) != hipSuccess ||
-      (e = dev_alloc_bytes(&f->push, field)) != hipSuccess ||
-      (e = dev_alloc_bytes(&f->func, field)) != hipSuccess ||
-      (e = dev_alloc(&f->bad, 1)) != hipSuccess) {
-    f->h = nullptr;
-    free_fault(f);
-    return fail(h, SBIM_E_OOM, "fault allocation failed: %s", hipGetErrorString(e));
-  }
-  const size_t b = n * sizeof(double);
-  if ((e = hipMemcpyAsync(f->prm, prm->tau0, 3 * b, hipMemcpyDeviceToDevice, h->stream)) ||
-      (e = hipMemcpyAsync(f->prm + 3 * n, prm->mu_s, b, hipMemcpyDeviceToDevice, h->stream)) ||
-      (e = hipMemcpyAsync(f->prm + 4 * n, prm->mu_k, b, hipMemcpyDeviceToDevice, h->stream)) ||
-      (e = hipMemcpyAsync(f->prm + 5 * n, prm->d_c, b, hipMemcpyDeviceToDevice, h->stream)) ||
-      (e = hipMemsetAsync(f->bad, 0, sizeof(long long), h->stream)) ||
-      (e = sbim::launch_fault_check(f->prm, f->prm + 3 * n, f->prm + 4 * n, f->prm + 5 * n,
-                                    f->cells, f->bad, h->stream))) {
-    free_fault(f);
-    return hip_fail(h, e, "fault parameter upload");
-  }
-  long long bad = 0;
-  if ((e = hipMemcpyAsync(&bad, f->bad, sizeof bad, hipMemcpyDeviceToHost, h->stream)) ||
-      (e = hipStreamSynchronize(h->stream))) {
-    free_fault(f);
-    return hip_fail(h, e, "fault parameter check");
-  }
-  if (bad) {
-    const long long cell = bad - 1;
-    free_fault(f);
-    return fail(h, SBIM_E_INVALID,
-                "fault parameters at cell (i1=%lld, i3=%lld): need finite values, d_c > 0, "
-                "0 <= mu_k <= mu_s",
-                cell / h->n3, cell % h->n3);
-  }
-  int rc = fault_clear(f);
-  if (rc) {
-    free_fault(f);
-    return rc;
-  }
-  *out = f;
-  return SBIM_OK;
-}
-
-int sbim_fault_step(sbim_fault *f, double *tau_out, double *rate_out) {
-  if (!f) return fail(nullptr, SBIM_E_INVALID, "fault is NULL");
-  sbim_handle *h = f->h;
-  if (h->step != f->steps)
-    return fail(h, SBIM_E_STATE, "the handle was stepped outside its fault (%lld vs %lld steps)",
-                h->step, f->steps);
-  int rc = push_fields(h, f->push, nullptr, sbim::VEL_ZERO);
-  if (rc) return rc;
-  hipError_t e = fft_inverse(h, h->out_spec, h->spec, f->func, nullptr);
-  if (e != hipSuccess) return hip_fail(h, e, "inverse FFT of the fault tractions");
-  const long long n = f->cells;
-  sbim::FaultArgs a;
-  a.functional = f->func;
-  a.tau0 = f->prm;
-  a.mu_s = f->prm + 3 * n;
-  a.mu_k = f->prm + 4 * n;
-  a.d_c = f->prm + 5 * n;
-  a.u = f->st + kRowU * n;
-  a.v = f->st + kRowV * n;
-  a.slip = f->st + kRowSlip * n;
-  a.rate = f->st + kRowRate * n;
-  a.tau = f->st + kRowTau * n;
-  a.tau_out = tau_out;
-  a.rate_out = rate_out;
-  a.push = f->push;
-  a.cells = n;
-  for (int i = 0; i < 3; ++i) {
-    a.zp[i] = f->zp[i];
-    a.zm[i] = f->zm[i];
-  }
-  a.dt = h->cfg.dt;
-  a.increment = h->cfg.input_kind == SBIM_INCREMENT;
-  e = sbim::launch_fault_step(h->fp64, f->mirror, a, h->stream);
-  if (e != hipSuccess) return hip_fail(h, e, "fault kernel");
-  f->steps += 1;
-  return SBIM_OK;
-}
-
-int sbim_fault_read(const sbim_fault *f, int field, double *dst) {
-  if (!f) return fail(nullptr, SBIM_E_INVALID, "fault is NULL");
-  sbim_handle *h = f->h;
-  if (!dst) return fail(h, SBIM_E_INVALID, "dst is NULL");
-  int row, rows;
-  switch (field) {
-    case SBIM_FAULT_TRACTION: row = kRowTau, rows = 3; break;
-    case SBIM_FAULT_SLIP_RATE: row = kRowRate, rows = 2; break;
-    case SBIM_FAULT_SLIP: row = kRowSlip, rows = 2; break;
-    case SBIM_FAULT_DISPLACEMENT: row = kRowU, rows = 6; break;
-    case SBIM_FAULT_VELOCITY: row = kRowV, rows = 6; break;
-    default: return fail(h, SBIM_E_INVALID, "unknown fault field %d", field);
-  }
-  hipError_t e = hipMemcpyAsync(dst, f->st + static_cast<long long>(row) * f->cells,
-                                sizeof(double) * rows * f->cells, hipMemcpyDeviceToDevice,
-                                h->stream);
-  if (e != hipSuccess) return hip_fail(h, e, "fault read");
-  return SBIM_OK;
-}
-
-int sbim_fault_reset(sbim_fault *f) {
-  if (!f) return fail(nullptr, SBIM_E_INVALID, "fault is NULL");
-  int rc = sbim_reset(f->h);
-  if (rc) return rc;
-  return fault_clear(f);
-}
-
-int sbim_fault_destroy(sbim_fault *f) {
-  free_fault(f);
-  return SBIM_OK;
-}
-
-}  // extern "C"
-
-// ---------------------------------------------------------------- strip
-
-// Finite-element strip of the hybrid scheme on the fault, closed at S+ (and
-// S-) by the handle's planes.  Float64 node state [12][nodes], 3 components
-// each: two displacement buffers (u_{t+1} read by the next step's stencil, the
-// other one written with u_{t+2}; `cur` names the first), the half-step velocity
-// and the velocity v_{t+1}; fault outputs [8][cells] (traction 3, slip rate 2,
-// slip 2, sliding 1).  Each step ends with the predictor of the next one, so
-// the push inputs of S+ (S-) are ready when the step begins.
-struct sbim_strip {
-  sbim_handle *h = nullptr;
-  int n2 = 0;                 // index of the top storage node layer (S+)
-  int fault_lo = -1;          // two-sided: storage layer of the lower fault copy
-  long long cells = 0, nodes = 0;
-  double *node = nullptr;     // u (two buffers), half-step velocity, velocity
-  int cur = 0;                // displacement buffer the next step's stencil reads
-  double dt_pred = 0;         // step size of the prediction held for the next step
-  double *cell = nullptr;     // fault outputs
-  double *prm = nullptr;      // tau0 (3), mu_s, mu_k, d_c
-  double *stencil = nullptr;  // [n2+1][27][9]
-  double *mass = nullptr;     // [n2+1]
-  void *push_u = nullptr, *push_v = nullptr, *tau_sbi = nullptr;  // [P][3][cells] working precision
-  double *r_fault = nullptr;  // two-sided: [2][3][cells]
-  long long *bad = nullptr;
-  long long steps = 0;
-};
-
-namespace {
-
-constexpr int kCellTau = 0, kCellRate = 3, kCellSlip = 5, kCellSliding = 7, kCellRows = 8;
-
-// Stiffness of a cube of side h with Lame constants (lam, mu): trilinear shape
-// functions, 2x2x2 Gauss points; dofs node-major (corner a = a1 + 2 a2 + 4 a3),
-// then x1, x2, x3.
-void cube_stiffness(double h, double lam, double mu, std::vector<double> &K) {
-  K.assign(24 * 24, 0.0);
-  const double g = 1.0 / std::sqrt(3.0);
-  const double pts[2] = {-g, g};
-  double D[6][6] = {};
-  for (int i = 0; i < 3; ++i) {
-    for (int j = 0; j < 3; ++j) D[i][j] = lam;
-    D[i][i] = lam + 2.0 * mu;
-    D[3 + i][3 + i] = mu;
-  }
-  const double jac = (h / 2.0) * (h / 2.0) * (h / 2.0);
-  for (double p0 : pts)
-    for (double p1 : pts)
-      for (double p2 : pts) {
-        const double p[3] = {p0, p1, p2};
-        double B[6][24] = {};
-        for (int a = 0; a < 8; ++a) {
-          double sgn[3], d[3];
-          for (int k = 0; k < 3; ++k) sgn[k] = ((a >> k) & 1) ? 1.0 : -1.0;
-          for (int k = 0; k < 3; ++k) {
-            double prod = sgn[k] / 8.0;
-            for (int m = 0; m < 3; ++m)
-              if (m != k) prod *= 1.0 + sgn[m] * p[m];
-            d[k] = prod * (2.0 / h);
-          }
-          // Voigt order (11, 22, 33, 23, 13, 12), engineering shear strains
-          B[0][3 * a] = d[0];
-          B[1][3 * a + 1] = d[1];
-          B[2][3 * a + 2] = d[2];
-          B[3][3 * a + 1] = d[2];
-          B[3][3 * a + 2] = d[1];
-          B[4][3 * a] = d[2];
-          B[4][3 * a + 2] = d[0];
-          B[5][3 * a] = d[1];
-          B[5][3 * a + 1] = d[0];
-        }
-        for (int i = 0; i < 24; ++i)
-          for (int j = 0; j < 24; ++j) {
-            double acc = 0.0;
-            for (int r = 0; r < 6; ++r) {
-              double db = 0.0;
-              for (int c = 0; c < 6; ++c) db += D[r][c] * B[c][j];
-              acc += B[r][i] * db;
-            }
-            K[i * 24 + j] += acc * jac;
-          }
-      }
-}
-
-void free_strip(sbim_strip *s) {
-  if (!s) return;
-  if (s->h) (void)hipStreamSynchronize(s->h->stream);
-  void *ptrs[] = {s->node, s->cell, s->prm, s->stencil, s->mass, s->push_u, s->push_v,
-                  s->tau_sbi, s->r_fault, s->bad};
-  for (void *p : ptrs)
-    if (p) (void)hipFree(p);
-  delete s;
-}
-
-int strip_clear(sbim_strip *s) {
-  sbim_handle *h = s->h;
-  // at rest: u_1 = 0 and v_{1/2} = 0, so the first push inputs are zero too
-  const size_t fb = static_cast<size_t>(h->cfg.nplanes) * 3 * s->cells * h->rsize;
-  hipError_t e = hipMemsetAsync(s->node, 0, sizeof(double) * 12 * s->nodes, h->stream);
-  if (e == hipSuccess)
-    e = hipMemsetAsync(s->cell, 0, sizeof(double) * kCellRows * s->cells, h->stream);
-  if (e == hipSuccess) e = hipMemsetAsync(s->push_u, 0, fb, h->stream);
-  if (e == hipSuccess) e = hipMemsetAsync(s->push_v, 0, fb, h->stream);
-  if (e != hipSuccess) return hip_fail(h, e, "clearing the strip state");
-  s->cur = 0;
-  s->dt_pred = h->cfg.dt;
-  s->steps = 0;
-  return SBIM_OK;
-}
-
-}  // namespace
-
-extern "C" {
-
-int sbim_strip_create(sbim_handle *h, const sbim_strip_config *sc, const sbim_fault_params *prm,
-                      sbim_strip **out) {
-  if (!out) return fail(h, SBIM_E_INVALID, "out is NULL");
-  *out = nullptr;
-  if (!h) return fail(nullptr, SBIM_E_INVALID, "handle is NULL");
-  if (!sc || !sc->rho || !sc->cp || !sc->cs)
-    return fail(h, SBIM_E_INVALID, "strip configuration: a pointer is NULL");
-  if (!prm || !prm->tau0 || !prm->mu_s || !prm->mu_k || !prm->d_c)
-    return fail(h, SBIM_E_INVALID, "fault parameters: a pointer is NULL");
-  const sbim_config &c = h->cfg;
-  const int La = sc->layers, Lb = sc->layers_below;
-  if (Lb == 0 && (c.nplanes != 1 || c.plane[0].side != 1))
-    return fail(h, SBIM_E_INVALID, "a strip needs a handle with one plane of side +1 (S+)");
-  if (Lb > 0 && (c.nplanes != 2 || c.plane[0].side != 1 || c.plane[1].side != -1))
-    return fail(h, SBIM_E_INVALID,
-                "a two-sided strip needs a handle with planes of sides +1 (S+) and -1 (S-)");
-  if (c.dx1 != c.dx3)
-    return fail(h, SBIM_E_INVALID, "strip elements are cubes: dx1 must equal dx3");
-  if (La < 1 || La > 4096 || Lb < 0 || Lb > 4096)
-    return fail(h, SBIM_E_INVALID, "strip layers must be in [1, 4096] above and [0, 4096] below, "
-                "got %d and %d", La, Lb);
-  if (Lb > 0 && (!sc->rho_below || !sc->cp_below || !sc->cs_below))
-    return fail(h, SBIM_E_INVALID, "strip configuration: a pointer of the lower side is NULL");
-  for (int side = 0; side < 2; ++side) {
-    const int L = side ? Lb : La;
-    const double *R = side ? sc->rho_below : sc->rho, *P = side ? sc->cp_below : sc->cp,
-                 *Q = side ? sc->cs_below : sc->cs;
-    for (int l = 0; l < L; ++l) {
-      const double r = R[l], p = P[l], q = Q[l];
-      if (!(r > 0 && q > 0 && p > q * std::sqrt(4.0 / 3.0)) || !std::isfinite(r) ||
-          !std::isfinite(p))
-        return fail(h, SBIM_E_INVALID,
-                    "strip layer %d%s: need rho > 0, cs > 0, cp > cs sqrt(4/3) (got %g, %g, %g)",
-                    l, side ? " below the fault" : "", r, p, q);
-    }
-  }
-  if (h->step != 0) return fail(h, SBIM_E_STATE, "a strip starts from a handle at step 0");
-  sbim_strip *s = new (std::nothrow) sbim_strip;
-  if (!s) return fail(h, SBIM_E_OOM, "host allocation failed");
-  s->h = h;
-  // storage node layers: [0, Lb] the block below the fault (S- first; empty when
-  // one-sided), then the block above it from the fault to S+
-  const int base = Lb > 0 ? Lb + 1 : 0;
-  s->fault_lo = Lb > 0 ? Lb : -1;
-  s->n2 = base + La;
-  s->cells = static_cast<long long>(h->n1) * h->n3;
-  s->nodes = (s->n2 + 1LL) * s->cells;
-  const double hx = c.dx1;
-  // element layers in storage order: (first storage node layer, material)
-  struct ELayer { int j0; double rho, cp, cs; };
-  std::vector<ELayer> el;
-  for (int l = 0; l < Lb; ++l) {      // listed from the fault outwards: storage bottom-up
-    const int k = Lb - 1 - l;
-    el.push_back({l, sc->rho_below[k], sc->cp_below[k], sc->cs_below[k]});
-  }
-  for (int l = 0; l < La; ++l) el.push_back({base + l, sc->rho[l], sc->cp[l], sc->cs[l]});
-  // stencil and lumped mass per node layer (no element crosses the split fault)
-  std::vector<double> st(static_cast<size_t>(s->n2 + 1) * 27 * 9, 0.0), ms(s->n2 + 1, 0.0);
-  std::vector<double> K;
-  for (const ELayer &E : el) {
-    const double rho = E.rho;
-    const double mu = rho * E.cs * E.cs;
-    const double lam = rho * E.cp * E.cp - 2.0 * mu;
-    cube_stiffness(hx, lam, mu, K);
-    for (int a2 = 0; a2 < 2; ++a2) {
-      const int j = E.j0 + a2;             // node layer of the element's corners with this a2
-      ms[j] += 4.0 * rho * hx * hx * hx / 8.0;
-      for (int a1 = 0; a1 < 2; ++a1)
-        for (int a3 = 0; a3 < 2; ++a3) {
-          const int a = a1 + 2 * a2 + 4 * a3;
-          for (int b = 0; b < 8; ++b) {
-            const int o1 = (b & 1) - a1, o2 = ((b >> 1) & 1) - a2, o3 = ((b >> 2) & 1) - a3;
-            const int o = (o1 + 1) + 3 * (o2 + 1) + 9 * (o3 + 1);
-            double *blk = &st[(static_cast<size_t>(j) * 27 + o) * 9];
-            for (int p = 0; p < 3; ++p)
-              for (int q = 0; q < 3; ++q) blk[3 * p + q] += K[(3 * a + p) * 24 + 3 * b + q];
-          }
-        }
-    }
-  }
-  const size_t n = static_cast<size_t>(s->cells);
-  const size_t fb = static_cast<size_t>(c.nplanes) * 3 * n * h->rsize;
-  hipError_t e;
-  if ((e = dev_alloc(&s->node, 12 * static_cast<size_t>(s->nodes))) != hipSuccess ||
-      (Lb > 0 && (e = dev_alloc(&s->r_fault, 6 * n)) != hipSuccess) ||
-      (e = dev_alloc(&s->cell, kCellRows * n)) != hipSuccess ||
-      (e = dev_alloc(&s->prm, 6 * n)) != hipSuccess ||
-      (e = dev_alloc(&s->stencil, st.size())) != hipSuccess ||
-      (e = dev_alloc(&s->mass, ms.size())) != hipSuccess ||
-      (e = dev_alloc_bytes(&s->push_u, fb)) != hipSuccess ||
-      (e = dev_alloc_bytes(&s->push_v, fb)) != hipSuccess ||
-      (e = dev_alloc_bytes(&s->tau_sbi, fb)) != hipSuccess ||
-      (e = dev_alloc(&s->bad, 1)) != hipSuccess) {
-    s->h = nullptr;
-    free_strip(s);
-    return fail(h, SBIM_E_OOM, "strip allocation failed: %s", hipGetErrorString(e));
-  }
-  const size_t b = n * sizeof(double);
-  long long bad = 0;
-  if ((e = upload(s->stencil, st.data(), st.size() * sizeof(double), h->stream)) ||
-      (e = upload(s->mass, ms.data(), ms.size() * sizeof(double), h->stream)) ||
-      (e = hipMemcpyAsync(s->prm, prm->tau0, 3 * b, hipMemcpyDeviceToDevice, h->stream)) ||
-      (e = hipMemcpyAsync(s->prm + 3 * n, prm->mu_s, b, hipMemcpyDeviceToDevice, h->stream)) ||
-      (e = hipMemcpyAsync(s->prm + 4 * n, prm->mu_k, b, hipMemcpyDeviceToDevice, h->stream)) ||
-      (e = hipMemcpyAsync(s->prm + 5 * n, prm->d_c, b, hipMemcpyDeviceToDevice, h->stream)) ||
-      (e = hipMemsetAsync(s->bad, 0, sizeof(long long), h->stream)) ||
-      (e = sbim::launch_fault_check(s->prm, s->prm + 3 * n, s->prm + 4 * n, s->prm + 5 * n,
-                                    s->cells, s->bad, h->stream)) ||
-      (e = hipMemcpyAsync(&bad, s->bad, sizeof bad, hipMemcpyDeviceToHost, h->stream)) ||
-      (e = hipStreamSynchronize(h->stream))) {
-    free_strip(s);
-    return hip_fail(h, e, "strip set-up");
-  }
-  if (bad) {
-    const long long cell = bad - 1;
-    free_strip(s);
-    return fail(h, SBIM_E_INVALID,
-                "fault parameters at cell (i1=%lld, i3=%lld): need finite values, d_c > 0, "
-                "0 <= mu_k <= mu_s",
-                cell / h->n3, cell % h->n3);
-  }
-  int rc = strip_clear(s);
-  if (rc) {
-    free_strip(s);
-    return rc;
-  }
-  *out = s;
-  return SBIM_OK;
-}
-
-int sbim_strip_step(sbim_strip *s, double *tau_out, double *rate_out) {
-  if (!s) return fail(nullptr, SBIM_E_INVALID, "strip is NULL");
-  sbim_handle *h = s->h;
-  if (h->step != s->steps)
-    return fail(h, SBIM_E_STATE, "the handle was stepped outside its strip (%lld vs %lld steps)",
-                h->step, s->steps);
-  const long long n = s->cells;
-  sbim::StripArgs a;
-  a.u = s->node + 3 * s->cur * s->nodes;
-  a.u_next = s->node + 3 * (1 - s->cur) * s->nodes;
-  a.vh = s->node + 6 * s->nodes;
-  a.v = s->node + 9 * s->nodes;
-  a.stencil = s->stencil;
-  a.mass = s->mass;
-  a.tau_sbi = s->tau_sbi;
-  a.push_u = s->push_u;
-  a.push_v = s->push_v;
-  a.tau0 = s->prm;
-  a.mu_s = s->prm + 3 * n;
-  a.mu_k = s->prm + 4 * n;
-  a.d_c = s->prm + 5 * n;
-  a.tau = s->cell + kCellTau * n;
-  a.rate = s->cell + kCellRate * n;
-  a.slip = s->cell + kCellSlip * n;
-  a.sliding = s->cell + kCellSliding * n;
-  a.tau_out = tau_out;
-  a.rate_out = rate_out;
-  a.nodes = s->nodes;
-  a.cells = n;
-  a.n1 = h->n1;
-  a.n3 = h->n3;
-  a.n2 = s->n2;
-  a.fault_lo = s->fault_lo;
-  a.r_fault = s->r_fault;
-  a.dt = h->cfg.dt;
-  a.area = h->cfg.dx1 * h->cfg.dx3;
-  a.increment = h->cfg.input_kind == SBIM_INCREMENT;
-  // push of u_{t+1} (or its increment) and the predicted velocity, written by
-  // the previous step's predictor, redone first if the step size has changed
-  // since (sbim_set_dt on a quasi-dynamic handle)
-  if (h->cfg.dt != s->dt_pred) {
-    hipError_t e0 = sbim::launch_strip_repredict(
-        h->fp64, s->node + 3 * s->cur * s->nodes, s->node + 3 * (1 - s->cur) * s->nodes,
-        s->node + 6 * s->nodes, s->node + 9 * s->nodes, s->push_u, s->push_v, s->nodes,
-        s->cells, s->fault_lo >= 0, h->cfg.input_kind == SBIM_INCREMENT, h->cfg.dt,
-        s->dt_pred, h->stream);
-    if (e0 != hipSuccess) return hip_fail(h, e0, "strip predictor for the new step size");
-    s->dt_pred = h->cfg.dt;
-  }
-  int rc = push_fields(h, s->push_u, s->push_v, sbim::VEL_INPUT);
-  if (rc) return rc;
-  hipError_t e = fft_inverse(h, h->out_spec, h->spec, s->tau_sbi, nullptr);
-  if (e != hipSuccess) return hip_fail(h, e, "inverse FFT of the S+ (and S-) tractions");
-  e = sbim::launch_strip_correct(h->fp64, a, h->stream);
-  if (e != hipSuccess) return hip_fail(h, e, "strip corrector");
-  if (s->fault_lo >= 0) {
-    e = sbim::launch_strip_fault2(a, h->stream);
-    if (e != hipSuccess) return hip_fail(h, e, "strip fault nodes");
-  }
-  s->cur = 1 - s->cur;
-  s->steps += 1;
-  return SBIM_OK;
-}
-
-int sbim_strip_read(const sbim_strip *s, int field, double *dst) {
-  if (!s) return fail(nullptr, SBIM_E_INVALID, "strip is NULL");
-  sbim_handle *h = s->h;
-  if (!dst) return fail(h, SBIM_E_INVALID, "dst is NULL");
-  const double *src;
-  long long count;
-  switch (field) {
-    case SBIM_STRIP_TRACTION: src = s->cell + kCellTau * s->cells, count = 3 * s->cells; break;
-    case SBIM_STRIP_SLIP_RATE: src = s->cell + kCellRate * s->cells, count = 2 * s->cells; break;
-    case SBIM_STRIP_SLIP: src = s->cell + kCellSlip * s->cells, count = 2 * s->cells; break;
-    case SBIM_STRIP_SLIDING: src = s->cell + kCellSliding * s->cells, count = s->cells; break;
-    case SBIM_STRIP_DISPLACEMENT:   // u_{t+1}: the buffer the last step's stencil read
-      src = s->node + 3 * (1 - s->cur) * s->nodes, count = 3 * s->nodes;
-      break;
-    case SBIM_STRIP_VELOCITY: src = s->node + 9 * s->nodes, count = 3 * s->nodes; break;
-    default: return fail(h, SBIM_E_INVALID, "unknown strip field %d", field);
-  }
-  hipError_t e = hipMemcpyAsync(dst, src, sizeof(double) * count, hipMemcpyDeviceToDevice,
-                                h->stream);
-  if (e != hipSuccess) return hip_fail(h, e, "strip read");
-  return SBIM_OK;
-}
-
-int sbim_strip_reset(sbim_strip *s) {
-  if (!s) return fail(nullptr, SBIM_E_INVALID, "strip is NULL");
-  int rc = sbim_reset(s->h);
-  if (rc) return rc;
-  return strip_clear(s);
-}
-
-int sbim_strip_destroy(sbim_strip *s) {
-  free_strip(s);
   return SBIM_OK;
 }
 
