@@ -7,7 +7,11 @@
 // Conventions (the paper fixes none): forward exp(-i k.x) on the stored half
 // spectrum (h3 = n3/2 + 1 bins along x3); the inverse drops the imaginary parts
 // of the i3 = 0 and i3 = n3/2 bins and applies the caller's scale.
+#include <algorithm>
 #include <cmath>
+#include <map>
+#include <mutex>
+#include <tuple>
 #include <type_traits>
 
 #include "internal.h"
@@ -206,13 +210,15 @@ __device__ void lds_fft(cplx<R> *buf, int N, int logN, int nseq, int dir,
 
 static_assert(kFftThreads * kFftPerThread == 4096, "one work-group covers the longest transform");
 
-// Tile of a transposed kernel from its work-group id.  Work-groups are dispatched
-// round-robin over the 8 XCDs (id mod 8); a grid that is a multiple of 8 maps
-// ids id = 8 k + x to tile x * (grid / 8) + k, so the tiles of one XCD are
-// consecutive and the partial cache lines of their transposed runs meet in one L2.
-__device__ __forceinline__ int xcd_tile(int id, int grid) {
-  if (grid % 8) return id;
-  return (id & 7) * (grid >> 3) + (id >> 3);
+// Tile of a transposed kernel from its tile id.  Work-groups are dispatched
+// round-robin over the 8 XCDs; with a persistent grid that is a multiple of 8,
+// the ids a work-group takes are congruent mod 8 to its XCD, and a tile count
+// that is a multiple of 8 maps ids 8 k + x to tile x * (ntiles / 8) + k, so the
+// tiles one XCD works on at a time are consecutive and the partial cache lines
+// of their transposed runs meet in one L2.
+__device__ __forceinline__ int xcd_tile(int id, int ntiles) {
+  if (ntiles % 8) return id;
+  return (id & 7) * (ntiles >> 3) + (id >> 3);
 }
 
 // Forward, step 1: rows x1 in [x0, x0 + R) of one field; each row of n3 reals
@@ -221,37 +227,61 @@ __device__ __forceinline__ int xcd_tile(int id, int grid) {
 //   X[k] = (Z[k] + conj Z[Nh-k]) / 2 - i e^{-2 pi i k/n3} (Z[k] - conj Z[Nh-k]) / 2.
 // The bins are written transposed, spec[f][k][x1], R consecutive x1 at a time.
 // Input reals of type Rin are widened to the transform's type R on load.
+// Persistent: work-group w takes tiles w, w + G, w + 2G, ... (G = the grid,
+// sized to the work-groups the GPU holds at once when there are more tiles) and
+// loads the next tile's rows into registers while the current tile is
+// transformed in LDS, so the input's memory latency overlaps the transform
+// (measured at 2048 x 2048: 198 -> 148 us for six fields).
 template <typename Rin, typename R, int MAXV>
 __global__ __launch_bounds__(kFftThreads) void r2c_t_kernel(
     const Rin *__restrict__ in, cplx<R> *__restrict__ spec, int n1, int n3, int logNh, int rows,
-    const cplx<R> *__restrict__ tw) {
+    const cplx<R> *__restrict__ tw, int ntiles) {
   extern __shared__ unsigned char smem_raw[];
   cplx<R> *buf = reinterpret_cast<cplx<R> *>(smem_raw);
   const int Nh = n3 >> 1;
   const int h3 = Nh + 1;
   const int tiles = n1 / rows;
-  const int tile = xcd_tile(blockIdx.x, gridDim.x);
-  const int f = tile / tiles;
-  const int x0 = (tile - f * tiles) * rows;
-  const cplx<Rin> *src =
-      reinterpret_cast<const cplx<Rin> *>(in + (static_cast<long long>(f) * n1 + x0) * n3);
-  for (int e = threadIdx.x; e < rows * Nh; e += kFftThreads) {
-    const cplx<Rin> v = src[e];
-    buf[e] = cplx<R>{static_cast<R>(v.x), static_cast<R>(v.y)};
-  }
-  __syncthreads();
-  lds_fft<R, kFftThreads, MAXV>(buf, Nh, logNh, rows, -1, tw);
+  const int cnt = rows * Nh;  // complex input points of a tile (<= kFftThreads * MAXV)
+  cplx<Rin> pre[MAXV];
+  auto load = [&](int id) {
+    const int tile = xcd_tile(id, ntiles);
+    const int f = tile / tiles;
+    const int x0 = (tile - f * tiles) * rows;
+    const cplx<Rin> *src =
+        reinterpret_cast<const cplx<Rin> *>(in + (static_cast<long long>(f) * n1 + x0) * n3);
+#pragma unroll
+    for (int i = 0; i < MAXV; ++i) {
+      const int e = threadIdx.x + i * kFftThreads;
+      if (e < cnt) pre[i] = src[e];
+    }
+  };
+  int id = blockIdx.x;
+  if (id < ntiles) load(id);
   const int step = kTwiddleN / n3;
-  cplx<R> *dst = spec + static_cast<long long>(f) * h3 * n1 + x0;
-  for (int e = threadIdx.x; e < rows * h3; e += kFftThreads) {
-    const int k = e / rows;
-    const int r = e - k * rows;
-    const cplx<R> zk = buf[r * Nh + (k == Nh ? 0 : k)];
-    const cplx<R> zc = cconj<R>(buf[r * Nh + (k == 0 ? 0 : Nh - k)]);
-    const cplx<R> ev = {(zk.x + zc.x) * R(0.5), (zk.y + zc.y) * R(0.5)};
-    const cplx<R> od = {(zk.x - zc.x) * R(0.5), (zk.y - zc.y) * R(0.5)};
-    const cplx<R> t = cmul<R>(od, twiddle<R>(tw, k * step, -1));
-    dst[static_cast<long long>(k) * n1 + r] = cplx<R>{ev.x + t.y, ev.y - t.x};  // ev - i t
+  for (; id < ntiles; id += gridDim.x) {
+    const int tile = xcd_tile(id, ntiles);
+    const int f = tile / tiles;
+    const int x0 = (tile - f * tiles) * rows;
+#pragma unroll
+    for (int i = 0; i < MAXV; ++i) {
+      const int e = threadIdx.x + i * kFftThreads;
+      if (e < cnt) buf[e] = cplx<R>{static_cast<R>(pre[i].x), static_cast<R>(pre[i].y)};
+    }
+    __syncthreads();
+    if (id + static_cast<int>(gridDim.x) < ntiles) load(id + gridDim.x);
+    lds_fft<R, kFftThreads, MAXV>(buf, Nh, logNh, rows, -1, tw);
+    cplx<R> *dst = spec + static_cast<long long>(f) * h3 * n1 + x0;
+    for (int e = threadIdx.x; e < rows * h3; e += kFftThreads) {
+      const int k = e / rows;
+      const int r = e - k * rows;
+      const cplx<R> zk = buf[r * Nh + (k == Nh ? 0 : k)];
+      const cplx<R> zc = cconj<R>(buf[r * Nh + (k == 0 ? 0 : Nh - k)]);
+      const cplx<R> ev = {(zk.x + zc.x) * R(0.5), (zk.y + zc.y) * R(0.5)};
+      const cplx<R> od = {(zk.x - zc.x) * R(0.5), (zk.y - zc.y) * R(0.5)};
+      const cplx<R> t = cmul<R>(od, twiddle<R>(tw, k * step, -1));
+      dst[static_cast<long long>(k) * n1 + r] = cplx<R>{ev.x + t.y, ev.y - t.x};  // ev - i t
+    }
+    __syncthreads();  // the next tile overwrites buf
   }
 }
 
@@ -363,6 +393,37 @@ int tile_rows(int n1, int Nh, size_t point_bytes, int extra_per_row) {
 }
 int rows_per_group(int n) { return max(1, 1024 / n); }
 
+// Grid of the persistent forward kernel: one work-group per tile when the
+// device holds them all at once, else the work-groups it holds (the kernel's
+// occupancy at this LDS size, queried once per kernel, LDS size and device) in
+// whole XCD rounds (a multiple of 8).
+template <typename K>
+int persistent_grid(K kernel, int ntiles, size_t lds_bytes) {
+  static std::mutex mu;
+  static std::map<std::tuple<const void *, size_t, int>, int> resident;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return ntiles;
+  const auto key = std::make_tuple(reinterpret_cast<const void *>(kernel), lds_bytes, dev);
+  int cap = 0;
+  {
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = resident.find(key);
+    if (it != resident.end()) {
+      cap = it->second;
+    } else {
+      int per_cu = 0, ncu = 0;
+      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kFftThreads, lds_bytes) !=
+              hipSuccess ||
+          hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return ntiles;
+      cap = std::max(1, per_cu) * std::max(1, ncu);
+      resident.emplace(key, cap);
+    }
+  }
+  if (ntiles <= cap) return ntiles;
+  return cap >= 8 ? cap - cap % 8 : cap;
+}
+
 template <typename F>
 hipError_t with_maxv(int points, F &&launch) {
   if (points <= kFftThreads * 4) return launch(std::integral_constant<int, 4>());
@@ -389,12 +450,14 @@ hipError_t forward_impl(const void *in, void *spec, int F, int n1, int n3, const
                         hipStream_t st) {
   const int Nh = n3 / 2, h3 = Nh + 1;
   const int rows = tile_rows(n1, Nh, sizeof(cplx<R>), 0);
+  const int ntiles = F * (n1 / rows);
+  const size_t lds = static_cast<size_t>(rows) * Nh * sizeof(cplx<R>);
   hipError_t e = with_maxv(rows * Nh, [&](auto mv) {
-    hipLaunchKernelGGL((r2c_t_kernel<Rin, R, decltype(mv)::value>),
-                       dim3(static_cast<unsigned>(F * (n1 / rows))), dim3(kFftThreads),
-                       static_cast<size_t>(rows) * Nh * sizeof(cplx<R>), st,
-                       static_cast<const Rin *>(in), static_cast<cplx<R> *>(spec), n1, n3,
-                       ilog2(Nh), rows, static_cast<const cplx<R> *>(tw));
+    auto kernel = r2c_t_kernel<Rin, R, decltype(mv)::value>;
+    hipLaunchKernelGGL(kernel, dim3(static_cast<unsigned>(persistent_grid(kernel, ntiles, lds))),
+                       dim3(kFftThreads), lds, st, static_cast<const Rin *>(in),
+                       static_cast<cplx<R> *>(spec), n1, n3, ilog2(Nh), rows,
+                       static_cast<const cplx<R> *>(tw), ntiles);
     return hipGetLastError();
   });
   if (e != hipSuccess) return e;
