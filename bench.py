@@ -40,6 +40,7 @@ sys.path.insert(0, ROOT)
 METRIC = "SBIM mode·history-steps/s + % HBM peak; FP32 vs FP64 at 1e-5 rel L2"
 UNIT = "mode·history-steps/s"
 HBM_PEAK_GBS = 8000.0
+MFMA_F32_PEAK_TFLOPS = 157.3     # dense float32 matrix-core peak of the MI355X
 PROFILES = os.path.join(ROOT, "profiles")
 
 
@@ -201,7 +202,9 @@ def measure_form(wl, precision, steps, warmup, device, inputs_cache):
         "mode_lags": lags,
         "first_timed_step": n0,
         "roofline": {
-            "kernel": f"step_kernel (push, traction and history sweep, depth {info['sweep_depth']})",
+            "kernel": (f"step_kernel{'_mfma' if info['sweep_matrix_cores'] else ''} (push, traction "
+                       f"and history sweep, depth {info['sweep_depth']}"
+                       f"{', matrix cores' if info['sweep_matrix_cores'] else ''})"),
             "bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": gbs / HBM_PEAK_GBS,
             "traffic": traffic,
@@ -212,6 +215,14 @@ def measure_form(wl, precision, steps, warmup, device, inputs_cache):
                                          if traffic and launches else None),
             "avg_launch_ms": conv_ms / launches if launches else None,
             "launches": launches,
+            "matrix_cores": {
+                "achieved": 20.0 * lags / (conv_ms * 1e-3) / 1e12,
+                "peak": MFMA_F32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": 20.0 * lags / (conv_ms * 1e-3) / 1e12 / MFMA_F32_PEAK_TFLOPS,
+                "note": ("the history products, 20 flop (10 FMAs) per plane, mode and lag, in the "
+                         "step launch time: on the matrix cores (16x16x4 float32) when "
+                         "sweep_matrix_cores is 1, the newest lags of each step on the vector units"),
+            } if info["sweep_matrix_cores"] else None,
             "direct_convolution_equivalent": {
                 "GBs": direct_bytes / (conv_ms * 1e-3) / 1e9,
                 "x_hbm_peak": direct_bytes / (conv_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
@@ -698,7 +709,10 @@ def main():
                       "mode_lags_per_step": res[f]["mode_lags"] / steps,
                       "step_kernel_GBs": res[f]["roofline"]["achieved"],
                       "step_kernel_frac": res[f]["roofline"]["frac"],
-                      "sweep_depth": res[f]["info"]["sweep_depth"], "init_s": res[f]["init_s"],
+                      "sweep_depth": res[f]["info"]["sweep_depth"],
+                      "sweep_matrix_cores": res[f]["info"]["sweep_matrix_cores"],
+                      "sweep_lag_chunks": res[f]["info"]["sweep_lag_chunks"],
+                      "init_s": res[f]["init_s"],
                       "ring_bytes": res[f]["info"]["ring_bytes"],
                       "table_bytes": res[f]["info"]["table_bytes"],
                       "kernel_classes": res[f]["info"]["kernel_classes"]} for f in forms},
