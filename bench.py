@@ -666,9 +666,12 @@ def main():
     steps = args.steps or default_timed_steps(wl)
     forms = [f for f in args.forms.split(",") if f]
     rforms = [f for f in args.rupture_forms.split(",") if f]
-    if not forms:                       # the rupture leg alone (profiling runs)
-        print(json.dumps({"rupture": rupture_leg(workloads.FAULTS[args.rupture], rforms, device,
-                                                 args.bimaterial) if rforms else None}))
+    if not forms:                       # the rupture and adjoint legs alone (profiling runs)
+        aforms = [f for f in args.adjoint_forms.split(",") if f]
+        print(json.dumps({
+            "rupture": rupture_leg(workloads.FAULTS[args.rupture], rforms, device,
+                                   args.bimaterial) if rforms else None,
+            "adjoint": adjoint_leg(device, aforms) if aforms else None}))
         return
     cache = {}
     res = {}
