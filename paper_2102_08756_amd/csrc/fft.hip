@@ -61,26 +61,33 @@ __device__ __forceinline__ cplx<R> rot4(cplx<R> a, int dir) {
 // remaining factor).  Every thread of the work-group must call it.  Each pass
 // stages its inputs in registers, synchronises, then writes the outputs.
 template <typename R, int NT, int MAXV>
-__device__ void lds_fft(cplx<R> *buf, int N, int logN, int nseq, int dir,
-                        const cplx<R> *__restrict__ tw) {
+__device__ __attribute__((always_inline)) void lds_fft(cplx<R> *buf, int N, int logN, int nseq,
+                                                       int dir, const cplx<R> *__restrict__ tw) {
   const int total = N * nseq;
   int logNs = 0;
+  // Each pass first loads, for every butterfly of the thread, its inputs from
+  // LDS and its twiddles from the (cached) table, then synchronises and writes
+  // the outputs.  The twiddle loads take a clamped butterfly index and no
+  // branch, so that all of them are in flight together.
   constexpr int B8 = (MAXV + 7) / 8;  // radix-8 butterflies per thread and pass
   // radix-8 passes
   for (; logNs + 3 <= logN; logNs += 3) {
     const int q8 = N >> 3;
     const int nbf = total >> 3;
-    cplx<R> v[B8][8];
+    const int Ns = 1 << logNs;
+    const int step = kTwiddleN >> (logNs + 3);  // 4096 / (8 Ns)
+    cplx<R> v[B8][8], w[B8][7];
 #pragma unroll
     for (int t = 0; t < B8; ++t) {
-      const int g = threadIdx.x + t * NT;
-      if (g < nbf) {
-        const int b = g >> (logN - 3);
-        const int j = g & (q8 - 1);
-        const int base = b * N + j;
+      const int g = min(static_cast<int>(threadIdx.x) + t * NT, nbf - 1);
+      const int b = g >> (logN - 3);
+      const int j = g & (q8 - 1);
+      const int k = j & (Ns - 1);
+      const int base = b * N + j;
 #pragma unroll
-        for (int r = 0; r < 8; ++r) v[t][r] = buf[base + r * q8];
-      }
+      for (int r = 1; r < 8; ++r) w[t][r - 1] = twiddle<R>(tw, r * k * step, dir);
+#pragma unroll
+      for (int r = 0; r < 8; ++r) v[t][r] = buf[base + r * q8];
     }
     __syncthreads();
 #pragma unroll
@@ -89,13 +96,11 @@ __device__ void lds_fft(cplx<R> *buf, int N, int logN, int nseq, int dir,
       if (g < nbf) {
         const int b = g >> (logN - 3);
         const int j = g & (q8 - 1);
-        const int Ns = 1 << logNs;
         const int k = j & (Ns - 1);
-        const int step = kTwiddleN >> (logNs + 3);  // 4096 / (8 Ns)
         cplx<R> a[8];
         a[0] = v[t][0];
 #pragma unroll
-        for (int r = 1; r < 8; ++r) a[r] = cmul<R>(v[t][r], twiddle<R>(tw, r * k * step, dir));
+        for (int r = 1; r < 8; ++r) a[r] = cmul<R>(v[t][r], w[t][r - 1]);
         // 8-point DFT as radix 2 x radix 4: e_r = a_r + a_{r+4},
         // o_r = (a_r - a_{r+4}) exp(dir 2 pi i r / 8); X[2m] = DFT4(e), X[2m+1] = DFT4(o)
         cplx<R> e[4], o[4];
@@ -132,18 +137,21 @@ __device__ void lds_fft(cplx<R> *buf, int N, int logN, int nseq, int dir,
   if (logNs + 2 == logN) {
     const int q4 = N >> 2;
     const int nbf = total >> 2;
+    const int Ns = 1 << logNs;
+    const int step = kTwiddleN >> (logNs + 2);  // 4096 / (4 Ns)
     constexpr int B4 = (MAXV + 3) / 4;
-    cplx<R> v[B4][4];
+    cplx<R> v[B4][4], w[B4][3];
 #pragma unroll
     for (int t = 0; t < B4; ++t) {
-      const int g = threadIdx.x + t * NT;
-      if (g < nbf) {
-        const int b = g >> (logN - 2);
-        const int j = g & (q4 - 1);
-        const int base = b * N + j;
+      const int g = min(static_cast<int>(threadIdx.x) + t * NT, nbf - 1);
+      const int b = g >> (logN - 2);
+      const int j = g & (q4 - 1);
+      const int k = j & (Ns - 1);
+      const int base = b * N + j;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) v[t][r] = buf[base + r * q4];
-      }
+      for (int r = 1; r < 4; ++r) w[t][r - 1] = twiddle<R>(tw, r * k * step, dir);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) v[t][r] = buf[base + r * q4];
     }
     __syncthreads();
 #pragma unroll
@@ -152,13 +160,11 @@ __device__ void lds_fft(cplx<R> *buf, int N, int logN, int nseq, int dir,
       if (g < nbf) {
         const int b = g >> (logN - 2);
         const int j = g & (q4 - 1);
-        const int Ns = 1 << logNs;
         const int k = j & (Ns - 1);
-        const int step = kTwiddleN >> (logNs + 2);  // 4096 / (4 Ns)
         cplx<R> a0 = v[t][0];
-        cplx<R> a1 = cmul<R>(v[t][1], twiddle<R>(tw, k * step, dir));
-        cplx<R> a2 = cmul<R>(v[t][2], twiddle<R>(tw, 2 * k * step, dir));
-        cplx<R> a3 = cmul<R>(v[t][3], twiddle<R>(tw, 3 * k * step, dir));
+        cplx<R> a1 = cmul<R>(v[t][1], w[t][0]);
+        cplx<R> a2 = cmul<R>(v[t][2], w[t][1]);
+        cplx<R> a3 = cmul<R>(v[t][3], w[t][2]);
         cplx<R> t0 = cadd<R>(a0, a2), t1 = csub<R>(a0, a2);
         cplx<R> t2 = cadd<R>(a1, a3);
         // dir * i * (a1 - a3): -i for the forward transform, +i for the inverse
@@ -177,28 +183,28 @@ __device__ void lds_fft(cplx<R> *buf, int N, int logN, int nseq, int dir,
   if (logNs < logN) {
     const int h2 = N >> 1;
     const int nbf = total >> 1;
-    cplx<R> v[MAXV / 2][2];
+    const int Ns = 1 << logNs;
+    const int step = kTwiddleN >> (logNs + 1);
+    constexpr int B2 = (MAXV + 1) / 2;
+    cplx<R> v[B2][2], w[B2];
 #pragma unroll
-    for (int t = 0; t < MAXV / 2; ++t) {
-      const int g = threadIdx.x + t * NT;
-      if (g < nbf) {
-        const int b = g >> (logN - 1);
-        const int j = g & (h2 - 1);
-        v[t][0] = buf[b * N + j];
-        v[t][1] = buf[b * N + j + h2];
-      }
+    for (int t = 0; t < B2; ++t) {
+      const int g = min(static_cast<int>(threadIdx.x) + t * NT, nbf - 1);
+      const int b = g >> (logN - 1);
+      const int j = g & (h2 - 1);
+      w[t] = twiddle<R>(tw, (j & (Ns - 1)) * step, dir);
+      v[t][0] = buf[b * N + j];
+      v[t][1] = buf[b * N + j + h2];
     }
     __syncthreads();
 #pragma unroll
-    for (int t = 0; t < MAXV / 2; ++t) {
+    for (int t = 0; t < B2; ++t) {
       const int g = threadIdx.x + t * NT;
       if (g < nbf) {
         const int b = g >> (logN - 1);
         const int j = g & (h2 - 1);
-        const int Ns = 1 << logNs;
         const int k = j & (Ns - 1);
-        const int step = kTwiddleN >> (logNs + 1);
-        cplx<R> a1 = cmul<R>(v[t][1], twiddle<R>(tw, k * step, dir));
+        cplx<R> a1 = cmul<R>(v[t][1], w[t]);
         const int out = b * N + ((j >> logNs) << (logNs + 1)) + k;
         buf[out] = cadd<R>(v[t][0], a1);
         buf[out + Ns] = csub<R>(v[t][0], a1);
@@ -233,7 +239,7 @@ __device__ __forceinline__ int xcd_tile(int id, int ntiles) {
 // transformed in LDS, so the input's memory latency overlaps the transform
 // (measured at 2048 x 2048: 198 -> 148 us for six fields).
 template <typename Rin, typename R, int MAXV>
-__global__ __launch_bounds__(kFftThreads) void r2c_t_kernel(
+__global__ __launch_bounds__(kFftThreads) __attribute__((amdgpu_waves_per_eu(2))) void r2c_t_kernel(
     const Rin *__restrict__ in, cplx<R> *__restrict__ spec, int n1, int n3, int logNh, int rows,
     const cplx<R> *__restrict__ tw, int ntiles) {
   extern __shared__ unsigned char smem_raw[];
@@ -271,15 +277,32 @@ __global__ __launch_bounds__(kFftThreads) void r2c_t_kernel(
     if (id + static_cast<int>(gridDim.x) < ntiles) load(id + gridDim.x);
     lds_fft<R, kFftThreads, MAXV>(buf, Nh, logNh, rows, -1, tw);
     cplx<R> *dst = spec + static_cast<long long>(f) * h3 * n1 + x0;
-    for (int e = threadIdx.x; e < rows * h3; e += kFftThreads) {
-      const int k = e / rows;
-      const int r = e - k * rows;
-      const cplx<R> zk = buf[r * Nh + (k == Nh ? 0 : k)];
-      const cplx<R> zc = cconj<R>(buf[r * Nh + (k == 0 ? 0 : Nh - k)]);
-      const cplx<R> ev = {(zk.x + zc.x) * R(0.5), (zk.y + zc.y) * R(0.5)};
-      const cplx<R> od = {(zk.x - zc.x) * R(0.5), (zk.y - zc.y) * R(0.5)};
-      const cplx<R> t = cmul<R>(od, twiddle<R>(tw, k * step, -1));
-      dst[static_cast<long long>(k) * n1 + r] = cplx<R>{ev.x + t.y, ev.y - t.x};  // ev - i t
+    // rows * h3 outputs in chunks of up to 9 per thread (two at 2048 points),
+    // unrolled so that the twiddle loads of a chunk are in flight together; the
+    // chunk is held to 9 for the registers of the next tile's prefetch
+    constexpr int kOutChunk = MAXV + 1 < 9 ? MAXV + 1 : 9;
+    const int nout = rows * h3;
+    for (int e0 = threadIdx.x; e0 < nout; e0 += kOutChunk * kFftThreads) {
+      cplx<R> twk[kOutChunk];
+#pragma unroll
+      for (int i = 0; i < kOutChunk; ++i) {
+        const int e = min(e0 + i * kFftThreads, nout - 1);  // clamped: loads without branches
+        twk[i] = twiddle<R>(tw, (e / rows) * step, -1);
+      }
+#pragma unroll
+      for (int i = 0; i < kOutChunk; ++i) {
+        const int e = e0 + i * kFftThreads;
+        if (e < nout) {
+          const int k = e / rows;
+          const int r = e - k * rows;
+          const cplx<R> zk = buf[r * Nh + (k == Nh ? 0 : k)];
+          const cplx<R> zc = cconj<R>(buf[r * Nh + (k == 0 ? 0 : Nh - k)]);
+          const cplx<R> ev = {(zk.x + zc.x) * R(0.5), (zk.y + zc.y) * R(0.5)};
+          const cplx<R> od = {(zk.x - zc.x) * R(0.5), (zk.y - zc.y) * R(0.5)};
+          const cplx<R> t = cmul<R>(od, twk[i]);
+          dst[static_cast<long long>(k) * n1 + r] = cplx<R>{ev.x + t.y, ev.y - t.x};  // ev - i t
+        }
+      }
     }
     __syncthreads();  // the next tile overwrites buf
   }
@@ -295,10 +318,26 @@ __global__ __launch_bounds__(kFftThreads) void cfft_rows_kernel(
   cplx<R> *buf = reinterpret_cast<cplx<R> *>(smem_raw);
   const long long row0 = static_cast<long long>(blockIdx.x) * per;
   const int nb = static_cast<int>(min(static_cast<long long>(per), nrows - row0));
-  for (int e = threadIdx.x; e < nb * n; e += kFftThreads) buf[e] = src[row0 * n + e];
+  const int cnt = nb * n;  // <= kFftThreads * MAXV
+  // every load of the work-group's rows in flight before the first LDS store
+  cplx<R> v[MAXV];
+#pragma unroll
+  for (int i = 0; i < MAXV; ++i) {
+    const int e = min(static_cast<int>(threadIdx.x) + i * kFftThreads, cnt - 1);  // clamped: no branch
+    v[i] = src[row0 * n + e];
+  }
+  // (unguarded, so that the compiler cannot sink each load into a guarded store:
+  // past cnt a lane rewrites point cnt - 1 with its own value)
+#pragma unroll
+  for (int i = 0; i < MAXV; ++i)
+    buf[min(static_cast<int>(threadIdx.x) + i * kFftThreads, cnt - 1)] = v[i];
   __syncthreads();
   lds_fft<R, kFftThreads, MAXV>(buf, n, logn, nb, dir, tw);
-  for (int e = threadIdx.x; e < nb * n; e += kFftThreads) dst[row0 * n + e] = buf[e];
+#pragma unroll
+  for (int i = 0; i < MAXV; ++i) {
+    const int e = threadIdx.x + i * kFftThreads;
+    if (e < cnt) dst[row0 * n + e] = buf[e];
+  }
 }
 
 // Inverse, last step: rows x1 in [x0, x0 + R) of one field from the transposed
@@ -321,35 +360,67 @@ __global__ __launch_bounds__(kFftThreads) void c2r_t_kernel(
   const int f = tile / tiles;
   const int x0 = (tile - f * tiles) * rows;
   const cplx<R> *src = spec + static_cast<long long>(f) * h3 * n1 + x0;
-  for (int e = threadIdx.x; e < rows * h3; e += kFftThreads) {
-    const int k = e / rows;
-    const int r = e - k * rows;
-    const cplx<R> v = src[static_cast<long long>(k) * n1 + r];
-    if (k < Nh)
-      buf[r * Nh + k] = v;
-    else
-      nyq[r] = v;
+  // rows * h3 inputs in chunks of MAXV + 1 per thread (one chunk unless the rows
+  // are very short), all loads of a chunk in flight before its LDS stores
+  const int nin = rows * h3;
+  cplx<R> v[MAXV + 1];
+  for (int e0 = threadIdx.x; e0 < nin; e0 += (MAXV + 1) * kFftThreads) {
+#pragma unroll
+    for (int i = 0; i <= MAXV; ++i) {
+      const int e = min(e0 + i * kFftThreads, nin - 1);  // clamped: loads without branches
+      const int k = e / rows;
+      v[i] = src[static_cast<long long>(k) * n1 + (e - k * rows)];
+    }
+#pragma unroll
+    for (int i = 0; i <= MAXV; ++i) {
+      const int e = e0 + i * kFftThreads;
+      if (e < nin) {
+        const int k = e / rows;
+        const int r = e - k * rows;
+        if (k < Nh)
+          buf[r * Nh + k] = v[i];
+        else
+          nyq[r] = v[i];
+      }
+    }
   }
   __syncthreads();
+  // pair (k, Nh - k) of each row: chunks of MAXV / 2 + 1 per thread, the twiddles
+  // of a chunk loaded together
   const int step = kTwiddleN / n3;
   const int half = Nh / 2 + 1;
-  for (int e = threadIdx.x; e < rows * half; e += kFftThreads) {
-    const int r = e / half;
-    const int k = e - r * half;
-    cplx<R> *row = buf + r * Nh;
-    if (k == 0) {
-      const R y0 = row[0].x, yn = nyq[r].x;
-      row[0] = cplx<R>{y0 + yn, y0 - yn};
-    } else {
-      const int m = Nh - k;
-      const cplx<R> yk = row[k], ym = row[m];
-      const cplx<R> a1 = cadd<R>(yk, cconj<R>(ym));
-      const cplx<R> b1 = cmul<R>(csub<R>(yk, cconj<R>(ym)), twiddle<R>(tw, k * step, +1));
-      row[k] = cplx<R>{a1.x - b1.y, a1.y + b1.x};
-      if (m != k) {
-        const cplx<R> a2 = cadd<R>(ym, cconj<R>(yk));
-        const cplx<R> b2 = cmul<R>(csub<R>(ym, cconj<R>(yk)), twiddle<R>(tw, m * step, +1));
-        row[m] = cplx<R>{a2.x - b2.y, a2.y + b2.x};
+  const int npre = rows * half;
+  for (int e0 = threadIdx.x; e0 < npre; e0 += (MAXV / 2 + 1) * kFftThreads) {
+    cplx<R> twk[MAXV / 2 + 1], twm[MAXV / 2 + 1];
+#pragma unroll
+    for (int i = 0; i <= MAXV / 2; ++i) {
+      const int e = min(e0 + i * kFftThreads, npre - 1);  // clamped: loads without branches
+      const int k = e - (e / half) * half;
+      twk[i] = twiddle<R>(tw, k * step, +1);
+      twm[i] = twiddle<R>(tw, (Nh - k) * step, +1);
+    }
+#pragma unroll
+    for (int i = 0; i <= MAXV / 2; ++i) {
+      const int e = e0 + i * kFftThreads;
+      if (e < npre) {
+        const int r = e / half;
+        const int k = e - r * half;
+        cplx<R> *row = buf + r * Nh;
+        if (k == 0) {
+          const R y0 = row[0].x, yn = nyq[r].x;
+          row[0] = cplx<R>{y0 + yn, y0 - yn};
+        } else {
+          const int m = Nh - k;
+          const cplx<R> yk = row[k], ym = row[m];
+          const cplx<R> a1 = cadd<R>(yk, cconj<R>(ym));
+          const cplx<R> b1 = cmul<R>(csub<R>(yk, cconj<R>(ym)), twk[i]);
+          row[k] = cplx<R>{a1.x - b1.y, a1.y + b1.x};
+          if (m != k) {
+            const cplx<R> a2 = cadd<R>(ym, cconj<R>(yk));
+            const cplx<R> b2 = cmul<R>(csub<R>(ym, cconj<R>(yk)), twm[i]);
+            row[m] = cplx<R>{a2.x - b2.y, a2.y + b2.x};
+          }
+        }
       }
     }
   }
@@ -358,16 +429,27 @@ __global__ __launch_bounds__(kFftThreads) void c2r_t_kernel(
   const long long o = (static_cast<long long>(f) * n1 + x0) * n3;
   cplx<R> *dst = reinterpret_cast<cplx<R> *>(out + o);
   const cplx<R> *addp = add ? reinterpret_cast<const cplx<R> *>(add + o) : nullptr;
-  for (int e = threadIdx.x; e < rows * Nh; e += kFftThreads) {
-    cplx<R> z = buf[e];
-    z.x *= scale;
-    z.y *= scale;
-    if (addp) {
-      const cplx<R> a = addp[e];
-      z.x += a.x;
-      z.y += a.y;
+  const int nout = rows * Nh;  // <= kFftThreads * MAXV
+  if (addp) {
+#pragma unroll
+    for (int i = 0; i < MAXV; ++i) {
+      const int e = min(static_cast<int>(threadIdx.x) + i * kFftThreads, nout - 1);
+      v[i] = addp[e];
     }
-    dst[e] = z;
+  }
+#pragma unroll
+  for (int i = 0; i < MAXV; ++i) {
+    const int e = threadIdx.x + i * kFftThreads;
+    if (e < nout) {
+      cplx<R> z = buf[e];
+      z.x *= scale;
+      z.y *= scale;
+      if (addp) {
+        z.x += v[i].x;
+        z.y += v[i].y;
+      }
+      dst[e] = z;
+    }
   }
 }
 
