@@ -35,12 +35,30 @@ __device__ __forceinline__ cplx<R> csub(cplx<R> a, cplx<R> b) { return {a.x - b.
 template <typename R>
 __device__ __forceinline__ cplx<R> cconj(cplx<R> a) { return {a.x, -a.y}; }
 
-// exp(dir * 2 pi i m / 4096) from the table of exp(-2 pi i m / 4096).
+// A work-group's twiddles come from a quarter-wave table in LDS for the
+// transform's period L (a power of two, 4 <= L <= 4096): q[r] = exp(-2 pi i r / L),
+// r < L/4, copied from the global 4096-point table once per work-group, so that
+// no radix pass waits for memory.  load_quarter fills it (every thread calls it;
+// the caller synchronises before the first use).
 template <typename R>
-__device__ __forceinline__ cplx<R> twiddle(const cplx<R> *__restrict__ tw, int m, int dir) {
-  cplx<R> t = tw[m & (kTwiddleN - 1)];
-  if (dir > 0) t.y = -t.y;
-  return t;
+__device__ __forceinline__ void load_quarter(cplx<R> *q, int logL, const cplx<R> *__restrict__ tw) {
+  const int n = 1 << (logL - 2);
+  const int stride = kTwiddleN >> logL;
+  for (int r = threadIdx.x; r < n; r += kFftThreads) q[r] = tw[r * stride];
+}
+// exp(dir 2 pi i j / 4096) for j a multiple of 4096 / L, from the quarter table:
+// with m = j L / 4096 = r + h L/4 (r < L/4), exp(-2 pi i m / L) = q[r] (-i)^h.
+template <typename R>
+__device__ __forceinline__ cplx<R> twq(const cplx<R> *q, int j, int logL, int dir) {
+  const int m = (j & (kTwiddleN - 1)) >> (kTwiddleLog - logL);
+  const int h = m >> (logL - 2);
+  const cplx<R> t = q[m & ((1 << (logL - 2)) - 1)];
+  // (-i)^h t: h = 0 (x, y), 1 (y, -x), 2 (-x, -y), 3 (-y, x)
+  R x = (h & 1) ? t.y : t.x;
+  R y = (h & 1) ? t.x : t.y;
+  if (h >= 2) x = -x;
+  if (h == 1 || h == 2) y = -y;
+  return cplx<R>{x, dir > 0 ? -y : y};
 }
 
 // (1 + dir i) / sqrt(2) times a, i.e. a * exp(dir i pi / 4).
@@ -62,13 +80,12 @@ __device__ __forceinline__ cplx<R> rot4(cplx<R> a, int dir) {
 // stages its inputs in registers, synchronises, then writes the outputs.
 template <typename R, int NT, int MAXV>
 __device__ __attribute__((always_inline)) void lds_fft(cplx<R> *buf, int N, int logN, int nseq,
-                                                       int dir, const cplx<R> *__restrict__ tw) {
+                                                       int dir, const cplx<R> *q, int logL) {
   const int total = N * nseq;
   int logNs = 0;
-  // Each pass first loads, for every butterfly of the thread, its inputs from
-  // LDS and its twiddles from the (cached) table, then synchronises and writes
-  // the outputs.  The twiddle loads take a clamped butterfly index and no
-  // branch, so that all of them are in flight together.
+  // Each pass reads the inputs of every butterfly of the thread from LDS,
+  // synchronises, then writes the outputs; twiddles come from the quarter table
+  // q of period L (a multiple of N) in LDS.
   constexpr int B8 = (MAXV + 7) / 8;  // radix-8 butterflies per thread and pass
   // radix-8 passes
   for (; logNs + 3 <= logN; logNs += 3) {
@@ -76,16 +93,11 @@ __device__ __attribute__((always_inline)) void lds_fft(cplx<R> *buf, int N, int 
     const int nbf = total >> 3;
     const int Ns = 1 << logNs;
     const int step = kTwiddleN >> (logNs + 3);  // 4096 / (8 Ns)
-    cplx<R> v[B8][8], w[B8][7];
+    cplx<R> v[B8][8];
 #pragma unroll
     for (int t = 0; t < B8; ++t) {
       const int g = min(static_cast<int>(threadIdx.x) + t * NT, nbf - 1);
-      const int b = g >> (logN - 3);
-      const int j = g & (q8 - 1);
-      const int k = j & (Ns - 1);
-      const int base = b * N + j;
-#pragma unroll
-      for (int r = 1; r < 8; ++r) w[t][r - 1] = twiddle<R>(tw, r * k * step, dir);
+      const int base = (g >> (logN - 3)) * N + (g & (q8 - 1));
 #pragma unroll
       for (int r = 0; r < 8; ++r) v[t][r] = buf[base + r * q8];
     }
@@ -100,7 +112,7 @@ __device__ __attribute__((always_inline)) void lds_fft(cplx<R> *buf, int N, int 
         cplx<R> a[8];
         a[0] = v[t][0];
 #pragma unroll
-        for (int r = 1; r < 8; ++r) a[r] = cmul<R>(v[t][r], w[t][r - 1]);
+        for (int r = 1; r < 8; ++r) a[r] = cmul<R>(v[t][r], twq<R>(q, r * k * step, logL, dir));
         // 8-point DFT as radix 2 x radix 4: e_r = a_r + a_{r+4},
         // o_r = (a_r - a_{r+4}) exp(dir 2 pi i r / 8); X[2m] = DFT4(e), X[2m+1] = DFT4(o)
         cplx<R> e[4], o[4];
@@ -140,16 +152,11 @@ __device__ __attribute__((always_inline)) void lds_fft(cplx<R> *buf, int N, int 
     const int Ns = 1 << logNs;
     const int step = kTwiddleN >> (logNs + 2);  // 4096 / (4 Ns)
     constexpr int B4 = (MAXV + 3) / 4;
-    cplx<R> v[B4][4], w[B4][3];
+    cplx<R> v[B4][4];
 #pragma unroll
     for (int t = 0; t < B4; ++t) {
       const int g = min(static_cast<int>(threadIdx.x) + t * NT, nbf - 1);
-      const int b = g >> (logN - 2);
-      const int j = g & (q4 - 1);
-      const int k = j & (Ns - 1);
-      const int base = b * N + j;
-#pragma unroll
-      for (int r = 1; r < 4; ++r) w[t][r - 1] = twiddle<R>(tw, r * k * step, dir);
+      const int base = (g >> (logN - 2)) * N + (g & (q4 - 1));
 #pragma unroll
       for (int r = 0; r < 4; ++r) v[t][r] = buf[base + r * q4];
     }
@@ -162,9 +169,9 @@ __device__ __attribute__((always_inline)) void lds_fft(cplx<R> *buf, int N, int 
         const int j = g & (q4 - 1);
         const int k = j & (Ns - 1);
         cplx<R> a0 = v[t][0];
-        cplx<R> a1 = cmul<R>(v[t][1], w[t][0]);
-        cplx<R> a2 = cmul<R>(v[t][2], w[t][1]);
-        cplx<R> a3 = cmul<R>(v[t][3], w[t][2]);
+        cplx<R> a1 = cmul<R>(v[t][1], twq<R>(q, k * step, logL, dir));
+        cplx<R> a2 = cmul<R>(v[t][2], twq<R>(q, 2 * k * step, logL, dir));
+        cplx<R> a3 = cmul<R>(v[t][3], twq<R>(q, 3 * k * step, logL, dir));
         cplx<R> t0 = cadd<R>(a0, a2), t1 = csub<R>(a0, a2);
         cplx<R> t2 = cadd<R>(a1, a3);
         // dir * i * (a1 - a3): -i for the forward transform, +i for the inverse
@@ -186,13 +193,12 @@ __device__ __attribute__((always_inline)) void lds_fft(cplx<R> *buf, int N, int 
     const int Ns = 1 << logNs;
     const int step = kTwiddleN >> (logNs + 1);
     constexpr int B2 = (MAXV + 1) / 2;
-    cplx<R> v[B2][2], w[B2];
+    cplx<R> v[B2][2];
 #pragma unroll
     for (int t = 0; t < B2; ++t) {
       const int g = min(static_cast<int>(threadIdx.x) + t * NT, nbf - 1);
       const int b = g >> (logN - 1);
       const int j = g & (h2 - 1);
-      w[t] = twiddle<R>(tw, (j & (Ns - 1)) * step, dir);
       v[t][0] = buf[b * N + j];
       v[t][1] = buf[b * N + j + h2];
     }
@@ -204,7 +210,7 @@ __device__ __attribute__((always_inline)) void lds_fft(cplx<R> *buf, int N, int 
         const int b = g >> (logN - 1);
         const int j = g & (h2 - 1);
         const int k = j & (Ns - 1);
-        cplx<R> a1 = cmul<R>(v[t][1], w[t]);
+        cplx<R> a1 = cmul<R>(v[t][1], twq<R>(q, k * step, logL, dir));
         const int out = b * N + ((j >> logNs) << (logNs + 1)) + k;
         buf[out] = cadd<R>(v[t][0], a1);
         buf[out + Ns] = csub<R>(v[t][0], a1);
@@ -248,6 +254,9 @@ __global__ __launch_bounds__(kFftThreads) __attribute__((amdgpu_waves_per_eu(2))
   const int h3 = Nh + 1;
   const int tiles = n1 / rows;
   const int cnt = rows * Nh;  // complex input points of a tile (<= kFftThreads * MAXV)
+  const int logL = logNh + 1;  // twiddle period: n3
+  cplx<R> *q = buf + cnt;      // quarter table, after the tile
+  load_quarter<R>(q, logL, tw);
   cplx<Rin> pre[MAXV];
   auto load = [&](int id) {
     const int tile = xcd_tile(id, ntiles);
@@ -275,34 +284,17 @@ __global__ __launch_bounds__(kFftThreads) __attribute__((amdgpu_waves_per_eu(2))
     }
     __syncthreads();
     if (id + static_cast<int>(gridDim.x) < ntiles) load(id + gridDim.x);
-    lds_fft<R, kFftThreads, MAXV>(buf, Nh, logNh, rows, -1, tw);
+    lds_fft<R, kFftThreads, MAXV>(buf, Nh, logNh, rows, -1, q, logL);
     cplx<R> *dst = spec + static_cast<long long>(f) * h3 * n1 + x0;
-    // rows * h3 outputs in chunks of up to 9 per thread (two at 2048 points),
-    // unrolled so that the twiddle loads of a chunk are in flight together; the
-    // chunk is held to 9 for the registers of the next tile's prefetch
-    constexpr int kOutChunk = MAXV + 1 < 9 ? MAXV + 1 : 9;
-    const int nout = rows * h3;
-    for (int e0 = threadIdx.x; e0 < nout; e0 += kOutChunk * kFftThreads) {
-      cplx<R> twk[kOutChunk];
-#pragma unroll
-      for (int i = 0; i < kOutChunk; ++i) {
-        const int e = min(e0 + i * kFftThreads, nout - 1);  // clamped: loads without branches
-        twk[i] = twiddle<R>(tw, (e / rows) * step, -1);
-      }
-#pragma unroll
-      for (int i = 0; i < kOutChunk; ++i) {
-        const int e = e0 + i * kFftThreads;
-        if (e < nout) {
-          const int k = e / rows;
-          const int r = e - k * rows;
-          const cplx<R> zk = buf[r * Nh + (k == Nh ? 0 : k)];
-          const cplx<R> zc = cconj<R>(buf[r * Nh + (k == 0 ? 0 : Nh - k)]);
-          const cplx<R> ev = {(zk.x + zc.x) * R(0.5), (zk.y + zc.y) * R(0.5)};
-          const cplx<R> od = {(zk.x - zc.x) * R(0.5), (zk.y - zc.y) * R(0.5)};
-          const cplx<R> t = cmul<R>(od, twk[i]);
-          dst[static_cast<long long>(k) * n1 + r] = cplx<R>{ev.x + t.y, ev.y - t.x};  // ev - i t
-        }
-      }
+    for (int e = threadIdx.x; e < rows * h3; e += kFftThreads) {
+      const int k = e / rows;
+      const int r = e - k * rows;
+      const cplx<R> zk = buf[r * Nh + (k == Nh ? 0 : k)];
+      const cplx<R> zc = cconj<R>(buf[r * Nh + (k == 0 ? 0 : Nh - k)]);
+      const cplx<R> ev = {(zk.x + zc.x) * R(0.5), (zk.y + zc.y) * R(0.5)};
+      const cplx<R> od = {(zk.x - zc.x) * R(0.5), (zk.y - zc.y) * R(0.5)};
+      const cplx<R> t = cmul<R>(od, twq<R>(q, k * step, logL, -1));
+      dst[static_cast<long long>(k) * n1 + r] = cplx<R>{ev.x + t.y, ev.y - t.x};  // ev - i t
     }
     __syncthreads();  // the next tile overwrites buf
   }
@@ -316,6 +308,8 @@ __global__ __launch_bounds__(kFftThreads) void cfft_rows_kernel(
     const cplx<R> *__restrict__ tw) {
   extern __shared__ unsigned char smem_raw[];
   cplx<R> *buf = reinterpret_cast<cplx<R> *>(smem_raw);
+  cplx<R> *q = buf + per * n;  // quarter table of period n, after the rows
+  load_quarter<R>(q, logn, tw);
   const long long row0 = static_cast<long long>(blockIdx.x) * per;
   const int nb = static_cast<int>(min(static_cast<long long>(per), nrows - row0));
   const int cnt = nb * n;  // <= kFftThreads * MAXV
@@ -332,7 +326,7 @@ __global__ __launch_bounds__(kFftThreads) void cfft_rows_kernel(
   for (int i = 0; i < MAXV; ++i)
     buf[min(static_cast<int>(threadIdx.x) + i * kFftThreads, cnt - 1)] = v[i];
   __syncthreads();
-  lds_fft<R, kFftThreads, MAXV>(buf, n, logn, nb, dir, tw);
+  lds_fft<R, kFftThreads, MAXV>(buf, n, logn, nb, dir, q, logn);
 #pragma unroll
   for (int i = 0; i < MAXV; ++i) {
     const int e = threadIdx.x + i * kFftThreads;
@@ -355,6 +349,9 @@ __global__ __launch_bounds__(kFftThreads) void c2r_t_kernel(
   const int Nh = n3 >> 1;
   const int h3 = Nh + 1;
   cplx<R> *nyq = buf + rows * Nh;  // bin k = Nh of each row
+  const int logL = logNh + 1;       // twiddle period: n3
+  cplx<R> *q = nyq + rows;          // quarter table
+  load_quarter<R>(q, logL, tw);
   const int tiles = n1 / rows;
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   const int f = tile / tiles;
@@ -385,47 +382,31 @@ __global__ __launch_bounds__(kFftThreads) void c2r_t_kernel(
     }
   }
   __syncthreads();
-  // pair (k, Nh - k) of each row: chunks of MAXV / 2 + 1 per thread, the twiddles
-  // of a chunk loaded together
+  // pair (k, Nh - k) of each row
   const int step = kTwiddleN / n3;
   const int half = Nh / 2 + 1;
-  const int npre = rows * half;
-  for (int e0 = threadIdx.x; e0 < npre; e0 += (MAXV / 2 + 1) * kFftThreads) {
-    cplx<R> twk[MAXV / 2 + 1], twm[MAXV / 2 + 1];
-#pragma unroll
-    for (int i = 0; i <= MAXV / 2; ++i) {
-      const int e = min(e0 + i * kFftThreads, npre - 1);  // clamped: loads without branches
-      const int k = e - (e / half) * half;
-      twk[i] = twiddle<R>(tw, k * step, +1);
-      twm[i] = twiddle<R>(tw, (Nh - k) * step, +1);
-    }
-#pragma unroll
-    for (int i = 0; i <= MAXV / 2; ++i) {
-      const int e = e0 + i * kFftThreads;
-      if (e < npre) {
-        const int r = e / half;
-        const int k = e - r * half;
-        cplx<R> *row = buf + r * Nh;
-        if (k == 0) {
-          const R y0 = row[0].x, yn = nyq[r].x;
-          row[0] = cplx<R>{y0 + yn, y0 - yn};
-        } else {
-          const int m = Nh - k;
-          const cplx<R> yk = row[k], ym = row[m];
-          const cplx<R> a1 = cadd<R>(yk, cconj<R>(ym));
-          const cplx<R> b1 = cmul<R>(csub<R>(yk, cconj<R>(ym)), twk[i]);
-          row[k] = cplx<R>{a1.x - b1.y, a1.y + b1.x};
-          if (m != k) {
-            const cplx<R> a2 = cadd<R>(ym, cconj<R>(yk));
-            const cplx<R> b2 = cmul<R>(csub<R>(ym, cconj<R>(yk)), twm[i]);
-            row[m] = cplx<R>{a2.x - b2.y, a2.y + b2.x};
-          }
-        }
+  for (int e = threadIdx.x; e < rows * half; e += kFftThreads) {
+    const int r = e / half;
+    const int k = e - r * half;
+    cplx<R> *row = buf + r * Nh;
+    if (k == 0) {
+      const R y0 = row[0].x, yn = nyq[r].x;
+      row[0] = cplx<R>{y0 + yn, y0 - yn};
+    } else {
+      const int m = Nh - k;
+      const cplx<R> yk = row[k], ym = row[m];
+      const cplx<R> a1 = cadd<R>(yk, cconj<R>(ym));
+      const cplx<R> b1 = cmul<R>(csub<R>(yk, cconj<R>(ym)), twq<R>(q, k * step, logL, +1));
+      row[k] = cplx<R>{a1.x - b1.y, a1.y + b1.x};
+      if (m != k) {
+        const cplx<R> a2 = cadd<R>(ym, cconj<R>(yk));
+        const cplx<R> b2 = cmul<R>(csub<R>(ym, cconj<R>(yk)), twq<R>(q, m * step, logL, +1));
+        row[m] = cplx<R>{a2.x - b2.y, a2.y + b2.x};
       }
     }
   }
   __syncthreads();
-  lds_fft<R, kFftThreads, MAXV>(buf, Nh, logNh, rows, +1, tw);
+  lds_fft<R, kFftThreads, MAXV>(buf, Nh, logNh, rows, +1, q, logL);
   const long long o = (static_cast<long long>(f) * n1 + x0) * n3;
   cplx<R> *dst = reinterpret_cast<cplx<R> *>(out + o);
   const cplx<R> *addp = add ? reinterpret_cast<const cplx<R> *>(add + o) : nullptr;
@@ -520,7 +501,7 @@ hipError_t cfft_launch(const void *src, void *dst, long long nrows, int n, int d
   return with_maxv(per * n, [&](auto mv) {
     hipLaunchKernelGGL((cfft_rows_kernel<R, decltype(mv)::value>),
                        dim3(static_cast<unsigned>((nrows + per - 1) / per)), dim3(kFftThreads),
-                       static_cast<size_t>(per) * n * sizeof(cplx<R>), st,
+                       (static_cast<size_t>(per) * n + n / 4) * sizeof(cplx<R>), st,
                        static_cast<const cplx<R> *>(src), static_cast<cplx<R> *>(dst), nrows, n,
                        ilog2(n), per, dir, static_cast<const cplx<R> *>(tw));
     return hipGetLastError();
@@ -533,7 +514,7 @@ hipError_t forward_impl(const void *in, void *spec, int F, int n1, int n3, const
   const int Nh = n3 / 2, h3 = Nh + 1;
   const int rows = tile_rows(n1, Nh, sizeof(cplx<R>), 0);
   const int ntiles = F * (n1 / rows);
-  const size_t lds = static_cast<size_t>(rows) * Nh * sizeof(cplx<R>);
+  const size_t lds = (static_cast<size_t>(rows) * Nh + n3 / 4) * sizeof(cplx<R>);
   hipError_t e = with_maxv(rows * Nh, [&](auto mv) {
     auto kernel = r2c_t_kernel<Rin, R, decltype(mv)::value>;
     hipLaunchKernelGGL(kernel, dim3(static_cast<unsigned>(persistent_grid(kernel, ntiles, lds))),
@@ -556,7 +537,7 @@ hipError_t inverse_impl(const void *spec, void *scratch, void *out, const void *
   return with_maxv(rows * Nh, [&](auto mv) {
     hipLaunchKernelGGL((c2r_t_kernel<R, decltype(mv)::value>),
                        dim3(static_cast<unsigned>(F * (n1 / rows))), dim3(kFftThreads),
-                       static_cast<size_t>(rows) * (Nh + 1) * sizeof(cplx<R>), st,
+                       (static_cast<size_t>(rows) * (Nh + 1) + n3 / 4) * sizeof(cplx<R>), st,
                        static_cast<const cplx<R> *>(scratch), static_cast<R *>(out),
                        static_cast<const R *>(add), n1, n3, ilog2(Nh), rows,
                        static_cast<R>(scale), static_cast<const cplx<R> *>(tw));
