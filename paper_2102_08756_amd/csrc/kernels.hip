@@ -20,6 +20,7 @@
 //   table   class-major rows: entry cls_off[class] + j holds (w11, w12, w22, w33)
 //           of lag j, j < W of the class.
 #include <cmath>
+#include <type_traits>
 
 #include "internal.h"
 
@@ -289,6 +290,17 @@ __device__ __forceinline__ void sweep_item(const SweepArgs &a, long long item) {
 
 typedef float v4f __attribute__((ext_vector_type(4)));
 
+// A value equal on every lane, moved to a scalar register.
+__device__ __forceinline__ long long uniform64(long long v) {
+  const unsigned lo = __builtin_amdgcn_readfirstlane(static_cast<unsigned>(v));
+  const unsigned hi = __builtin_amdgcn_readfirstlane(static_cast<unsigned>(static_cast<unsigned long long>(v) >> 32));
+  return static_cast<long long>((static_cast<unsigned long long>(hi) << 32) | lo);
+}
+
+// Word 3 of a raw buffer resource on gfx9-family chips (data format 32 bits,
+// no swizzle): what untyped dword loads through __builtin_amdgcn_make_buffer_rsrc need.
+constexpr int kBufferWord3 = 0x00020000;
+
 // Kernel-row blocks a compensated quad sweep sums in plain float32 (the
 // matrix-core accumulators) before folding them into its compensated sums:
 // 8 blocks of 4 lags.
@@ -297,6 +309,15 @@ constexpr int kQuadFold = 8;
 // ahead of its products (measured on gfx950: 2 to 8 within 3%; 2 fits the
 // compensated form's register budget best).
 constexpr int kQuadAhead = 2;
+
+// f(integral_constant<int, 0>) ... f(integral_constant<int, N - 1>), in order.
+template <int N, typename F>
+__device__ __forceinline__ void static_for(F &&f) {
+  if constexpr (N > 0) {
+    static_for<N - 1>(f);
+    f(std::integral_constant<int, N - 1>());
+  }
+}
 
 // The sweep on the matrix cores, for float32 history of two planes that share
 // their kernel rows (one material group, one window for every mode).  Its
@@ -364,7 +385,7 @@ __device__ __forceinline__ void quad_sweep(const SweepArgs &a, long long wg, int
   const int p = s_ >> 3, mq = (s_ >> 1) & 3, reim = s_ & 1;
   const long long sq = b * kLanes + 4 * j;  // first sorted position of the quad
   if (sq >= M) return;                      // past the last mode (uniform); M is a multiple of 4
-  const int cap = a.blk_cap[b];
+  const int cap = __builtin_amdgcn_readfirstlane(a.blk_cap[b]);
   const int wl = __builtin_amdgcn_readfirstlane(a.win[sq]);  // the class's window (its first
                                                              // position is a mode)
   const int nent = wl > 0 ? static_cast<int>(max(0LL, min(static_cast<long long>(cap) - 1, t0) - 1)) : 0;
@@ -380,28 +401,53 @@ __device__ __forceinline__ void quad_sweep(const SweepArgs &a, long long wg, int
     for (int t = 0; t < 5; ++t) C[g][t] = v4f{0.f, 0.f, 0.f, 0.f};
   Acc<float, COMP> acc[G][5][4];
   if (beta1 > beta0) {
-    const float4 *__restrict__ rowp = static_cast<const float4 *>(a.table) + a.cls_off[a.cls[sq]];
-    // History addresses: the block's slot 0 (uniform) plus a 32-bit offset per
-    // lane, slot x at x * dstep floats (the host keeps cap * dstep below 2^31).
-    const float *__restrict__ run =
-        static_cast<const float *>(a.ring) + a.blk_off[b] * (2LL * 3 * kLanes * 2);
-    const int dstep = a.blk_stride[b] * (2 * 3 * kLanes * 2);
+    // The quad's operands come through buffer loads: a resource per work-group
+    // (the block's slot 0 of the ring, the class's first kernel row) and a
+    // 32-bit byte offset per lane; a load past the resource's range returns 0.
+    // (Buffer loads also keep the compiler from moving a prefetch down to its
+    // use, which it does with plain loads.)
+    // (every value a resource is built from is read as uniform, so that the
+    // resources live in scalar registers)
+    const long long cls0 = uniform64(a.cls_off[__builtin_amdgcn_readfirstlane(a.cls[sq])]);
+    const float4 *rowp = static_cast<const float4 *>(a.table) + cls0;
+    const __amdgpu_buffer_rsrc_t rows_rsrc = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<float4 *>(rowp), 0, (wl + 1) * 16, kBufferWord3);
+    // History: slot x of the block at x * dstep floats (the host keeps the
+    // block's capacity times dstep below 2^30 floats, so byte offsets fit 32 bits).
+    const float *run =
+        static_cast<const float *>(a.ring) + uniform64(a.blk_off[b]) * (2LL * 3 * kLanes * 2);
+    const int dstep = __builtin_amdgcn_readfirstlane(a.blk_stride[b]) * (2 * 3 * kLanes * 2);
+    const __amdgpu_buffer_rsrc_t ring_rsrc = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<float *>(run), 0, ((cap - 1) * dstep + 2 * 3 * kLanes * 2) * 4, kBufferWord3);
     const int col = ((p * 3) * kLanes + 4 * j + mq) * 2 + reim;
+    // (the builtins return the loaded bits as integers)
+    auto hist = [&](int x, int c) {
+      return __builtin_bit_cast(
+          float, __builtin_amdgcn_raw_buffer_load_b32(
+                     ring_rsrc, (x * dstep + col + c * kLanes * 2) * 4, 0, 0));
+    };
+    auto row = [&](int r) {
+      const v4f v = __builtin_bit_cast(
+          v4f, __builtin_amdgcn_raw_buffer_load_b128(rows_rsrc, min(r, wl) * 16, 0, 0));
+      return float4{v[0], v[1], v[2], v[3]};
+    };
     // The history loads run kQuadAhead blocks ahead of the products (they come
     // from memory); xl is the ring slot of this lane's lag in the next block to load.
+    // Every load is issued unconditionally, also for blocks past the range (their
+    // values are never used), so that the loop below has no branch around a load
+    // and each product waits only for the loads of its own block, not for the
+    // ones in flight behind them.  Those loads stay in range: the slot index is
+    // clamped at 0 (it only goes negative when cap < 4, and then the range has a
+    // single block) and the rows clamp to the class's zero row.
     int xl = static_cast<int>((((t0 - (2 + 4 * beta0) - k_) % cap) + cap) % cap);
     float bq[kQuadAhead][3];
 #pragma unroll
     for (int q = 0; q < kQuadAhead; ++q) {
-      if (beta0 + q < beta1) {
-        const float *hl = run + (xl * dstep + col);
 #pragma unroll
-        for (int c = 0; c < 3; ++c) bq[q][c] = hl[c * kLanes * 2];
-        // the next block's slot is 4 lags older; cap >= 4 whenever a chunk has
-        // a second block
-        xl -= 4;
-        if (xl < 0) xl += cap;
-      }
+      for (int c = 0; c < 3; ++c) bq[q][c] = hist(max(xl, 0), c);
+      // the next block's slot is 4 lags older
+      xl -= 4;
+      if (xl < 0) xl += cap;
     }
     // Kernel-row operands: the top 16-step group's rows are loaded (as far ahead
     // as the history, since the rows' leading edge comes from memory); the
@@ -411,58 +457,63 @@ __device__ __forceinline__ void quad_sweep(const SweepArgs &a, long long wg, int
     const int r0 = k_ + s_;
     float4 fq[kQuadAhead];
 #pragma unroll
-    for (int q = 0; q < kQuadAhead; ++q)
-      if (beta0 + q < beta1) fq[q] = rowp[min(2 + 4 * (beta0 + q) + r0 + 16 * (G - 1), wl)];
-    float4 a0 = G == 2 ? rowp[min(2 + 4 * beta0 + r0, wl)] : float4{0.f, 0.f, 0.f, 0.f};
+    for (int q = 0; q < kQuadAhead; ++q) fq[q] = row(2 + 4 * (beta0 + q) + r0 + 16 * (G - 1));
+    float4 a0 = G == 2 ? row(2 + 4 * beta0 + r0) : float4{0.f, 0.f, 0.f, 0.f};
     int fold = 0;
-    for (int base = beta0; base < beta1; base += kQuadAhead) {
+    // One 4-lag block from register set Q (a compile-time index).
+    auto block = [&](auto qc, int beta) {
+      constexpr int q = decltype(qc)::value;
+      const float4 top = fq[q];
+      float4 rw[G];
+      if constexpr (G == 2) {
+        rw[0] = a0;
+        rw[1] = top;
+      } else {
+        rw[0] = top;
+      }
 #pragma unroll
-      for (int q = 0; q < kQuadAhead; ++q) {
-        const int beta = base + q;
-        if (beta >= beta1) break;           // uniform over the wavefront
-        const float4 top = fq[q];
-        float4 rw[G];
-        if constexpr (G == 2) {
-          rw[0] = a0;
-          rw[1] = top;
-        } else {
-          rw[0] = top;
-        }
+      for (int g = 0; g < G; ++g) {
+        C[g][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(rw[g].x, bq[q][0], C[g][0], 0, 0, 0);
+        C[g][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(rw[g].y, bq[q][1], C[g][1], 0, 0, 0);
+        C[g][2] = __builtin_amdgcn_mfma_f32_16x16x4f32(rw[g].z, bq[q][1], C[g][2], 0, 0, 0);
+        C[g][3] = __builtin_amdgcn_mfma_f32_16x16x4f32(rw[g].y, bq[q][0], C[g][3], 0, 0, 0);
+        C[g][4] = __builtin_amdgcn_mfma_f32_16x16x4f32(rw[g].w, bq[q][2], C[g][4], 0, 0, 0);
+      }
+      if constexpr (G == 2) a0 = shift_rows4(a0, top);
+      // this register set now takes block beta + kQuadAhead (loaded also past the
+      // range, see above)
 #pragma unroll
-        for (int g = 0; g < G; ++g) {
-          C[g][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(rw[g].x, bq[q][0], C[g][0], 0, 0, 0);
-          C[g][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(rw[g].y, bq[q][1], C[g][1], 0, 0, 0);
-          C[g][2] = __builtin_amdgcn_mfma_f32_16x16x4f32(rw[g].z, bq[q][1], C[g][2], 0, 0, 0);
-          C[g][3] = __builtin_amdgcn_mfma_f32_16x16x4f32(rw[g].y, bq[q][0], C[g][3], 0, 0, 0);
-          C[g][4] = __builtin_amdgcn_mfma_f32_16x16x4f32(rw[g].w, bq[q][2], C[g][4], 0, 0, 0);
-        }
-        if constexpr (G == 2) a0 = shift_rows4(a0, top);
-        // this register set now takes block beta + kQuadAhead
-        if (beta + kQuadAhead < beta1) {
-          const float *hl = run + (xl * dstep + col);
+      for (int c = 0; c < 3; ++c) bq[q][c] = hist(max(xl, 0), c);
+      fq[q] = row(2 + 4 * (beta + kQuadAhead) + r0 + 16 * (G - 1));
+      // keep the scheduler from sinking these loads towards their use
+      __builtin_amdgcn_sched_barrier(0);
+      xl -= 4;
+      if (xl < 0) xl += cap;
+      if constexpr (COMP) {
+        // fold the plain partial sums of the last kQuadFold blocks (uniform branch)
+        if (++fold == kQuadFold) {
+          fold = 0;
 #pragma unroll
-          for (int c = 0; c < 3; ++c) bq[q][c] = hl[c * kLanes * 2];
-          fq[q] = rowp[min(2 + 4 * (beta + kQuadAhead) + r0 + 16 * (G - 1), wl)];
-          xl -= 4;
-          if (xl < 0) xl += cap;
-        }
-        if constexpr (COMP) {
-          // fold the plain partial sums of the last kQuadFold blocks (uniform branch)
-          if (++fold == kQuadFold) {
-            fold = 0;
+          for (int g = 0; g < G; ++g)
 #pragma unroll
-            for (int g = 0; g < G; ++g)
+            for (int t = 0; t < 5; ++t)
 #pragma unroll
-              for (int t = 0; t < 5; ++t)
-#pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                  acc[g][t][v].fold(C[g][t][v]);
-                  C[g][t][v] = 0.f;
-                }
-          }
+              for (int v = 0; v < 4; ++v) {
+                acc[g][t][v].fold(C[g][t][v]);
+                C[g][t][v] = 0.f;
+              }
         }
       }
-    }
+    };
+    // Whole rounds of kQuadAhead blocks with no branch between the loads of one
+    // block and the products of the next (so the compiler's waits are exact:
+    // the products of a block wait for its own loads only), then the rest.
+    int base = beta0;
+    for (; base + kQuadAhead <= beta1; base += kQuadAhead)
+      static_for<kQuadAhead>([&](auto qc) { block(qc, base + decltype(qc)::value); });
+    static_for<kQuadAhead - 1>([&](auto qc) {
+      if (base + decltype(qc)::value < beta1) block(qc, base + decltype(qc)::value);
+    });
   }
 #pragma unroll
   for (int g = 0; g < G; ++g)

@@ -566,14 +566,14 @@ int sbim_init(const sbim_config *cfg, sbim_handle **out) {
     need += g.M * (4 * 3 + 32) + g.nblocks * 16 + g.nclasses * 20;
   }
   if (h->mfma) {
-    // The quad sweep addresses a block's history with 32-bit offsets from its
-    // slot 0: every block's capacity times its slot stride must stay below 2^31
-    // floats, else the vector-unit sweep plans the group instead.
+    // The quad sweep addresses a block's history with 32-bit byte offsets from
+    // its slot 0: every block's capacity times its slot stride must stay below
+    // 2^30 floats, else the vector-unit sweep plans the group instead.
     const Group &g0 = h->g[0];
     bool fits = true;
     for (long long b = 0; b < g0.nblocks; ++b)
       if (static_cast<long long>(plan[0].blk_cap[b]) * plan[0].blk_stride[b] * 2 * 3 * sbim::kLanes * 2 >=
-          (1LL << 31))
+          (1LL << 30))
         fits = false;
     if (!fits) {
       h->mfma = false;
