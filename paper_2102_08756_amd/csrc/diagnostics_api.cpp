@@ -83,6 +83,7 @@ int sbim_get_info(const sbim_handle *h, sbim_info *out) {
   out->sweep_depth = h->depth;
   out->sweep_matrix_cores = h->mfma ? 1 : 0;
   out->sweep_lag_chunks = h->mfma ? h->lag_chunks : 0;
+  out->sweep_quads = h->mfma ? h->sweep_quads : 0;
   return SBIM_OK;
 }
 

@@ -90,6 +90,7 @@ struct sbim_handle {
   int depth = 1;                  // sweep depth: steps served by one pass over a block's history
   bool mfma = false;              // history sweep on the matrix cores (quads of one class)
   int lag_chunks = 1;             // matrix-core sweep: wavefronts per quad, each a lag range
+  int sweep_quads = 1;            // matrix-core sweep: quads per work-group (1, 2 or 4)
   void *twiddle = nullptr;        // [4096] complex real_t, exp(-2 pi i m / 4096)
   void *twiddle64 = nullptr;      // the same in float64 (== twiddle for SBIM_FP64)
   void *spec = nullptr;           // [P][3][h3][n1] complex float64: spectrum of the pushed field

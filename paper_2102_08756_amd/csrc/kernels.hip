@@ -367,27 +367,32 @@ __device__ __forceinline__ float4 shift_rows4(float4 cur, float4 above) {
 }
 
 template <bool COMP, int G>
-__device__ __forceinline__ void quad_sweep(const SweepArgs &a, long long wg, int LG,
+__device__ __forceinline__ void quad_sweep(const SweepArgs &a, long long wg, int LG, int QW,
                                            float *__restrict__ lds) {
   constexpr int D = 16 * G;
-  const long long kb = (wg >> 7) * 8 + (wg & 7);
-  if (kb >= a.nphase) return;                      // uniform over the work-group
-  const int j = static_cast<int>((wg >> 3) & 15);  // quad of the block
+  // Wavefront w of the work-group: quad qi = w / LG of the work-group's QW
+  // quads, lag range chunk = w mod LG (uniform: kept in scalar registers, so
+  // the loop control below is scalar).
+  const int w = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
+  const int chunk = w % LG, qi = w / LG;
+  const int per_block = 16 / QW;  // work-groups per block
+  const long long kb = (wg / (8 * per_block)) * 8 + (wg & 7);
+  if (kb >= a.nphase) return;     // uniform over the work-group
+  const int j = static_cast<int>((wg >> 3) % per_block) * QW + qi;  // quad of the block
   const long long M = a.M, step = a.step;
   const long long t0 = step + 1;
   const long long b = t0 % D + D * kb;
-  // the lag range of this wavefront (uniform: kept in scalar registers, so the
-  // loop control below is scalar)
-  const int chunk = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
   const int lane = threadIdx.x & 63;
   const int s_ = lane & 15;                 // A row (step in group) / B column
   const int k_ = lane >> 4;                 // lag within a 4-lag block
   const int p = s_ >> 3, mq = (s_ >> 1) & 3, reim = s_ & 1;
   const long long sq = b * kLanes + 4 * j;  // first sorted position of the quad
-  if (sq >= M) return;                      // past the last mode (uniform); M is a multiple of 4
+  // Past the last mode (M is a multiple of 4) a quad has no work; it still takes
+  // part in the work-group's barrier below (uniform over the wavefront).
+  const bool active = sq < M;
   const int cap = __builtin_amdgcn_readfirstlane(a.blk_cap[b]);
-  const int wl = __builtin_amdgcn_readfirstlane(a.win[sq]);  // the class's window (its first
-                                                             // position is a mode)
+  // the class's window (its first position is a mode)
+  const int wl = active ? __builtin_amdgcn_readfirstlane(a.win[sq]) : 0;
   const int nent = wl > 0 ? static_cast<int>(max(0LL, min(static_cast<long long>(cap) - 1, t0) - 1)) : 0;
   const int nblk = (nent + 3) / 4;
   const int per = (nblk + LG - 1) / LG;
@@ -525,6 +530,7 @@ __device__ __forceinline__ void quad_sweep(const SweepArgs &a, long long wg, int
   if (LG > 1) {
     constexpr int NV = G * 5 * 4;
     constexpr int PER = COMP ? 2 : 1;
+    lds += static_cast<long long>(qi) * (LG - 1) * NV * PER * kLanes;  // this quad's partial sums
     if (chunk > 0) {
       float *dst = lds + static_cast<long long>(chunk - 1) * NV * PER * kLanes + lane;
 #pragma unroll
@@ -559,7 +565,7 @@ __device__ __forceinline__ void quad_sweep(const SweepArgs &a, long long wg, int
       }
     }
   }
-  if (chunk != 0) return;
+  if (chunk != 0 || !active) return;
   float *__restrict__ pending = static_cast<float *>(a.pending);
   const long long col_off = (static_cast<long long>(p) * kSums + reim) * M + sq + mq;
 #pragma unroll
@@ -683,13 +689,32 @@ __device__ __forceinline__ void mode_step(const ModeArgs &a, int p, long long s)
       for (int k = 0; k < kSums; ++k) part[k] = COMP ? R(0) : acc[k].s;
       fma_lag<R>(part, rowp[0], u0);
       const cplx<R> *rp = ring + base * rec_len + static_cast<long long>(p) * 3 * kLanes + lane;
-      int x = x0;
-#pragma unroll 2
-      for (int j = 1; j < fresh; ++j) {
-        x = (x == 0 ? cap : x) - 1;
-        const cplx<R> *qp = rp + static_cast<long long>(x) * stride * rec_len;
-        const cplx<R> u[3] = {qp[0], qp[kLanes], qp[2 * kLanes]};
-        fma_lag<R>(part, rowp[j], u);
+      // The older lags in batches of FB, every load of a batch in flight before
+      // its products: the lag index is clamped (fresh <= W <= cap, so the ring
+      // slot stays in the block's ring), the loads need no branch, and lags
+      // past `fresh` take zero weights, which leave the sums unchanged.
+      constexpr int FB = 4;  // measured on gfx950: as fast as 8 with fewer registers
+      for (int j0 = 1; j0 < fresh; j0 += FB) {
+        cplx<R> u[FB][3];
+        W w[FB];
+#pragma unroll
+        for (int i = 0; i < FB; ++i) {
+          const int j = min(j0 + i, fresh - 1);
+          int x = x0 - j;
+          if (x < 0) x += cap;
+          const cplx<R> *qp = rp + static_cast<long long>(x) * stride * rec_len;
+          u[i][0] = qp[0];
+          u[i][1] = qp[kLanes];
+          u[i][2] = qp[2 * kLanes];
+          w[i] = rowp[j];
+        }
+#pragma unroll
+        for (int i = 0; i < FB; ++i) {
+          const bool on = j0 + i < fresh;
+          const W wi = {on ? w[i].x : R(0), on ? w[i].y : R(0), on ? w[i].z : R(0),
+                        on ? w[i].w : R(0)};
+          fma_lag<R>(part, wi, u[i]);
+        }
       }
 #pragma unroll
       for (int k = 0; k < kSums; ++k) {
@@ -806,14 +831,14 @@ __global__ __launch_bounds__(kLanes) __attribute__((amdgpu_waves_per_eu(2))) voi
 // sums of wavefronts 1 .. LG-1 of a quad.
 template <bool COMP, int G, int WAVES>
 __global__ __launch_bounds__(4 * kLanes) __attribute__((amdgpu_waves_per_eu(WAVES))) void
-step_kernel_mfma(SweepArgs sa, ModeArgs ma, long long sweep_wgs, long long nblocks, int LG) {
+step_kernel_mfma(SweepArgs sa, ModeArgs ma, long long sweep_wgs, long long nblocks, int LG, int QW) {
   extern __shared__ float quad_lds[];
   const long long wg = blockIdx.x;
   if (wg < sweep_wgs) {
-    quad_sweep<COMP, G>(sa, wg, LG, quad_lds);
+    quad_sweep<COMP, G>(sa, wg, LG, QW, quad_lds);
     return;
   }
-  const long long k = (wg - sweep_wgs) * LG + (threadIdx.x >> 6);
+  const long long k = (wg - sweep_wgs) * (LG * QW) + (threadIdx.x >> 6);
   if (k >= nblocks * ma.np) return;
   const int p = static_cast<int>(k / nblocks);
   const long long s = (k - p * nblocks) * kLanes + (threadIdx.x & 63);
@@ -1000,22 +1025,22 @@ hipError_t step_launch_q(const sbim_handle *h, const Group &g, const SweepArgs &
   SweepArgs sa = sa0;
   const int phase = static_cast<int>((sa.step + 1) % D);
   sa.nphase = g.nblocks > phase ? (g.nblocks - phase + D - 1) / D : 0;
-  const int LG = h->lag_chunks;
-  const long long sweep_wgs = (sa.nphase + 7) / 8 * 8 * 16;
-  const long long mode_wgs = (g.nblocks * g.np + LG - 1) / LG;
-  const size_t lds =
-      static_cast<size_t>(LG - 1) * G * 5 * 4 * (COMP ? 2 : 1) * kLanes * sizeof(float);
+  const int LG = h->lag_chunks, QW = h->sweep_quads;
+  const long long sweep_wgs = (sa.nphase + 7) / 8 * 8 * (16 / QW);
+  const long long mode_wgs = (g.nblocks * g.np + LG * QW - 1) / (LG * QW);
+  const size_t lds = static_cast<size_t>(QW) * (LG - 1) * G * 5 * 4 * (COMP ? 2 : 1) * kLanes *
+                     sizeof(float);
   if (ev0) {
     const hipError_t e = hipEventRecord(ev0, h->stream);
     if (e != hipSuccess) return e;
   }
-  // Register budget: three wavefronts per SIMD (168 registers).  The compensated
-  // two-group form then keeps a few registers in scratch; measured on gfx950 it
-  // still runs 4-8% faster than at two wavefronts per SIMD, whose 1024 resident
-  // two-wavefront work-groups leave the 1040 quads of a 512^2 phase a second round.
+  // Register budget: three wavefronts per SIMD (168 registers; the compensated
+  // two-group form takes 165).  At two wavefronts per SIMD the 1024 resident
+  // two-wavefront work-groups leave the 1040 quads of a 512^2 phase a second
+  // round (measured on gfx950: 4-8% slower).
   constexpr int WAVES = 3;
   hipLaunchKernelGGL((step_kernel_mfma<COMP, G, WAVES>), dim3(static_cast<unsigned>(sweep_wgs + mode_wgs)),
-                     dim3(LG * kLanes), lds, h->stream, sa, ma, sweep_wgs, g.nblocks, LG);
+                     dim3(LG * QW * kLanes), lds, h->stream, sa, ma, sweep_wgs, g.nblocks, LG, QW);
   hipError_t e = hipGetLastError();
   if (e == hipSuccess && ev1) e = hipEventRecord(ev1, h->stream);
   return e;

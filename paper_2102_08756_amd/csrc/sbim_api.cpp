@@ -596,17 +596,27 @@ int sbim_init(const sbim_config *cfg, sbim_handle **out) {
   if (h->mfma) {
     // Wavefronts per quad (lag ranges, each at least 16 blocks of 4 lags),
     // measured on gfx950 (two planes 512^2 at W = 1000, 1024^2 at W = 2000):
-    // two for the compensated form; four for plain float32 when a phase has
-    // under 2048 quads, else two.
+    // two for the compensated form (its registers allow three wavefronts per
+    // SIMD), four for plain float32.
     const Group &g = h->g[0];
-    const long long quads = (g.nblocks + h->depth - 1) / h->depth * 16;
     const int nblk = (std::max(0, g.wmax - 2) + 3) / 4;
-    const int want = h->comp ? 2 : (quads < 2048 ? 4 : 2);
+    const int want = h->comp ? 2 : 4;
     h->lag_chunks = 1;
     while (h->lag_chunks < want && nblk >= 16 * 2 * h->lag_chunks) h->lag_chunks *= 2;
     if (const char *env = std::getenv("SBIM_SWEEP_CHUNKS")) {  // tuning override
       const int v = std::atoi(env);
       if (v == 1 || v == 2 || v == 4) h->lag_chunks = v;
+    }
+    // Quads per work-group: neighbouring quads of a block share the cache lines
+    // of their history (a line holds 4 quads' pieces), and in one work-group they
+    // stream them together.  Measured on gfx950: two for the compensated form when
+    // a phase has 2048 quads or more (1024^2 at W = 2000: 5% faster), else one
+    // (two planes 512^2 at W = 1000, and plain float32 with four lag ranges).
+    const long long quads = (g.nblocks + h->depth - 1) / h->depth * 16;
+    h->sweep_quads = (h->comp && quads >= 2048 && h->lag_chunks <= 2) ? 2 : 1;
+    if (const char *env = std::getenv("SBIM_SWEEP_QUADS")) {  // tuning override
+      const int v = std::atoi(env);
+      if ((v == 1 || v == 2 || v == 4) && v * h->lag_chunks <= 4) h->sweep_quads = v;
     }
   }
   // input spectra are float64 in every form; the traction spectrum is real_t

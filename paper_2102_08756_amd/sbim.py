@@ -62,7 +62,7 @@ class _Info(ctypes.Structure):
                 ("state_bytes", ctypes.c_longlong), ("step", ctypes.c_longlong),
                 ("backward_step", ctypes.c_longlong), ("material_groups", ctypes.c_int),
                 ("sweep_depth", ctypes.c_int), ("sweep_matrix_cores", ctypes.c_int),
-                ("sweep_lag_chunks", ctypes.c_int)]
+                ("sweep_lag_chunks", ctypes.c_int), ("sweep_quads", ctypes.c_int)]
 
 
 class _FaultParams(ctypes.Structure):

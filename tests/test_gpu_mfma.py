@@ -89,10 +89,33 @@ def test_matrix_core_sweep_matches_oracle(refs, case, precision, depth, chunks, 
     assert err < 1e-5
 
 
+@pytest.mark.parametrize("quads,chunks", [(2, 1), (2, 2), (4, 1)])
+@pytest.mark.parametrize("precision", ["fp32", "fp32_comp"])
+def test_matrix_core_sweep_quads_per_work_group(refs, precision, quads, chunks, monkeypatch):
+    """Several groups of four modes per work-group (each its own lag ranges and LDS
+    partial sums), including blocks whose last groups are past the last mode."""
+    monkeypatch.setenv("SBIM_SWEEP_KIND", "mfma")
+    monkeypatch.setenv("SBIM_SWEEP_DEPTH", "32")
+    monkeypatch.setenv("SBIM_SWEEP_CHUNKS", str(chunks))
+    monkeypatch.setenv("SBIM_SWEEP_QUADS", str(quads))
+    for case in sorted(CASES):
+        kind = "increment" if quads == 2 else "absolute"
+        cfg = dict(CASES[case][0], input_kind=kind)
+        u, ref = refs[case, kind]
+        got, info = run_gpu(cfg, u, precision)
+        assert info["sweep_matrix_cores"] == 1
+        assert info["sweep_lag_chunks"] == chunks and info["sweep_quads"] == quads
+        err = rel_l2(got, ref)
+        print(f"[mfma] {case} {kind} {precision} quads {quads} chunks {chunks}: rel-L2 {err:.3e}",
+              flush=True)
+        assert err < 1e-5
+
+
 def test_matrix_core_sweep_is_the_default_for_long_windows(monkeypatch):
     monkeypatch.delenv("SBIM_SWEEP_KIND", raising=False)
     monkeypatch.delenv("SBIM_SWEEP_DEPTH", raising=False)
     monkeypatch.delenv("SBIM_SWEEP_CHUNKS", raising=False)
+    monkeypatch.delenv("SBIM_SWEEP_QUADS", raising=False)
     long_w = dict(n1=64, n3=64, window_cap=100, planes=TWO)
     for precision, want in (("fp32", 1), ("fp32_comp", 1), ("fp64", 0)):
         sb = SBIM(Config.from_dict(long_w, precision=precision), device=DEV)
