@@ -109,10 +109,22 @@ __device__ __attribute__((always_inline)) void lds_fft(cplx<R> *buf, int N, int 
         const int b = g >> (logN - 3);
         const int j = g & (q8 - 1);
         const int k = j & (Ns - 1);
+        // twiddles w^r, w = exp(dir 2 pi i k / (8 Ns)): w, w^2 and w^4 from the
+        // table, the others as products of two or three of them (a few units in
+        // the last place, against seven table reconstructions)
+        const cplx<R> w1 = twq<R>(q, k * step, logL, dir);
+        const cplx<R> w2 = twq<R>(q, 2 * k * step, logL, dir);
+        const cplx<R> w4 = twq<R>(q, 4 * k * step, logL, dir);
+        const cplx<R> w3 = cmul<R>(w1, w2);
         cplx<R> a[8];
         a[0] = v[t][0];
-#pragma unroll
-        for (int r = 1; r < 8; ++r) a[r] = cmul<R>(v[t][r], twq<R>(q, r * k * step, logL, dir));
+        a[1] = cmul<R>(v[t][1], w1);
+        a[2] = cmul<R>(v[t][2], w2);
+        a[3] = cmul<R>(v[t][3], w3);
+        a[4] = cmul<R>(v[t][4], w4);
+        a[5] = cmul<R>(v[t][5], cmul<R>(w1, w4));
+        a[6] = cmul<R>(v[t][6], cmul<R>(w2, w4));
+        a[7] = cmul<R>(v[t][7], cmul<R>(w3, w4));
         // 8-point DFT as radix 2 x radix 4: e_r = a_r + a_{r+4},
         // o_r = (a_r - a_{r+4}) exp(dir 2 pi i r / 8); X[2m] = DFT4(e), X[2m+1] = DFT4(o)
         cplx<R> e[4], o[4];
@@ -169,9 +181,11 @@ __device__ __attribute__((always_inline)) void lds_fft(cplx<R> *buf, int N, int 
         const int j = g & (q4 - 1);
         const int k = j & (Ns - 1);
         cplx<R> a0 = v[t][0];
-        cplx<R> a1 = cmul<R>(v[t][1], twq<R>(q, k * step, logL, dir));
-        cplx<R> a2 = cmul<R>(v[t][2], twq<R>(q, 2 * k * step, logL, dir));
-        cplx<R> a3 = cmul<R>(v[t][3], twq<R>(q, 3 * k * step, logL, dir));
+        const cplx<R> w1 = twq<R>(q, k * step, logL, dir);
+        const cplx<R> w2 = twq<R>(q, 2 * k * step, logL, dir);
+        cplx<R> a1 = cmul<R>(v[t][1], w1);
+        cplx<R> a2 = cmul<R>(v[t][2], w2);
+        cplx<R> a3 = cmul<R>(v[t][3], cmul<R>(w1, w2));
         cplx<R> t0 = cadd<R>(a0, a2), t1 = csub<R>(a0, a2);
         cplx<R> t2 = cadd<R>(a1, a3);
         // dir * i * (a1 - a3): -i for the forward transform, +i for the inverse
