@@ -454,15 +454,18 @@ int ilog2(int n) {
   return l;
 }
 
-// Work-group shapes.  The transposed kernels (r2c_t, c2r_t) take at least 4
-// rows where LDS allows (their transposed accesses are `rows` consecutive
-// points long, and shorter runs multiply the HBM traffic, measured), else
-// about 1024 points; the row kernels take about 1024 points.  MAXV, the points
-// a thread stages in registers per pass, is the smallest power of two that
-// covers the work-group's points.
+// Work-group shapes.  The transposed kernels (r2c_t, c2r_t) take 4 rows up to
+// 1024-point rows (their transposed accesses are `rows` consecutive points
+// long; consecutive tiles of one XCD complete each other's cache lines), 2 rows
+// from 2048 points, where a work-group's LDS and registers would otherwise
+// hold the GPU to two work-groups per CU (measured on gfx950: 2048 x 2048
+// forward 114 -> 100 us, inverse 68 -> 62 us; at 1024 points 2 rows are
+// slower); the row kernels take about 1024 points.  MAXV, the points a thread
+// stages in registers per pass, is the smallest power of two that covers the
+// work-group's points.
 constexpr size_t kMaxLds = 64 * 1024;
 int tile_rows(int n1, int Nh, size_t point_bytes, int extra_per_row) {
-  int rows = max(4, 1024 / Nh);
+  int rows = Nh >= 1024 ? 2 : max(4, 1024 / Nh);
   while (rows > 1 && (rows > n1 || rows * Nh > kFftThreads * kFftPerThread ||
                       static_cast<size_t>(rows) * (Nh + extra_per_row) * point_bytes > kMaxLds))
     rows >>= 1;
