@@ -715,6 +715,7 @@ def main():
                       "sweep_depth": res[f]["info"]["sweep_depth"],
                       "sweep_matrix_cores": res[f]["info"]["sweep_matrix_cores"],
                       "sweep_lag_chunks": res[f]["info"]["sweep_lag_chunks"],
+                      "sweep_quads": res[f]["info"]["sweep_quads"],
                       "init_s": res[f]["init_s"],
                       "ring_bytes": res[f]["info"]["ring_bytes"],
                       "table_bytes": res[f]["info"]["table_bytes"],
