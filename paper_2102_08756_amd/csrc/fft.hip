@@ -92,14 +92,14 @@ __device__ __attribute__((always_inline)) void lds_fft(cplx<R> *buf, int N, int 
     const int q8 = N >> 3;
     const int nbf = total >> 3;
     const int Ns = 1 << logNs;
-    const int step = kTwiddleN >> (logNs + 3);  // 4096 / (8 Ns)
+    const int lstep = kTwiddleLog - logNs - 3;  // step = 4096 / (8 Ns) = 2^lstep
     cplx<R> v[B8][8];
 #pragma unroll
     for (int t = 0; t < B8; ++t) {
       const int g = min(static_cast<int>(threadIdx.x) + t * NT, nbf - 1);
-      const int base = (g >> (logN - 3)) * N + (g & (q8 - 1));
+      const int base = ((g >> (logN - 3)) << logN) + (g & (q8 - 1));
 #pragma unroll
-      for (int r = 0; r < 8; ++r) v[t][r] = buf[base + r * q8];
+      for (int r = 0; r < 8; ++r) v[t][r] = buf[base + (r << (logN - 3))];
     }
     __syncthreads();
 #pragma unroll
@@ -112,9 +112,10 @@ __device__ __attribute__((always_inline)) void lds_fft(cplx<R> *buf, int N, int 
         // twiddles w^r, w = exp(dir 2 pi i k / (8 Ns)): w, w^2 and w^4 from the
         // table, the others as products of two or three of them (a few units in
         // the last place, against seven table reconstructions)
-        const cplx<R> w1 = twq<R>(q, k * step, logL, dir);
-        const cplx<R> w2 = twq<R>(q, 2 * k * step, logL, dir);
-        const cplx<R> w4 = twq<R>(q, 4 * k * step, logL, dir);
+        const int ks = k << lstep;  // k * step
+        const cplx<R> w1 = twq<R>(q, ks, logL, dir);
+        const cplx<R> w2 = twq<R>(q, ks << 1, logL, dir);
+        const cplx<R> w4 = twq<R>(q, ks << 2, logL, dir);
         const cplx<R> w3 = cmul<R>(w1, w2);
         cplx<R> a[8];
         a[0] = v[t][0];
@@ -136,22 +137,22 @@ __device__ __attribute__((always_inline)) void lds_fft(cplx<R> *buf, int N, int 
         o[1] = rot8<R>(o[1], dir);
         o[2] = rot4<R>(o[2], dir);
         o[3] = rot4<R>(rot8<R>(o[3], dir), dir);
-        const int out = b * N + ((j >> logNs) << (logNs + 3)) + k;
+        const int out = (b << logN) + ((j >> logNs) << (logNs + 3)) + k;
         {
           const cplx<R> t0 = cadd<R>(e[0], e[2]), t1 = csub<R>(e[0], e[2]);
           const cplx<R> t2 = cadd<R>(e[1], e[3]), t3 = rot4<R>(csub<R>(e[1], e[3]), dir);
           buf[out] = cadd<R>(t0, t2);
-          buf[out + 2 * Ns] = cadd<R>(t1, t3);
-          buf[out + 4 * Ns] = csub<R>(t0, t2);
-          buf[out + 6 * Ns] = csub<R>(t1, t3);
+          buf[out + (2 << logNs)] = cadd<R>(t1, t3);
+          buf[out + (4 << logNs)] = csub<R>(t0, t2);
+          buf[out + (6 << logNs)] = csub<R>(t1, t3);
         }
         {
           const cplx<R> t0 = cadd<R>(o[0], o[2]), t1 = csub<R>(o[0], o[2]);
           const cplx<R> t2 = cadd<R>(o[1], o[3]), t3 = rot4<R>(csub<R>(o[1], o[3]), dir);
-          buf[out + Ns] = cadd<R>(t0, t2);
-          buf[out + 3 * Ns] = cadd<R>(t1, t3);
-          buf[out + 5 * Ns] = csub<R>(t0, t2);
-          buf[out + 7 * Ns] = csub<R>(t1, t3);
+          buf[out + (1 << logNs)] = cadd<R>(t0, t2);
+          buf[out + (3 << logNs)] = cadd<R>(t1, t3);
+          buf[out + (5 << logNs)] = csub<R>(t0, t2);
+          buf[out + (7 << logNs)] = csub<R>(t1, t3);
         }
       }
     }
@@ -162,15 +163,15 @@ __device__ __attribute__((always_inline)) void lds_fft(cplx<R> *buf, int N, int 
     const int q4 = N >> 2;
     const int nbf = total >> 2;
     const int Ns = 1 << logNs;
-    const int step = kTwiddleN >> (logNs + 2);  // 4096 / (4 Ns)
+    const int lstep = kTwiddleLog - logNs - 2;  // step = 4096 / (4 Ns) = 2^lstep
     constexpr int B4 = (MAXV + 3) / 4;
     cplx<R> v[B4][4];
 #pragma unroll
     for (int t = 0; t < B4; ++t) {
       const int g = min(static_cast<int>(threadIdx.x) + t * NT, nbf - 1);
-      const int base = (g >> (logN - 2)) * N + (g & (q4 - 1));
+      const int base = ((g >> (logN - 2)) << logN) + (g & (q4 - 1));
 #pragma unroll
-      for (int r = 0; r < 4; ++r) v[t][r] = buf[base + r * q4];
+      for (int r = 0; r < 4; ++r) v[t][r] = buf[base + (r << (logN - 2))];
     }
     __syncthreads();
 #pragma unroll
@@ -181,8 +182,8 @@ __device__ __attribute__((always_inline)) void lds_fft(cplx<R> *buf, int N, int 
         const int j = g & (q4 - 1);
         const int k = j & (Ns - 1);
         cplx<R> a0 = v[t][0];
-        const cplx<R> w1 = twq<R>(q, k * step, logL, dir);
-        const cplx<R> w2 = twq<R>(q, 2 * k * step, logL, dir);
+        const cplx<R> w1 = twq<R>(q, k << lstep, logL, dir);
+        const cplx<R> w2 = twq<R>(q, k << (lstep + 1), logL, dir);
         cplx<R> a1 = cmul<R>(v[t][1], w1);
         cplx<R> a2 = cmul<R>(v[t][2], w2);
         cplx<R> a3 = cmul<R>(v[t][3], cmul<R>(w1, w2));
@@ -190,11 +191,11 @@ __device__ __attribute__((always_inline)) void lds_fft(cplx<R> *buf, int N, int 
         cplx<R> t2 = cadd<R>(a1, a3);
         // dir * i * (a1 - a3): -i for the forward transform, +i for the inverse
         cplx<R> t3 = rot4<R>(csub<R>(a1, a3), dir);
-        const int out = b * N + ((j >> logNs) << (logNs + 2)) + k;
+        const int out = (b << logN) + ((j >> logNs) << (logNs + 2)) + k;
         buf[out] = cadd<R>(t0, t2);
-        buf[out + Ns] = cadd<R>(t1, t3);
-        buf[out + 2 * Ns] = csub<R>(t0, t2);
-        buf[out + 3 * Ns] = csub<R>(t1, t3);
+        buf[out + (1 << logNs)] = cadd<R>(t1, t3);
+        buf[out + (2 << logNs)] = csub<R>(t0, t2);
+        buf[out + (3 << logNs)] = csub<R>(t1, t3);
       }
     }
     __syncthreads();
@@ -205,7 +206,7 @@ __device__ __attribute__((always_inline)) void lds_fft(cplx<R> *buf, int N, int 
     const int h2 = N >> 1;
     const int nbf = total >> 1;
     const int Ns = 1 << logNs;
-    const int step = kTwiddleN >> (logNs + 1);
+    const int lstep = kTwiddleLog - logNs - 1;  // step = 4096 / (2 Ns) = 2^lstep
     constexpr int B2 = (MAXV + 1) / 2;
     cplx<R> v[B2][2];
 #pragma unroll
@@ -213,8 +214,8 @@ __device__ __attribute__((always_inline)) void lds_fft(cplx<R> *buf, int N, int 
       const int g = min(static_cast<int>(threadIdx.x) + t * NT, nbf - 1);
       const int b = g >> (logN - 1);
       const int j = g & (h2 - 1);
-      v[t][0] = buf[b * N + j];
-      v[t][1] = buf[b * N + j + h2];
+      v[t][0] = buf[(b << logN) + j];
+      v[t][1] = buf[(b << logN) + j + h2];
     }
     __syncthreads();
 #pragma unroll
@@ -224,10 +225,10 @@ __device__ __attribute__((always_inline)) void lds_fft(cplx<R> *buf, int N, int 
         const int b = g >> (logN - 1);
         const int j = g & (h2 - 1);
         const int k = j & (Ns - 1);
-        cplx<R> a1 = cmul<R>(v[t][1], twq<R>(q, k * step, logL, dir));
-        const int out = b * N + ((j >> logNs) << (logNs + 1)) + k;
+        cplx<R> a1 = cmul<R>(v[t][1], twq<R>(q, k << lstep, logL, dir));
+        const int out = (b << logN) + ((j >> logNs) << (logNs + 1)) + k;
         buf[out] = cadd<R>(v[t][0], a1);
-        buf[out + Ns] = csub<R>(v[t][0], a1);
+        buf[out + (1 << logNs)] = csub<R>(v[t][0], a1);
       }
     }
     __syncthreads();
@@ -261,7 +262,7 @@ __device__ __forceinline__ int xcd_tile(int id, int ntiles) {
 template <typename Rin, typename R, int MAXV>
 __global__ __launch_bounds__(kFftThreads) __attribute__((amdgpu_waves_per_eu(2))) void r2c_t_kernel(
     const Rin *__restrict__ in, cplx<R> *__restrict__ spec, int n1, int n3, int logNh, int rows,
-    const cplx<R> *__restrict__ tw, int ntiles) {
+    const cplx<R> *__restrict__ tw, int ntiles, int logrows, int logn1) {
   extern __shared__ unsigned char smem_raw[];
   cplx<R> *buf = reinterpret_cast<cplx<R> *>(smem_raw);
   const int Nh = n3 >> 1;
@@ -286,7 +287,7 @@ __global__ __launch_bounds__(kFftThreads) __attribute__((amdgpu_waves_per_eu(2))
   };
   int id = blockIdx.x;
   if (id < ntiles) load(id);
-  const int step = kTwiddleN / n3;
+  const int lstep = kTwiddleLog - logL;  // 4096 / n3 = 2^lstep
   for (; id < ntiles; id += gridDim.x) {
     const int tile = xcd_tile(id, ntiles);
     const int f = tile / tiles;
@@ -301,14 +302,15 @@ __global__ __launch_bounds__(kFftThreads) __attribute__((amdgpu_waves_per_eu(2))
     lds_fft<R, kFftThreads, MAXV>(buf, Nh, logNh, rows, -1, q, logL);
     cplx<R> *dst = spec + static_cast<long long>(f) * h3 * n1 + x0;
     for (int e = threadIdx.x; e < rows * h3; e += kFftThreads) {
-      const int k = e / rows;
-      const int r = e - k * rows;
-      const cplx<R> zk = buf[r * Nh + (k == Nh ? 0 : k)];
-      const cplx<R> zc = cconj<R>(buf[r * Nh + (k == 0 ? 0 : Nh - k)]);
+      const int k = e >> logrows;
+      const int r = e & (rows - 1);
+      const int row = r << logNh;
+      const cplx<R> zk = buf[row + (k == Nh ? 0 : k)];
+      const cplx<R> zc = cconj<R>(buf[row + (k == 0 ? 0 : Nh - k)]);
       const cplx<R> ev = {(zk.x + zc.x) * R(0.5), (zk.y + zc.y) * R(0.5)};
       const cplx<R> od = {(zk.x - zc.x) * R(0.5), (zk.y - zc.y) * R(0.5)};
-      const cplx<R> t = cmul<R>(od, twq<R>(q, k * step, logL, -1));
-      dst[static_cast<long long>(k) * n1 + r] = cplx<R>{ev.x + t.y, ev.y - t.x};  // ev - i t
+      const cplx<R> t = cmul<R>(od, twq<R>(q, k << lstep, logL, -1));
+      dst[(static_cast<long long>(k) << logn1) + r] = cplx<R>{ev.x + t.y, ev.y - t.x};  // ev - i t
     }
     __syncthreads();  // the next tile overwrites buf
   }
@@ -357,7 +359,8 @@ __global__ __launch_bounds__(kFftThreads) void cfft_rows_kernel(
 template <typename R, int MAXV>
 __global__ __launch_bounds__(kFftThreads) void c2r_t_kernel(
     const cplx<R> *__restrict__ spec, R *__restrict__ out, const R *__restrict__ add, int n1,
-    int n3, int logNh, int rows, R scale, const cplx<R> *__restrict__ tw) {
+    int n3, int logNh, int rows, R scale, const cplx<R> *__restrict__ tw, int logrows, int logn1,
+    float inv_half) {
   extern __shared__ unsigned char smem_raw[];
   cplx<R> *buf = reinterpret_cast<cplx<R> *>(smem_raw);
   const int Nh = n3 >> 1;
@@ -379,30 +382,30 @@ __global__ __launch_bounds__(kFftThreads) void c2r_t_kernel(
 #pragma unroll
     for (int i = 0; i <= MAXV; ++i) {
       const int e = min(e0 + i * kFftThreads, nin - 1);  // clamped: loads without branches
-      const int k = e / rows;
-      v[i] = src[static_cast<long long>(k) * n1 + (e - k * rows)];
+      v[i] = src[(static_cast<long long>(e >> logrows) << logn1) + (e & (rows - 1))];
     }
 #pragma unroll
     for (int i = 0; i <= MAXV; ++i) {
       const int e = e0 + i * kFftThreads;
       if (e < nin) {
-        const int k = e / rows;
-        const int r = e - k * rows;
+        const int k = e >> logrows;
+        const int r = e & (rows - 1);
         if (k < Nh)
-          buf[r * Nh + k] = v[i];
+          buf[(r << logNh) + k] = v[i];
         else
           nyq[r] = v[i];
       }
     }
   }
   __syncthreads();
-  // pair (k, Nh - k) of each row
-  const int step = kTwiddleN / n3;
+  // pair (k, Nh - k) of each row; r = e / half in float32 (exact: e < 2^13 and
+  // (e + 1/2) / half stays at least 1 / (2 half) from an integer)
+  const int lstep = kTwiddleLog - logL;  // 4096 / n3 = 2^lstep
   const int half = Nh / 2 + 1;
   for (int e = threadIdx.x; e < rows * half; e += kFftThreads) {
-    const int r = e / half;
+    const int r = static_cast<int>((static_cast<float>(e) + 0.5f) * inv_half);
     const int k = e - r * half;
-    cplx<R> *row = buf + r * Nh;
+    cplx<R> *row = buf + (r << logNh);
     if (k == 0) {
       const R y0 = row[0].x, yn = nyq[r].x;
       row[0] = cplx<R>{y0 + yn, y0 - yn};
@@ -410,11 +413,11 @@ __global__ __launch_bounds__(kFftThreads) void c2r_t_kernel(
       const int m = Nh - k;
       const cplx<R> yk = row[k], ym = row[m];
       const cplx<R> a1 = cadd<R>(yk, cconj<R>(ym));
-      const cplx<R> b1 = cmul<R>(csub<R>(yk, cconj<R>(ym)), twq<R>(q, k * step, logL, +1));
+      const cplx<R> b1 = cmul<R>(csub<R>(yk, cconj<R>(ym)), twq<R>(q, k << lstep, logL, +1));
       row[k] = cplx<R>{a1.x - b1.y, a1.y + b1.x};
       if (m != k) {
         const cplx<R> a2 = cadd<R>(ym, cconj<R>(yk));
-        const cplx<R> b2 = cmul<R>(csub<R>(ym, cconj<R>(yk)), twq<R>(q, m * step, logL, +1));
+        const cplx<R> b2 = cmul<R>(csub<R>(ym, cconj<R>(yk)), twq<R>(q, m << lstep, logL, +1));
         row[m] = cplx<R>{a2.x - b2.y, a2.y + b2.x};
       }
     }
@@ -537,7 +540,7 @@ hipError_t forward_impl(const void *in, void *spec, int F, int n1, int n3, const
     hipLaunchKernelGGL(kernel, dim3(static_cast<unsigned>(persistent_grid(kernel, ntiles, lds))),
                        dim3(kFftThreads), lds, st, static_cast<const Rin *>(in),
                        static_cast<cplx<R> *>(spec), n1, n3, ilog2(Nh), rows,
-                       static_cast<const cplx<R> *>(tw), ntiles);
+                       static_cast<const cplx<R> *>(tw), ntiles, ilog2(rows), ilog2(n1));
     return hipGetLastError();
   });
   if (e != hipSuccess) return e;
@@ -557,7 +560,8 @@ hipError_t inverse_impl(const void *spec, void *scratch, void *out, const void *
                        (static_cast<size_t>(rows) * (Nh + 1) + n3 / 4) * sizeof(cplx<R>), st,
                        static_cast<const cplx<R> *>(scratch), static_cast<R *>(out),
                        static_cast<const R *>(add), n1, n3, ilog2(Nh), rows,
-                       static_cast<R>(scale), static_cast<const cplx<R> *>(tw));
+                       static_cast<R>(scale), static_cast<const cplx<R> *>(tw), ilog2(rows),
+                       ilog2(n1), 1.0f / static_cast<float>(Nh / 2 + 1));
     return hipGetLastError();
   });
 }
