@@ -422,14 +422,21 @@ __device__ __forceinline__ void quad_sweep(const SweepArgs &a, long long wg, int
     const float *run =
         static_cast<const float *>(a.ring) + uniform64(a.blk_off[b]) * (2LL * 3 * kLanes * 2);
     const int dstep = __builtin_amdgcn_readfirstlane(a.blk_stride[b]) * (2 * 3 * kLanes * 2);
+    // (byte counts and offsets in unsigned 32-bit arithmetic: they reach 2^32 - 1)
+    const unsigned udstep = static_cast<unsigned>(dstep);
     const __amdgpu_buffer_rsrc_t ring_rsrc = __builtin_amdgcn_make_buffer_rsrc(
-        const_cast<float *>(run), 0, ((cap - 1) * dstep + 2 * 3 * kLanes * 2) * 4, kBufferWord3);
+        const_cast<float *>(run), 0,
+        static_cast<int>((static_cast<unsigned>(cap - 1) * udstep + 2u * 3u * kLanes * 2u) * 4u),
+        kBufferWord3);
     const int col = ((p * 3) * kLanes + 4 * j + mq) * 2 + reim;
     // (the builtins return the loaded bits as integers)
     auto hist = [&](int x, int c) {
       return __builtin_bit_cast(
           float, __builtin_amdgcn_raw_buffer_load_b32(
-                     ring_rsrc, (x * dstep + col + c * kLanes * 2) * 4, 0, 0));
+                     ring_rsrc,
+                     static_cast<int>((static_cast<unsigned>(x) * udstep +
+                                       static_cast<unsigned>(col + c * kLanes * 2)) * 4u),
+                     0, 0));
     };
     auto row = [&](int r) {
       const v4f v = __builtin_bit_cast(
