@@ -309,12 +309,17 @@ int sbim_mode_kernel(sbim_handle *h, int p, int i1, int i3, double *host_out, in
 
 /*
  * Timing of the push / history sweep launch (the dominant kernel of a step):
- * when enabled, HIP events bracket each of its launches made by
- * sbim_push_displacement on the handle's stream; sbim_conv_timing synchronises
- * and returns the summed device time (ms) and the launch count since the last
- * sbim_profile_conv.
+ * with every = n >= 1, HIP events on the handle's stream bracket every n-th of
+ * its launches made by sbim_push_displacement (the first, the (n+1)-th, ...,
+ * counted from this call); every = 0 turns the timing off.  A bracketed launch
+ * also pays for its two event records (a few microseconds at the start and end
+ * of the launch), so sampling with n > 1 keeps that cost off most steps.
+ * sbim_conv_timing synchronises and returns the summed device time (ms) and
+ * the number of bracketed launches since the last sbim_profile_conv.
+ * Synchronises the handle's stream.  Errors: SBIM_E_INVALID for a NULL handle
+ * or every < 0.
  */
-int sbim_profile_conv(sbim_handle *h, int enable);
+int sbim_profile_conv(sbim_handle *h, int every);
 int sbim_conv_timing(sbim_handle *h, double *total_ms, long long *launches);
 
 /*

@@ -296,12 +296,14 @@ int sbim_mode_kernel(sbim_handle *h, int p, int i1, int i3, double *host_out, in
   return w;
 }
 
-int sbim_profile_conv(sbim_handle *h, int enable) {
+int sbim_profile_conv(sbim_handle *h, int every) {
   if (!h) return fail(nullptr, SBIM_E_INVALID, "handle is NULL");
+  if (every < 0) return fail(h, SBIM_E_INVALID, "sbim_profile_conv: every must be >= 0");
   hipError_t e = hipStreamSynchronize(h->stream);
   if (e != hipSuccess) return hip_fail(h, e, "sbim_profile_conv sync");
   h->ev_used = 0;
-  h->profile = enable != 0;
+  h->profile_every = every;
+  h->profile_seen = 0;
   return SBIM_OK;
 }
 

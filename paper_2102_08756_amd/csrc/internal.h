@@ -98,7 +98,8 @@ struct sbim_handle {
   void *out_spec = nullptr;       // [P][3][h3][n1] complex: traction spectrum of the last push
   void *out_adj = nullptr;        // the same for the last sbim_backward (allocated on first use)
   long long *count_scratch = nullptr;  // device address of the static partial counts (checks.hip)
-  bool profile = false;
+  int profile_every = 0;          // bracket every n-th step launch with events (0: off)
+  long long profile_seen = 0;     // step launches since sbim_profile_conv
   std::vector<hipEvent_t> ev_start, ev_stop;  // reusable pool
   size_t ev_used = 0;                          // pairs recorded since sbim_profile_conv
   std::string err;

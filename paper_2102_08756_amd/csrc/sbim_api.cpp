@@ -407,11 +407,11 @@ int ensure_adjoint(sbim_handle *h) {
 }
 
 // The launch of step `w.step` for one group (push, traction spectrum and the
-// sweep for the coming steps), bracketed by a pair of the handle's reusable
-// events while sbim_profile_conv is on.
+// sweep for the coming steps); while sbim_profile_conv is on, every n-th such
+// launch is bracketed by a pair of the handle's reusable events.
 int step_group(sbim_handle *h, Group &g, const sbim::StepLaunch &w, bool timed) {
   hipError_t e;
-  if (timed && h->profile) {
+  if (timed && h->profile_every > 0 && h->profile_seen++ % h->profile_every == 0) {
     if (h->ev_used == h->ev_start.size()) {  // grow the reusable event pool
       hipEvent_t e0, e1;
       if ((e = hipEventCreate(&e0)) != hipSuccess) return hip_fail(h, e, "hipEventCreate");

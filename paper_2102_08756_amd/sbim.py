@@ -373,8 +373,10 @@ class SBIM:
         w = np.frombuffer(buf, dtype=np.float64).reshape(4, max(max_lags, 1))[:, :min(rc, max_lags)]
         return rc, w.copy()
 
-    def profile_conv(self, enable=True):
-        self._check(self._L.sbim_profile_conv(self._h, 1 if enable else 0))
+    def profile_conv(self, enable=True, every=1):
+        """Time every ``every``-th step launch with HIP events (all of them by default);
+        ``enable=False`` turns the timing off."""
+        self._check(self._L.sbim_profile_conv(self._h, int(every) if enable else 0))
 
     def conv_timing(self):
         ms, n = ctypes.c_double(), ctypes.c_longlong()

@@ -282,3 +282,29 @@ def test_oversize_ring_is_refused_before_allocating():
     cfg_d = dict(SMALL["tiny4"], input_kind="absolute")
     u, _, _ = _inputs(cfg_d, 3, 5)
     np.testing.assert_allclose(run_gpu(cfg_d, u, "fp64"), oracle.forward(cfg_d, u), rtol=1e-10, atol=1e-12)
+
+
+@pytest.mark.parametrize("every", [1, 3])
+def test_launch_timing_every_nth(every):
+    """sbim_profile_conv(h, n) brackets the first step launch after the call and every n-th
+    after it; timing changes no result; n < 0 is refused."""
+    from paper_2102_08756_amd import SBIMError
+    cfg_d = dict(SMALL["two_planes_shared"], input_kind="increment")
+    u, _, _ = _inputs(cfg_d, 10, 11)
+    sb = SBIM(Config.from_dict(cfg_d, precision="fp32_comp"), device=DEV)
+    u_t = torch.tensor(u, dtype=torch.float32, device=DEV)
+    sb.profile_conv(True, every)
+    out = np.empty(u.shape)
+    for n in range(u.shape[0]):
+        sb.push(u_t[n])
+        out[n] = sb.tractions().double().cpu().numpy()
+    ms, launches = sb.conv_timing()
+    assert launches == (u.shape[0] + every - 1) // every
+    assert ms > 0.0
+    with pytest.raises(SBIMError, match="SBIM_E_INVALID"):
+        sb.profile_conv(True, -1)
+    sb.profile_conv(False)
+    sb.push(u_t[0])
+    assert sb.conv_timing() == (0.0, 0)
+    sb.close()
+    assert np.array_equal(out, run_gpu(cfg_d, u, "fp32_comp"))
