@@ -74,11 +74,26 @@ __device__ __forceinline__ cplx<R> rot4(cplx<R> a, int dir) {
   return dir < 0 ? cplx<R>{a.y, -a.x} : cplx<R>{-a.y, a.x};
 }
 
-// In-place FFT of nseq contiguous sequences of length N = 2^logN held in LDS:
-// Stockham autosort passes of radix 8 (then one of radix 4 or 2 for the
-// remaining factor).  Every thread of the work-group must call it.  Each pass
-// stages its inputs in registers, synchronises, then writes the outputs.
-template <typename R, int NT, int MAXV>
+// LDS slot of point i of a tile.  Padded tiles leave one slot unused after
+// every 8 points: the first radix-8 pass stores each thread's 8 outputs
+// contiguously (a 128-byte stride between the lanes for float64), which
+// without padding puts whole wavefronts on a few LDS banks.  Small tiles (at
+// most 4 points per thread) are padded; larger ones are not, since their LDS
+// size limits the work-groups per CU.
+template <bool PAD>
+__device__ __forceinline__ int pad(int i) {
+  return PAD ? i + (i >> 3) : i;
+}
+__host__ __device__ constexpr int padded_points(int cnt, bool pad) {
+  return pad ? cnt + (cnt + 7) / 8 : cnt;
+}
+
+// In-place FFT of nseq contiguous sequences of length N = 2^logN held in LDS
+// (point i at slot pad<PAD>(i)): Stockham autosort passes of radix 8 (then one
+// of radix 4 or 2 for the remaining factor).  Every thread of the work-group
+// must call it.  Each pass stages its inputs in registers, synchronises, then
+// writes the outputs.
+template <typename R, int NT, int MAXV, bool PAD>
 __device__ __attribute__((always_inline)) void lds_fft(cplx<R> *buf, int N, int logN, int nseq,
                                                        int dir, const cplx<R> *q, int logL) {
   const int total = N * nseq;
@@ -99,7 +114,7 @@ __device__ __attribute__((always_inline)) void lds_fft(cplx<R> *buf, int N, int 
       const int g = min(static_cast<int>(threadIdx.x) + t * NT, nbf - 1);
       const int base = ((g >> (logN - 3)) << logN) + (g & (q8 - 1));
 #pragma unroll
-      for (int r = 0; r < 8; ++r) v[t][r] = buf[base + (r << (logN - 3))];
+      for (int r = 0; r < 8; ++r) v[t][r] = buf[pad<PAD>(base + (r << (logN - 3)))];
     }
     __syncthreads();
 #pragma unroll
@@ -141,18 +156,18 @@ __device__ __attribute__((always_inline)) void lds_fft(cplx<R> *buf, int N, int 
         {
           const cplx<R> t0 = cadd<R>(e[0], e[2]), t1 = csub<R>(e[0], e[2]);
           const cplx<R> t2 = cadd<R>(e[1], e[3]), t3 = rot4<R>(csub<R>(e[1], e[3]), dir);
-          buf[out] = cadd<R>(t0, t2);
-          buf[out + (2 << logNs)] = cadd<R>(t1, t3);
-          buf[out + (4 << logNs)] = csub<R>(t0, t2);
-          buf[out + (6 << logNs)] = csub<R>(t1, t3);
+          buf[pad<PAD>(out)] = cadd<R>(t0, t2);
+          buf[pad<PAD>(out + (2 << logNs))] = cadd<R>(t1, t3);
+          buf[pad<PAD>(out + (4 << logNs))] = csub<R>(t0, t2);
+          buf[pad<PAD>(out + (6 << logNs))] = csub<R>(t1, t3);
         }
         {
           const cplx<R> t0 = cadd<R>(o[0], o[2]), t1 = csub<R>(o[0], o[2]);
           const cplx<R> t2 = cadd<R>(o[1], o[3]), t3 = rot4<R>(csub<R>(o[1], o[3]), dir);
-          buf[out + (1 << logNs)] = cadd<R>(t0, t2);
-          buf[out + (3 << logNs)] = cadd<R>(t1, t3);
-          buf[out + (5 << logNs)] = csub<R>(t0, t2);
-          buf[out + (7 << logNs)] = csub<R>(t1, t3);
+          buf[pad<PAD>(out + (1 << logNs))] = cadd<R>(t0, t2);
+          buf[pad<PAD>(out + (3 << logNs))] = cadd<R>(t1, t3);
+          buf[pad<PAD>(out + (5 << logNs))] = csub<R>(t0, t2);
+          buf[pad<PAD>(out + (7 << logNs))] = csub<R>(t1, t3);
         }
       }
     }
@@ -171,7 +186,7 @@ __device__ __attribute__((always_inline)) void lds_fft(cplx<R> *buf, int N, int 
       const int g = min(static_cast<int>(threadIdx.x) + t * NT, nbf - 1);
       const int base = ((g >> (logN - 2)) << logN) + (g & (q4 - 1));
 #pragma unroll
-      for (int r = 0; r < 4; ++r) v[t][r] = buf[base + (r << (logN - 2))];
+      for (int r = 0; r < 4; ++r) v[t][r] = buf[pad<PAD>(base + (r << (logN - 2)))];
     }
     __syncthreads();
 #pragma unroll
@@ -192,10 +207,10 @@ __device__ __attribute__((always_inline)) void lds_fft(cplx<R> *buf, int N, int 
         // dir * i * (a1 - a3): -i for the forward transform, +i for the inverse
         cplx<R> t3 = rot4<R>(csub<R>(a1, a3), dir);
         const int out = (b << logN) + ((j >> logNs) << (logNs + 2)) + k;
-        buf[out] = cadd<R>(t0, t2);
-        buf[out + (1 << logNs)] = cadd<R>(t1, t3);
-        buf[out + (2 << logNs)] = csub<R>(t0, t2);
-        buf[out + (3 << logNs)] = csub<R>(t1, t3);
+        buf[pad<PAD>(out)] = cadd<R>(t0, t2);
+        buf[pad<PAD>(out + (1 << logNs))] = cadd<R>(t1, t3);
+        buf[pad<PAD>(out + (2 << logNs))] = csub<R>(t0, t2);
+        buf[pad<PAD>(out + (3 << logNs))] = csub<R>(t1, t3);
       }
     }
     __syncthreads();
@@ -214,8 +229,8 @@ __device__ __attribute__((always_inline)) void lds_fft(cplx<R> *buf, int N, int 
       const int g = min(static_cast<int>(threadIdx.x) + t * NT, nbf - 1);
       const int b = g >> (logN - 1);
       const int j = g & (h2 - 1);
-      v[t][0] = buf[(b << logN) + j];
-      v[t][1] = buf[(b << logN) + j + h2];
+      v[t][0] = buf[pad<PAD>((b << logN) + j)];
+      v[t][1] = buf[pad<PAD>((b << logN) + j + h2)];
     }
     __syncthreads();
 #pragma unroll
@@ -227,8 +242,8 @@ __device__ __attribute__((always_inline)) void lds_fft(cplx<R> *buf, int N, int 
         const int k = j & (Ns - 1);
         cplx<R> a1 = cmul<R>(v[t][1], twq<R>(q, k << lstep, logL, dir));
         const int out = (b << logN) + ((j >> logNs) << (logNs + 1)) + k;
-        buf[out] = cadd<R>(v[t][0], a1);
-        buf[out + (1 << logNs)] = csub<R>(v[t][0], a1);
+        buf[pad<PAD>(out)] = cadd<R>(v[t][0], a1);
+        buf[pad<PAD>(out + (1 << logNs))] = csub<R>(v[t][0], a1);
       }
     }
     __syncthreads();
@@ -268,9 +283,10 @@ __global__ __launch_bounds__(kFftThreads) __attribute__((amdgpu_waves_per_eu(2))
   const int Nh = n3 >> 1;
   const int h3 = Nh + 1;
   const int tiles = n1 / rows;
+  constexpr bool PAD = MAXV == 4;
   const int cnt = rows * Nh;  // complex input points of a tile (<= kFftThreads * MAXV)
   const int logL = logNh + 1;  // twiddle period: n3
-  cplx<R> *q = buf + cnt;      // quarter table, after the tile
+  cplx<R> *q = buf + padded_points(cnt, PAD);  // quarter table, after the tile
   load_quarter<R>(q, logL, tw);
   cplx<Rin> pre[MAXV];
   auto load = [&](int id) {
@@ -295,18 +311,18 @@ __global__ __launch_bounds__(kFftThreads) __attribute__((amdgpu_waves_per_eu(2))
 #pragma unroll
     for (int i = 0; i < MAXV; ++i) {
       const int e = threadIdx.x + i * kFftThreads;
-      if (e < cnt) buf[e] = cplx<R>{static_cast<R>(pre[i].x), static_cast<R>(pre[i].y)};
+      if (e < cnt) buf[pad<PAD>(e)] = cplx<R>{static_cast<R>(pre[i].x), static_cast<R>(pre[i].y)};
     }
     __syncthreads();
     if (id + static_cast<int>(gridDim.x) < ntiles) load(id + gridDim.x);
-    lds_fft<R, kFftThreads, MAXV>(buf, Nh, logNh, rows, -1, q, logL);
+    lds_fft<R, kFftThreads, MAXV, PAD>(buf, Nh, logNh, rows, -1, q, logL);
     cplx<R> *dst = spec + static_cast<long long>(f) * h3 * n1 + x0;
     for (int e = threadIdx.x; e < rows * h3; e += kFftThreads) {
       const int k = e >> logrows;
       const int r = e & (rows - 1);
       const int row = r << logNh;
-      const cplx<R> zk = buf[row + (k == Nh ? 0 : k)];
-      const cplx<R> zc = cconj<R>(buf[row + (k == 0 ? 0 : Nh - k)]);
+      const cplx<R> zk = buf[pad<PAD>(row + (k == Nh ? 0 : k))];
+      const cplx<R> zc = cconj<R>(buf[pad<PAD>(row + (k == 0 ? 0 : Nh - k))]);
       const cplx<R> ev = {(zk.x + zc.x) * R(0.5), (zk.y + zc.y) * R(0.5)};
       const cplx<R> od = {(zk.x - zc.x) * R(0.5), (zk.y - zc.y) * R(0.5)};
       const cplx<R> t = cmul<R>(od, twq<R>(q, k << lstep, logL, -1));
@@ -323,8 +339,9 @@ __global__ __launch_bounds__(kFftThreads) void cfft_rows_kernel(
     const cplx<R> *src, cplx<R> *dst, long long nrows, int n, int logn, int per, int dir,
     const cplx<R> *__restrict__ tw) {
   extern __shared__ unsigned char smem_raw[];
+  constexpr bool PAD = MAXV == 4;
   cplx<R> *buf = reinterpret_cast<cplx<R> *>(smem_raw);
-  cplx<R> *q = buf + per * n;  // quarter table of period n, after the rows
+  cplx<R> *q = buf + padded_points(per * n, PAD);  // quarter table of period n, after the rows
   load_quarter<R>(q, logn, tw);
   const long long row0 = static_cast<long long>(blockIdx.x) * per;
   const int nb = static_cast<int>(min(static_cast<long long>(per), nrows - row0));
@@ -340,13 +357,13 @@ __global__ __launch_bounds__(kFftThreads) void cfft_rows_kernel(
   // past cnt a lane rewrites point cnt - 1 with its own value)
 #pragma unroll
   for (int i = 0; i < MAXV; ++i)
-    buf[min(static_cast<int>(threadIdx.x) + i * kFftThreads, cnt - 1)] = v[i];
+    buf[pad<PAD>(min(static_cast<int>(threadIdx.x) + i * kFftThreads, cnt - 1))] = v[i];
   __syncthreads();
-  lds_fft<R, kFftThreads, MAXV>(buf, n, logn, nb, dir, q, logn);
+  lds_fft<R, kFftThreads, MAXV, PAD>(buf, n, logn, nb, dir, q, logn);
 #pragma unroll
   for (int i = 0; i < MAXV; ++i) {
     const int e = threadIdx.x + i * kFftThreads;
-    if (e < cnt) dst[row0 * n + e] = buf[e];
+    if (e < cnt) dst[row0 * n + e] = buf[pad<PAD>(e)];
   }
 }
 
@@ -362,10 +379,11 @@ __global__ __launch_bounds__(kFftThreads) void c2r_t_kernel(
     int n3, int logNh, int rows, R scale, const cplx<R> *__restrict__ tw, int logrows, int logn1,
     float inv_half) {
   extern __shared__ unsigned char smem_raw[];
+  constexpr bool PAD = MAXV == 4;
   cplx<R> *buf = reinterpret_cast<cplx<R> *>(smem_raw);
   const int Nh = n3 >> 1;
   const int h3 = Nh + 1;
-  cplx<R> *nyq = buf + rows * Nh;  // bin k = Nh of each row
+  cplx<R> *nyq = buf + padded_points(rows * Nh, PAD);  // bin k = Nh of each row
   const int logL = logNh + 1;       // twiddle period: n3
   cplx<R> *q = nyq + rows;          // quarter table
   load_quarter<R>(q, logL, tw);
@@ -391,7 +409,7 @@ __global__ __launch_bounds__(kFftThreads) void c2r_t_kernel(
         const int k = e >> logrows;
         const int r = e & (rows - 1);
         if (k < Nh)
-          buf[(r << logNh) + k] = v[i];
+          buf[pad<PAD>((r << logNh) + k)] = v[i];
         else
           nyq[r] = v[i];
       }
@@ -405,25 +423,25 @@ __global__ __launch_bounds__(kFftThreads) void c2r_t_kernel(
   for (int e = threadIdx.x; e < rows * half; e += kFftThreads) {
     const int r = static_cast<int>((static_cast<float>(e) + 0.5f) * inv_half);
     const int k = e - r * half;
-    cplx<R> *row = buf + (r << logNh);
+    const int rb = r << logNh;  // the row's first point
     if (k == 0) {
-      const R y0 = row[0].x, yn = nyq[r].x;
-      row[0] = cplx<R>{y0 + yn, y0 - yn};
+      const R y0 = buf[pad<PAD>(rb)].x, yn = nyq[r].x;
+      buf[pad<PAD>(rb)] = cplx<R>{y0 + yn, y0 - yn};
     } else {
       const int m = Nh - k;
-      const cplx<R> yk = row[k], ym = row[m];
+      const cplx<R> yk = buf[pad<PAD>(rb + k)], ym = buf[pad<PAD>(rb + m)];
       const cplx<R> a1 = cadd<R>(yk, cconj<R>(ym));
       const cplx<R> b1 = cmul<R>(csub<R>(yk, cconj<R>(ym)), twq<R>(q, k << lstep, logL, +1));
-      row[k] = cplx<R>{a1.x - b1.y, a1.y + b1.x};
+      buf[pad<PAD>(rb + k)] = cplx<R>{a1.x - b1.y, a1.y + b1.x};
       if (m != k) {
         const cplx<R> a2 = cadd<R>(ym, cconj<R>(yk));
         const cplx<R> b2 = cmul<R>(csub<R>(ym, cconj<R>(yk)), twq<R>(q, m << lstep, logL, +1));
-        row[m] = cplx<R>{a2.x - b2.y, a2.y + b2.x};
+        buf[pad<PAD>(rb + m)] = cplx<R>{a2.x - b2.y, a2.y + b2.x};
       }
     }
   }
   __syncthreads();
-  lds_fft<R, kFftThreads, MAXV>(buf, Nh, logNh, rows, +1, q, logL);
+  lds_fft<R, kFftThreads, MAXV, PAD>(buf, Nh, logNh, rows, +1, q, logL);
   const long long o = (static_cast<long long>(f) * n1 + x0) * n3;
   cplx<R> *dst = reinterpret_cast<cplx<R> *>(out + o);
   const cplx<R> *addp = add ? reinterpret_cast<const cplx<R> *>(add + o) : nullptr;
@@ -439,7 +457,7 @@ __global__ __launch_bounds__(kFftThreads) void c2r_t_kernel(
   for (int i = 0; i < MAXV; ++i) {
     const int e = threadIdx.x + i * kFftThreads;
     if (e < nout) {
-      cplx<R> z = buf[e];
+      cplx<R> z = buf[pad<PAD>(e)];
       z.x *= scale;
       z.y *= scale;
       if (addp) {
@@ -519,9 +537,10 @@ hipError_t cfft_launch(const void *src, void *dst, long long nrows, int n, int d
                        const void *tw, hipStream_t st) {
   const int per = rows_per_group(n);
   return with_maxv(per * n, [&](auto mv) {
+    constexpr bool pad = decltype(mv)::value == 4;  // as the kernel pads its tile
     hipLaunchKernelGGL((cfft_rows_kernel<R, decltype(mv)::value>),
                        dim3(static_cast<unsigned>((nrows + per - 1) / per)), dim3(kFftThreads),
-                       (static_cast<size_t>(per) * n + n / 4) * sizeof(cplx<R>), st,
+                       (static_cast<size_t>(padded_points(per * n, pad)) + n / 4) * sizeof(cplx<R>), st,
                        static_cast<const cplx<R> *>(src), static_cast<cplx<R> *>(dst), nrows, n,
                        ilog2(n), per, dir, static_cast<const cplx<R> *>(tw));
     return hipGetLastError();
@@ -534,8 +553,9 @@ hipError_t forward_impl(const void *in, void *spec, int F, int n1, int n3, const
   const int Nh = n3 / 2, h3 = Nh + 1;
   const int rows = tile_rows(n1, Nh, sizeof(cplx<R>), 0);
   const int ntiles = F * (n1 / rows);
-  const size_t lds = (static_cast<size_t>(rows) * Nh + n3 / 4) * sizeof(cplx<R>);
   hipError_t e = with_maxv(rows * Nh, [&](auto mv) {
+    constexpr bool pad = decltype(mv)::value == 4;  // as the kernel pads its tile
+    const size_t lds = (static_cast<size_t>(padded_points(rows * Nh, pad)) + n3 / 4) * sizeof(cplx<R>);
     auto kernel = r2c_t_kernel<Rin, R, decltype(mv)::value>;
     hipLaunchKernelGGL(kernel, dim3(static_cast<unsigned>(persistent_grid(kernel, ntiles, lds))),
                        dim3(kFftThreads), lds, st, static_cast<const Rin *>(in),
@@ -555,9 +575,12 @@ hipError_t inverse_impl(const void *spec, void *scratch, void *out, const void *
   if (e != hipSuccess) return e;
   const int rows = tile_rows(n1, Nh, sizeof(cplx<R>), 1);
   return with_maxv(rows * Nh, [&](auto mv) {
+    constexpr bool pad = decltype(mv)::value == 4;  // as the kernel pads its tile
     hipLaunchKernelGGL((c2r_t_kernel<R, decltype(mv)::value>),
                        dim3(static_cast<unsigned>(F * (n1 / rows))), dim3(kFftThreads),
-                       (static_cast<size_t>(rows) * (Nh + 1) + n3 / 4) * sizeof(cplx<R>), st,
+                       (static_cast<size_t>(padded_points(rows * Nh, pad)) + rows + n3 / 4) *
+                           sizeof(cplx<R>),
+                       st,
                        static_cast<const cplx<R> *>(scratch), static_cast<R *>(out),
                        static_cast<const R *>(add), n1, n3, ilog2(Nh), rows,
                        static_cast<R>(scale), static_cast<const cplx<R> *>(tw), ilog2(rows),
