@@ -795,6 +795,17 @@ __device__ __forceinline__ void mode_step(const ModeArgs &a, int p, long long s)
   }
 }
 
+// Mode items in XCD-contiguous order.  Work-group ids go round-robin over the 8
+// XCDs, so id m of a launch's mode part (which starts at a multiple of 8) runs on
+// XCD m mod 8; it takes item (m mod 8) * per + m / 8 of the n items, so each XCD
+// works through a contiguous eighth of the sorted blocks (nearby q), whose
+// natural-order spectrum gathers and traction scatters then share cache lines
+// in that XCD's L2.  The mode part has 8 * per ids; the ones past n return.
+__device__ __forceinline__ long long xcd_chunk(long long m, long long n) {
+  return (m & 7) * ((n + 7) / 8) + (m >> 3);
+}
+inline long long xcd_chunk_ids(long long n) { return (n + 7) / 8 * 8; }
+
 // One launch per step of mode-space work: the sweep items of the blocks whose
 // turn it is, then one mode item per (64-mode block, plane).  The two kinds
 // share no data (see sweep_item), so the latency-bound push gathers and
@@ -807,7 +818,8 @@ __device__ __forceinline__ void step_items(const SweepArgs &sa, const ModeArgs &
     sweep_item<R, S, T, COMP>(sa, item);
     return;
   }
-  const long long k = item - sweep_items;
+  const long long k = xcd_chunk(item - sweep_items, nblocks * ma.np);
+  if (k >= nblocks * ma.np) return;
   const int p = static_cast<int>(k / nblocks);
   const long long s = (k - p * nblocks) * kLanes + threadIdx.x;
   if (s < ma.M) mode_step<R, COMP>(ma, p, s);
@@ -849,7 +861,10 @@ step_kernel_mfma(SweepArgs sa, ModeArgs ma, long long sweep_wgs, long long nbloc
     quad_sweep<COMP, G>(sa, wg, LG, QW, quad_lds);
     return;
   }
-  const long long k = (wg - sweep_wgs) * (LG * QW) + (threadIdx.x >> 6);
+  const long long mode_wgs = (nblocks * ma.np + LG * QW - 1) / (LG * QW);
+  const long long mw = xcd_chunk(wg - sweep_wgs, mode_wgs);
+  if (mw >= mode_wgs) return;
+  const long long k = mw * (LG * QW) + (threadIdx.x >> 6);
   if (k >= nblocks * ma.np) return;
   const int p = static_cast<int>(k / nblocks);
   const long long s = (k - p * nblocks) * kLanes + (threadIdx.x & 63);
@@ -1010,7 +1025,7 @@ hipError_t step_launch_s(const sbim_handle *h, const Group &g, const SweepArgs &
   sa.nphase = g.nblocks > phase ? (g.nblocks - phase + D - 1) / D : 0;
   const long long sweep_items =
       (sa.nphase + 7) / 8 * 8 * (sweep_lag_groups<R, S, T, COMP>() * T) * g.np;
-  const long long items = sweep_items + g.nblocks * g.np;
+  const long long items = sweep_items + xcd_chunk_ids(g.nblocks * g.np);
   if (ev0) {
     const hipError_t e = hipEventRecord(ev0, h->stream);
     if (e != hipSuccess) return e;
@@ -1050,7 +1065,8 @@ hipError_t step_launch_q(const sbim_handle *h, const Group &g, const SweepArgs &
   // two-wavefront work-groups leave the 1040 quads of a 512^2 phase a second
   // round (measured on gfx950: 4-8% slower).
   constexpr int WAVES = 3;
-  hipLaunchKernelGGL((step_kernel_mfma<COMP, G, WAVES>), dim3(static_cast<unsigned>(sweep_wgs + mode_wgs)),
+  hipLaunchKernelGGL((step_kernel_mfma<COMP, G, WAVES>),
+                     dim3(static_cast<unsigned>(sweep_wgs + xcd_chunk_ids(mode_wgs))),
                      dim3(LG * QW * kLanes), lds, h->stream, sa, ma, sweep_wgs, g.nblocks, LG, QW);
   hipError_t e = hipGetLastError();
   if (e == hipSuccess && ev1) e = hipEventRecord(ev1, h->stream);
