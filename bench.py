@@ -149,6 +149,12 @@ def default_timed_steps(wl):
     return max(1, wl.steps - wl.window_cap)
 
 
+def bracketed_steps(n0, steps, every):
+    """The timed steps whose step launch sbim_profile_conv(h, every) brackets with events:
+    the first after the call and every ``every``-th after it."""
+    return range(n0, n0 + steps, every)
+
+
 def measure_form(wl, precision, steps, warmup, device, inputs_cache):
     """Time ``steps`` steps of the job at a full history window: ``warmup`` steps and a
     reset, the job's first steps untimed (the window fills), then the timed ones."""
@@ -185,10 +191,11 @@ def measure_form(wl, precision, steps, warmup, device, inputs_cache):
     sb.profile_conv(False)
     lags = 0.0
     conv_lags = conv_bytes = 0.0   # mode-lags and algorithmic bytes of the bracketed launches
+    bracketed = set(bracketed_steps(n0, steps, every))
     for n in range(n0, n0 + steps):
         a, b = sb.step_work(n)
         lags += a
-        if (n - n0) % every == 0:
+        if n in bracketed:
             conv_lags += a
             conv_bytes += b
     info = sb.info()

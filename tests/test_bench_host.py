@@ -67,6 +67,21 @@ def test_timed_steps_start_at_a_full_window():
         assert min(wl.window_cap, n0 + 1) == wl.window_cap
 
 
+def test_bracketed_launches_meet_every_sweep_phase():
+    """bench.py times the step launch of every TIMING_EVERY-th timed step; the stride is
+    prime to every sweep depth the library picks, so over one default run the bracketed
+    steps meet each phase (n + 1) mod D of the sweep, and their count is what
+    sbim_conv_timing returns for that run."""
+    import math
+    every = bench.TIMING_EVERY
+    for depth in (1, 2, 4, 6, 8, 12, 16, 32):
+        assert math.gcd(every, depth) == 1
+        phases = {(n + 1) % depth for n in bench.bracketed_steps(1000, 1000, every)}
+        assert phases == set(range(depth))
+    assert len(bench.bracketed_steps(1980, 20, every)) == 3
+    assert list(bench.bracketed_steps(1000, 15, every)) == [1000, 1007, 1014]
+
+
 def test_host_cpu_reports_cores_and_model():
     h = bench.host_cpu()
     assert h["nproc"] >= 1 and h["logical_cpus"] >= h["nproc"]
