@@ -48,11 +48,12 @@ PROFILES = os.path.join(ROOT, "profiles")
 
 
 def kernel_source_hash():
-    """Hash of the kernel sources with comments and blank lines stripped (a comment edit
-    does not invalidate recorded counters; any code change does)."""
+    """Hash of the step kernel's sources and of the host code that picks its launch shape,
+    with comments and blank lines stripped (a comment edit does not invalidate recorded
+    counters; any code change does)."""
     import re
     h = hashlib.sha256()
-    for f in ("kernels.hip", "internal.h"):
+    for f in ("kernels.hip", "internal.h", "sbim_api.cpp"):
         with open(os.path.join(ROOT, "paper_2102_08756_amd", "csrc", f)) as fh:
             for line in fh:
                 code = re.sub(r"//.*", "", line).rstrip()

@@ -609,11 +609,11 @@ int sbim_init(const sbim_config *cfg, sbim_handle **out) {
     }
     // Quads per work-group: neighbouring quads of a block share the cache lines
     // of their history (a line holds 4 quads' pieces), and in one work-group they
-    // stream them together.  Measured on gfx950: two for the compensated form when
-    // a phase has 2048 quads or more (1024^2 at W = 2000: 5% faster), else one
-    // (two planes 512^2 at W = 1000, and plain float32 with four lag ranges).
-    const long long quads = (g.nblocks + h->depth - 1) / h->depth * 16;
-    h->sweep_quads = (h->comp && quads >= 2048 && h->lag_chunks <= 2) ? 2 : 1;
+    // stream them together.  Measured on gfx950: two for the compensated form
+    // (1024^2 at W = 2000: 5% faster; 512^2 at W = 1000: 1% faster since the
+    // mode items run XCD-contiguous, 1% slower before), one for plain float32 with
+    // its four lag ranges (two quads of two ranges: 6% slower at 512^2).
+    h->sweep_quads = (h->comp && h->lag_chunks <= 2) ? 2 : 1;
     if (const char *env = std::getenv("SBIM_SWEEP_QUADS")) {  // tuning override
       const int v = std::atoi(env);
       if ((v == 1 || v == 2 || v == 4) && v * h->lag_chunks <= 4) h->sweep_quads = v;
