@@ -131,8 +131,8 @@ typedef struct {
                                   SBIM_SWEEP_CHUNKS overrides it, for tuning */
   int sweep_quads;             /* matrix-core sweep: groups of four modes per work-group
                                   (1, 2 or 4, at most 4 / sweep_lag_chunks; 0 otherwise):
-                                  2 for the compensated form when a sweep phase holds 2048
-                                  groups or more, else 1; SBIM_SWEEP_QUADS overrides it,
+                                  2 for the compensated form (two lag ranges), 1 for
+                                  plain float32 (four); SBIM_SWEEP_QUADS overrides it,
                                   for tuning */
 } sbim_info;
 
