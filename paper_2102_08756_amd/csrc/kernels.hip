@@ -1061,9 +1061,10 @@ hipError_t step_launch_q(const sbim_handle *h, const Group &g, const SweepArgs &
     if (e != hipSuccess) return e;
   }
   // Register budget: three wavefronts per SIMD (168 registers; the compensated
-  // two-group form takes 165).  At two wavefronts per SIMD the 1024 resident
-  // two-wavefront work-groups leave the 1040 quads of a 512^2 phase a second
-  // round (measured on gfx950: 4-8% slower).
+  // two-group form takes 165).  At two wavefronts per SIMD the 2080 sweep
+  // wavefronts of a 512^2 phase (1040 quads, two lag ranges each) do not all
+  // fit at once, and the rest take a second round (measured on gfx950 with one
+  // quad per work-group: 4-8% slower).
   constexpr int WAVES = 3;
   hipLaunchKernelGGL((step_kernel_mfma<COMP, G, WAVES>),
                      dim3(static_cast<unsigned>(sweep_wgs + xcd_chunk_ids(mode_wgs))),
